@@ -1,0 +1,830 @@
+/*
+ * hrpp_oracle.c -- TEST INFRASTRUCTURE ONLY (not part of the product).
+ *
+ * A plain, slow, sequential-per-ray CPU model of Hash-Based Ray Path
+ * Prediction (HRPP; Demoullin, Gubran and Aamodt, "Hash-Based Ray Path
+ * Prediction: Skipping BVH Traversal Computation by Exploiting Ray
+ * Locality").  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this file.  It shares no code, header or
+ * constant table with the GPU library; the two meet only through the
+ * seeded inputs and the canonical BVH export.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ * Every floating-point operation below is a single IEEE-754 binary32
+ * operation, rounded to nearest-even, with no contraction and no
+ * flush-to-zero, in the order written.
+ *
+ * What the paper fixes and what is our reading is stated at each function.
+ * Sections cited: "Overview" (HRPP direct flow), "Precision and Recall"
+ * (true/false positives, re-adding failed rays to the ray pool),
+ * "HRPP Hash Function" (conflict insertion without duplicates), "Limit
+ * Study" (separate hit-any / hit-all predictors, no replacement policy).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <omp.h>
+
+#define NONE32 0xFFFFFFFFu
+#define EMPTY_TAG 0xFFFFFFFFFFFFFFFFull
+
+/* Counter slots (all uint64).  The order is part of the oracle's interface. */
+enum {
+    S_RAYS, S_INVALID, S_HITS, S_LOOKUPS, S_POSITIVES, S_PRED_HITS, S_FALSE_POS,
+    S_TRAVERSALS, S_NODES_VISITED, S_INTERIOR_VISITED, S_LEAF_VISITED, S_BOX_TESTS,
+    S_TRI_TESTS, S_NODES_SKIPPED, S_RECORDS, S_TAG_CLAIMS, S_LEAF_INSERTS, S_DROPPED,
+    S_CONFLICTS, S_COUNT
+};
+#define STATS_SLOTS 24
+
+/* ------------------------------------------------------------------------ */
+/* Scalar helpers: IEEE minNum / maxNum (a NaN operand is ignored).          */
+/* ------------------------------------------------------------------------ */
+static float min_num(float a, float b)
+{
+    if (a != a) return b;
+    if (b != b) return a;
+    return (b < a) ? b : a;
+}
+static float max_num(float a, float b)
+{
+    if (a != a) return b;
+    if (b != b) return a;
+    return (b > a) ? b : a;
+}
+static float bits_to_float(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+static uint32_t float_to_bits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+
+/* ------------------------------------------------------------------------ */
+/* Canonical BVH (the layout both builders export).                          */
+/* Nodes in depth-first pre-order; an interior node's left child is the     */
+/* next node, its right child is right[i]; a leaf has right[i] = NONE32 and  */
+/* owns triangles [first[i], first[i]+count[i]) of the BVH-ordered array.    */
+/* depth[i] = number of interior ancestors.  perm[k] = original primitive id */
+/* of BVH-ordered triangle k.                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t num_nodes;
+    uint32_t num_tris;
+    float *box;        /* 6 per node: min xyz, max xyz */
+    uint32_t *right;
+    uint32_t *first;
+    uint32_t *count;
+    uint32_t *depth;
+    uint32_t *perm;
+} orc_bvh;
+
+/* ======================================================================== */
+/* BVH construction (the paper treats the BVH as given; this is our         */
+/* deterministic binned-SAH reading, specified so that an independent       */
+/* implementation reproduces it bit for bit).                               */
+/* ======================================================================== */
+typedef struct {
+    const float *tris;   /* 9 floats per original triangle */
+    float *tb;           /* per original triangle: bounds min xyz, max xyz */
+    float *tc;           /* per original triangle: centroid xyz */
+    uint32_t *idx;       /* working permutation */
+    uint32_t *tmp;
+    orc_bvh *out;
+    uint32_t leaf_max, bins, max_depth;
+    int error;
+} build_ctx;
+
+/* half surface area of a box, in double */
+static double half_area(const float *mn, const float *mx)
+{
+    double dx = (double)mx[0] - (double)mn[0];
+    double dy = (double)mx[1] - (double)mn[1];
+    double dz = (double)mx[2] - (double)mn[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+static uint32_t bin_of(float c, float cmin, float k, uint32_t bins)
+{
+    float f = (c - cmin) * k;
+    uint32_t b = (uint32_t)f;             /* f >= 0 and finite here */
+    if (b > bins - 1) b = bins - 1;
+    return b;
+}
+
+static uint32_t build_node(build_ctx *ctx, uint32_t begin, uint32_t end, uint32_t depth)
+{
+    orc_bvh *o = ctx->out;
+    uint32_t node = o->num_nodes++;
+    uint32_t n = end - begin;
+    float mn[3] = { INFINITY, INFINITY, INFINITY }, mx[3] = { -INFINITY, -INFINITY, -INFINITY };
+    float cmn[3] = { INFINITY, INFINITY, INFINITY }, cmx[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (uint32_t i = begin; i < end; i++) {
+        const float *b = ctx->tb + 6 * (size_t)ctx->idx[i];
+        const float *c = ctx->tc + 3 * (size_t)ctx->idx[i];
+        for (int a = 0; a < 3; a++) {
+            if (b[a] < mn[a]) mn[a] = b[a];
+            if (b[a + 3] > mx[a]) mx[a] = b[a + 3];
+            if (c[a] < cmn[a]) cmn[a] = c[a];
+            if (c[a] > cmx[a]) cmx[a] = c[a];
+        }
+    }
+    for (int a = 0; a < 3; a++) { o->box[6 * node + a] = mn[a]; o->box[6 * node + 3 + a] = mx[a]; }
+    o->depth[node] = depth;
+    if (n <= ctx->leaf_max) {
+        o->right[node] = NONE32;
+        o->first[node] = begin;
+        o->count[node] = n;
+        return node;
+    }
+    if (depth + 1 > ctx->max_depth) { ctx->error = 1; o->right[node] = NONE32; o->first[node] = begin; o->count[node] = n; return node; }
+
+    /* binned SAH: cost(split) = A(L)*|L| + A(R)*|R|; minimal cost wins,
+       ties go to the smaller axis, then the smaller split position */
+    uint32_t B = ctx->bins;
+    double best = INFINITY;
+    int best_axis = -1;
+    uint32_t best_split = 0;
+    float best_k = 0.0f;
+    uint32_t *cnt = (uint32_t *)malloc(sizeof(uint32_t) * B);
+    float *bmn = (float *)malloc(sizeof(float) * 3 * B), *bmx = (float *)malloc(sizeof(float) * 3 * B);
+    for (int a = 0; a < 3; a++) {
+        float extent = cmx[a] - cmn[a];
+        if (!(extent > 0.0f)) continue;
+        float k = (float)B / extent;
+        if (!isfinite(k)) continue;
+        for (uint32_t j = 0; j < B; j++) {
+            cnt[j] = 0;
+            for (int q = 0; q < 3; q++) { bmn[3 * j + q] = INFINITY; bmx[3 * j + q] = -INFINITY; }
+        }
+        for (uint32_t i = begin; i < end; i++) {
+            uint32_t t = ctx->idx[i];
+            uint32_t j = bin_of(ctx->tc[3 * (size_t)t + a], cmn[a], k, B);
+            const float *b = ctx->tb + 6 * (size_t)t;
+            cnt[j]++;
+            for (int q = 0; q < 3; q++) {
+                if (b[q] < bmn[3 * j + q]) bmn[3 * j + q] = b[q];
+                if (b[q + 3] > bmx[3 * j + q]) bmx[3 * j + q] = b[q + 3];
+            }
+        }
+        for (uint32_t s = 1; s < B; s++) {
+            float lmn[3] = { INFINITY, INFINITY, INFINITY }, lmx[3] = { -INFINITY, -INFINITY, -INFINITY };
+            float rmn[3] = { INFINITY, INFINITY, INFINITY }, rmx[3] = { -INFINITY, -INFINITY, -INFINITY };
+            uint32_t nl = 0, nr = 0;
+            for (uint32_t j = 0; j < B; j++) {
+                float *xmn = j < s ? lmn : rmn, *xmx = j < s ? lmx : rmx;
+                if (j < s) nl += cnt[j]; else nr += cnt[j];
+                if (cnt[j] == 0) continue;
+                for (int q = 0; q < 3; q++) {
+                    if (bmn[3 * j + q] < xmn[q]) xmn[q] = bmn[3 * j + q];
+                    if (bmx[3 * j + q] > xmx[q]) xmx[q] = bmx[3 * j + q];
+                }
+            }
+            if (nl == 0 || nr == 0) continue;
+            double cost = half_area(lmn, lmx) * (double)nl + half_area(rmn, rmx) * (double)nr;
+            if (cost < best) { best = cost; best_axis = a; best_split = s; best_k = k; }
+        }
+    }
+    free(cnt); free(bmn); free(bmx);
+
+    uint32_t mid;
+    if (best_axis < 0) {
+        mid = begin + n / 2;          /* all centroids coincide: split the list in half */
+    } else {
+        /* stable partition: bin < split goes left, original relative order kept */
+        uint32_t w = begin;
+        uint32_t r = 0;
+        for (uint32_t i = begin; i < end; i++) {
+            uint32_t t = ctx->idx[i];
+            if (bin_of(ctx->tc[3 * (size_t)t + best_axis], cmn[best_axis], best_k, B) < best_split) ctx->idx[w++] = t;
+            else ctx->tmp[r++] = t;
+        }
+        memcpy(ctx->idx + w, ctx->tmp, sizeof(uint32_t) * r);
+        mid = w;
+    }
+    o->first[node] = 0;
+    o->count[node] = 0;
+    build_node(ctx, begin, mid, depth + 1);
+    o->right[node] = build_node(ctx, mid, end, depth + 1);
+    return node;
+}
+
+/* Build the binned-SAH BVH.  Arrays of out must hold 2n-1 nodes and n
+   permutation entries.  Returns 0 on success, -1 on bad input, -2 when a
+   leaf would exceed max_depth. */
+int orc_build_sah(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t bins,
+                  uint32_t max_depth, orc_bvh *out)
+{
+    if (n == 0 || leaf_max < 1 || leaf_max > 8 || bins < 2 || n >= (1u << 28) || max_depth > 120) return -1;
+    for (size_t i = 0; i < 9 * (size_t)n; i++) if (!isfinite(tris[i])) return -1;
+    build_ctx ctx;
+    memset(&ctx, 0, sizeof ctx);
+    ctx.tris = tris;
+    ctx.tb = (float *)malloc(sizeof(float) * 6 * (size_t)n);
+    ctx.tc = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+    ctx.idx = out->perm;
+    ctx.tmp = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    ctx.out = out;
+    ctx.leaf_max = leaf_max; ctx.bins = bins; ctx.max_depth = max_depth;
+    for (uint32_t t = 0; t < n; t++) {
+        const float *v = tris + 9 * (size_t)t;
+        for (int a = 0; a < 3; a++) {
+            float lo = v[a], hi = v[a];
+            if (v[3 + a] < lo) lo = v[3 + a];
+            if (v[6 + a] < lo) lo = v[6 + a];
+            if (v[3 + a] > hi) hi = v[3 + a];
+            if (v[6 + a] > hi) hi = v[6 + a];
+            ctx.tb[6 * (size_t)t + a] = lo;
+            ctx.tb[6 * (size_t)t + 3 + a] = hi;
+            ctx.tc[3 * (size_t)t + a] = (lo + hi) * 0.5f;
+        }
+        ctx.idx[t] = t;
+    }
+    out->num_nodes = 0;
+    out->num_tris = n;
+    build_node(&ctx, 0, n, 0);
+    free(ctx.tb); free(ctx.tc); free(ctx.tmp);
+    return ctx.error ? -2 : 0;
+}
+
+/* A second, deliberately different builder used to show that query results
+   do not depend on the tree's shape: split at the median centroid along the
+   axis of largest centroid extent (ties by original id). */
+static const float *g_med_c;
+static int g_med_axis;
+static int med_cmp(const void *pa, const void *pb)
+{
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    float ca = g_med_c[3 * (size_t)a + g_med_axis], cb = g_med_c[3 * (size_t)b + g_med_axis];
+    if (ca < cb) return -1;
+    if (ca > cb) return 1;
+    return a < b ? -1 : (a > b);
+}
+
+static uint32_t build_median_node(build_ctx *ctx, uint32_t begin, uint32_t end, uint32_t depth)
+{
+    orc_bvh *o = ctx->out;
+    uint32_t node = o->num_nodes++;
+    uint32_t n = end - begin;
+    float mn[3] = { INFINITY, INFINITY, INFINITY }, mx[3] = { -INFINITY, -INFINITY, -INFINITY };
+    float cmn[3] = { INFINITY, INFINITY, INFINITY }, cmx[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (uint32_t i = begin; i < end; i++) {
+        const float *b = ctx->tb + 6 * (size_t)ctx->idx[i];
+        const float *c = ctx->tc + 3 * (size_t)ctx->idx[i];
+        for (int a = 0; a < 3; a++) {
+            if (b[a] < mn[a]) mn[a] = b[a];
+            if (b[a + 3] > mx[a]) mx[a] = b[a + 3];
+            if (c[a] < cmn[a]) cmn[a] = c[a];
+            if (c[a] > cmx[a]) cmx[a] = c[a];
+        }
+    }
+    for (int a = 0; a < 3; a++) { o->box[6 * node + a] = mn[a]; o->box[6 * node + 3 + a] = mx[a]; }
+    o->depth[node] = depth;
+    if (n <= ctx->leaf_max || depth + 1 > ctx->max_depth) {
+        if (n > ctx->leaf_max) ctx->error = 1;
+        o->right[node] = NONE32; o->first[node] = begin; o->count[node] = n;
+        return node;
+    }
+    int axis = 0;
+    for (int a = 1; a < 3; a++) if (cmx[a] - cmn[a] > cmx[axis] - cmn[axis]) axis = a;
+    g_med_c = ctx->tc; g_med_axis = axis;
+    qsort(ctx->idx + begin, n, sizeof(uint32_t), med_cmp);
+    uint32_t mid = begin + n / 2;
+    o->first[node] = 0; o->count[node] = 0;
+    build_median_node(ctx, begin, mid, depth + 1);
+    o->right[node] = build_median_node(ctx, mid, end, depth + 1);
+    return node;
+}
+
+int orc_build_median(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t max_depth, orc_bvh *out)
+{
+    if (n == 0 || leaf_max < 1 || leaf_max > 8 || n >= (1u << 28) || max_depth > 120) return -1;
+    build_ctx ctx;
+    memset(&ctx, 0, sizeof ctx);
+    ctx.tris = tris;
+    ctx.tb = (float *)malloc(sizeof(float) * 6 * (size_t)n);
+    ctx.tc = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+    ctx.idx = out->perm;
+    ctx.out = out;
+    ctx.leaf_max = leaf_max; ctx.max_depth = max_depth;
+    for (uint32_t t = 0; t < n; t++) {
+        const float *v = tris + 9 * (size_t)t;
+        for (int a = 0; a < 3; a++) {
+            float lo = fminf(fminf(v[a], v[3 + a]), v[6 + a]);
+            float hi = fmaxf(fmaxf(v[a], v[3 + a]), v[6 + a]);
+            ctx.tb[6 * (size_t)t + a] = lo;
+            ctx.tb[6 * (size_t)t + 3 + a] = hi;
+            ctx.tc[3 * (size_t)t + a] = (lo + hi) * 0.5f;
+        }
+        ctx.idx[t] = t;
+    }
+    out->num_nodes = 0;
+    out->num_tris = n;
+    build_median_node(&ctx, 0, n, 0);
+    free(ctx.tb); free(ctx.tc);
+    return ctx.error ? -2 : 0;
+}
+
+/* ======================================================================== */
+/* Ray primitives                                                           */
+/* ======================================================================== */
+
+/* A ray is valid when its origin and direction are finite, the direction is
+   not the zero vector, neither bound is NaN and tmin < tmax (tmax may be
+   +inf).  Invalid rays are misses that are never hashed or traversed. */
+static int ray_valid(const float *r)
+{
+    for (int a = 0; a < 3; a++) if (!isfinite(r[a]) || !isfinite(r[4 + a])) return 0;
+    if (r[4] == 0.0f && r[5] == 0.0f && r[6] == 0.0f) return 0;
+    if (isnan(r[3]) || isnan(r[7])) return 0;
+    return r[3] < r[7];
+}
+
+/* Slab test of one box against the interval [tmin, tcur].  The far distance
+   is scaled by 1 + 3*2^-23 (>= 1 + 2*gamma_3), the conservative bound of
+   Ize, "Robust BVH Ray Traversal" (JCGT 2013), so rounding in the slab
+   distances never rejects a box the exact ray enters. */
+static int slab(const float *b, const float *o, const float *inv, float tmin, float tcur, float *tnear_out)
+{
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        float t0 = (b[a] - o[a]) * inv[a];
+        float t1 = (b[3 + a] - o[a]) * inv[a];
+        lo[a] = min_num(t0, t1);
+        hi[a] = max_num(t0, t1);
+    }
+    float tnear = max_num(max_num(max_num(lo[0], lo[1]), lo[2]), tmin);
+    float tfar = min_num(min_num(min_num(hi[0], hi[1]), hi[2]), tcur) * bits_to_float(0x3F800003u);
+    *tnear_out = tnear;
+    return tnear <= tfar;
+}
+
+/* Moller-Trumbore ray/triangle test (Moller and Trumbore 1997), two-sided,
+   in binary32: e1 = v1-v0, e2 = v2-v0, p = d x e2, det = e1.p; det == 0
+   misses; inv = 1/det; s = o-v0; u = (s.p)*inv in [0,1]; q = s x e1;
+   v = (d.q)*inv >= 0 with u+v <= 1; t = (e2.q)*inv.  dot(a,b) is
+   (ax*bx + ay*by) + az*bz.  Returns 1 and (t,u,v) when inside the
+   triangle; the caller applies its interval. */
+static int moller_trumbore(const float *v0, const float *v1, const float *v2, const float *o,
+                           const float *d, float *t_out, float *u_out, float *v_out)
+{
+    float e1[3] = { v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2] };
+    float e2[3] = { v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2] };
+    float p[3] = { d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0] };
+    float det = (e1[0] * p[0] + e1[1] * p[1]) + e1[2] * p[2];
+    if (det == 0.0f) return 0;
+    float inv = 1.0f / det;
+    float s[3] = { o[0] - v0[0], o[1] - v0[1], o[2] - v0[2] };
+    float u = ((s[0] * p[0] + s[1] * p[1]) + s[2] * p[2]) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return 0;
+    float q[3] = { s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0] };
+    float v = ((d[0] * q[0] + d[1] * q[1]) + d[2] * q[2]) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return 0;
+    *t_out = ((e2[0] * q[0] + e2[1] * q[1]) + e2[2] * q[2]) * inv;
+    *u_out = u;
+    *v_out = v;
+    return 1;
+}
+
+/* ======================================================================== */
+/* Ray hash (our reading for the configured predictor: the paper's hash    */
+/* maps origin and direction bits to an index, "HRPP Hash Function"; the   */
+/* workloads here quantise the origin on a grid over the scene bounds and  */
+/* the direction on an octahedral map (Meyer et al. 2010; Cigolle et al.,  */
+/* JCGT 2014), then fold the key into the table by Fibonacci hashing).     */
+/* ======================================================================== */
+typedef struct {
+    float bmin[3];
+    float scale[3];
+    uint32_t qo, qd, log2n;
+} hash_params;
+
+static void hash_setup(hash_params *h, const float *root_box, uint32_t qo, uint32_t qd, uint32_t log2n)
+{
+    for (int a = 0; a < 3; a++) {
+        float ext = root_box[3 + a] - root_box[a];
+        float s = (float)(1u << qo) / ext;
+        if (!(ext > 0.0f) || !isfinite(s)) s = 0.0f;
+        h->bmin[a] = root_box[a];
+        h->scale[a] = s;
+    }
+    h->qo = qo; h->qd = qd; h->log2n = log2n;
+}
+
+static uint32_t quantize(float x, float maxcell)
+{
+    float c = floorf(x);
+    if (!(c >= 0.0f)) c = 0.0f;          /* also maps NaN to cell 0 */
+    else if (c > maxcell) c = maxcell;
+    return (uint32_t)c;
+}
+
+static float sign_not_neg(float x) { return x >= 0.0f ? 1.0f : -1.0f; }
+
+static void hash_ray(const hash_params *h, const float *o, const float *d, uint64_t *key, uint32_t *idx)
+{
+    uint32_t cell[3];
+    float maxo = (float)((1u << h->qo) - 1u);
+    for (int a = 0; a < 3; a++) cell[a] = quantize((o[a] - h->bmin[a]) * h->scale[a], maxo);
+    /* octahedral map of d onto [-1,1]^2 */
+    float l1 = (fabsf(d[0]) + fabsf(d[1])) + fabsf(d[2]);
+    float inv = 1.0f / l1;
+    float px = d[0] * inv, py = d[1] * inv;
+    if (d[2] < 0.0f) {
+        float fx = (1.0f - fabsf(py)) * sign_not_neg(px);
+        float fy = (1.0f - fabsf(px)) * sign_not_neg(py);
+        px = fx; py = fy;
+    }
+    float half = (float)(1u << (h->qd - 1u));
+    float maxd = (float)((1u << h->qd) - 1u);
+    uint32_t bu = quantize((px + 1.0f) * half, maxd);
+    uint32_t bv = quantize((py + 1.0f) * half, maxd);
+    uint64_t k = (uint64_t)cell[0] | ((uint64_t)cell[1] << h->qo) | ((uint64_t)cell[2] << (2 * h->qo))
+               | ((uint64_t)bu << (3 * h->qo)) | ((uint64_t)bv << (3 * h->qo + h->qd));
+    *key = k;
+    *idx = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> (64u - h->log2n));
+}
+
+/* Exported for the hash pins. */
+void orc_hash(const float *root_box, uint32_t qo, uint32_t qd, uint32_t log2n, const float *rays,
+              uint32_t n, uint64_t *keys, uint32_t *idxs)
+{
+    hash_params h;
+    hash_setup(&h, root_box, qo, qd, log2n);
+    for (uint32_t i = 0; i < n; i++) hash_ray(&h, rays + 8 * (size_t)i, rays + 8 * (size_t)i + 4, keys + i, idxs + i);
+}
+
+/* Exported for the Moller-Trumbore pin. */
+int orc_mt(const float *tri9, const float *ray8, float *tuv)
+{
+    return moller_trumbore(tri9, tri9 + 3, tri9 + 6, ray8, ray8 + 4, tuv, tuv + 1, tuv + 2);
+}
+
+/* Exported for the slab pin. */
+int orc_slab(const float *box6, const float *ray8, float tcur, float *tnear)
+{
+    float inv[3] = { 1.0f / ray8[4], 1.0f / ray8[5], 1.0f / ray8[6] };
+    return slab(box6, ray8, inv, ray8[3], tcur, tnear);
+}
+
+/* ======================================================================== */
+/* Traversal                                                                */
+/* ======================================================================== */
+typedef struct {
+    const orc_bvh *bvh;
+    const float *vtx;          /* 9 floats per BVH-ordered triangle */
+    const uint32_t *leaf_depth_by_first; /* depth of the leaf starting at triangle k */
+} scene;
+
+typedef struct {
+    float t, u, v;
+    uint32_t prim;   /* original id; NONE32 = none */
+    uint32_t leaf;   /* canonical leaf id holding prim */
+} best_hit;
+
+static uint32_t leaf_id(uint32_t first, uint32_t count) { return (first << 3) | (count - 1u); }
+
+/* Test the triangles of one leaf.  ANY: returns 1 on the first hit inside
+   (tmin, tmax).  CLOSEST: updates *b with the lexicographically smallest
+   (t, prim) inside (tmin, tmax); returns 1 if *b changed. */
+static int test_leaf(const scene *sc, uint32_t first, uint32_t count, const float *r, int closest,
+                     best_hit *b, uint64_t *st)
+{
+    int changed = 0;
+    for (uint32_t k = first; k < first + count; k++) {
+        const float *v = sc->vtx + 9 * (size_t)k;
+        float t, u, w;
+        st[S_TRI_TESTS]++;
+        if (!moller_trumbore(v, v + 3, v + 6, r, r + 4, &t, &u, &w)) continue;
+        if (!(r[3] < t && t < r[7])) continue;
+        uint32_t prim = sc->bvh->perm[k];
+        if (!closest) {
+            b->t = t; b->u = u; b->v = w; b->prim = prim; b->leaf = leaf_id(first, count);
+            return 1;
+        }
+        if (t < b->t || (t == b->t && prim < b->prim)) {
+            b->t = t; b->u = u; b->v = w; b->prim = prim; b->leaf = leaf_id(first, count);
+            changed = 1;
+        }
+    }
+    return changed;
+}
+
+/* Plain stack traversal.  Order fully fixed:
+   root box tested first (one box test); at an interior node both child
+   boxes are tested against [tmin, tcur] (two box tests); with both hit,
+   the child with the smaller entry distance is visited first (left on a
+   tie) and the other is pushed with its entry distance; a popped node is
+   visited only if its stored entry distance still passes the slab
+   criterion against the current tcur (tnear <= tcur * (1 + 3*2^-23), which
+   is exactly the slab test re-run with the shrunken interval).  Leaves test
+   their triangles in BVH order.  Any-hit stops at the first hit. */
+static int traverse(const scene *sc, const float *r, const float *inv, int closest, best_hit *b, uint64_t *st)
+{
+    const orc_bvh *bvh = sc->bvh;
+    uint32_t stack_node[128];
+    float stack_t[128];
+    int sp = 0;
+    float tmin = r[3];
+    float tcur = closest ? (b->prim != NONE32 ? b->t : r[7]) : r[7];
+    float tn;
+    int found = (b->prim != NONE32);
+    const float pad = bits_to_float(0x3F800003u);
+
+    st[S_TRAVERSALS]++;
+    st[S_BOX_TESTS]++;
+    if (!slab(bvh->box, r, inv, tmin, tcur, &tn)) return found;
+    uint32_t node = 0;
+    for (;;) {
+        st[S_NODES_VISITED]++;
+        if (bvh->right[node] != NONE32) {
+            uint32_t L = node + 1, R = bvh->right[node];
+            float tl, tr;
+            st[S_INTERIOR_VISITED]++;
+            st[S_BOX_TESTS] += 2;
+            int hl = slab(bvh->box + 6 * (size_t)L, r, inv, tmin, tcur, &tl);
+            int hr = slab(bvh->box + 6 * (size_t)R, r, inv, tmin, tcur, &tr);
+            if (hl && hr) {
+                if (tr < tl) { stack_node[sp] = L; stack_t[sp] = tl; sp++; node = R; }
+                else         { stack_node[sp] = R; stack_t[sp] = tr; sp++; node = L; }
+                continue;
+            }
+            if (hl) { node = L; continue; }
+            if (hr) { node = R; continue; }
+        } else {
+            st[S_LEAF_VISITED]++;
+            if (test_leaf(sc, bvh->first[node], bvh->count[node], r, closest, b, st)) {
+                found = 1;
+                if (!closest) return 1;
+                tcur = b->t;
+            }
+        }
+        /* pop */
+        for (;;) {
+            if (sp == 0) return found;
+            sp--;
+            if (stack_t[sp] <= tcur * pad) break;
+        }
+        node = stack_node[sp];
+    }
+}
+
+/* ======================================================================== */
+/* HRPP per ray ("Overview" direct flow; "Precision and Recall")            */
+/* ======================================================================== */
+enum { Q_ANY = 0, Q_CLOSEST = 1 };
+enum { C_PAPER = 0, C_EXACT = 1 };
+
+typedef struct {
+    uint64_t *tag;      /* [N] */
+    uint32_t *slot;     /* [N * W] */
+    uint32_t W;
+    hash_params h;
+} table;
+
+typedef struct {
+    uint8_t has;        /* record emitted */
+    uint32_t idx;
+    uint64_t key;
+    uint32_t leaf;
+} record;
+
+/* per-ray outcome codes (optional output used by the pins) */
+enum { OUT_INVALID = 0, OUT_TRAVERSED = 1, OUT_PRED_HIT = 2, OUT_FALSE_POS = 3 };
+
+static void trace_one(const scene *sc, const table *tb, const float *r, int query, int cmode,
+                      uint8_t *occ, float *hit4, record *rec, uint8_t *outcome, uint64_t *st)
+{
+    best_hit b = { INFINITY, 0.0f, 0.0f, NONE32, NONE32 };
+    int closest = (query == Q_CLOSEST);
+    rec->has = 0;
+    if (outcome) *outcome = OUT_INVALID;
+    st[S_RAYS]++;
+    if (!ray_valid(r)) {
+        st[S_INVALID]++;
+        goto write;
+    }
+    float inv[3] = { 1.0f / r[4], 1.0f / r[5], 1.0f / r[6] };
+    int hit = 0;
+    if (tb) {
+        uint64_t key; uint32_t idx;
+        hash_ray(&tb->h, r, r + 4, &key, &idx);
+        st[S_LOOKUPS]++;
+        const uint32_t *slots = tb->slot + (size_t)idx * tb->W;
+        int positive = (tb->tag[idx] == key && slots[0] != NONE32);
+        if (positive) {
+            st[S_POSITIVES]++;
+            /* evaluate the predicted leaves in slot order */
+            for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) {
+                uint32_t first = slots[s] >> 3, count = (slots[s] & 7u) + 1u;
+                st[S_NODES_VISITED]++;
+                st[S_LEAF_VISITED]++;
+                if (test_leaf(sc, first, count, r, closest, &b, st)) {
+                    hit = 1;
+                    if (!closest) break;
+                }
+            }
+        }
+        if (positive && hit && !(closest && cmode == C_EXACT)) {
+            /* true positive: interior traversal skipped */
+            st[S_PRED_HITS]++;
+            st[S_NODES_SKIPPED] += sc->leaf_depth_by_first[b.leaf >> 3];
+            if (outcome) *outcome = OUT_PRED_HIT;
+        } else {
+            if (positive && !(closest && cmode == C_EXACT)) st[S_FALSE_POS]++;
+            if (outcome) *outcome = positive ? OUT_FALSE_POS : OUT_TRAVERSED;
+            uint32_t seed_leaf = b.leaf;
+            int found;
+            if (closest && cmode == C_EXACT) {
+                found = traverse(sc, r, inv, 1, &b, st);
+            } else {
+                b.t = INFINITY; b.prim = NONE32; b.leaf = NONE32;
+                found = traverse(sc, r, inv, closest, &b, st);
+            }
+            if (closest && cmode == C_EXACT && positive) {
+                /* success iff the final best lies in a predicted leaf */
+                int in_pred = 0;
+                for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) if (found && slots[s] == b.leaf) in_pred = 1;
+                if (in_pred) st[S_PRED_HITS]++; else st[S_FALSE_POS]++;
+                if (outcome) *outcome = in_pred ? OUT_PRED_HIT : OUT_FALSE_POS;
+                (void)seed_leaf;
+            }
+            hit = found;
+            if (found) {
+                rec->has = 1; rec->idx = idx; rec->key = key; rec->leaf = b.leaf;
+                st[S_RECORDS]++;
+            }
+        }
+    } else {
+        hit = traverse(sc, r, inv, closest, &b, st);
+        if (outcome) *outcome = OUT_TRAVERSED;
+    }
+    if (hit) st[S_HITS]++;
+    else { b.t = INFINITY; b.u = 0.0f; b.v = 0.0f; b.prim = NONE32; }
+write:
+    if (occ) *occ = (uint8_t)(b.prim != NONE32);
+    if (hit4) {
+        if (b.prim == NONE32) { b.t = INFINITY; b.u = 0.0f; b.v = 0.0f; }
+        hit4[0] = b.t; hit4[1] = b.u; hit4[2] = b.v; hit4[3] = bits_to_float(b.prim);
+    }
+}
+
+/* ======================================================================== */
+/* Epoch-end update (our batch-synchronous reading of the paper's insertion */
+/* rule: "the leaf node of the conflicting ray is inserted into the        */
+/* existing predictor entry ... only if it is not already present";        */
+/* entries have W slots and there is no eviction, as the paper has no      */
+/* replacement policy).  For every entry touched by this epoch's records:  */
+/*  1. the key of the record with the smallest ray id owns the entry; if   */
+/*     the stored tag differs, the tag is replaced and all slots emptied;   */
+/*  2. records with another key are discarded (conflicts);                 */
+/*  3. the owner key's leaves not yet present are inserted, in increasing  */
+/*     leaf-id order, into the empty slots (front to back); leaves that do  */
+/*     not fit are dropped (every record whose leaf is absent from the      */
+/*     final entry counts one drop).                                        */
+/* ======================================================================== */
+typedef struct { uint32_t idx; uint32_t rid; } rec_ref;
+static int rec_ref_cmp(const void *pa, const void *pb)
+{
+    const rec_ref *a = (const rec_ref *)pa, *b = (const rec_ref *)pb;
+    if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
+    return a->rid < b->rid ? -1 : (a->rid > b->rid);
+}
+static int u32_cmp(const void *pa, const void *pb)
+{
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    return a < b ? -1 : (a > b);
+}
+
+static void update_table(table *tb, const record *recs, uint32_t base, uint32_t count, uint64_t *st)
+{
+    rec_ref *refs = (rec_ref *)malloc(sizeof(rec_ref) * (count ? count : 1));
+    uint32_t m = 0;
+    for (uint32_t i = 0; i < count; i++) if (recs[i].has) { refs[m].idx = recs[i].idx; refs[m].rid = base + i; m++; }
+    qsort(refs, m, sizeof(rec_ref), rec_ref_cmp);
+    uint32_t W = tb->W;
+    uint32_t *fresh = (uint32_t *)malloc(sizeof(uint32_t) * (m ? m : 1));
+    for (uint32_t g = 0; g < m;) {
+        uint32_t e = g;
+        while (e < m && refs[e].idx == refs[g].idx) e++;
+        uint32_t idx = refs[g].idx;
+        uint64_t kstar = recs[refs[g].rid - base].key;
+        uint32_t *slots = tb->slot + (size_t)idx * W;
+        if (tb->tag[idx] != kstar) {
+            tb->tag[idx] = kstar;
+            for (uint32_t s = 0; s < W; s++) slots[s] = NONE32;
+            st[S_TAG_CLAIMS]++;
+        }
+        uint32_t used = 0;
+        while (used < W && slots[used] != NONE32) used++;
+        /* distinct owner-key leaves not already present */
+        uint32_t nf = 0;
+        for (uint32_t j = g; j < e; j++) {
+            const record *r = &recs[refs[j].rid - base];
+            if (r->key != kstar) { st[S_CONFLICTS]++; continue; }
+            int present = 0;
+            for (uint32_t s = 0; s < used; s++) if (slots[s] == r->leaf) present = 1;
+            for (uint32_t f = 0; f < nf; f++) if (fresh[f] == r->leaf) present = 1;
+            if (!present) fresh[nf++] = r->leaf;
+        }
+        qsort(fresh, nf, sizeof(uint32_t), u32_cmp);
+        for (uint32_t f = 0; f < nf && used < W; f++) { slots[used++] = fresh[f]; st[S_LEAF_INSERTS]++; }
+        for (uint32_t j = g; j < e; j++) {
+            const record *r = &recs[refs[j].rid - base];
+            if (r->key != kstar) continue;
+            int present = 0;
+            for (uint32_t s = 0; s < used; s++) if (slots[s] == r->leaf) present = 1;
+            if (!present) st[S_DROPPED]++;
+        }
+        g = e;
+    }
+    free(refs);
+    free(fresh);
+}
+
+/* ======================================================================== */
+/* Entry point                                                              */
+/* ======================================================================== */
+
+/* Trace n rays.  query: 0 any-hit, 1 closest.  cmode: 0 PAPER, 1 EXACT
+   (closest only).  tags/slots NULL = plain traversal, otherwise the table
+   (log2n entries of W slots) is read and updated in place, epochs of
+   `epoch` rays in ray order.  occ (n bytes) or hits (4 floats per ray: t,
+   u, v, prim bits) receive the results; stats (STATS_SLOTS uint64) are
+   accumulated; outcome (n bytes, optional) receives 0 invalid, 1 traversed
+   without a positive prediction, 2 prediction hit, 3 false positive.
+   nthreads <= 0 uses the OpenMP default.  Returns 0, or -1
+   on bad arguments. */
+int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t n, int query, int cmode,
+              uint64_t *tags, uint32_t *slots, uint32_t log2n, uint32_t W, uint32_t qo, uint32_t qd,
+              uint32_t epoch, uint8_t *occ, float *hits, uint64_t *stats, uint8_t *outcome, int nthreads)
+{
+    if (!bvh || bvh->num_nodes == 0) return -1;
+    if (tags && (W < 1 || log2n < 1 || log2n > 31 || qo < 1 || qo > 10 || qd < 1 || qd > 10 || epoch < 1)) return -1;
+    scene sc;
+    sc.bvh = bvh;
+    sc.vtx = vtx;
+    uint32_t *ldepth = (uint32_t *)malloc(sizeof(uint32_t) * (bvh->num_tris + 1));
+    for (uint32_t i = 0; i < bvh->num_nodes; i++) if (bvh->right[i] == NONE32) ldepth[bvh->first[i]] = bvh->depth[i];
+    sc.leaf_depth_by_first = ldepth;
+    table tb, *ptb = NULL;
+    if (tags) {
+        tb.tag = tags; tb.slot = slots; tb.W = W;
+        hash_setup(&tb.h, bvh->box, qo, qd, log2n);
+        ptb = &tb;
+    }
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    uint32_t E = ptb ? epoch : (n ? n : 1);
+    record *recs = (record *)malloc(sizeof(record) * (size_t)(E < n ? E : (n ? n : 1)));
+    for (uint32_t base = 0; base < n; base += E) {
+        uint32_t cnt = (n - base < E) ? n - base : E;
+        uint64_t acc[STATS_SLOTS];
+        memset(acc, 0, sizeof acc);
+        #pragma omp parallel
+        {
+            uint64_t loc[STATS_SLOTS];
+            memset(loc, 0, sizeof loc);
+            #pragma omp for schedule(dynamic, 256)
+            for (uint32_t i = 0; i < cnt; i++) {
+                uint32_t rid = base + i;
+                trace_one(&sc, ptb, rays + 8 * (size_t)rid, query, cmode, occ ? occ + rid : NULL,
+                          hits ? hits + 4 * (size_t)rid : NULL, &recs[i], outcome ? outcome + rid : NULL, loc);
+            }
+            #pragma omp critical
+            for (int s = 0; s < STATS_SLOTS; s++) acc[s] += loc[s];
+        }
+        if (ptb) update_table(ptb, recs, base, cnt, acc);
+        for (int s = 0; s < STATS_SLOTS; s++) stats[s] += acc[s];
+    }
+    free(recs);
+    free(ldepth);
+    return 0;
+}
+
+/* Brute force over all triangles (original order), same binary32 test:
+   the plain definition of the any-hit flag and of the exact closest hit
+   (lexicographic (t, prim) minimum inside (tmin, tmax)). */
+void orc_brute_force(const float *tris, uint32_t ntri, const float *rays, uint32_t n, int closest,
+                     uint8_t *occ, float *hits, int nthreads)
+{
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (uint32_t i = 0; i < n; i++) {
+        const float *r = rays + 8 * (size_t)i;
+        float bt = INFINITY, bu = 0.0f, bv = 0.0f;
+        uint32_t bp = NONE32;
+        if (ray_valid(r)) {
+            for (uint32_t k = 0; k < ntri; k++) {
+                const float *v = tris + 9 * (size_t)k;
+                float t, u, w;
+                if (!moller_trumbore(v, v + 3, v + 6, r, r + 4, &t, &u, &w)) continue;
+                if (!(r[3] < t && t < r[7])) continue;
+                if (t < bt || (t == bt && k < bp)) { bt = t; bu = u; bv = w; bp = k; if (!closest) break; }
+            }
+        }
+        if (occ) occ[i] = (uint8_t)(bp != NONE32);
+        if (hits) {
+            if (bp == NONE32 || !closest) { if (bp == NONE32) { bt = INFINITY; bu = 0.0f; bv = 0.0f; } }
+            hits[4 * (size_t)i] = bt; hits[4 * (size_t)i + 1] = bu; hits[4 * (size_t)i + 2] = bv;
+            hits[4 * (size_t)i + 3] = bits_to_float(bp);
+        }
+    }
+}
+
+uint32_t orc_float_bits(float f) { return float_to_bits(f); }

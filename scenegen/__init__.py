@@ -1,0 +1,355 @@
+"""Seeded synthetic scenes and rays for the HRPP workloads.
+
+This module is shared input plumbing: both the CPU oracle's tests and the GPU
+library's tests/benchmarks draw their inputs from here.  It holds none of the
+method's arithmetic (no hashing, no BVH, no ray-box or ray-triangle test):
+it only produces triangle soups, heightfields, cameras and ray arrays with
+numpy's PCG64 generator.
+
+Conventions
+-----------
+* Triangles: float32 array ``[n, 3, 3]`` (vertex, xyz).  The primitive id of a
+  triangle is its row index.
+* Rays: float32 array ``[n, 8]`` laid out as ``ox oy oz tmin dx dy dz tmax``
+  (32 bytes per ray).
+* Hits (input to the secondary-ray builders): float32 ``t`` and uint32
+  ``prim`` arrays; ``prim == 0xFFFFFFFF`` means a miss.
+
+The paper's own scenes (PBRT's Teapot ... Sportscar) are not available; the
+generators below are the stand-ins, with sizes chosen to match the paper's
+scale (a one-million-triangle scene, like its Buddha) and its 8 samples per
+pixel (AO rays per primary hit).
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+MISS = np.uint32(0xFFFFFFFF)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# Scenes
+# ---------------------------------------------------------------------------
+
+def triangle_soup(seed: int, n: int, edge: float = 0.05) -> np.ndarray:
+    """``n`` near-equilateral triangles scattered in the unit cube.
+
+    Centroid uniform in [0,1]^3, edge ``edge * U[0.8, 1.2]``, plane normal
+    uniform on the sphere, in-plane rotation uniform in [0, 2pi).
+    """
+    g = rng(seed)
+    c = g.random((n, 3))
+    e = edge * g.uniform(0.8, 1.2, n)
+    nz = g.uniform(-1.0, 1.0, n)
+    phi = g.uniform(0.0, 2 * np.pi, n)
+    r = np.sqrt(np.maximum(0.0, 1.0 - nz * nz))
+    nrm = np.stack([r * np.cos(phi), r * np.sin(phi), nz], axis=1)
+    # orthonormal tangent frame (any helper vector not parallel to the normal)
+    helper = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    t1 = np.cross(nrm, helper)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(nrm, t1)
+    ang = g.uniform(0.0, 2 * np.pi, n)
+    rad = e / np.sqrt(3.0)  # circumradius of an equilateral triangle
+    verts = np.empty((n, 3, 3))
+    for k in range(3):
+        a = ang + k * (2 * np.pi / 3)
+        verts[:, k, :] = c + rad[:, None] * (np.cos(a)[:, None] * t1 + np.sin(a)[:, None] * t2)
+    return verts.astype(np.float32)
+
+
+def _value_noise_fbm(g: np.random.Generator, x: np.ndarray, z: np.ndarray,
+                     octaves: int = 6, lacunarity: float = 2.0, gain: float = 0.5,
+                     base_freq: float = 4.0) -> np.ndarray:
+    """Fractal sum of value noise on [0,1]^2, normalised to [-1, 1]."""
+    total = np.zeros_like(x, dtype=np.float64)
+    amp, freq, norm = 1.0, base_freq, 0.0
+    for _ in range(octaves):
+        res = int(math.ceil(freq)) + 2
+        lattice = g.uniform(-1.0, 1.0, (res, res))
+        fx, fz = x * freq, z * freq
+        ix, iz = np.floor(fx).astype(np.int64), np.floor(fz).astype(np.int64)
+        tx, tz = fx - ix, fz - iz
+        sx, sz = tx * tx * (3 - 2 * tx), tz * tz * (3 - 2 * tz)  # smoothstep
+        v00 = lattice[ix, iz]
+        v10 = lattice[ix + 1, iz]
+        v01 = lattice[ix, iz + 1]
+        v11 = lattice[ix + 1, iz + 1]
+        a = v00 + (v10 - v00) * sx
+        b = v01 + (v11 - v01) * sx
+        total += amp * (a + (b - a) * sz)
+        norm += amp
+        amp *= gain
+        freq *= lacunarity
+    return total / norm
+
+
+class Heightfield:
+    """A noise heightfield over [0,1]^2 in (x, z), y = amplitude * fBm."""
+
+    def __init__(self, seed: int, amplitude: float = 0.1):
+        self.seed = seed
+        self.amplitude = amplitude
+        # draw all octave lattices up front so height() is a pure function
+        self._g_state = rng(seed).bit_generator.state
+
+    def height(self, x: np.ndarray, z: np.ndarray) -> np.ndarray:
+        g = np.random.Generator(np.random.PCG64())
+        g.bit_generator.state = self._g_state
+        return self.amplitude * _value_noise_fbm(g, np.asarray(x, np.float64), np.asarray(z, np.float64))
+
+    def triangles(self, side: int) -> np.ndarray:
+        """``side x side`` vertex grid, quads split on the (0,0)-(1,1) diagonal, row-major."""
+        u = np.linspace(0.0, 1.0, side)
+        X, Z = np.meshgrid(u, u, indexing="ij")      # X[i, j] = u[i], Z[i, j] = u[j]
+        Y = self.height(X, Z)
+        V = np.stack([X, Y, Z], axis=-1)             # [side, side, 3]
+        v00 = V[:-1, :-1].reshape(-1, 3)
+        v10 = V[1:, :-1].reshape(-1, 3)
+        v01 = V[:-1, 1:].reshape(-1, 3)
+        v11 = V[1:, 1:].reshape(-1, 3)
+        # quad q -> triangles 2q (v00, v10, v11) and 2q+1 (v00, v11, v01)
+        t = np.empty((v00.shape[0] * 2, 3, 3))
+        t[0::2, 0], t[0::2, 1], t[0::2, 2] = v00, v10, v11
+        t[1::2, 0], t[1::2, 1], t[1::2, 2] = v00, v11, v01
+        return t.astype(np.float32)
+
+
+def _cube_triangles(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """12 triangles of axis-aligned boxes [lo, hi] (arrays [m, 3])."""
+    m = lo.shape[0]
+    corners = np.empty((m, 8, 3))
+    for k in range(8):
+        corners[:, k, 0] = np.where(k & 1, hi[:, 0], lo[:, 0])
+        corners[:, k, 1] = np.where(k & 2, hi[:, 1], lo[:, 1])
+        corners[:, k, 2] = np.where(k & 4, hi[:, 2], lo[:, 2])
+    faces = [(0, 2, 6, 4), (1, 5, 7, 3),   # x = lo, x = hi
+             (0, 4, 5, 1), (2, 3, 7, 6),   # y = lo, y = hi
+             (0, 1, 3, 2), (4, 6, 7, 5)]   # z = lo, z = hi
+    out = np.empty((m, 12, 3, 3))
+    for f, (a, b, c, d) in enumerate(faces):
+        out[:, 2 * f, 0], out[:, 2 * f, 1], out[:, 2 * f, 2] = corners[:, a], corners[:, b], corners[:, c]
+        out[:, 2 * f + 1, 0], out[:, 2 * f + 1, 1], out[:, 2 * f + 1, 2] = corners[:, a], corners[:, c], corners[:, d]
+    return out.reshape(m * 12, 3, 3)
+
+
+def terrain_scene(seed: int = 2, side: int = 724, n_boxes: int = 4096,
+                  total: int = 1 << 20, amplitude: float = 0.1):
+    """The one-million-triangle test scene: heightfield plus boxes sitting on it.
+
+    Returns ``(tris, heightfield)``.  The first ``total - 12 * n_boxes``
+    heightfield triangles (row-major) are kept, then all box triangles, so the
+    count is exactly ``total``.
+    """
+    hf = Heightfield(seed, amplitude)
+    ht = hf.triangles(side)
+    g = rng(seed + 1000)
+    s = g.uniform(0.005, 0.05, n_boxes)
+    cx, cz = g.random(n_boxes), g.random(n_boxes)
+    base = hf.height(cx, cz)
+    lo = np.stack([cx - s / 2, base, cz - s / 2], axis=1)
+    hi = np.stack([cx + s / 2, base + s, cz + s / 2], axis=1)
+    bt = _cube_triangles(lo, hi).astype(np.float32)
+    keep = total - bt.shape[0]
+    if keep > ht.shape[0] or keep < 0:
+        raise ValueError("heightfield too small for the requested total")
+    return np.concatenate([ht[:keep], bt], axis=0), hf
+
+
+def scaled_terrain_scene(seed: int, total: int, amplitude: float = 0.1):
+    """A smaller copy of :func:`terrain_scene` (same recipe, ~``total`` triangles)."""
+    n_boxes = max(1, total // 256)
+    side = int(math.ceil(math.sqrt((total - 12 * n_boxes) / 2.0))) + 2
+    return terrain_scene(seed, side=side, n_boxes=n_boxes, total=total, amplitude=amplitude)
+
+
+# ---------------------------------------------------------------------------
+# Rays
+# ---------------------------------------------------------------------------
+
+def pack_rays(o: np.ndarray, d: np.ndarray, tmin, tmax) -> np.ndarray:
+    n = o.shape[0]
+    r = np.empty((n, 8), np.float32)
+    r[:, 0:3] = o
+    r[:, 3] = tmin
+    r[:, 4:7] = d
+    r[:, 7] = tmax
+    return r
+
+
+def tiny_shadow_rays(seed: int = 1, n: int = 4096) -> np.ndarray:
+    """Shadow rays from the floor y=0 to a 0.2x0.2 area light at y=1.5.
+
+    Direction unnormalised (target - origin), interval (0, 1).
+    """
+    g = rng(seed + 7)
+    o = np.stack([g.random(n), np.zeros(n), g.random(n)], axis=1)
+    tgt = np.stack([0.5 + g.uniform(-0.1, 0.1, n), np.full(n, 1.5), 0.5 + g.uniform(-0.1, 0.1, n)], axis=1)
+    o32 = o.astype(np.float32)
+    d32 = (tgt.astype(np.float32) - o32).astype(np.float32)
+    return pack_rays(o32, d32, 0.0, 1.0)
+
+
+BAYER4 = np.array([[0, 8, 2, 10], [12, 4, 14, 6], [3, 11, 1, 9], [15, 7, 13, 5]])
+
+
+def pixel_order(width: int, height: int, order: str = "bayer") -> np.ndarray:
+    """Pixel linear ids (y * width + x) in trace order.
+
+    ``bayer``: 16 interleaved passes; pass j holds the pixels whose
+    (x mod 4, y mod 4) cell has Bayer rank j; row-major within a pass.
+    ``rowmajor``: plain row-major.
+    """
+    ids = np.arange(width * height)
+    if order == "rowmajor":
+        return ids
+    x, y = ids % width, ids // width
+    rank = BAYER4[y % 4, x % 4]
+    return ids[np.argsort(rank, kind="stable")]
+
+
+class Camera:
+    def __init__(self, eye=(0.5, 0.5, 0.3), look=(0.5, 0.0, 0.5), up=(0.0, 1.0, 0.0),
+                 vfov_deg: float = 40.0, width: int = 1920, height: int = 1080):
+        self.eye = np.asarray(eye, np.float64)
+        self.look = np.asarray(look, np.float64)
+        self.up = np.asarray(up, np.float64)
+        self.vfov = vfov_deg
+        self.width, self.height = width, height
+
+    def rays(self, order: str = "bayer"):
+        """Unit-direction primary rays through pixel centres, interval (0, inf).
+
+        Returns ``(rays, pixel_ids)`` with rays in trace order.
+        """
+        w = self.look - self.eye
+        w /= np.linalg.norm(w)
+        u = np.cross(w, self.up)
+        u /= np.linalg.norm(u)
+        v = np.cross(u, w)
+        th = math.tan(math.radians(self.vfov) / 2)
+        aspect = self.width / self.height
+        pid = pixel_order(self.width, self.height, order)
+        px, py = pid % self.width, pid // self.width
+        sx = (2 * (px + 0.5) / self.width - 1) * th * aspect
+        sy = (1 - 2 * (py + 0.5) / self.height) * th
+        d = w[None, :] + sx[:, None] * u[None, :] + sy[:, None] * v[None, :]
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        o = np.broadcast_to(self.eye, d.shape)
+        return pack_rays(o.astype(np.float32), d.astype(np.float32), 0.0, np.inf), pid
+
+    def assert_all_hit_terrain(self, rays: np.ndarray, amplitude: float) -> None:
+        """Check, without tracing, that every ray must hit the heightfield.
+
+        A descending ray that crosses y = +amp and y = -amp inside the
+        footprint [0,1]^2 crosses the continuous surface in between.
+        """
+        o, d = rays[:, 0:3].astype(np.float64), rays[:, 4:7].astype(np.float64)
+        if np.any(d[:, 1] >= 0):
+            raise AssertionError("a primary ray does not descend")
+        for yplane in (amplitude, -amplitude):
+            t = (yplane - o[:, 1]) / d[:, 1]
+            p = o + t[:, None] * d
+            if np.any((p[:, 0] < 0) | (p[:, 0] > 1) | (p[:, 2] < 0) | (p[:, 2] > 1)):
+                raise AssertionError("a primary ray leaves the terrain footprint")
+
+
+def _face_normals(tris: np.ndarray, prim: np.ndarray) -> np.ndarray:
+    t = tris[prim].astype(np.float64)
+    n = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    return n / np.linalg.norm(n, axis=1, keepdims=True)
+
+
+def _hit_frame(tris, rays, t, prim, eps):
+    if np.any(prim == MISS):
+        raise ValueError("secondary rays need every primary ray to hit")
+    o, d = rays[:, 0:3].astype(np.float64), rays[:, 4:7].astype(np.float64)
+    p = o + t.astype(np.float64)[:, None] * d
+    n = _face_normals(tris, prim)
+    facing = np.where((np.sum(n * d, axis=1) < 0)[:, None], n, -n)
+    return p + eps * facing, facing
+
+
+def shadow_rays_from_hits(tris, rays, t, prim, seed: int, light_center=(0.5, 1.0, 0.5),
+                          light_size: float = 0.1, eps: float = 1e-4) -> np.ndarray:
+    """One shadow ray per hit point towards a square area light (y = const).
+
+    Origin offset by ``eps`` along the normal facing the incoming ray;
+    direction = light sample - origin (unnormalised); interval (0, 1).
+    """
+    o, _ = _hit_frame(tris, rays, t, prim, eps)
+    g = rng(seed + 11)
+    n = o.shape[0]
+    lc = np.asarray(light_center, np.float64)
+    s = np.stack([lc[0] + light_size * g.uniform(-0.5, 0.5, n), np.full(n, lc[1]),
+                  lc[2] + light_size * g.uniform(-0.5, 0.5, n)], axis=1)
+    o32 = o.astype(np.float32)
+    d32 = (s.astype(np.float32) - o32).astype(np.float32)
+    return pack_rays(o32, d32, 0.0, 1.0)
+
+
+def _concentric_disk(u1, u2):
+    """Shirley-Chiu concentric square-to-disk map."""
+    a, b = 2 * u1 - 1, 2 * u2 - 1
+    r = np.where(np.abs(a) > np.abs(b), a, b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        phi = np.where(np.abs(a) > np.abs(b), (np.pi / 4) * (b / a), np.pi / 2 - (np.pi / 4) * (a / b))
+    phi = np.where((a == 0) & (b == 0), 0.0, phi)
+    return r * np.cos(phi), r * np.sin(phi)
+
+
+def _onb(n):
+    """Branchless orthonormal basis (Duff et al. 2017) around unit normals."""
+    s = np.where(n[:, 2] >= 0, 1.0, -1.0)
+    a = -1.0 / (s + n[:, 2])
+    b = n[:, 0] * n[:, 1] * a
+    t1 = np.stack([1 + s * n[:, 0] * n[:, 0] * a, s * b, -s * n[:, 0]], axis=1)
+    t2 = np.stack([b, s + n[:, 1] * n[:, 1] * a, -n[:, 1]], axis=1)
+    return t1, t2
+
+
+def ao_rays_from_hits(tris, rays, t, prim, seed: int, samples: int = 8, tmax: float = 0.05,
+                      eps: float = 1e-4) -> np.ndarray:
+    """``samples`` cosine-weighted hemisphere rays per hit, sample-major order.
+
+    Unit directions about the facing normal; interval (0, tmax).
+    """
+    o, nf = _hit_frame(tris, rays, t, prim, eps)
+    t1, t2 = _onb(nf)
+    g = rng(seed + 13)
+    m = o.shape[0]
+    out = []
+    for _ in range(samples):
+        x, y = _concentric_disk(g.random(m), g.random(m))
+        z = np.sqrt(np.maximum(0.0, 1 - x * x - y * y))
+        d = x[:, None] * t1 + y[:, None] * t2 + z[:, None] * nf
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        out.append(pack_rays(o.astype(np.float32), d.astype(np.float32), 0.0, tmax))
+    return np.concatenate(out, axis=0)
+
+
+def surface_points(tris: np.ndarray, count: int, seed: int):
+    """Points sampled uniformly by area on ``tris`` with their unit normals."""
+    g = rng(seed)
+    t = tris.astype(np.float64)
+    area = 0.5 * np.linalg.norm(np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0]), axis=1)
+    cdf = np.cumsum(area)
+    pick = np.searchsorted(cdf, g.random(count) * cdf[-1], side="right")
+    pick = np.minimum(pick, t.shape[0] - 1)
+    r1, r2 = np.sqrt(g.random(count)), g.random(count)
+    a, b = 1 - r1, r1 * (1 - r2)
+    tt = t[pick]
+    p = a[:, None] * tt[:, 0] + b[:, None] * tt[:, 1] + (1 - a - b)[:, None] * tt[:, 2]
+    n = np.cross(tt[:, 1] - tt[:, 0], tt[:, 2] - tt[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    return p, n
+
+
+def scene_diagonal(tris: np.ndarray) -> float:
+    v = tris.reshape(-1, 3).astype(np.float64)
+    return float(np.linalg.norm(v.max(0) - v.min(0)))
