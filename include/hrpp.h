@@ -1,0 +1,217 @@
+/*
+ * hrpp.h -- C ABI of the MI355X (gfx950) Hash-Based Ray Path Prediction library.
+ *
+ * Method: Demoullin, Gubran and Aamodt, "Hash-Based Ray Path Prediction:
+ * Skipping BVH Traversal Computation by Exploiting Ray Locality".  Before a
+ * ray enters the BVH its origin and direction are hashed into a predictor
+ * table that maps the hash to leaf nodes reached by earlier similar rays
+ * (section "Overview").  The predicted leaves are tested first; if that
+ * yields a valid intersection the interior traversal is skipped, otherwise
+ * the ray traverses normally (section "Precision and Recall").  A traversed
+ * ray inserts its leaf into its entry unless already present (section "HRPP
+ * Hash Function").  Hit-any and hit-all rays use separate predictors
+ * (section "Limit Study").
+ *
+ * Conventions for every entry point:
+ *  - Pointers prefixed d_ are device (HBM) pointers, h_ host pointers.
+ *  - The caller owns all device memory: rays, results, stats, and the
+ *    backing stores of BVHs and predictors, sized by *_required_bytes.
+ *    The library owns only the opaque handle structs (host heap).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued and the call returns; nothing synchronises unless stated.
+ *  - Arguments are validated on the host before anything is enqueued; an
+ *    invalid argument returns HRPP_EINVAL and enqueues nothing.
+ *  - Handles are not thread-safe.  Calls that use one predictor must be
+ *    issued on one stream or ordered by the caller.
+ *  - Floating point: binary32, round to nearest even, no contraction, no
+ *    flush-to-zero, correctly rounded division.
+ */
+#ifndef HRPP_H
+#define HRPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HRPP_OK = 0,
+    HRPP_EINVAL = 1,   /* bad argument or descriptor */
+    HRPP_ENOMEM = 2,   /* caller buffer too small, or host allocation failed */
+    HRPP_EDEVICE = 3,  /* a HIP runtime call failed */
+    HRPP_EDEPTH = 4,   /* the BVH would exceed max_depth */
+    HRPP_EBUSY = 5     /* serving queue full / budget exhausted */
+} hrpp_status;
+
+/* A ray: origin, interval start, direction (need not be unit), interval end.
+ * 32 bytes, 16-byte aligned arrays.  Hits are accepted for tmin < t < tmax.
+ * A ray is invalid (reported as a miss, counted in `invalid`, never hashed
+ * or traversed) if o or d has a non-finite component, d is the zero
+ * vector, a bound is NaN, or !(tmin < tmax).  tmax may be +inf. */
+typedef struct { float ox, oy, oz, tmin, dx, dy, dz, tmax; } hrpp_ray;
+
+/* Closest-hit result: distance, barycentrics of v1 and v2, original
+ * primitive index.  A miss is t = +inf, u = v = 0, prim = 0xFFFFFFFF. */
+typedef struct { float t, u, v; uint32_t prim; } hrpp_hit;
+
+/* BVH build parameters (the paper takes the binary BVH as given; this
+ * library builds a deterministic binned-SAH tree).  leaf_max in [1, 8]
+ * (4 by default), sah_bins in [2, 256] (32), max_depth in [1, 64] (64). */
+typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
+
+/* Predictor parameters.
+ *  log2_entries  T: table of 2^T entries, T in [1, 26]
+ *  ways          W: leaf slots per entry, 1..8 (entry = 32 B for W <= 4, 64 B otherwise)
+ *  origin_bits   q_o: origin cells per axis = 2^q_o over the scene bounds, 1..10
+ *  dir_bits      q_d: octahedral direction bins per axis = 2^q_d, 1..10
+ *  epoch_rays    E: rays per epoch; rays of epoch k see the table as it stood
+ *                after epoch k-1 (batch-synchronous update), 1..2^22
+ *  hash_mode     0 = grid origin + octahedral direction (the only mode built)
+ *  go_up_level   0 = predict leaves (the only level built) */
+typedef struct {
+    uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level;
+} hrpp_predictor_desc;
+
+/* Work counters, accumulated (added to) by every trace call that is given
+ * a stats pointer.  Definitions (section "Precision and Recall" names the
+ * outcomes; the counting rules are this library's):
+ *  rays, invalid, hits          rays seen / invalid / with a hit
+ *  lookups, positives           table probes / probes whose entry holds the key
+ *  pred_hits, false_pos         positives that did / did not succeed in the
+ *                               predicted leaves (EXACT: final hit in a
+ *                               predicted leaf or not)
+ *  traversals                   full stack traversals run
+ *  nodes_visited                interior + leaf visits (predicted leaves included)
+ *  interior_visited, leaf_visited, box_tests, tri_tests
+ *  nodes_skipped                sum over prediction successes of the
+ *                               predicted leaf's interior-ancestor count
+ *  records                      update records emitted (traversed rays with a hit)
+ *  tag_claims, leaf_inserts     entries (re)claimed / leaves written
+ *  dropped                      owner-key records whose leaf did not fit
+ *  conflicts                    records discarded because another key owns the entry */
+#define HRPP_STATS_SLOTS 24
+typedef struct {
+    uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
+             nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
+             records, tag_claims, leaf_inserts, dropped, conflicts, reserved[5];
+} hrpp_stats;
+
+enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };
+
+typedef struct hrpp_bvh hrpp_bvh;
+typedef struct hrpp_predictor hrpp_predictor;
+
+/* Canonical (device-independent) form of a built BVH: nodes in depth-first
+ * pre-order, left child = next node.  Arrays are caller-owned host buffers
+ * of num_nodes entries (box: 6 floats per node, min xyz then max xyz) and
+ * num_tris entries (tri_perm: BVH position -> original primitive id). */
+typedef struct {
+    float *box;
+    uint32_t *right;      /* right child id; 0xFFFFFFFF for a leaf */
+    uint32_t *first_tri;  /* leaf: first BVH-ordered triangle; interior: 0 */
+    uint32_t *count;      /* leaf: triangle count; interior: 0 */
+    uint32_t *depth;      /* interior ancestors */
+    uint32_t *tri_perm;
+} hrpp_bvh_canon;
+
+/* Upper bound of the device bytes a BVH over num_tris triangles needs. */
+size_t hrpp_bvh_required_bytes(uint32_t num_tris, const hrpp_bvh_desc *desc);
+
+/* Build a BVH on the host from h_verts (9 floats per triangle: v0 v1 v2,
+ * original order = primitive id) and upload its GPU layout into d_buf
+ * (bytes >= hrpp_bvh_required_bytes, 256-byte aligned) on `stream`.
+ * h_verts may be freed when the call returns.  Errors: EINVAL (null
+ * pointers, num_tris == 0 or >= 2^28, non-finite vertex, bad desc),
+ * ENOMEM (bytes too small), EDEPTH (tree deeper than max_depth), EDEVICE. */
+hrpp_status hrpp_build_bvh(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                           void *d_buf, size_t bytes, void *stream, hrpp_bvh **out);
+
+/* The two halves of hrpp_build_bvh, for callers that build on a host
+ * thread and upload later: build the tree only (host memory, no HIP call;
+ * the handle can be exported but not traced until uploaded) ... */
+hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                hrpp_bvh **out);
+
+/* ... exact device bytes of its GPU layout ... */
+size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh);
+
+/* ... and write the GPU layout into d_buf (256-byte aligned, bytes >=
+ * hrpp_bvh_device_bytes).  Synchronises `stream`.  Uploading again to
+ * another buffer moves the BVH there (predictors stay bound to it). */
+hrpp_status hrpp_bvh_upload(hrpp_bvh *bvh, void *d_buf, size_t bytes, void *stream);
+
+/* Node count, triangle count and maximum leaf depth of a built BVH. */
+hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *num_tris,
+                          uint32_t *max_depth);
+
+/* Copy the canonical form of the tree into caller-owned host arrays
+ * (sized from hrpp_bvh_info).  Synchronous, host only. */
+hrpp_status hrpp_bvh_export(const hrpp_bvh *bvh, hrpp_bvh_canon *h_out);
+
+/* Release the handle (the caller's device buffer is not touched). */
+void hrpp_bvh_destroy(hrpp_bvh *bvh);
+
+/* Device bytes a predictor needs: the table (2^T entries of 32/64 B) plus
+ * per-epoch scratch (fallback queue, update records, claim words). */
+size_t hrpp_predictor_required_bytes(const hrpp_predictor_desc *desc);
+
+/* Bytes of the table alone (what hrpp_predictor_export copies). */
+size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc);
+
+/* Create a predictor bound to `bvh` (its hash grid spans the BVH's root
+ * box) in d_buf (256-byte aligned), and enqueue its reset on `stream`.
+ * Errors: EINVAL (bad desc, hash_mode or go_up_level other than 0),
+ * ENOMEM (bytes too small). */
+hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf,
+                                  size_t bytes, void *stream, hrpp_predictor **out);
+
+/* Enqueue a reset: every entry empty (all bytes 0xFF), scratch cleared. */
+hrpp_status hrpp_predictor_reset(hrpp_predictor *pred, void *stream);
+
+/* Copy the table to host memory after the work on `stream` (synchronises
+ * the stream).  Layout per entry: uint64 tag (all-ones = empty), then
+ * `ways` uint32 slots (0xFFFFFFFF = empty; a leaf id is
+ * (first_tri << 3) | (count - 1)), then a uint32 claim word (0xFFFFFFFF
+ * between calls) and 0xFF padding up to the entry size (32 B for
+ * ways <= 4, else 64 B). */
+hrpp_status hrpp_predictor_export(const hrpp_predictor *pred, void *h_dst, size_t bytes, void *stream);
+
+/* Overwrite the table from host memory (same layout as export); for
+ * checkpoint/restore.  Synchronises the stream. */
+hrpp_status hrpp_predictor_import(hrpp_predictor *pred, const void *h_src, size_t bytes, void *stream);
+
+void hrpp_predictor_destroy(hrpp_predictor *pred);
+
+/* Any-hit (shadow / hit-any) query for n rays d_rays[0..n).  d_occluded[i]
+ * = 1 if some triangle is hit inside (tmin, tmax), else 0.  pred NULL =
+ * plain traversal; otherwise rays are processed in epochs of epoch_rays in
+ * index order: hash, lookup, test the predicted leaves (stop at the first
+ * hit), traverse the rest, then update the table.  The flag does not depend
+ * on the predictor.  d_stats (may be NULL) is accumulated.  n == 0 is a
+ * no-op.  Errors: EINVAL (null arrays with n > 0, n >= 2^31, predictor
+ * built for another BVH). */
+hrpp_status hrpp_trace_anyhit(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
+                              uint8_t *d_occluded, hrpp_stats *d_stats, void *stream);
+
+/* Closest-hit (hit-all) query.  mode HRPP_CLOSEST_PAPER: a positive ray
+ * whose predicted leaves hold a hit returns the best hit among them and
+ * skips traversal (the paper's semantics: it may not be the closest).
+ * HRPP_CLOSEST_EXACT: the best predicted hit only seeds the traversal's
+ * interval, so the result is always the closest hit (ties: smaller prim).
+ * Other arguments as for hrpp_trace_anyhit. */
+hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
+                               uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream);
+
+/* Synchronise `stream`; report HRPP_EDEVICE if a HIP error is pending and
+ * HRPP_EDEPTH if a kernel tracing `bvh` (may be NULL) found a traversal
+ * stack too small (cannot happen for trees built by hrpp_build_bvh). */
+hrpp_status hrpp_get_error(const hrpp_bvh *bvh, void *stream);
+
+const char *hrpp_status_string(hrpp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HRPP_H */

@@ -1,0 +1,362 @@
+// C ABI of the HRPP library: argument checking, device layout, epoch
+// sequencing.  Every step of the query path runs in the kernels of
+// hrpp_kernels.hip; this file only validates, lays out memory and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hrpp.h"
+#include "hrpp_internal.h"
+#include "hrpp_kernels.h"
+
+using namespace hrpp;
+
+namespace {
+
+std::atomic<uint64_t> g_uid{1};
+
+constexpr size_t kHeaderBytes = 256;   // BVH buffer header: [0] device error word
+
+uint32_t max_persistent_blocks() {
+    static uint32_t cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached = (uint32_t)cus * 16u;
+    }
+    return cached;
+}
+
+bool desc_ok(const hrpp_predictor_desc *d) {
+    return d && d->log2_entries >= 1 && d->log2_entries <= 26 && d->ways >= 1 && d->ways <= 8 &&
+           d->origin_bits >= 1 && d->origin_bits <= 10 && d->dir_bits >= 1 && d->dir_bits <= 10 &&
+           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->hash_mode == 0 && d->go_up_level == 0;
+}
+
+uint32_t entry_bytes_for(uint32_t ways) { return ways <= 4 ? 32u : 64u; }
+
+struct PredLayout {
+    size_t table, topw, rec_key, rec_idx, rec_leaf, rec_status, queue, ctrl, total;
+};
+
+PredLayout pred_layout(const hrpp_predictor_desc *d) {
+    PredLayout L{};
+    const size_t N = size_t(1) << d->log2_entries, E = d->epoch_rays, W = d->ways;
+    size_t off = 0;
+    L.table = off; off += align256(N * entry_bytes_for(d->ways));
+    L.topw = off; off += align256(E * W * 4);
+    L.rec_key = off; off += align256(E * 8);
+    L.rec_idx = off; off += align256(E * 4);
+    L.rec_leaf = off; off += align256(E * 4);
+    L.rec_status = off; off += align256(E * 4);
+    L.queue = off; off += align256(E * 8);
+    L.ctrl = off; off += 256;
+    L.total = off;
+    return L;
+}
+
+hrpp_status check(hipError_t e) { return e == hipSuccess ? HRPP_OK : HRPP_EDEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+const char *hrpp_status_string(hrpp_status s) {
+    switch (s) {
+        case HRPP_OK: return "ok";
+        case HRPP_EINVAL: return "invalid argument";
+        case HRPP_ENOMEM: return "buffer too small or out of memory";
+        case HRPP_EDEVICE: return "HIP runtime error";
+        case HRPP_EDEPTH: return "BVH deeper than max_depth";
+        case HRPP_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+size_t hrpp_bvh_required_bytes(uint32_t num_tris, const hrpp_bvh_desc *desc) {
+    if (num_tris == 0 || !desc) return 0;
+    const size_t interior = num_tris > 1 ? (size_t)num_tris - 1 : 0;   // at most n - 1 interior nodes
+    return kHeaderBytes + align256(interior * kNodeBytes) + align256((size_t)num_tris * kTriBytes);
+}
+
+hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                hrpp_bvh **out) {
+    if (!h_verts || !desc || !out || num_tris == 0 || num_tris >= (1u << 28)) return HRPP_EINVAL;
+    *out = nullptr;
+    hrpp_bvh *b = new (std::nothrow) hrpp_bvh();
+    if (!b) return HRPP_ENOMEM;
+    hrpp_status st = build_sah_tree(h_verts, num_tris, *desc, b->canon);
+    if (st != HRPP_OK) { delete b; return st; }
+    const CanonTree &t = b->canon;
+    b->uid = g_uid.fetch_add(1);
+    b->num_tris = num_tris;
+    b->num_nodes = (uint32_t)t.right.size();
+    b->max_depth = t.max_depth;
+    b->leaf_max = desc->leaf_max;
+    for (int a = 0; a < 6; a++) b->root_box[a] = t.box[a];
+    uint32_t ni = 0;
+    for (uint32_t i = 0; i < b->num_nodes; i++)
+        if (t.right[i] != kNone) ni++;
+    b->num_interior = ni;
+    b->verts.assign(h_verts, h_verts + 9 * (size_t)num_tris);
+    b->d_nodes = nullptr;
+    b->d_tris = nullptr;
+    *out = b;
+    return HRPP_OK;
+}
+
+size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh) {
+    if (!bvh) return 0;
+    return kHeaderBytes + align256((size_t)bvh->num_interior * kNodeBytes) + align256((size_t)bvh->num_tris * kTriBytes);
+}
+
+hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream) {
+    if (!b || !d_buf || b->verts.empty()) return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_buf) % 256) return HRPP_EINVAL;
+    if (bytes < hrpp_bvh_device_bytes(b)) return HRPP_ENOMEM;
+    const CanonTree &t = b->canon;
+    const uint32_t m = b->num_nodes, n = b->num_tris;
+    const float *h_verts = b->verts.data();
+    // interior nodes keep their DFS order
+    std::vector<uint32_t> iid(m, kNone);
+    uint32_t ni = 0;
+    for (uint32_t i = 0; i < m; i++)
+        if (t.right[i] != kNone) iid[i] = ni++;
+    auto ref_of = [&](uint32_t node) -> uint32_t {
+        if (t.right[node] == kNone) return kLeafFlag | (t.first[node] << 3) | (t.count[node] - 1u);
+        return iid[node];
+    };
+    b->root_ref = ref_of(0);
+    std::vector<float> hn((size_t)ni * 16);
+    for (uint32_t i = 0; i < m; i++) {
+        if (t.right[i] == kNone) continue;
+        float *p = &hn[(size_t)iid[i] * 16];
+        const float *L = &t.box[6 * (size_t)(i + 1)];
+        const float *R = &t.box[6 * (size_t)t.right[i]];
+        for (int a = 0; a < 6; a++) { p[a] = L[a]; p[6 + a] = R[a]; }
+        const uint32_t refs[4] = {ref_of(i + 1), ref_of(t.right[i]), 0u, 0u};
+        std::memcpy(p + 12, refs, sizeof refs);
+    }
+    std::vector<uint32_t> leaf_depth(n, 0);
+    for (uint32_t i = 0; i < m; i++)
+        if (t.right[i] == kNone)
+            for (uint32_t k = t.first[i]; k < t.first[i] + t.count[i]; k++) leaf_depth[k] = t.depth[i];
+    // triangle record: v0 + prim | e1 + leaf depth | e2 + 0, with e = v - v0 in binary32
+    std::vector<float> ht((size_t)n * 12);
+    for (uint32_t k = 0; k < n; k++) {
+        const uint32_t prim = t.perm[k];
+        const float *v = h_verts + 9 * (size_t)prim;
+        float *p = &ht[(size_t)k * 12];
+        p[0] = v[0]; p[1] = v[1]; p[2] = v[2];
+        std::memcpy(&p[3], &prim, 4);
+        p[4] = v[3] - v[0]; p[5] = v[4] - v[1]; p[6] = v[5] - v[2];
+        std::memcpy(&p[7], &leaf_depth[k], 4);
+        p[8] = v[6] - v[0]; p[9] = v[7] - v[1]; p[10] = v[8] - v[2];
+        p[11] = 0.0f;
+    }
+    char *base = static_cast<char *>(d_buf);
+    char *d_nodes = base + kHeaderBytes;
+    char *d_tris = d_nodes + align256((size_t)ni * kNodeBytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemsetAsync(base, 0, kHeaderBytes, s);
+    if (e == hipSuccess && ni) e = hipMemcpyAsync(d_nodes, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_tris, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // host staging buffers die here
+    if (e != hipSuccess) return HRPP_EDEVICE;
+    b->d_nodes = d_nodes;
+    b->d_tris = d_tris;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_build_bvh(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc, void *d_buf,
+                           size_t bytes, void *stream, hrpp_bvh **out) {
+    if (!h_verts || !desc || !d_buf || !out || num_tris == 0 || num_tris >= (1u << 28)) return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_buf) % 256) return HRPP_EINVAL;
+    if (bytes < hrpp_bvh_required_bytes(num_tris, desc)) return HRPP_ENOMEM;
+    hrpp_bvh *b = nullptr;
+    hrpp_status st = hrpp_bvh_build_host(h_verts, num_tris, desc, &b);
+    if (st != HRPP_OK) return st;
+    st = hrpp_bvh_upload(b, d_buf, bytes, stream);
+    if (st != HRPP_OK) { delete b; *out = nullptr; return st; }
+    *out = b;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *num_tris, uint32_t *max_depth) {
+    if (!bvh) return HRPP_EINVAL;
+    if (num_nodes) *num_nodes = bvh->num_nodes;
+    if (num_tris) *num_tris = bvh->num_tris;
+    if (max_depth) *max_depth = bvh->max_depth;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_bvh_export(const hrpp_bvh *bvh, hrpp_bvh_canon *o) {
+    if (!bvh || !o || !o->box || !o->right || !o->first_tri || !o->count || !o->depth || !o->tri_perm)
+        return HRPP_EINVAL;
+    const CanonTree &t = bvh->canon;
+    std::memcpy(o->box, t.box.data(), t.box.size() * 4);
+    std::memcpy(o->right, t.right.data(), t.right.size() * 4);
+    std::memcpy(o->first_tri, t.first.data(), t.first.size() * 4);
+    std::memcpy(o->count, t.count.data(), t.count.size() * 4);
+    std::memcpy(o->depth, t.depth.data(), t.depth.size() * 4);
+    std::memcpy(o->tri_perm, t.perm.data(), t.perm.size() * 4);
+    return HRPP_OK;
+}
+
+void hrpp_bvh_destroy(hrpp_bvh *bvh) { delete bvh; }
+
+size_t hrpp_predictor_required_bytes(const hrpp_predictor_desc *desc) {
+    if (!desc_ok(desc)) return 0;
+    return pred_layout(desc).total;
+}
+
+size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc) {
+    if (!desc_ok(desc)) return 0;
+    return (size_t(1) << desc->log2_entries) * entry_bytes_for(desc->ways);
+}
+
+hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
+    if (!p) return HRPP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t E = p->desc.epoch_rays;
+    launch_fill32(static_cast<uint32_t *>(p->d_table), p->table_bytes / 4, kNone, s);
+    launch_fill32(p->d_topw, E * p->desc.ways, kNone, s);
+    launch_fill32(p->d_rec_idx, E, kNone, s);
+    launch_fill32(p->d_ctrl, 64, 0u, s);
+    return check(hipGetLastError());
+}
+
+hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf, size_t bytes,
+                                  void *stream, hrpp_predictor **out) {
+    if (!bvh || !bvh->d_nodes || !desc_ok(desc) || !d_buf || !out) return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_buf) % 256) return HRPP_EINVAL;
+    const PredLayout L = pred_layout(desc);
+    if (bytes < L.total) return HRPP_ENOMEM;
+    *out = nullptr;
+    hrpp_predictor *p = new (std::nothrow) hrpp_predictor();
+    if (!p) return HRPP_ENOMEM;
+    char *base = static_cast<char *>(d_buf);
+    p->bvh_uid = bvh->uid;
+    p->desc = *desc;
+    p->entry_bytes = entry_bytes_for(desc->ways);
+    p->table_bytes = (size_t(1) << desc->log2_entries) * p->entry_bytes;
+    p->d_table = base + L.table;
+    p->d_topw = reinterpret_cast<uint32_t *>(base + L.topw);
+    p->d_rec_key = reinterpret_cast<uint64_t *>(base + L.rec_key);
+    p->d_rec_idx = reinterpret_cast<uint32_t *>(base + L.rec_idx);
+    p->d_rec_leaf = reinterpret_cast<uint32_t *>(base + L.rec_leaf);
+    p->d_rec_status = reinterpret_cast<uint32_t *>(base + L.rec_status);
+    p->d_queue = reinterpret_cast<uint64_t *>(base + L.queue);
+    p->d_ctrl = reinterpret_cast<uint32_t *>(base + L.ctrl);
+    // hash grid over the scene box: scale = 2^qo / extent (0 for a flat or
+    // degenerate axis), computed once in binary32
+    for (int a = 0; a < 3; a++) {
+        const float ext = bvh->root_box[3 + a] - bvh->root_box[a];
+        float sc = (float)(1u << desc->origin_bits) / ext;
+        if (!(ext > 0.0f) || !std::isfinite(sc)) sc = 0.0f;
+        p->bmin[a] = bvh->root_box[a];
+        p->scale[a] = sc;
+    }
+    hrpp_status st = hrpp_predictor_reset(p, stream);
+    if (st != HRPP_OK) { delete p; return st; }
+    *out = p;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_predictor_export(const hrpp_predictor *p, void *h_dst, size_t bytes, void *stream) {
+    if (!p || !h_dst || bytes < p->table_bytes) return HRPP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(h_dst, p->d_table, p->table_bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return check(e);
+}
+
+hrpp_status hrpp_predictor_import(hrpp_predictor *p, const void *h_src, size_t bytes, void *stream) {
+    if (!p || !h_src || bytes < p->table_bytes) return HRPP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(p->d_table, h_src, p->table_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return check(e);
+}
+
+void hrpp_predictor_destroy(hrpp_predictor *p) { delete p; }
+
+static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
+                                bool any, bool exact, uint8_t *d_occ, hrpp_hit *d_hits, hrpp_stats *d_stats,
+                                void *stream) {
+    if (!bvh || !bvh->d_nodes) return HRPP_EINVAL;
+    if (n == 0) return HRPP_OK;
+    if (n >= (1u << 31) || !d_rays || (any ? !d_occ : !d_hits)) return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || (!any && reinterpret_cast<uintptr_t>(d_hits) % 16))
+        return HRPP_EINVAL;
+    if (pred && pred->bvh_uid != bvh->uid) return HRPP_EINVAL;
+    TraceArgs a{};
+    a.nodes = bvh->d_nodes;
+    a.tris = bvh->d_tris;
+    for (int i = 0; i < 6; i++) a.root_box[i] = bvh->root_box[i];
+    a.root_ref = bvh->root_ref;
+    a.stack_cap = std::max<uint32_t>(1u, bvh->max_depth);
+    a.max_blocks = max_persistent_blocks();
+    a.rays = d_rays;
+    a.occluded = d_occ;
+    a.hits = d_hits;
+    a.stats = reinterpret_cast<unsigned long long *>(d_stats);
+    a.error = reinterpret_cast<uint32_t *>(static_cast<char *>(const_cast<void *>(bvh->d_nodes)) - kHeaderBytes);
+    uint32_t epoch = n;
+    if (pred) {
+        const hrpp_predictor_desc &d = pred->desc;
+        a.table = pred->d_table;
+        a.entry_bytes = pred->entry_bytes;
+        a.ways = d.ways;
+        for (int i = 0; i < 3; i++) { a.hash.bmin[i] = pred->bmin[i]; a.hash.scale[i] = pred->scale[i]; }
+        a.hash.maxo = (float)((1u << d.origin_bits) - 1u);
+        a.hash.maxd = (float)((1u << d.dir_bits) - 1u);
+        a.hash.half = (float)(1u << (d.dir_bits - 1u));
+        a.hash.qo = d.origin_bits;
+        a.hash.qd = d.dir_bits;
+        a.hash.log2n = d.log2_entries;
+        a.ctrl = pred->d_ctrl;
+        a.queue = pred->d_queue;
+        a.rec_key = pred->d_rec_key;
+        a.rec_idx = pred->d_rec_idx;
+        a.rec_leaf = pred->d_rec_leaf;
+        a.rec_status = pred->d_rec_status;
+        a.topw = pred->d_topw;
+        epoch = d.epoch_rays;
+    }
+    launch_trace(a, n, any, exact, pred != nullptr, epoch, static_cast<hipStream_t>(stream));
+    return check(hipGetLastError());
+}
+
+hrpp_status hrpp_trace_anyhit(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
+                              uint8_t *d_occluded, hrpp_stats *d_stats, void *stream) {
+    return trace_common(bvh, pred, d_rays, n, true, false, d_occluded, nullptr, d_stats, stream);
+}
+
+hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
+                               uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream) {
+    if (mode != HRPP_CLOSEST_PAPER && mode != HRPP_CLOSEST_EXACT) return HRPP_EINVAL;
+    return trace_common(bvh, pred, d_rays, n, false, mode == HRPP_CLOSEST_EXACT, nullptr, d_hits, d_stats, stream);
+}
+
+hrpp_status hrpp_get_error(const hrpp_bvh *bvh, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return HRPP_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return HRPP_EDEVICE;
+    if (bvh && bvh->d_nodes) {
+        uint32_t word = 0;
+        const void *err = static_cast<const char *>(bvh->d_nodes) - kHeaderBytes;
+        if (hipMemcpy(&word, err, 4, hipMemcpyDeviceToHost) != hipSuccess) return HRPP_EDEVICE;
+        if (word & 1u) return HRPP_EDEPTH;
+    }
+    return HRPP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal definitions shared by the host builder and the HIP kernels of the
+// HRPP library.  Not part of the public ABI (see include/hrpp.h).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "hrpp.h"
+
+namespace hrpp {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kLeafFlag = 0x80000000u;   // node reference names a leaf
+constexpr uint64_t kEmptyTag = 0xFFFFFFFFFFFFFFFFull;
+constexpr int kMaxDepth = 64;                  // deepest leaf the kernels accept
+
+// Counter slots, in the order of hrpp_stats.
+enum Stat : int {
+    kRays, kInvalid, kHits, kLookups, kPositives, kPredHits, kFalsePos, kTraversals,
+    kNodesVisited, kInteriorVisited, kLeafVisited, kBoxTests, kTriTests, kNodesSkipped,
+    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kNumStats
+};
+
+// Canonical depth-first pre-order tree, as produced by the builder.
+struct CanonTree {
+    std::vector<float> box;        // 6 per node
+    std::vector<uint32_t> right;   // kNone for leaves
+    std::vector<uint32_t> first;
+    std::vector<uint32_t> count;
+    std::vector<uint32_t> depth;
+    std::vector<uint32_t> perm;    // BVH position -> original primitive id
+    uint32_t max_depth = 0;
+};
+
+// Deterministic binned-SAH build; returns HRPP_OK, HRPP_EINVAL or HRPP_EDEPTH.
+hrpp_status build_sah_tree(const float *verts, uint32_t n, const hrpp_bvh_desc &desc, CanonTree &out);
+
+// GPU layout sizes.
+constexpr size_t kNodeBytes = 64;   // two child boxes + two references
+constexpr size_t kTriBytes = 48;    // v0+prim | e1+leaf depth | e2+pad
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace hrpp
+
+// Opaque handles (defined here so the builder and the API share them).
+struct hrpp_bvh {
+    uint64_t uid;
+    uint32_t num_tris, num_nodes, num_interior, max_depth, leaf_max;
+    float root_box[6];
+    uint32_t root_ref;          // kLeafFlag|leaf id when the root is a leaf, else 0
+    const void *d_nodes;        // num_interior * 64 B
+    const void *d_tris;         // num_tris * 48 B
+    hrpp::CanonTree canon;
+    std::vector<float> verts;   // host copy of the input, used by the upload
+};
+
+struct hrpp_predictor {
+    uint64_t bvh_uid;
+    hrpp_predictor_desc desc;
+    uint32_t entry_bytes;       // 32 or 64
+    float bmin[3], scale[3];    // hash grid over the BVH root box
+    // device regions inside the caller's buffer
+    void *d_table;              // 2^T entries
+    uint32_t *d_topw;           // E * W fresh-leaf lists (per claiming ray)
+    uint64_t *d_rec_key;        // E
+    uint32_t *d_rec_idx;        // E (kNone = no record)
+    uint32_t *d_rec_leaf;       // E
+    uint32_t *d_rec_status;     // E
+    uint64_t *d_queue;          // E fallback entries: ray id | seed leaf << 32
+    uint32_t *d_ctrl;           // [0] queue count, [1] error word
+    size_t table_bytes;
+};

@@ -1,0 +1,51 @@
+// Kernel argument blocks and launchers of the HRPP library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hrpp {
+
+// Hash grid of one predictor (see hash_ray in hrpp_kernels.hip).
+struct HashArgs {
+    float bmin[3];
+    float scale[3];     // 2^qo / extent per axis (0 for a flat axis)
+    float maxo;         // 2^qo - 1
+    float maxd;         // 2^qd - 1
+    float half;         // 2^(qd - 1)
+    uint32_t qo, qd, log2n;
+};
+
+struct TraceArgs {
+    // scene
+    const void *nodes;            // interior nodes, 64 B each
+    const void *tris;             // triangles, 48 B each
+    float root_box[6];
+    uint32_t root_ref;
+    uint32_t stack_cap;           // LDS stack slots per lane (>= deepest leaf)
+    uint32_t max_blocks;          // grid cap of the persistent plain traversal
+    // rays and results
+    const void *rays;             // hrpp_ray[n]
+    uint8_t *occluded;            // any-hit output
+    void *hits;                   // closest-hit output (hrpp_hit[n])
+    unsigned long long *stats;    // hrpp_stats or null
+    uint32_t *error;              // device error word
+    // predictor (null table = plain)
+    void *table;
+    uint32_t entry_bytes;
+    uint32_t ways;
+    HashArgs hash;
+    uint32_t *ctrl;               // [0] queue count
+    uint64_t *queue;
+    uint64_t *rec_key;
+    uint32_t *rec_idx;
+    uint32_t *rec_leaf;
+    uint32_t *rec_status;
+    uint32_t *topw;
+};
+
+void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, hipStream_t s);
+void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
+
+}  // namespace hrpp

@@ -1,0 +1,605 @@
+// HIP kernels of the HRPP library for CDNA4 (gfx950, wave64).
+//
+// Per epoch of E rays (rays of epoch k see the table after epoch k-1):
+//   k_predict    one lane per ray: validate, hash, probe the table, test the
+//                predicted leaves; successes write their result, the rest
+//                are appended to the fallback queue (one atomic per wave).
+//   k_traverse   stack traversal of the queued rays (or of every ray in
+//                plain mode); emits one update record per traversed hit and
+//                claims the record's entry with a 32-bit atomicMin on the
+//                ray id (the smallest ray id owns the entry).
+//   k_update_*   three passes over the epoch's records that turn the table
+//                of epoch k-1 into the table of epoch k.
+//
+// Section references are to Demoullin, Gubran and Aamodt, "Hash-Based Ray
+// Path Prediction".  Every floating-point expression below is written in
+// the same operation order as the library's specification (binary32, no
+// contraction: the file is compiled with -ffp-contract=off).
+#include <hip/hip_runtime.h>
+
+#include "hrpp_internal.h"
+#include "hrpp_kernels.h"
+
+namespace hrpp {
+
+// ---------------------------------------------------------------------------
+// Scalar building blocks
+// ---------------------------------------------------------------------------
+
+// Conservative far-distance factor 1 + 3 * 2^-23 (Ize, "Robust BVH Ray
+// Traversal", JCGT 2013: >= 1 + 2 * gamma_3 covers rounding of the slab
+// distances).
+__device__ __forceinline__ float far_pad() { return __uint_as_float(0x3F800003u); }
+
+__device__ __forceinline__ bool ray_is_valid(const float4 &a, const float4 &b) {
+    bool fin = __builtin_isfinite(a.x) && __builtin_isfinite(a.y) && __builtin_isfinite(a.z) &&
+               __builtin_isfinite(b.x) && __builtin_isfinite(b.y) && __builtin_isfinite(b.z);
+    bool nonzero = !(b.x == 0.0f && b.y == 0.0f && b.z == 0.0f);
+    bool interval = !__builtin_isnan(a.w) && !__builtin_isnan(b.w) && (a.w < b.w);
+    return fin && nonzero && interval;
+}
+
+struct RayState {
+    float ox, oy, oz, dx, dy, dz, ix, iy, iz, tmin, tmax;
+};
+
+// Slab test of one box against [tmin, tcur]; fminf/fmaxf ignore a NaN operand
+// (IEEE minNum/maxNum, the gfx9 v_min/v_max behaviour in IEEE mode).
+__device__ __forceinline__ bool slab(float x0, float y0, float z0, float x1, float y1, float z1,
+                                     const RayState &r, float tcur, float &tnear) {
+    float t0x = (x0 - r.ox) * r.ix, t1x = (x1 - r.ox) * r.ix;
+    float t0y = (y0 - r.oy) * r.iy, t1y = (y1 - r.oy) * r.iy;
+    float t0z = (z0 - r.oz) * r.iz, t1z = (z1 - r.oz) * r.iz;
+    float lox = fminf(t0x, t1x), hix = fmaxf(t0x, t1x);
+    float loy = fminf(t0y, t1y), hiy = fmaxf(t0y, t1y);
+    float loz = fminf(t0z, t1z), hiz = fmaxf(t0z, t1z);
+    tnear = fmaxf(fmaxf(fmaxf(lox, loy), loz), r.tmin);
+    float tfar = fminf(fminf(fminf(hix, hiy), hiz), tcur) * far_pad();
+    return tnear <= tfar;
+}
+
+// Moller-Trumbore on a stored triangle {v0, e1 = v1 - v0, e2 = v2 - v0}.
+__device__ __forceinline__ bool intersect_tri(const float4 &A, const float4 &B, const float4 &C,
+                                              const RayState &r, float &t, float &u, float &v) {
+    const float e1x = B.x, e1y = B.y, e1z = B.z;
+    const float e2x = C.x, e2y = C.y, e2z = C.z;
+    float px = r.dy * e2z - r.dz * e2y;
+    float py = r.dz * e2x - r.dx * e2z;
+    float pz = r.dx * e2y - r.dy * e2x;
+    float det = (e1x * px + e1y * py) + e1z * pz;
+    if (det == 0.0f) return false;
+    float inv = 1.0f / det;
+    float sx = r.ox - A.x, sy = r.oy - A.y, sz = r.oz - A.z;
+    u = ((sx * px + sy * py) + sz * pz) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return false;
+    float qx = sy * e1z - sz * e1y;
+    float qy = sz * e1x - sx * e1z;
+    float qz = sx * e1y - sy * e1x;
+    v = ((r.dx * qx + r.dy * qy) + r.dz * qz) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
+    t = ((e2x * qx + e2y * qy) + e2z * qz) * inv;
+    return true;
+}
+
+__device__ __forceinline__ uint32_t quantize(float x, float maxcell) {
+    float c = floorf(x);
+    if (!(c >= 0.0f)) c = 0.0f;
+    else if (c > maxcell) c = maxcell;
+    return (uint32_t)c;
+}
+
+// Ray hash: origin cell on a 2^qo grid over the scene box, direction on a
+// 2^qd x 2^qd octahedral map, packed into a key and folded into the table
+// index by Fibonacci hashing (the section "HRPP Hash Function" asks for a
+// hash that sends similar rays to the same entry).
+__device__ __forceinline__ void hash_ray(const HashArgs &h, const RayState &r, uint64_t &key, uint32_t &idx) {
+    const float maxo = h.maxo, maxd = h.maxd, half = h.half;
+    uint32_t cx = quantize((r.ox - h.bmin[0]) * h.scale[0], maxo);
+    uint32_t cy = quantize((r.oy - h.bmin[1]) * h.scale[1], maxo);
+    uint32_t cz = quantize((r.oz - h.bmin[2]) * h.scale[2], maxo);
+    float l1 = (fabsf(r.dx) + fabsf(r.dy)) + fabsf(r.dz);
+    float inv = 1.0f / l1;
+    float px = r.dx * inv, py = r.dy * inv;
+    if (r.dz < 0.0f) {
+        float fx = (1.0f - fabsf(py)) * (px >= 0.0f ? 1.0f : -1.0f);
+        float fy = (1.0f - fabsf(px)) * (py >= 0.0f ? 1.0f : -1.0f);
+        px = fx;
+        py = fy;
+    }
+    uint32_t bu = quantize((px + 1.0f) * half, maxd);
+    uint32_t bv = quantize((py + 1.0f) * half, maxd);
+    const uint32_t qo = h.qo, qd = h.qd;
+    key = (uint64_t)cx | ((uint64_t)cy << qo) | ((uint64_t)cz << (2 * qo)) | ((uint64_t)bu << (3 * qo)) |
+          ((uint64_t)bv << (3 * qo + qd));
+    idx = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64u - h.log2n));
+}
+
+// ---------------------------------------------------------------------------
+// Counters: per-lane registers, reduced per block, one atomic per counter
+// per block.
+// ---------------------------------------------------------------------------
+struct Counters {
+    uint32_t v[kNumStats];
+    __device__ void zero() {
+#pragma unroll
+        for (int i = 0; i < kNumStats; i++) v[i] = 0;
+    }
+};
+
+template <bool STATS>
+__device__ __forceinline__ void flush_counters(Counters &c, unsigned long long *stats) {
+    if constexpr (STATS) {
+        __shared__ unsigned long long red[kNumStats];
+        if (threadIdx.x < kNumStats) red[threadIdx.x] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kNumStats; i++) {
+            uint32_t x = c.v[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+            if ((threadIdx.x & 63) == 0 && x) atomicAdd(&red[i], (unsigned long long)x);
+        }
+        __syncthreads();
+        if (threadIdx.x < kNumStats && red[threadIdx.x]) atomicAdd(&stats[threadIdx.x], red[threadIdx.x]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf test (shared by prediction and traversal)
+// ---------------------------------------------------------------------------
+struct Best {
+    float t, u, v;
+    uint32_t prim, leaf;
+};
+
+// ANY: returns true at the first hit inside (tmin, tmax).  CLOSEST: keeps the
+// lexicographically smallest (t, prim) and returns true if it changed.
+template <bool ANY>
+__device__ __forceinline__ bool test_leaf(const float4 *__restrict__ tris, uint32_t leaf, const RayState &r,
+                                          Best &b, Counters &c) {
+    const uint32_t first = leaf >> 3, cnt = (leaf & 7u) + 1u;
+    bool changed = false;
+    for (uint32_t k = first; k < first + cnt; k++) {
+        const float4 A = tris[3 * (size_t)k + 0];
+        const float4 B = tris[3 * (size_t)k + 1];
+        const float4 C = tris[3 * (size_t)k + 2];
+        c.v[kTriTests]++;
+        float t, u, v;
+        if (!intersect_tri(A, B, C, r, t, u, v)) continue;
+        if (!(r.tmin < t && t < r.tmax)) continue;
+        const uint32_t prim = __float_as_uint(A.w);
+        if constexpr (ANY) {
+            b.t = t; b.u = u; b.v = v; b.prim = prim; b.leaf = leaf;
+            return true;
+        } else {
+            if (t < b.t || (t == b.t && prim < b.prim)) {
+                b.t = t; b.u = u; b.v = v; b.prim = prim; b.leaf = leaf;
+                changed = true;
+            }
+        }
+    }
+    return changed;
+}
+
+// ---------------------------------------------------------------------------
+// Stack traversal.  Fixed order: root box test; at an interior node both
+// child boxes are tested against [tmin, tcur]; with both hit the nearer
+// child (left on a tie) is taken and the other pushed with its entry
+// distance; a popped node is visited only if its entry distance still passes
+// against the current tcur; leaves test triangles in BVH order.
+// The per-lane stack lives in LDS, lane-interleaved (slot * blockDim + lane)
+// so that the 64 lanes of a wave touch 64 consecutive dwords.
+// ---------------------------------------------------------------------------
+template <bool ANY>
+__device__ __forceinline__ bool traverse(const TraceArgs &a, const RayState &r, Best &b, Counters &c,
+                                         uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
+    const float4 *__restrict__ nodes = (const float4 *)a.nodes;
+    const float4 *__restrict__ tris = (const float4 *)a.tris;
+    float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
+    bool found = (b.prim != kNone);
+    float tn;
+    c.v[kTraversals]++;
+    c.v[kBoxTests]++;
+    if (!slab(a.root_box[0], a.root_box[1], a.root_box[2], a.root_box[3], a.root_box[4], a.root_box[5], r, tcur, tn))
+        return found;
+    uint32_t ref = a.root_ref;
+    uint32_t sp = 0;
+    for (;;) {
+        c.v[kNodesVisited]++;
+        if (!(ref & kLeafFlag)) {
+            c.v[kInteriorVisited]++;
+            c.v[kBoxTests] += 2;
+            const float4 n0 = nodes[4 * (size_t)ref + 0];
+            const float4 n1 = nodes[4 * (size_t)ref + 1];
+            const float4 n2 = nodes[4 * (size_t)ref + 2];
+            const uint4 n3 = ((const uint4 *)nodes)[4 * (size_t)ref + 3];
+            float tl, tr;
+            const bool hl = slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, r, tcur, tl);
+            const bool hr = slab(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, r, tcur, tr);
+            if (hl && hr) {
+                uint32_t push_ref;
+                float push_t;
+                if (tr < tl) { push_ref = n3.x; push_t = tl; ref = n3.y; }
+                else         { push_ref = n3.y; push_t = tr; ref = n3.x; }
+                if (sp >= cap) { atomicOr(a.error, 1u); return found; }
+                stk_node[sp * stride] = push_ref;
+                if constexpr (!ANY) stk_t[sp * stride] = push_t;
+                sp++;
+                continue;
+            }
+            if (hl) { ref = n3.x; continue; }
+            if (hr) { ref = n3.y; continue; }
+        } else {
+            c.v[kLeafVisited]++;
+            if (test_leaf<ANY>(tris, ref & ~kLeafFlag, r, b, c)) {
+                found = true;
+                if constexpr (ANY) return true;
+                tcur = b.t;
+            }
+        }
+        // pop
+        for (;;) {
+            if (sp == 0) return found;
+            sp--;
+            if constexpr (ANY) break;
+            else if (stk_t[sp * stride] <= tcur * far_pad()) break;
+        }
+        ref = stk_node[sp * stride];
+    }
+}
+
+__device__ __forceinline__ RayState load_ray(const float4 *rays, uint32_t rid, float4 &a, float4 &b) {
+    a = rays[2 * (size_t)rid + 0];
+    b = rays[2 * (size_t)rid + 1];
+    RayState r;
+    r.ox = a.x; r.oy = a.y; r.oz = a.z; r.tmin = a.w;
+    r.dx = b.x; r.dy = b.y; r.dz = b.z; r.tmax = b.w;
+    r.ix = 1.0f / b.x; r.iy = 1.0f / b.y; r.iz = 1.0f / b.z;
+    return r;
+}
+
+template <bool ANY>
+__device__ __forceinline__ void write_result(const TraceArgs &a, uint32_t rid, bool hit, const Best &b) {
+    if constexpr (ANY) {
+        a.occluded[rid] = hit ? 1 : 0;
+    } else {
+        float4 h;
+        if (hit) { h.x = b.t; h.y = b.u; h.z = b.v; h.w = __uint_as_float(b.prim); }
+        else     { h.x = __builtin_inff(); h.y = 0.0f; h.z = 0.0f; h.w = __uint_as_float(kNone); }
+        ((float4 *)a.hits)[rid] = h;
+    }
+}
+
+// Table entry access.  Entry: u64 tag | u32 slot[W] | u32 claim | padding.
+__device__ __forceinline__ const uint32_t *entry_ptr(const TraceArgs &a, uint32_t idx) {
+    return (const uint32_t *)((const char *)a.table + (size_t)idx * a.entry_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// K1: predict
+// ---------------------------------------------------------------------------
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uint32_t count) {
+    Counters c;
+    c.zero();
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool enq = false;
+    uint32_t rid = base + i;
+    uint32_t seed_leaf = kNone;
+    if (i < count) {
+        float4 ra, rb;
+        RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
+        c.v[kRays]++;
+        if (!ray_is_valid(ra, rb)) {
+            c.v[kInvalid]++;
+            write_result<ANY>(a, rid, false, Best{});
+        } else {
+            uint64_t key;
+            uint32_t idx;
+            hash_ray(a.hash, r, key, idx);
+            c.v[kLookups]++;
+            const uint32_t *e = entry_ptr(a, idx);
+            const uint64_t tag = *(const uint64_t *)e;
+            const uint32_t W = a.ways;
+            Best b;
+            b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
+            bool positive = (tag == key) && (e[2] != kNone);
+            bool hit = false;
+            if (positive) {
+                c.v[kPositives]++;
+                for (uint32_t s = 0; s < W; s++) {
+                    const uint32_t leaf = e[2 + s];
+                    if (leaf == kNone) break;
+                    c.v[kNodesVisited]++;
+                    c.v[kLeafVisited]++;
+                    if (test_leaf<ANY>((const float4 *)a.tris, leaf, r, b, c)) {
+                        hit = true;
+                        if (ANY) break;
+                    }
+                }
+            }
+            if (EXACT) {
+                // every valid ray traverses; the best predicted hit seeds it
+                if (!ANY) {
+                    float4 h;
+                    h.x = b.t; h.y = b.u; h.z = b.v; h.w = __uint_as_float(b.prim);
+                    ((float4 *)a.hits)[rid] = h;
+                }
+                seed_leaf = b.leaf;
+                enq = true;
+            } else if (positive && hit) {
+                c.v[kPredHits]++;
+                c.v[kHits]++;
+                // depth of the leaf is stored with its first triangle
+                const float4 B0 = ((const float4 *)a.tris)[3 * (size_t)(b.leaf >> 3) + 1];
+                c.v[kNodesSkipped] += __float_as_uint(B0.w);
+                write_result<ANY>(a, rid, true, b);
+            } else {
+                if (positive) c.v[kFalsePos]++;
+                enq = true;
+            }
+        }
+    }
+    // wave-aggregated append to the fallback queue
+    const uint64_t mask = __ballot(enq);
+    if (mask) {
+        const uint32_t lane = __lane_id();
+        const uint32_t leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t qbase = 0;
+        if (lane == leader) qbase = atomicAdd(&a.ctrl[0], (uint32_t)__popcll(mask));
+        qbase = __shfl(qbase, leader);
+        if (enq) {
+            const uint32_t pos = qbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            a.queue[pos] = (uint64_t)rid | ((uint64_t)seed_leaf << 32);
+        }
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+// ---------------------------------------------------------------------------
+// K2: traverse (PLAIN: all rays of [base, base+count); HRPP: the queue)
+// ---------------------------------------------------------------------------
+template <bool ANY, bool EXACT, bool HRPP, bool STATS>
+__global__ __launch_bounds__(128) void k_traverse(TraceArgs a, uint32_t base, uint32_t count) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t stride = blockDim.x;
+    const uint32_t cap = a.stack_cap;
+    uint32_t *stk_node = lds + threadIdx.x;
+    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    Counters c;
+    c.zero();
+    const uint32_t total = HRPP ? *(volatile uint32_t *)&a.ctrl[0] : count;
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+        uint32_t rid, seed_leaf = kNone;
+        if (HRPP) {
+            const uint64_t q = a.queue[i];
+            rid = (uint32_t)q;
+            seed_leaf = (uint32_t)(q >> 32);
+        } else {
+            rid = base + i;
+        }
+        float4 ra, rb;
+        RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
+        if (!HRPP) {
+            c.v[kRays]++;
+            if (!ray_is_valid(ra, rb)) {
+                c.v[kInvalid]++;
+                write_result<ANY>(a, rid, false, Best{});
+                continue;
+            }
+        }
+        Best b;
+        b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
+        if (!ANY && EXACT && HRPP) {
+            const float4 s = ((const float4 *)a.hits)[rid];
+            b.t = s.x; b.u = s.y; b.v = s.z; b.prim = __float_as_uint(s.w); b.leaf = seed_leaf;
+        }
+        const bool hit = traverse<ANY>(a, r, b, c, stk_node, stk_t, stride, cap);
+        write_result<ANY>(a, rid, hit, b);
+        if (hit) c.v[kHits]++;
+        if (HRPP) {
+            uint64_t key;
+            uint32_t idx;
+            hash_ray(a.hash, r, key, idx);
+            if (!ANY && EXACT) {
+                const uint32_t *e = entry_ptr(a, idx);
+                const bool positive = (*(const uint64_t *)e == key) && (e[2] != kNone);
+                if (positive) {
+                    bool in_pred = false;
+                    for (uint32_t s = 0; s < a.ways; s++) {
+                        const uint32_t l = e[2 + s];
+                        if (l == kNone) break;
+                        if (hit && l == b.leaf) in_pred = true;
+                    }
+                    if (in_pred) c.v[kPredHits]++;
+                    else c.v[kFalsePos]++;
+                }
+            }
+            if (hit) {
+                const uint32_t slot = rid - base;
+                a.rec_key[slot] = key;
+                a.rec_idx[slot] = idx;
+                a.rec_leaf[slot] = b.leaf;
+                uint32_t *e = (uint32_t *)entry_ptr(a, idx);
+                atomicMin(&e[2 + a.ways], rid);
+                c.v[kRecords]++;
+            }
+        }
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+// ---------------------------------------------------------------------------
+// K3: epoch-end update (section "HRPP Hash Function": a conflicting ray's
+// leaf is inserted into the existing entry unless already present; there is
+// no replacement policy, section "Precision and Recall").  Deterministic
+// batch form: the key of the smallest ray id owns an entry touched this
+// epoch; the owner's new leaves go into the free slots in increasing leaf-id
+// order; the rest are dropped.
+//   U1 (records): classify each record against the claim winner; collect the
+//       owner's fresh leaves in a sorted, duplicate-free list of W (atomicMin
+//       insertion cascade) kept per claiming ray.
+//   U2 (winning records): rewrite the entry, release the claim.
+//   U3 (records): count drops, clear the record slot, reset the queue count.
+// ---------------------------------------------------------------------------
+enum : uint32_t { kRecConflict = 1, kRecPresent = 2, kRecFresh = 3 };
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_update_classify(TraceArgs a, uint32_t base, uint32_t count) {
+    Counters c;
+    c.zero();
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count && a.rec_idx[i] != kNone) {
+        const uint32_t idx = a.rec_idx[i];
+        const uint32_t W = a.ways;
+        const uint32_t *e = entry_ptr(a, idx);
+        const uint32_t owner = e[2 + W];                // smallest ray id (claim)
+        const uint64_t kstar = a.rec_key[owner - base];
+        const uint32_t leaf = a.rec_leaf[i];
+        uint32_t status;
+        if (a.rec_key[i] != kstar) {
+            status = kRecConflict;
+            c.v[kConflicts]++;
+        } else {
+            bool present = false;
+            if (*(const uint64_t *)e == kstar) {
+                for (uint32_t s = 0; s < W; s++) {
+                    const uint32_t l = e[2 + s];
+                    if (l == kNone) break;
+                    if (l == leaf) present = true;
+                }
+            }
+            if (present) {
+                status = kRecPresent;
+            } else {
+                status = kRecFresh;
+                // sorted insertion of `leaf` into the owner's list of W smallest
+                uint32_t *list = a.topw + (size_t)(owner - base) * W;
+                uint32_t x = leaf;
+                for (uint32_t s = 0; s < W && x != kNone; s++) {
+                    const uint32_t old = atomicMin(&list[s], x);
+                    if (old == x) break;           // already listed
+                    if (old > x) x = old;          // x took this place; carry the old value on
+                }
+            }
+        }
+        a.rec_status[i] = status;
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_update_apply(TraceArgs a, uint32_t base, uint32_t count) {
+    Counters c;
+    c.zero();
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count && a.rec_idx[i] != kNone) {
+        const uint32_t idx = a.rec_idx[i];
+        const uint32_t W = a.ways;
+        uint32_t *e = (uint32_t *)entry_ptr(a, idx);
+        if (e[2 + W] == base + i) {                    // this ray owns the entry
+            const uint64_t kstar = a.rec_key[i];
+            uint32_t used = 0;
+            if (*(const uint64_t *)e != kstar) {
+                *(uint64_t *)e = kstar;
+                for (uint32_t s = 0; s < W; s++) e[2 + s] = kNone;
+                c.v[kTagClaims]++;
+            } else {
+                while (used < W && e[2 + used] != kNone) used++;
+            }
+            uint32_t *list = a.topw + (size_t)i * W;
+            for (uint32_t s = 0; s < W; s++) {
+                const uint32_t l = list[s];
+                if (l != kNone && used < W) {
+                    e[2 + used++] = l;
+                    c.v[kLeafInserts]++;
+                }
+                list[s] = kNone;
+            }
+            e[2 + W] = kNone;                          // release the claim
+        }
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t base, uint32_t count) {
+    Counters c;
+    c.zero();
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) a.ctrl[0] = 0;
+    if (i < count && a.rec_idx[i] != kNone) {
+        if (a.rec_status[i] == kRecFresh) {
+            const uint32_t *e = entry_ptr(a, a.rec_idx[i]);
+            const uint32_t leaf = a.rec_leaf[i];
+            bool present = false;
+            for (uint32_t s = 0; s < a.ways; s++)
+                if (e[2 + s] == leaf) present = true;
+            if (!present) c.v[kDropped]++;
+        }
+        a.rec_idx[i] = kNone;
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+// Fill a region with a 32-bit pattern (predictor reset; a kernel rather than
+// a memset so that the call can sit inside a captured graph).
+__global__ void k_fill32(uint32_t *p, size_t n, uint32_t value) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
+
+template <bool ANY, bool EXACT, bool STATS>
+static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipStream_t s) {
+    const uint32_t g256 = ceil_div(count, 256);
+    hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_traverse<ANY, EXACT, true, STATS>), dim3(ceil_div(count, 128)), dim3(128), lds, s, a,
+                       base, count);
+    hipLaunchKernelGGL((k_update_classify<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    hipLaunchKernelGGL((k_update_apply<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    hipLaunchKernelGGL((k_update_finish<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+}
+
+template <bool ANY, bool STATS>
+static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
+    const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
+    const uint32_t blocks = std::min<uint32_t>(ceil_div(n, 128), a.max_blocks);
+    hipLaunchKernelGGL((k_traverse<ANY, false, false, STATS>), dim3(blocks), dim3(128), lds, s, a, 0u, n);
+}
+
+void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, hipStream_t s) {
+    const bool st = a.stats != nullptr;
+    if (!hrpp) {
+        if (any) { if (st) launch_plain<true, true>(a, n, s); else launch_plain<true, false>(a, n, s); }
+        else     { if (st) launch_plain<false, true>(a, n, s); else launch_plain<false, false>(a, n, s); }
+        return;
+    }
+    for (uint32_t base = 0; base < n; base += epoch) {
+        const uint32_t cnt = std::min(epoch, n - base);
+        if (any) {
+            if (st) launch_epoch<true, false, true>(a, base, cnt, s);
+            else    launch_epoch<true, false, false>(a, base, cnt, s);
+        } else if (exact) {
+            if (st) launch_epoch<false, true, true>(a, base, cnt, s);
+            else    launch_epoch<false, true, false>(a, base, cnt, s);
+        } else {
+            if (st) launch_epoch<false, false, true>(a, base, cnt, s);
+            else    launch_epoch<false, false, false>(a, base, cnt, s);
+        }
+    }
+}
+
+void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s) {
+    if (n == 0) return;
+    const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, s, p, n, value);
+}
+
+}  // namespace hrpp

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libhrpp.so (include/hrpp.h).
+
+Argument marshalling only: every step of the query path runs in the
+library's HIP kernels.  PyTorch provides device memory (``torch.empty`` on
+``cuda``) and the current stream.  The binding refuses to run without the
+compiled library -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhrpp.so")
+
+STAT_NAMES = [
+    "rays", "invalid", "hits", "lookups", "positives", "pred_hits", "false_pos", "traversals",
+    "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
+    "records", "tag_claims", "leaf_inserts", "dropped", "conflicts",
+]
+STATS_SLOTS = 24
+CLOSEST_MODES = {"paper": 0, "exact": 1}
+EXPORTED = [
+    "hrpp_bvh_required_bytes", "hrpp_build_bvh", "hrpp_bvh_build_host", "hrpp_bvh_device_bytes",
+    "hrpp_bvh_upload", "hrpp_bvh_info", "hrpp_bvh_export", "hrpp_bvh_destroy",
+    "hrpp_predictor_required_bytes", "hrpp_predictor_table_bytes", "hrpp_predictor_create",
+    "hrpp_predictor_reset", "hrpp_predictor_export", "hrpp_predictor_import", "hrpp_predictor_destroy",
+    "hrpp_trace_anyhit", "hrpp_trace_closest", "hrpp_get_error", "hrpp_status_string",
+]
+
+
+class HrppError(RuntimeError):
+    pass
+
+
+class _BvhDesc(C.Structure):
+    _fields_ = [("leaf_max", C.c_uint32), ("sah_bins", C.c_uint32), ("max_depth", C.c_uint32)]
+
+
+class _PredDesc(C.Structure):
+    _fields_ = [("log2_entries", C.c_uint32), ("ways", C.c_uint32), ("origin_bits", C.c_uint32),
+                ("dir_bits", C.c_uint32), ("epoch_rays", C.c_uint32), ("hash_mode", C.c_uint32),
+                ("go_up_level", C.c_uint32)]
+
+
+class _Canon(C.Structure):
+    _fields_ = [("box", C.c_void_p), ("right", C.c_void_p), ("first_tri", C.c_void_p),
+                ("count", C.c_void_p), ("depth", C.c_void_p), ("tri_perm", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhrpp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HrppError(f"HRPP HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    vp, u32, sz = C.c_void_p, C.c_uint32, C.c_size_t
+    lib.hrpp_bvh_required_bytes.restype = sz
+    lib.hrpp_bvh_required_bytes.argtypes = [u32, vp]
+    lib.hrpp_build_bvh.argtypes = [vp, u32, vp, vp, sz, vp, C.POINTER(vp)]
+    lib.hrpp_bvh_build_host.argtypes = [vp, u32, vp, C.POINTER(vp)]
+    lib.hrpp_bvh_device_bytes.restype = sz
+    lib.hrpp_bvh_device_bytes.argtypes = [vp]
+    lib.hrpp_bvh_upload.argtypes = [vp, vp, sz, vp]
+    lib.hrpp_bvh_info.argtypes = [vp, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
+    lib.hrpp_bvh_export.argtypes = [vp, vp]
+    lib.hrpp_bvh_destroy.argtypes = [vp]
+    lib.hrpp_bvh_destroy.restype = None
+    lib.hrpp_predictor_required_bytes.restype = sz
+    lib.hrpp_predictor_required_bytes.argtypes = [vp]
+    lib.hrpp_predictor_table_bytes.restype = sz
+    lib.hrpp_predictor_table_bytes.argtypes = [vp]
+    lib.hrpp_predictor_create.argtypes = [vp, vp, vp, sz, vp, C.POINTER(vp)]
+    lib.hrpp_predictor_reset.argtypes = [vp, vp]
+    lib.hrpp_predictor_export.argtypes = [vp, vp, sz, vp]
+    lib.hrpp_predictor_import.argtypes = [vp, vp, sz, vp]
+    lib.hrpp_predictor_destroy.argtypes = [vp]
+    lib.hrpp_predictor_destroy.restype = None
+    lib.hrpp_trace_anyhit.argtypes = [vp, vp, vp, u32, vp, vp, vp]
+    lib.hrpp_trace_closest.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
+    lib.hrpp_get_error.argtypes = [vp, vp]
+    lib.hrpp_status_string.restype = C.c_char_p
+    lib.hrpp_status_string.argtypes = [C.c_int]
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = load_library().hrpp_status_string(status).decode()
+        raise HrppError(f"{what}: {msg} ({status})")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _aligned(nbytes: int, device):
+    """A uint8 device buffer with a 256-byte aligned view of nbytes."""
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw, raw[off:off + nbytes]
+
+
+class BVH:
+    """A BVH built on the host and resident in device memory."""
+
+    def __init__(self, tris: np.ndarray, leaf_max: int = 4, sah_bins: int = 32, max_depth: int = 64,
+                 device: str | None = "cuda"):
+        """Build the tree on the host; upload it to ``device`` unless None."""
+        lib = load_library()
+        v = np.ascontiguousarray(np.asarray(tris, np.float32).reshape(-1, 9))
+        self.num_tris = int(v.shape[0])
+        self.desc = _BvhDesc(leaf_max, sah_bins, max_depth)
+        h = C.c_void_p()
+        _check(lib.hrpp_bvh_build_host(v.ctypes.data, self.num_tris, C.byref(self.desc), C.byref(h)),
+               "hrpp_bvh_build_host")
+        self.handle = h
+        nn, nt, md = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib.hrpp_bvh_info(h, C.byref(nn), C.byref(nt), C.byref(md)), "hrpp_bvh_info")
+        self.num_nodes, self.max_depth = nn.value, md.value
+        self.device_bytes = lib.hrpp_bvh_device_bytes(h)
+        self.buffer = None
+        if device is not None:
+            self.upload(device)
+
+    def upload(self, device: str = "cuda"):
+        self._raw, self.buffer = _aligned(self.device_bytes, device)
+        _check(load_library().hrpp_bvh_upload(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream()),
+               "hrpp_bvh_upload")
+
+    def export(self) -> dict:
+        """Canonical depth-first tree as numpy arrays."""
+        m, n = self.num_nodes, self.num_tris
+        out = dict(box=np.zeros((m, 6), np.float32), right=np.zeros(m, np.uint32), first=np.zeros(m, np.uint32),
+                   count=np.zeros(m, np.uint32), depth=np.zeros(m, np.uint32), perm=np.zeros(n, np.uint32))
+        c = _Canon(out["box"].ctypes.data, out["right"].ctypes.data, out["first"].ctypes.data,
+                   out["count"].ctypes.data, out["depth"].ctypes.data, out["perm"].ctypes.data)
+        _check(load_library().hrpp_bvh_export(self.handle, C.byref(c)), "hrpp_bvh_export")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hrpp_bvh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Predictor:
+    """A predictor table bound to one BVH (one per query type, hit-any / hit-all)."""
+
+    def __init__(self, bvh: BVH, log2_entries: int = 12, ways: int = 4, origin_bits: int = 5, dir_bits: int = 6,
+                 epoch_rays: int = 1 << 17, hash_mode: int = 0, go_up_level: int = 0, device: str = "cuda"):
+        lib = load_library()
+        self.desc = _PredDesc(log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level)
+        need = lib.hrpp_predictor_required_bytes(C.byref(self.desc))
+        if need == 0:
+            raise HrppError("hrpp_predictor_required_bytes: invalid descriptor")
+        self.table_bytes = lib.hrpp_predictor_table_bytes(C.byref(self.desc))
+        self.entry_bytes = 32 if ways <= 4 else 64
+        self._raw, self.buffer = _aligned(need, device)
+        h = C.c_void_p()
+        _check(lib.hrpp_predictor_create(bvh.handle, C.byref(self.desc), self.buffer.data_ptr(), need, _stream(),
+                                         C.byref(h)), "hrpp_predictor_create")
+        self.handle = h
+        self.bvh = bvh
+        self.device_bytes = need
+
+    @property
+    def ways(self) -> int:
+        return self.desc.ways
+
+    def reset(self):
+        _check(load_library().hrpp_predictor_reset(self.handle, _stream()), "hrpp_predictor_reset")
+
+    def export_raw(self) -> np.ndarray:
+        buf = np.empty(self.table_bytes, np.uint8)
+        _check(load_library().hrpp_predictor_export(self.handle, buf.ctypes.data, buf.nbytes, _stream()),
+               "hrpp_predictor_export")
+        return buf
+
+    def export(self):
+        """(tags uint64 [N], slots uint32 [N, W]) of the current table."""
+        raw = self.export_raw().reshape(-1, self.entry_bytes)
+        tags = raw[:, 0:8].copy().view(np.uint64).reshape(-1)
+        slots = raw[:, 8:8 + 4 * self.ways].copy().view(np.uint32).reshape(-1, self.ways)
+        return tags, slots
+
+    def import_raw(self, raw: np.ndarray):
+        raw = np.ascontiguousarray(raw, np.uint8)
+        _check(load_library().hrpp_predictor_import(self.handle, raw.ctypes.data, raw.nbytes, _stream()),
+               "hrpp_predictor_import")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hrpp_predictor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def new_stats(device: str = "cuda") -> torch.Tensor:
+    return torch.zeros(STATS_SLOTS, dtype=torch.int64, device=device)
+
+
+def stats_dict(stats: torch.Tensor) -> dict:
+    v = stats.detach().cpu().numpy().astype(np.uint64)
+    return {k: int(v[i]) for i, k in enumerate(STAT_NAMES)}
+
+
+def _rays_ok(rays: torch.Tensor):
+    if not (rays.is_cuda and rays.dtype == torch.float32 and rays.dim() == 2 and rays.shape[1] == 8
+            and rays.is_contiguous()):
+        raise HrppError("rays must be a contiguous cuda float32 tensor of shape [n, 8]")
+
+
+def trace_anyhit(bvh: BVH, pred: Predictor | None, rays: torch.Tensor, out: torch.Tensor | None = None,
+                 stats: torch.Tensor | None = None) -> torch.Tensor:
+    """Occlusion flags (uint8 [n]) for rays [n, 8]."""
+    _rays_ok(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=rays.device)
+    _check(load_library().hrpp_trace_anyhit(bvh.handle, pred.handle if pred is not None else None, rays.data_ptr(),
+                                            n, out.data_ptr(), stats.data_ptr() if stats is not None else None,
+                                            _stream()), "hrpp_trace_anyhit")
+    return out
+
+
+def trace_closest(bvh: BVH, pred: Predictor | None, rays: torch.Tensor, mode: str = "paper",
+                  out: torch.Tensor | None = None, stats: torch.Tensor | None = None) -> torch.Tensor:
+    """Closest hits as float32 [n, 4] (t, u, v, prim bits) for rays [n, 8]."""
+    _rays_ok(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    _check(load_library().hrpp_trace_closest(bvh.handle, pred.handle if pred is not None else None,
+                                             rays.data_ptr(), n, CLOSEST_MODES[mode], out.data_ptr(),
+                                             stats.data_ptr() if stats is not None else None, _stream()),
+           "hrpp_trace_closest")
+    return out
+
+
+def get_error(bvh: BVH | None = None):
+    _check(load_library().hrpp_get_error(bvh.handle if bvh is not None else None, _stream()), "hrpp_get_error")

@@ -266,13 +266,16 @@ def _face_normals(tris: np.ndarray, prim: np.ndarray) -> np.ndarray:
 
 
 def _hit_frame(tris, rays, t, prim, eps):
-    if np.any(prim == MISS):
-        raise ValueError("secondary rays need every primary ray to hit")
+    """Offset hit points and facing normals; rows of missed primaries are
+    returned with ``ok = False`` (their secondary rays are made invalid)."""
+    ok = prim != MISS
+    safe = np.where(ok, prim, 0)
+    tt = np.where(ok, t, 0.0).astype(np.float64)
     o, d = rays[:, 0:3].astype(np.float64), rays[:, 4:7].astype(np.float64)
-    p = o + t.astype(np.float64)[:, None] * d
-    n = _face_normals(tris, prim)
+    p = o + tt[:, None] * d
+    n = _face_normals(tris, safe)
     facing = np.where((np.sum(n * d, axis=1) < 0)[:, None], n, -n)
-    return p + eps * facing, facing
+    return p + eps * facing, facing, ok
 
 
 def shadow_rays_from_hits(tris, rays, t, prim, seed: int, light_center=(0.5, 1.0, 0.5),
@@ -280,9 +283,11 @@ def shadow_rays_from_hits(tris, rays, t, prim, seed: int, light_center=(0.5, 1.0
     """One shadow ray per hit point towards a square area light (y = const).
 
     Origin offset by ``eps`` along the normal facing the incoming ray;
-    direction = light sample - origin (unnormalised); interval (0, 1).
+    direction = light sample - origin (unnormalised); interval (0, 1).  A
+    primary ray that missed (a binary32 crack between triangles can let a
+    ray through) yields an invalid ray (zero direction).
     """
-    o, _ = _hit_frame(tris, rays, t, prim, eps)
+    o, _, ok = _hit_frame(tris, rays, t, prim, eps)
     g = rng(seed + 11)
     n = o.shape[0]
     lc = np.asarray(light_center, np.float64)
@@ -290,6 +295,7 @@ def shadow_rays_from_hits(tris, rays, t, prim, seed: int, light_center=(0.5, 1.0
                   lc[2] + light_size * g.uniform(-0.5, 0.5, n)], axis=1)
     o32 = o.astype(np.float32)
     d32 = (s.astype(np.float32) - o32).astype(np.float32)
+    d32[~ok] = 0.0
     return pack_rays(o32, d32, 0.0, 1.0)
 
 
@@ -317,9 +323,10 @@ def ao_rays_from_hits(tris, rays, t, prim, seed: int, samples: int = 8, tmax: fl
                       eps: float = 1e-4) -> np.ndarray:
     """``samples`` cosine-weighted hemisphere rays per hit, sample-major order.
 
-    Unit directions about the facing normal; interval (0, tmax).
+    Unit directions about the facing normal; interval (0, tmax).  Rays of
+    missed primaries are invalid (zero direction).
     """
-    o, nf = _hit_frame(tris, rays, t, prim, eps)
+    o, nf, ok = _hit_frame(tris, rays, t, prim, eps)
     t1, t2 = _onb(nf)
     g = rng(seed + 13)
     m = o.shape[0]
@@ -329,6 +336,7 @@ def ao_rays_from_hits(tris, rays, t, prim, seed: int, samples: int = 8, tmax: fl
         z = np.sqrt(np.maximum(0.0, 1 - x * x - y * y))
         d = x[:, None] * t1 + y[:, None] * t2 + z[:, None] * nf
         d /= np.linalg.norm(d, axis=1, keepdims=True)
+        d[~ok] = 0.0
         out.append(pack_rays(o.astype(np.float32), d.astype(np.float32), 0.0, tmax))
     return np.concatenate(out, axis=0)
 
@@ -353,3 +361,37 @@ def surface_points(tris: np.ndarray, count: int, seed: int):
 def scene_diagonal(tris: np.ndarray) -> float:
     v = tris.reshape(-1, 3).astype(np.float64)
     return float(np.linalg.norm(v.max(0) - v.min(0)))
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (sizes of the benchmark configurations)
+# ---------------------------------------------------------------------------
+
+TINY = dict(seed=1, n_tris=256, n_rays=4096, log2_entries=12, ways=4, origin_bits=5, dir_bits=6, epoch=256)
+AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin_bits=5, dir_bits=6,
+                epoch=1 << 17, light_center=(0.5, 1.0, 0.5), light_size=0.1)
+INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=20, ways=8, origin_bits=5,
+                  dir_bits=6, epoch=1 << 17, tmax_frac=0.05)
+
+
+def tiny_workload():
+    """256-triangle soup and 4,096 shadow rays to an area light."""
+    w = TINY
+    return triangle_soup(w["seed"], w["n_tris"]), tiny_shadow_rays(w["seed"], w["n_rays"])
+
+
+def camera_for(width: int, height: int) -> Camera:
+    return Camera(width=width, height=height)
+
+
+def terrain_workload(total: int = 1 << 20, width: int = 1920, height: int = 1080, seed: int = 2,
+                     order: str = "bayer"):
+    """Scene and primary rays of the at-scale workload (optionally scaled down)."""
+    if total == 1 << 20:
+        tris, hf = terrain_scene(seed)
+    else:
+        tris, hf = scaled_terrain_scene(seed, total)
+    cam = camera_for(width, height)
+    rays, pid = cam.rays(order)
+    cam.assert_all_hit_terrain(rays, hf.amplitude)
+    return tris, rays

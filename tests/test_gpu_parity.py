@@ -1,0 +1,251 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Any-hit flags, closest hits (t, u, v, prim bit patterns), every counter and
+the predictor table bytes must match exactly; both sides run the same
+binary32 operation sequence.  (The stated tolerance for floating-point
+outputs -- t within 1e-5 relative, barycentrics within 1e-5 absolute -- is
+therefore met with zero error; a mismatch beyond it fails as well.)
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+NONE32 = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def hrpp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_01304_amd as h
+    h.load_library()
+    return h
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(hrpp, bvh, rays, query="any", mode="paper", pred=None, stats=None):
+    import torch
+    r = torch.from_numpy(np.ascontiguousarray(rays, np.float32)).cuda()
+    st = stats if stats is not None else hrpp.new_stats()
+    if query == "any":
+        out = hrpp.trace_anyhit(bvh, pred, r, stats=st)
+    else:
+        out = hrpp.trace_closest(bvh, pred, r, mode=mode, stats=st)
+    torch.cuda.synchronize()
+    hrpp.get_error(bvh)
+    return out.cpu().numpy(), hrpp.stats_dict(st)
+
+
+def assert_same_result(query, got, want):
+    if query == "any":
+        assert got.dtype == np.uint8
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, f"{bad.size} flags differ, first rays {bad[:8]}"
+    else:
+        g, w = got.view(np.uint32), want.view(np.uint32)
+        bad = np.nonzero(np.any(g != w, axis=1))[0]
+        if bad.size:
+            i = bad[0]
+            raise AssertionError(f"{bad.size} hits differ; ray {i}: gpu {got[i]} {g[i, 3]} oracle {want[i]} {w[i, 3]}")
+
+
+def assert_same_table(pred, tb: oracle.Table):
+    tags, slots = pred.export()
+    assert np.array_equal(tags, tb.tags), f"{int(np.count_nonzero(tags != tb.tags))} tags differ"
+    assert np.array_equal(slots, tb.slots), f"{int(np.count_nonzero(np.any(slots != tb.slots, 1)))} entries differ"
+
+
+def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None, calls=1, leaf_max=4):
+    """Run `calls` successive traces of `rays` on both sides and compare all."""
+    _say(f"{name}: {tris.shape[0]} tris, {rays.shape[0]} rays, {query}/{mode}, pred={pred_cfg}, calls={calls}")
+    bvh = hrpp.BVH(tris, leaf_max=leaf_max)
+    ob = oracle.build_sah(tris, leaf_max=leaf_max)
+    vtx = oracle.bvh_vertices(tris, ob)
+    pred = tb = None
+    if pred_cfg is not None:
+        T, W, qo, qd, E = pred_cfg
+        pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E)
+        tb = oracle.Table(T, W, qo, qd)
+    gst = hrpp.new_stats()
+    for c in range(calls):
+        got, gs = gpu_run(hrpp, bvh, rays, query, mode, pred, gst)
+        want, ws = oracle.trace(ob, tris, rays, query=query, mode=mode, table=tb,
+                                epoch=pred_cfg[4] if pred_cfg else 1 << 30, vtx=vtx)
+        assert_same_result(query, got, want)
+        if c == 0:
+            acc = dict(ws)
+        else:
+            acc = {k: acc[k] + ws[k] for k in acc}
+        assert gs == acc, {k: (gs[k], acc[k]) for k in acc if gs[k] != acc[k]}
+        if pred is not None:
+            assert_same_table(pred, tb)
+    return got, gs
+
+
+# ---------------------------------------------------------------------------
+# Tiny workload: 256 triangles, 4,096 shadow rays
+# ---------------------------------------------------------------------------
+
+def test_tiny_plain_anyhit(hrpp):
+    tris, rays = sg.tiny_workload()
+    occ, st = check_case(hrpp, "tiny plain", tris, rays)
+    assert st["hits"] > 400
+
+
+@pytest.mark.parametrize("epoch", [256, 1, 4096, 1000, 5000])
+def test_tiny_hrpp_anyhit(hrpp, epoch):
+    tris, rays = sg.tiny_workload()
+    check_case(hrpp, f"tiny hrpp E={epoch}", tris, rays, pred_cfg=(12, 4, 5, 6, epoch))
+
+
+def test_tiny_hrpp_successive_calls_accumulate(hrpp):
+    tris, rays = sg.tiny_workload()
+    _, st = check_case(hrpp, "tiny hrpp x3", tris, rays, pred_cfg=(12, 4, 5, 6, 256), calls=3)
+    assert st["pred_hits"] > 0
+
+
+@pytest.mark.parametrize("mode", ["paper", "exact"])
+def test_tiny_closest(hrpp, mode):
+    tris, rays = sg.tiny_workload()
+    rays = rays.copy()
+    rays[:, 7] = np.inf
+    check_case(hrpp, f"tiny closest plain {mode}", tris, rays, query="closest", mode=mode)
+    check_case(hrpp, f"tiny closest hrpp {mode}", tris, rays, query="closest", mode=mode,
+               pred_cfg=(12, 4, 5, 6, 256), calls=2)
+
+
+# ---------------------------------------------------------------------------
+# Scaled terrain: several epochs, coherent primaries, shadow and AO rays
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def small_terrain():
+    tris, prim = sg.terrain_workload(total=30000, width=320, height=180)
+    return tris, prim
+
+
+@pytest.mark.parametrize("mode", ["paper", "exact"])
+def test_terrain_primary_closest(hrpp, small_terrain, mode):
+    tris, prim = small_terrain
+    _, st = check_case(hrpp, f"terrain primary {mode}", tris, prim, query="closest", mode=mode,
+                       pred_cfg=(14, 8, 5, 6, 4096))
+    assert st["pred_hits"] > 1000
+
+
+def test_terrain_shadow_and_ao(hrpp, small_terrain):
+    tris, prim = small_terrain
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    t, p = he[:, 0], he[:, 3].view(np.uint32)
+    shadow = sg.shadow_rays_from_hits(tris, prim, t, p, seed=2)
+    check_case(hrpp, "terrain shadow plain", tris, shadow)
+    check_case(hrpp, "terrain shadow hrpp", tris, shadow, pred_cfg=(14, 8, 5, 6, 4096))
+    ao = sg.ao_rays_from_hits(tris, prim[:4000], t[:4000], p[:4000], seed=3, samples=8,
+                              tmax=0.05 * sg.scene_diagonal(tris))
+    check_case(hrpp, "terrain ao plain", tris, ao)
+    check_case(hrpp, "terrain ao hrpp", tris, ao, pred_cfg=(14, 8, 4, 4, 2048))
+
+
+@pytest.mark.parametrize("cfg", [(1, 1, 2, 2, 512), (4, 2, 3, 3, 777), (10, 8, 7, 7, 64), (16, 3, 1, 1, 4096)])
+def test_terrain_table_shapes(hrpp, small_terrain, cfg):
+    # tiny tables (heavy collisions), one way (drops), odd epochs (ragged tails)
+    tris, prim = small_terrain
+    check_case(hrpp, f"terrain table {cfg}", tris, prim[:20000], query="closest", mode="paper", pred_cfg=cfg)
+    check_case(hrpp, f"terrain table {cfg} exact", tris, prim[:20000], query="closest", mode="exact", pred_cfg=cfg)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+
+def test_edge_cases(hrpp):
+    import torch
+    tris, rays = sg.tiny_workload()
+    _say("edge: n = 0")
+    bvh = hrpp.BVH(tris)
+    pred = hrpp.Predictor(bvh, 12, 4, 5, 6, 256)
+    st = hrpp.new_stats()
+    empty = torch.empty((0, 8), dtype=torch.float32, device="cuda")
+    hrpp.trace_anyhit(bvh, pred, empty, stats=st)
+    hrpp.trace_closest(bvh, pred, empty, stats=st)
+    torch.cuda.synchronize()
+    assert all(v == 0 for v in hrpp.stats_dict(st).values())
+    # invalid rays mixed into valid ones
+    bad = rays.copy()
+    bad[::7, 4:7] = 0.0
+    bad[1::11, 0] = np.nan
+    bad[2::13, 7] = bad[2::13, 3]
+    bad[3::17, 5] = np.inf
+    _, s = check_case(hrpp, "edge invalid rays", tris, bad, pred_cfg=(12, 4, 5, 6, 100))
+    assert s["invalid"] > 500
+    check_case(hrpp, "edge invalid rays closest", tris, bad, query="closest", mode="exact", pred_cfg=(12, 4, 5, 6, 100))
+    # one ray; a single-triangle scene (the root is a leaf); leaf_max 1 and 8
+    check_case(hrpp, "edge one ray", tris, rays[:1], pred_cfg=(12, 4, 5, 6, 256))
+    one = tris[:1]
+    r1 = sg.pack_rays(np.tile(one[0].mean(0) + [0, 0.5, 0], (64, 1)).astype(np.float32),
+                      np.tile(np.float32([0.001, -1, 0.002]), (64, 1)), 0.0, np.inf)
+    check_case(hrpp, "edge root leaf", one, r1, pred_cfg=(4, 1, 3, 3, 8))
+    check_case(hrpp, "edge root leaf closest", one, r1, query="closest", pred_cfg=(4, 1, 3, 3, 8))
+    check_case(hrpp, "edge leaf_max 1", tris, rays, pred_cfg=(12, 4, 5, 6, 256), leaf_max=1)
+    check_case(hrpp, "edge leaf_max 8", tris, rays, query="closest", mode="paper", pred_cfg=(12, 8, 5, 6, 256),
+               leaf_max=8)
+
+
+def test_determinism_and_reset(hrpp, small_terrain):
+    import torch
+    tris, prim = small_terrain
+    _say("determinism")
+    bvh = hrpp.BVH(tris)
+    pred = hrpp.Predictor(bvh, 14, 8, 5, 6, 4096)
+    r = torch.from_numpy(prim).cuda()
+    outs = []
+    for _ in range(3):
+        pred.reset()
+        st = hrpp.new_stats()
+        h = hrpp.trace_closest(bvh, pred, r, mode="paper", stats=st)
+        torch.cuda.synchronize()
+        outs.append((h.cpu().numpy().tobytes(), pred.export_raw().tobytes(), tuple(hrpp.stats_dict(st).items())))
+    assert outs[0] == outs[1] == outs[2]
+    # export / import round trip restores the trajectory
+    pred.reset()
+    hrpp.trace_closest(bvh, pred, r[:10000], mode="paper")
+    saved = pred.export_raw()
+    h1 = hrpp.trace_closest(bvh, pred, r[10000:], mode="paper").cpu().numpy()
+    pred.reset()
+    pred.import_raw(saved)
+    h2 = hrpp.trace_closest(bvh, pred, r[10000:], mode="paper").cpu().numpy()
+    assert np.array_equal(h1.view(np.uint32), h2.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# Full size: the 1M-triangle scene at 1920x1080, in the benchmark's launch
+# configuration (hit-all predictor 2^20 x 8 for primaries, hit-any predictor
+# for shadow rays, epochs of 2^17 rays)
+# ---------------------------------------------------------------------------
+
+def test_full_size_primary_and_shadow(hrpp):
+    w = sg.AT_SCALE
+    tris, prim = sg.terrain_workload()
+    cfg = (w["log2_entries"], w["ways"], w["origin_bits"], w["dir_bits"], w["epoch"])
+    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg)
+    assert st["rays"] == 1920 * 1080
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    check_case(hrpp, "full primary exact (plain)", tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
+                                      light_center=w["light_center"], light_size=w["light_size"])
+    check_case(hrpp, "full shadow plain", tris, shadow)
+    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg)
