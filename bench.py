@@ -1,0 +1,304 @@
+#!/usr/bin/env python
+"""Throughput of Hash-Based Ray Path Prediction versus plain BVH traversal on one MI355X.
+
+One step = the whole query path over one frame of the at-scale workload
+(1,048,576-triangle terrain + boxes, SAH BVH with leaves of <= 4):
+  1. reset the hit-all and hit-any predictors (2^20 entries x 8 leaves),
+  2. 1920x1080 primary rays, closest hit (the paper's semantics: a
+     successful prediction is accepted), hit-all predictor,
+  3. one shadow ray per primary hit towards a 0.1 x 0.1 area light, any hit,
+     hit-any predictor,
+with epochs of 2^17 rays.  The same rays are also traced without a
+predictor ("plain").  Rays and the BVH are resident in HBM before timing;
+shadow rays are built once, in setup, from the GPU's exact primary hits.
+
+Prints one JSON line.  Options: --steps, --warmup, --no-cpu-baseline,
+--no-ao (skip the incoherent AO measurement), --gpus (only 1 is supported).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s HRPP vs plain BVH traversal (shadow/AO), % nodes skipped, p99 lat"
+HBM_PEAK_GBS = 8000.0
+NODE_B, TRI_B, RAY_B = 64, 48, 32
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ao", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) * 1e3 / steps
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
+    """Algorithmic bytes of one kernel kind over one step (both calls)."""
+    tot = 0
+    for st, n, out_b in ((st_any, n_any, 1), (st_all, n_all, 16)):
+        trav_tri = st["tri_tests"] - st["pred_tri_tests"]
+        if kind == "k_traverse_plain":
+            tot += n * (RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * st["tri_tests"]
+        elif kind == "k_traverse_queue":
+            tot += (st["traversals"] * (8 + RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * trav_tri
+                    + st["records"] * (16 + 4))
+        elif kind == "k_predict":
+            tot += (n * RAY_B + st["lookups"] * entry_b + TRI_B * st["pred_tri_tests"]
+                    + st["pred_hits"] * out_b + st["traversals"] * 8)
+        elif kind.startswith("k_update"):
+            tot += st["records"] * (16 + 4 + 4 + entry_b)
+    return tot
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the query path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1910_01304_amd as hrpp
+    import scenegen as sg
+
+    hrpp.load_library()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    w = sg.AT_SCALE
+    log("generating the at-scale workload")
+    tris, prim = sg.terrain_workload()
+    n_prim = prim.shape[0]
+    t0 = time.perf_counter()
+    bvh = hrpp.BVH(tris)
+    build_s = time.perf_counter() - t0
+    log(f"BVH: {bvh.num_nodes} nodes, depth {bvh.max_depth}, built in {build_s:.2f} s")
+    pcfg = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=w["origin_bits"],
+                dir_bits=w["dir_bits"], epoch_rays=w["epoch"])
+    pred_all = hrpp.Predictor(bvh, **pcfg)
+    pred_any = hrpp.Predictor(bvh, **pcfg)
+    prim_d = torch.from_numpy(prim).cuda()
+    he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
+                                      light_center=w["light_center"], light_size=w["light_size"])
+    shadow_d = torch.from_numpy(shadow).cuda()
+    n_sh = shadow.shape[0]
+    hits_out = torch.empty((n_prim, 4), dtype=torch.float32, device="cuda")
+    occ_out = torch.empty(n_sh, dtype=torch.uint8, device="cuda")
+    rays_per_step = n_prim + n_sh
+
+    def primary_hrpp():
+        pred_all.reset()
+        hrpp.trace_closest(bvh, pred_all, prim_d, mode="paper", out=hits_out)
+
+    def shadow_hrpp():
+        pred_any.reset()
+        hrpp.trace_anyhit(bvh, pred_any, shadow_d, out=occ_out)
+
+    def step_hrpp():
+        primary_hrpp()
+        shadow_hrpp()
+
+    def primary_plain():
+        hrpp.trace_closest(bvh, None, prim_d, mode="paper", out=hits_out)
+
+    def shadow_plain():
+        hrpp.trace_anyhit(bvh, None, shadow_d, out=occ_out)
+
+    def step_plain():
+        primary_plain()
+        shadow_plain()
+
+    log("timing")
+    ms_hrpp, wall_hrpp = timed(torch, step_hrpp, args.steps, args.warmup)
+    ms_plain, wall_plain = timed(torch, step_plain, args.steps, args.warmup)
+    parts = {}
+    for name, fn in (("primary_hrpp", primary_hrpp), ("primary_plain", primary_plain),
+                     ("shadow_hrpp", shadow_hrpp), ("shadow_plain", shadow_plain)):
+        parts[name] = timed(torch, fn, args.steps, 1)[0]
+
+    # counters of one step (separate pass with stats on)
+    def counted(fn_any, fn_all):
+        sa, sb = hrpp.new_stats(), hrpp.new_stats()
+        fn_all(sb)
+        fn_any(sa)
+        torch.cuda.synchronize()
+        return hrpp.stats_dict(sa), hrpp.stats_dict(sb)
+
+    def h_all(st):
+        pred_all.reset()
+        hrpp.trace_closest(bvh, pred_all, prim_d, mode="paper", out=hits_out, stats=st)
+
+    def h_any(st):
+        pred_any.reset()
+        hrpp.trace_anyhit(bvh, pred_any, shadow_d, out=occ_out, stats=st)
+
+    h_sa, h_sb = counted(h_any, h_all)
+    p_sa, p_sb = counted(lambda st: hrpp.trace_anyhit(bvh, None, shadow_d, out=occ_out, stats=st),
+                         lambda st: hrpp.trace_closest(bvh, None, prim_d, mode="paper", out=hits_out, stats=st))
+    hrpp.get_error(bvh)
+
+    def pct_saved(key, h, p):
+        return 100.0 * (1.0 - h[key] / p[key]) if p[key] else 0.0
+
+    def mrays(n, ms):
+        return n / (ms * 1e-3) / 1e6
+
+    prim_info = dict(
+        rays=n_prim, query="closest (paper semantics)", hrpp_mrays_s=mrays(n_prim, parts["primary_hrpp"]),
+        plain_mrays_s=mrays(n_prim, parts["primary_plain"]),
+        pct_nodes_skipped=pct_saved("nodes_visited", h_sb, p_sb),
+        pct_box_tests_skipped=pct_saved("box_tests", h_sb, p_sb),
+        prediction_hit_rate=h_sb["pred_hits"] / n_prim, false_positive_rate=h_sb["false_pos"] / n_prim)
+    shadow_info = dict(
+        rays=n_sh, query="any hit", hrpp_mrays_s=mrays(n_sh, parts["shadow_hrpp"]),
+        plain_mrays_s=mrays(n_sh, parts["shadow_plain"]),
+        pct_nodes_skipped=pct_saved("nodes_visited", h_sa, p_sa),
+        pct_box_tests_skipped=pct_saved("box_tests", h_sa, p_sa),
+        prediction_hit_rate=h_sa["pred_hits"] / n_sh, false_positive_rate=h_sa["false_pos"] / n_sh,
+        occluded_fraction=h_sa["hits"] / n_sh)
+    nodes_h = h_sa["nodes_visited"] + h_sb["nodes_visited"]
+    nodes_p = p_sa["nodes_visited"] + p_sb["nodes_visited"]
+    box_h = h_sa["box_tests"] + h_sb["box_tests"]
+    box_p = p_sa["box_tests"] + p_sb["box_tests"]
+
+    # live per-kernel timing (HIP events on the launch stream) for the roofline
+    roofline = None
+    kernels = {}
+    if not args.no_profile:
+        entry_b = pred_all.entry_bytes
+        reps = max(1, args.steps)
+        for label, fn, sts in (("hrpp", step_hrpp, (h_sa, h_sb)), ("plain", step_plain, (p_sa, p_sb))):
+            torch.cuda.synchronize()
+            hrpp.profile_start()
+            for _ in range(reps):
+                fn()
+            prof = hrpp.profile_stop()
+            for k, (launches, total_ms) in prof.items():
+                nb = kernel_bytes(k, sts[0], sts[1], entry_b, n_sh, n_prim)
+                per_launch_b = nb * reps / launches
+                avg_ms = total_ms / launches
+                kernels[f"{label}:{k}"] = dict(launches_per_step=launches // reps, avg_us=avg_ms * 1e3,
+                                               ms_per_step=total_ms / reps, bytes_per_launch=per_launch_b,
+                                               gbs=per_launch_b / (avg_ms * 1e-3) / 1e9)
+        dom = max((k for k in kernels if k.startswith("hrpp:")), key=lambda k: kernels[k]["ms_per_step"])
+        d = kernels[dom]
+        roofline = {"bound": "hbm", "kernel": dom.split(":", 1)[1], "achieved": round(d["gbs"], 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+                    "traffic": None, "avg_launch_us": round(d["avg_us"], 2),
+                    "algorithmic_bytes_per_launch": int(d["bytes_per_launch"])}
+
+    ao_info = None
+    if not args.no_ao:
+        wi = sg.INCOHERENT
+        log("incoherent AO workload")
+        cam_rays, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+        cam_d = torch.from_numpy(cam_rays).cuda()
+        hh = hrpp.trace_closest(bvh, None, cam_d, mode="exact").cpu().numpy()
+        ao = sg.ao_rays_from_hits(tris, cam_rays, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                                  samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+        ao_d = torch.from_numpy(ao).cuda()
+        ao_out = torch.empty(ao.shape[0], dtype=torch.uint8, device="cuda")
+        pred_ao = hrpp.Predictor(bvh, log2_entries=wi["log2_entries"], ways=wi["ways"], origin_bits=wi["origin_bits"],
+                                 dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"])
+
+        def ao_hrpp():
+            pred_ao.reset()
+            hrpp.trace_anyhit(bvh, pred_ao, ao_d, out=ao_out)
+
+        ms_ao_h = timed(torch, ao_hrpp, max(1, args.steps // 2), 1)[0]
+        ms_ao_p = timed(torch, lambda: hrpp.trace_anyhit(bvh, None, ao_d, out=ao_out), max(1, args.steps // 2), 1)[0]
+        sh_, sp_ = hrpp.new_stats(), hrpp.new_stats()
+        pred_ao.reset()
+        hrpp.trace_anyhit(bvh, pred_ao, ao_d, out=ao_out, stats=sh_)
+        hrpp.trace_anyhit(bvh, None, ao_d, out=ao_out, stats=sp_)
+        torch.cuda.synchronize()
+        a_h, a_p = hrpp.stats_dict(sh_), hrpp.stats_dict(sp_)
+        ao_info = dict(rays=int(ao.shape[0]), query="any hit", hrpp_mrays_s=mrays(ao.shape[0], ms_ao_h),
+                       plain_mrays_s=mrays(ao.shape[0], ms_ao_p),
+                       pct_nodes_skipped=pct_saved("nodes_visited", a_h, a_p),
+                       pct_box_tests_skipped=pct_saved("box_tests", a_h, a_p),
+                       prediction_hit_rate=a_h["pred_hits"] / ao.shape[0],
+                       false_positive_rate=a_h["false_pos"] / ao.shape[0],
+                       occluded_fraction=a_h["hits"] / ao.shape[0])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("oracle on the host cores")
+        ob = oracle.build_sah(tris)
+        vtx = oracle.bvh_vertices(tris, ob)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        times = []
+        for _ in range(5):
+            ta = oracle.Table(w["log2_entries"], w["ways"], w["origin_bits"], w["dir_bits"])
+            tb = oracle.Table(w["log2_entries"], w["ways"], w["origin_bits"], w["dir_bits"])
+            c0 = time.perf_counter()
+            oracle.trace(ob, tris, prim, query="closest", mode="paper", table=ta, epoch=w["epoch"], vtx=vtx,
+                         nthreads=threads)
+            oracle.trace(ob, tris, shadow, query="any", table=tb, epoch=w["epoch"], vtx=vtx, nthreads=threads)
+            times.append(time.perf_counter() - c0)
+        med = statistics.median(times)
+        cpu = {"value": round(rays_per_step / med / 1e6, 3), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+               "sample": f"the full step ({rays_per_step} rays, HRPP, same tables and epochs), median of 5 runs, "
+                         f"{med:.2f} s each"}
+
+    value = mrays(rays_per_step, ms_hrpp)
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_hrpp, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) + shadow any-hit, "
+                               "HRPP 2^20 x 8, q_o 5, q_d 6, epoch 2^17",
+                   "triangles": int(tris.shape[0]), "rays_per_step": int(rays_per_step),
+                   "bvh_nodes": int(bvh.num_nodes), "bvh_depth": int(bvh.max_depth)},
+        "plain_mrays_s": round(mrays(rays_per_step, ms_plain), 2),
+        "plain_ms_per_step": round(ms_plain, 4),
+        "speedup_vs_plain": round(ms_plain / ms_hrpp, 4),
+        "wall_ms_per_step": {"hrpp": round(wall_hrpp, 4), "plain": round(wall_plain, 4)},
+        "pct_nodes_skipped": round(100.0 * (1 - nodes_h / nodes_p), 3),
+        "pct_box_tests_skipped": round(100.0 * (1 - box_h / box_p), 3),
+        "primary": prim_info, "shadow": shadow_info, "ao": ao_info,
+        "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
+        "p99_latency_ms": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -90,12 +90,15 @@ typedef struct {
  *  records                      update records emitted (traversed rays with a hit)
  *  tag_claims, leaf_inserts     entries (re)claimed / leaves written
  *  dropped                      owner-key records whose leaf did not fit
- *  conflicts                    records discarded because another key owns the entry */
+ *  conflicts                    records discarded because another key owns the entry
+ *  pred_leaf_visited, pred_tri_tests  the part of leaf_visited / tri_tests spent
+ *                               on predicted leaves */
 #define HRPP_STATS_SLOTS 24
 typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
              nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
-             records, tag_claims, leaf_inserts, dropped, conflicts, reserved[5];
+             records, tag_claims, leaf_inserts, dropped, conflicts, pred_leaf_visited, pred_tri_tests,
+             reserved[3];
 } hrpp_stats;
 
 enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };
@@ -203,6 +206,16 @@ hrpp_status hrpp_trace_anyhit(const hrpp_bvh *bvh, hrpp_predictor *pred, const h
  * Other arguments as for hrpp_trace_anyhit. */
 hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
                                uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream);
+
+/* Per-kernel timing for measurement.  Between hrpp_profile_start() and
+ * hrpp_profile_stop(), every kernel the library launches is bracketed by two
+ * HIP events recorded on the launch stream.  Stop waits for those events and
+ * writes one record per kernel kind that ran (up to `capacity`; *count gets
+ * the number of kinds).  Process-global and not thread-safe; timing adds a
+ * few microseconds per launch, so time throughput with profiling off. */
+typedef struct { char name[32]; uint64_t launches; double total_ms; } hrpp_kernel_time;
+hrpp_status hrpp_profile_start(void);
+hrpp_status hrpp_profile_stop(hrpp_kernel_time *out, uint32_t capacity, uint32_t *count);
 
 /* Synchronise `stream`; report HRPP_EDEVICE if a HIP error is pending and
  * HRPP_EDEPTH if a kernel tracing `bvh` (may be NULL) found a traversal

@@ -15,7 +15,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 STAT_NAMES = [
     "rays", "invalid", "hits", "lookups", "positives", "pred_hits", "false_pos", "traversals",
     "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
-    "records", "tag_claims", "leaf_inserts", "dropped", "conflicts",
+    "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
 ]
 STATS_SLOTS = 24
 NONE32 = 0xFFFFFFFF

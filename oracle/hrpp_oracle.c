@@ -34,7 +34,7 @@ enum {
     S_RAYS, S_INVALID, S_HITS, S_LOOKUPS, S_POSITIVES, S_PRED_HITS, S_FALSE_POS,
     S_TRAVERSALS, S_NODES_VISITED, S_INTERIOR_VISITED, S_LEAF_VISITED, S_BOX_TESTS,
     S_TRI_TESTS, S_NODES_SKIPPED, S_RECORDS, S_TAG_CLAIMS, S_LEAF_INSERTS, S_DROPPED,
-    S_CONFLICTS, S_COUNT
+    S_CONFLICTS, S_PRED_LEAF_VISITED, S_PRED_TRI_TESTS, S_COUNT
 };
 #define STATS_SLOTS 24
 
@@ -610,16 +610,19 @@ static void trace_one(const scene *sc, const table *tb, const float *r, int quer
         int positive = (tb->tag[idx] == key && slots[0] != NONE32);
         if (positive) {
             st[S_POSITIVES]++;
+            uint64_t tri_before = st[S_TRI_TESTS];
             /* evaluate the predicted leaves in slot order */
             for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) {
                 uint32_t first = slots[s] >> 3, count = (slots[s] & 7u) + 1u;
                 st[S_NODES_VISITED]++;
                 st[S_LEAF_VISITED]++;
+                st[S_PRED_LEAF_VISITED]++;
                 if (test_leaf(sc, first, count, r, closest, &b, st)) {
                     hit = 1;
                     if (!closest) break;
                 }
             }
+            st[S_PRED_TRI_TESTS] += st[S_TRI_TESTS] - tri_before;
         }
         if (positive && hit && !(closest && cmode == C_EXACT)) {
             /* true positive: interior traversal skipped */

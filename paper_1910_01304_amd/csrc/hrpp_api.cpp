@@ -346,6 +346,30 @@ hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const 
     return trace_common(bvh, pred, d_rays, n, false, mode == HRPP_CLOSEST_EXACT, nullptr, d_hits, d_stats, stream);
 }
 
+hrpp_status hrpp_profile_start(void) {
+    profile_start();
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_profile_stop(hrpp_kernel_time *out, uint32_t capacity, uint32_t *count) {
+    double ms[kNumKernelKinds];
+    uint64_t launches[kNumKernelKinds];
+    const int err = profile_stop(ms, launches);
+    uint32_t n = 0;
+    for (int k = 0; k < kNumKernelKinds; k++) {
+        if (launches[k] == 0) continue;
+        if (out && n < capacity) {
+            std::memset(&out[n], 0, sizeof(hrpp_kernel_time));
+            std::strncpy(out[n].name, kernel_kind_name(k), sizeof(out[n].name) - 1);
+            out[n].launches = launches[k];
+            out[n].total_ms = ms[k];
+        }
+        n++;
+    }
+    if (count) *count = n;
+    return err ? HRPP_EDEVICE : HRPP_OK;
+}
+
 hrpp_status hrpp_get_error(const hrpp_bvh *bvh, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipStreamSynchronize(s) != hipSuccess) return HRPP_EDEVICE;

@@ -19,7 +19,7 @@ constexpr int kMaxDepth = 64;                  // deepest leaf the kernels accep
 enum Stat : int {
     kRays, kInvalid, kHits, kLookups, kPositives, kPredHits, kFalsePos, kTraversals,
     kNodesVisited, kInteriorVisited, kLeafVisited, kBoxTests, kTriTests, kNodesSkipped,
-    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kNumStats
+    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kPredLeafVisited, kPredTriTests, kNumStats
 };
 
 // Canonical depth-first pre-order tree, as produced by the builder.

@@ -45,6 +45,14 @@ struct TraceArgs {
     uint32_t *topw;
 };
 
+enum KernelKind : int {
+    kKindPredict, kKindTraverseQueue, kKindTraversePlain, kKindUpdateClassify, kKindUpdateApply,
+    kKindUpdateFinish, kKindFill, kNumKernelKinds
+};
+const char *kernel_kind_name(int k);
+void profile_start();
+int profile_stop(double *ms, uint64_t *launches);   // synchronises the recorded events
+
 void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, hipStream_t s);
 void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
 

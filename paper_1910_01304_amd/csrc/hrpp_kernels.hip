@@ -17,6 +17,9 @@
 // contraction: the file is compiled with -ffp-contract=off).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "hrpp_internal.h"
 #include "hrpp_kernels.h"
 
@@ -340,6 +343,9 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
             }
         }
     }
+    // every leaf and triangle test of this kernel is on a predicted leaf
+    c.v[kPredLeafVisited] = c.v[kLeafVisited];
+    c.v[kPredTriTests] = c.v[kTriTests];
     // wave-aggregated append to the fallback queue
     const uint64_t mask = __ballot(enq);
     if (mask) {
@@ -551,6 +557,76 @@ __global__ void k_fill32(uint32_t *p, size_t n, uint32_t value) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-kernel timing (measurement only): when enabled, each launch is
+// bracketed by two HIP events recorded on the launch stream.
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRecord {
+    int kind;
+    hipEvent_t start, stop;
+};
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pooled_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    int kind;
+    ProfScope(int k, hipStream_t st) : s(st), kind(k) {
+        if (!g_prof_on) return;
+        a = pooled_event();
+        b = pooled_event();
+        if (a) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!g_prof_on || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        g_prof.push_back({kind, a, b});
+    }
+};
+}  // namespace
+
+const char *kernel_kind_name(int k) {
+    static const char *names[kNumKernelKinds] = {"k_predict", "k_traverse_queue", "k_traverse_plain",
+                                                 "k_update_classify", "k_update_apply", "k_update_finish",
+                                                 "k_fill32"};
+    return (k >= 0 && k < kNumKernelKinds) ? names[k] : "unknown";
+}
+
+void profile_start() {
+    g_prof_on = true;
+}
+
+int profile_stop(double *ms, uint64_t *launches) {
+    g_prof_on = false;
+    for (int k = 0; k < kNumKernelKinds; k++) { ms[k] = 0.0; launches[k] = 0; }
+    int err = 0;
+    for (auto &r : g_prof) {
+        float t = 0.0f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
+            err = 1;
+        ms[r.kind] += t;
+        launches[r.kind]++;
+        g_event_pool.push_back(r.start);
+        g_event_pool.push_back(r.stop);
+    }
+    g_prof.clear();
+    return err;
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 static inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
@@ -558,19 +634,35 @@ static inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b
 template <bool ANY, bool EXACT, bool STATS>
 static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipStream_t s) {
     const uint32_t g256 = ceil_div(count, 256);
-    hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    {
+        ProfScope p(kKindPredict, s);
+        hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    }
     const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_traverse<ANY, EXACT, true, STATS>), dim3(ceil_div(count, 128)), dim3(128), lds, s, a,
-                       base, count);
-    hipLaunchKernelGGL((k_update_classify<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
-    hipLaunchKernelGGL((k_update_apply<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
-    hipLaunchKernelGGL((k_update_finish<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    {
+        ProfScope p(kKindTraverseQueue, s);
+        hipLaunchKernelGGL((k_traverse<ANY, EXACT, true, STATS>), dim3(ceil_div(count, 128)), dim3(128), lds, s, a,
+                           base, count);
+    }
+    {
+        ProfScope p(kKindUpdateClassify, s);
+        hipLaunchKernelGGL((k_update_classify<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    }
+    {
+        ProfScope p(kKindUpdateApply, s);
+        hipLaunchKernelGGL((k_update_apply<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    }
+    {
+        ProfScope p(kKindUpdateFinish, s);
+        hipLaunchKernelGGL((k_update_finish<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    }
 }
 
 template <bool ANY, bool STATS>
 static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
     const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     const uint32_t blocks = std::min<uint32_t>(ceil_div(n, 128), a.max_blocks);
+    ProfScope p(kKindTraversePlain, s);
     hipLaunchKernelGGL((k_traverse<ANY, false, false, STATS>), dim3(blocks), dim3(128), lds, s, a, 0u, n);
 }
 
@@ -599,6 +691,7 @@ void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrp
 void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s) {
     if (n == 0) return;
     const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
+    ProfScope prof(kKindFill, s);
     hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, s, p, n, value);
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhrpp.so")
 STAT_NAMES = [
     "rays", "invalid", "hits", "lookups", "positives", "pred_hits", "false_pos", "traversals",
     "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
-    "records", "tag_claims", "leaf_inserts", "dropped", "conflicts",
+    "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
 ]
 STATS_SLOTS = 24
 CLOSEST_MODES = {"paper": 0, "exact": 1}
@@ -29,6 +29,7 @@ EXPORTED = [
     "hrpp_predictor_required_bytes", "hrpp_predictor_table_bytes", "hrpp_predictor_create",
     "hrpp_predictor_reset", "hrpp_predictor_export", "hrpp_predictor_import", "hrpp_predictor_destroy",
     "hrpp_trace_anyhit", "hrpp_trace_closest", "hrpp_get_error", "hrpp_status_string",
+    "hrpp_profile_start", "hrpp_profile_stop",
 ]
 
 
@@ -44,6 +45,10 @@ class _PredDesc(C.Structure):
     _fields_ = [("log2_entries", C.c_uint32), ("ways", C.c_uint32), ("origin_bits", C.c_uint32),
                 ("dir_bits", C.c_uint32), ("epoch_rays", C.c_uint32), ("hash_mode", C.c_uint32),
                 ("go_up_level", C.c_uint32)]
+
+
+class _KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("total_ms", C.c_double)]
 
 
 class _Canon(C.Structure):
@@ -87,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_trace_anyhit.argtypes = [vp, vp, vp, u32, vp, vp, vp]
     lib.hrpp_trace_closest.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
     lib.hrpp_get_error.argtypes = [vp, vp]
+    lib.hrpp_profile_stop.argtypes = [vp, u32, C.POINTER(u32)]
     lib.hrpp_status_string.restype = C.c_char_p
     lib.hrpp_status_string.argtypes = [C.c_int]
     _lib = lib
@@ -260,3 +266,16 @@ def trace_closest(bvh: BVH, pred: Predictor | None, rays: torch.Tensor, mode: st
 
 def get_error(bvh: BVH | None = None):
     _check(load_library().hrpp_get_error(bvh.handle if bvh is not None else None, _stream()), "hrpp_get_error")
+
+
+def profile_start():
+    """Start per-kernel event timing inside the library."""
+    _check(load_library().hrpp_profile_start(), "hrpp_profile_start")
+
+
+def profile_stop() -> dict:
+    """Stop timing; returns {kernel name: (launches, total ms)}."""
+    arr = (_KernelTime * 16)()
+    n = C.c_uint32()
+    _check(load_library().hrpp_profile_stop(arr, 16, C.byref(n)), "hrpp_profile_stop")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, 16))}

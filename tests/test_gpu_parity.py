@@ -249,3 +249,21 @@ def test_full_size_primary_and_shadow(hrpp):
                                       light_center=w["light_center"], light_size=w["light_size"])
     check_case(hrpp, "full shadow plain", tris, shadow)
     check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg)
+
+
+def test_results_do_not_depend_on_stats(hrpp, small_terrain):
+    # the benchmark times the path without counters; it must compute the same
+    import torch
+    tris, prim = small_terrain
+    _say("stats on/off")
+    bvh = hrpp.BVH(tris)
+    r = torch.from_numpy(prim).cuda()
+    res = []
+    for with_stats in (True, False):
+        pa = hrpp.Predictor(bvh, 14, 8, 5, 6, 4096)
+        st = hrpp.new_stats() if with_stats else None
+        h = hrpp.trace_closest(bvh, pa, r, mode="paper", stats=st).cpu().numpy()
+        o = hrpp.trace_anyhit(bvh, pa, r, stats=st).cpu().numpy()
+        hp = hrpp.trace_closest(bvh, None, r, mode="exact", stats=st).cpu().numpy()
+        res.append((h.tobytes(), o.tobytes(), hp.tobytes(), pa.export_raw().tobytes()))
+    assert res[0] == res[1]
