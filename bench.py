@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "Mrays/s HRPP vs plain BVH traversal (shadow/AO), % nodes skipped, p99 lat"
 HBM_PEAK_GBS = 8000.0
-NODE_B, TRI_B, RAY_B = 64, 48, 32
+NODE_B, TRI_B, RAY_B, LEAFBOX_B = 64, 48, 32, 32
 
 
 def log(msg):
@@ -71,12 +71,14 @@ def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
         trav_tri = st["tri_tests"] - st["pred_tri_tests"]
         if kind == "k_traverse_plain":
             tot += n * (RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * st["tri_tests"]
+        elif kind == "k_predict":
+            # ray, table entry, predicted leaf boxes and triangles, results of successes, queue append
+            tot += (n * RAY_B + st["lookups"] * entry_b + LEAFBOX_B * st["pred_box_tests"]
+                    + TRI_B * st["pred_tri_tests"] + st["pred_hits"] * out_b + st["traversals"] * 8)
         elif kind == "k_traverse_queue":
+            # queue entry, ray, nodes, triangles, result, record + claim
             tot += (st["traversals"] * (8 + RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * trav_tri
                     + st["records"] * (16 + 4))
-        elif kind == "k_predict":
-            tot += (n * RAY_B + st["lookups"] * entry_b + TRI_B * st["pred_tri_tests"]
-                    + st["pred_hits"] * out_b + st["traversals"] * 8)
         elif kind.startswith("k_update"):
             tot += st["records"] * (16 + 4 + 4 + entry_b)
     return tot
@@ -130,9 +132,23 @@ def main():
         pred_any.reset()
         hrpp.trace_anyhit(bvh, pred_any, shadow_d, out=occ_out)
 
+    # the hit-all and hit-any queries are independent (separate predictors,
+    # resident inputs): issue them on two streams so their epoch chains overlap
+    s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def on_two_streams(fa, fb):
+        cur = torch.cuda.current_stream()
+        s_a.wait_stream(cur)
+        s_b.wait_stream(cur)
+        with torch.cuda.stream(s_a):
+            fa()
+        with torch.cuda.stream(s_b):
+            fb()
+        cur.wait_stream(s_a)
+        cur.wait_stream(s_b)
+
     def step_hrpp():
-        primary_hrpp()
-        shadow_hrpp()
+        on_two_streams(primary_hrpp, shadow_hrpp)
 
     def primary_plain():
         hrpp.trace_closest(bvh, None, prim_d, mode="paper", out=hits_out)
@@ -141,8 +157,7 @@ def main():
         hrpp.trace_anyhit(bvh, None, shadow_d, out=occ_out)
 
     def step_plain():
-        primary_plain()
-        shadow_plain()
+        on_two_streams(primary_plain, shadow_plain)
 
     log("timing")
     ms_hrpp, wall_hrpp = timed(torch, step_hrpp, args.steps, args.warmup)

@@ -91,14 +91,16 @@ typedef struct {
  *  tag_claims, leaf_inserts     entries (re)claimed / leaves written
  *  dropped                      owner-key records whose leaf did not fit
  *  conflicts                    records discarded because another key owns the entry
- *  pred_leaf_visited, pred_tri_tests  the part of leaf_visited / tri_tests spent
- *                               on predicted leaves */
+ *  pred_leaf_visited, pred_tri_tests, pred_box_tests
+ *                               the part of leaf_visited / tri_tests / box_tests
+ *                               spent on predicted leaves (a predicted leaf's box
+ *                               is tested first; its triangles only if it is hit) */
 #define HRPP_STATS_SLOTS 24
 typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
              nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
              records, tag_claims, leaf_inserts, dropped, conflicts, pred_leaf_visited, pred_tri_tests,
-             reserved[3];
+             pred_box_tests, reserved[2];
 } hrpp_stats;
 
 enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };

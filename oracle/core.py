@@ -16,6 +16,7 @@ STAT_NAMES = [
     "rays", "invalid", "hits", "lookups", "positives", "pred_hits", "false_pos", "traversals",
     "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
     "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
+    "pred_box_tests",
 ]
 STATS_SLOTS = 24
 NONE32 = 0xFFFFFFFF

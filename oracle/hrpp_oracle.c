@@ -34,7 +34,7 @@ enum {
     S_RAYS, S_INVALID, S_HITS, S_LOOKUPS, S_POSITIVES, S_PRED_HITS, S_FALSE_POS,
     S_TRAVERSALS, S_NODES_VISITED, S_INTERIOR_VISITED, S_LEAF_VISITED, S_BOX_TESTS,
     S_TRI_TESTS, S_NODES_SKIPPED, S_RECORDS, S_TAG_CLAIMS, S_LEAF_INSERTS, S_DROPPED,
-    S_CONFLICTS, S_PRED_LEAF_VISITED, S_PRED_TRI_TESTS, S_COUNT
+    S_CONFLICTS, S_PRED_LEAF_VISITED, S_PRED_TRI_TESTS, S_PRED_BOX_TESTS, S_COUNT
 };
 #define STATS_SLOTS 24
 
@@ -470,6 +470,7 @@ typedef struct {
     const orc_bvh *bvh;
     const float *vtx;          /* 9 floats per BVH-ordered triangle */
     const uint32_t *leaf_depth_by_first; /* depth of the leaf starting at triangle k */
+    const uint32_t *leaf_node_by_first;  /* node index of the leaf starting at triangle k */
 } scene;
 
 typedef struct {
@@ -611,9 +612,16 @@ static void trace_one(const scene *sc, const table *tb, const float *r, int quer
         if (positive) {
             st[S_POSITIVES]++;
             uint64_t tri_before = st[S_TRI_TESTS];
-            /* evaluate the predicted leaves in slot order */
+            /* evaluate the predicted leaves in slot order: a leaf's box is
+               tested against [tmin, tcur] (tcur = tmax, or the best hit so
+               far for closest hit) and its triangles only if the box is hit */
             for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) {
                 uint32_t first = slots[s] >> 3, count = (slots[s] & 7u) + 1u;
+                float tn;
+                float tcur = (closest && b.prim != NONE32) ? b.t : r[7];
+                st[S_BOX_TESTS]++;
+                st[S_PRED_BOX_TESTS]++;
+                if (!slab(sc->bvh->box + 6 * (size_t)sc->leaf_node_by_first[first], r, inv, r[3], tcur, &tn)) continue;
                 st[S_NODES_VISITED]++;
                 st[S_LEAF_VISITED]++;
                 st[S_PRED_LEAF_VISITED]++;
@@ -764,8 +772,11 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
     sc.bvh = bvh;
     sc.vtx = vtx;
     uint32_t *ldepth = (uint32_t *)malloc(sizeof(uint32_t) * (bvh->num_tris + 1));
-    for (uint32_t i = 0; i < bvh->num_nodes; i++) if (bvh->right[i] == NONE32) ldepth[bvh->first[i]] = bvh->depth[i];
+    uint32_t *lnode = (uint32_t *)malloc(sizeof(uint32_t) * (bvh->num_tris + 1));
+    for (uint32_t i = 0; i < bvh->num_nodes; i++)
+        if (bvh->right[i] == NONE32) { ldepth[bvh->first[i]] = bvh->depth[i]; lnode[bvh->first[i]] = i; }
     sc.leaf_depth_by_first = ldepth;
+    sc.leaf_node_by_first = lnode;
     table tb, *ptb = NULL;
     if (tags) {
         tb.tag = tags; tb.slot = slots; tb.W = W;
@@ -797,6 +808,7 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
     }
     free(recs);
     free(ldepth);
+    free(lnode);
     return 0;
 }
 

@@ -83,7 +83,8 @@ const char *hrpp_status_string(hrpp_status s) {
 size_t hrpp_bvh_required_bytes(uint32_t num_tris, const hrpp_bvh_desc *desc) {
     if (num_tris == 0 || !desc) return 0;
     const size_t interior = num_tris > 1 ? (size_t)num_tris - 1 : 0;   // at most n - 1 interior nodes
-    return kHeaderBytes + align256(interior * kNodeBytes) + align256((size_t)num_tris * kTriBytes);
+    return kHeaderBytes + align256(interior * kNodeBytes) + align256((size_t)num_tris * kTriBytes) +
+           align256((size_t)num_tris * kLeafBoxBytes);
 }
 
 hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
@@ -108,13 +109,15 @@ hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const h
     b->verts.assign(h_verts, h_verts + 9 * (size_t)num_tris);
     b->d_nodes = nullptr;
     b->d_tris = nullptr;
+    b->d_leafbox = nullptr;
     *out = b;
     return HRPP_OK;
 }
 
 size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh) {
     if (!bvh) return 0;
-    return kHeaderBytes + align256((size_t)bvh->num_interior * kNodeBytes) + align256((size_t)bvh->num_tris * kTriBytes);
+    return kHeaderBytes + align256((size_t)bvh->num_interior * kNodeBytes) +
+           align256((size_t)bvh->num_tris * kTriBytes) + align256((size_t)bvh->num_tris * kLeafBoxBytes);
 }
 
 hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream) {
@@ -161,17 +164,29 @@ hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream
         p[8] = v[6] - v[0]; p[9] = v[7] - v[1]; p[10] = v[8] - v[2];
         p[11] = 0.0f;
     }
+    // leaf boxes, indexed by the leaf's first triangle: min xyz, max x | max yz, depth, count
+    std::vector<float> hl((size_t)n * 8, 0.0f);
+    for (uint32_t i = 0; i < m; i++) {
+        if (t.right[i] != kNone) continue;
+        float *p = &hl[(size_t)t.first[i] * 8];
+        for (int a = 0; a < 6; a++) p[a] = t.box[6 * (size_t)i + a];
+        std::memcpy(&p[6], &t.depth[i], 4);
+        std::memcpy(&p[7], &t.count[i], 4);
+    }
     char *base = static_cast<char *>(d_buf);
     char *d_nodes = base + kHeaderBytes;
     char *d_tris = d_nodes + align256((size_t)ni * kNodeBytes);
+    char *d_leafbox = d_tris + align256((size_t)n * kTriBytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemsetAsync(base, 0, kHeaderBytes, s);
     if (e == hipSuccess && ni) e = hipMemcpyAsync(d_nodes, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_tris, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_leafbox, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host staging buffers die here
     if (e != hipSuccess) return HRPP_EDEVICE;
     b->d_nodes = d_nodes;
     b->d_tris = d_tris;
+    b->d_leafbox = d_leafbox;
     return HRPP_OK;
 }
 
@@ -300,6 +315,7 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
     TraceArgs a{};
     a.nodes = bvh->d_nodes;
     a.tris = bvh->d_tris;
+    a.leafbox = bvh->d_leafbox;
     for (int i = 0; i < 6; i++) a.root_box[i] = bvh->root_box[i];
     a.root_ref = bvh->root_ref;
     a.stack_cap = std::max<uint32_t>(1u, bvh->max_depth);

@@ -19,7 +19,7 @@ constexpr int kMaxDepth = 64;                  // deepest leaf the kernels accep
 enum Stat : int {
     kRays, kInvalid, kHits, kLookups, kPositives, kPredHits, kFalsePos, kTraversals,
     kNodesVisited, kInteriorVisited, kLeafVisited, kBoxTests, kTriTests, kNodesSkipped,
-    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kPredLeafVisited, kPredTriTests, kNumStats
+    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kPredLeafVisited, kPredTriTests, kPredBoxTests, kNumStats
 };
 
 // Canonical depth-first pre-order tree, as produced by the builder.
@@ -39,6 +39,7 @@ hrpp_status build_sah_tree(const float *verts, uint32_t n, const hrpp_bvh_desc &
 // GPU layout sizes.
 constexpr size_t kNodeBytes = 64;   // two child boxes + two references
 constexpr size_t kTriBytes = 48;    // v0+prim | e1+leaf depth | e2+pad
+constexpr size_t kLeafBoxBytes = 32;  // per BVH triangle position: box of the leaf starting there + depth
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace hrpp
@@ -51,6 +52,7 @@ struct hrpp_bvh {
     uint32_t root_ref;          // kLeafFlag|leaf id when the root is a leaf, else 0
     const void *d_nodes;        // num_interior * 64 B
     const void *d_tris;         // num_tris * 48 B
+    const void *d_leafbox;      // num_tris * 32 B (valid at leaf start positions)
     hrpp::CanonTree canon;
     std::vector<float> verts;   // host copy of the input, used by the upload
 };

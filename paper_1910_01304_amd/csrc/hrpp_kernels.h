@@ -21,6 +21,7 @@ struct TraceArgs {
     // scene
     const void *nodes;            // interior nodes, 64 B each
     const void *tris;             // triangles, 48 B each
+    const void *leafbox;          // leaf boxes by first triangle, 32 B each
     float root_box[6];
     uint32_t root_ref;
     uint32_t stack_cap;           // LDS stack slots per lane (>= deepest leaf)

@@ -3,11 +3,12 @@
 // Per epoch of E rays (rays of epoch k see the table after epoch k-1):
 //   k_predict    one lane per ray: validate, hash, probe the table, test the
 //                predicted leaves; successes write their result, the rest
-//                are appended to the fallback queue (one atomic per wave).
-//   k_traverse   stack traversal of the queued rays (or of every ray in
-//                plain mode); emits one update record per traversed hit and
-//                claims the record's entry with a 32-bit atomicMin on the
-//                ray id (the smallest ray id owns the entry).
+//                are appended to the epoch's fallback queue (one atomic per
+//                wave).
+//   k_traverse_queue  stack traversal of the queued rays; emits one update
+//                record per traversed hit and claims the record's entry with
+//                a 32-bit atomicMin on the ray id (the smallest id owns it).
+//   k_traverse_plain  stack traversal of every ray (no predictor).
 //   k_update_*   three passes over the epoch's records that turn the table
 //                of epoch k-1 into the table of epoch k.
 //
@@ -257,8 +258,14 @@ __device__ __forceinline__ RayState load_ray(const float4 *rays, uint32_t rid, f
     RayState r;
     r.ox = a.x; r.oy = a.y; r.oz = a.z; r.tmin = a.w;
     r.dx = b.x; r.dy = b.y; r.dz = b.z; r.tmax = b.w;
-    r.ix = 1.0f / b.x; r.iy = 1.0f / b.y; r.iz = 1.0f / b.z;
+    r.ix = 0.0f; r.iy = 0.0f; r.iz = 0.0f;
     return r;
+}
+
+// Reciprocal direction (three correctly rounded binary32 divisions), needed
+// only by box tests.
+__device__ __forceinline__ void set_inverse(RayState &r) {
+    r.ix = 1.0f / r.dx; r.iy = 1.0f / r.dy; r.iz = 1.0f / r.dz;
 }
 
 template <bool ANY>
@@ -279,7 +286,164 @@ __device__ __forceinline__ const uint32_t *entry_ptr(const TraceArgs &a, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// K1: predict
+// Per-ray phases
+// ---------------------------------------------------------------------------
+
+// Prediction for ray `rid` ("Overview": hash, look up, evaluate the predicted
+// leaves).  Returns true if the ray must still traverse; then *seed_leaf is
+// the leaf of the best predicted hit (EXACT) or kNone.
+template <bool ANY, bool EXACT>
+__device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Counters &c, uint32_t &seed_leaf) {
+    float4 ra, rb;
+    RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
+    seed_leaf = kNone;
+    c.v[kRays]++;
+    if (!ray_is_valid(ra, rb)) {
+        c.v[kInvalid]++;
+        write_result<ANY>(a, rid, false, Best{});
+        return false;
+    }
+    uint64_t key;
+    uint32_t idx;
+    hash_ray(a.hash, r, key, idx);
+    c.v[kLookups]++;
+    const uint32_t *e = entry_ptr(a, idx);
+    const uint64_t tag = *(const uint64_t *)e;
+    const uint32_t W = a.ways;
+    Best b;
+    b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
+    const bool positive = (tag == key) && (e[2] != kNone);
+    bool hit = false;
+    if (positive) {
+        c.v[kPositives]++;
+        set_inverse(r);
+        const float4 *__restrict__ lbox = (const float4 *)a.leafbox;
+        // predicted leaves in slot order: the leaf's box against [tmin, tcur]
+        // (tcur = tmax, or the best hit so far for closest hit), then its
+        // triangles if the box is hit
+        for (uint32_t s = 0; s < W; s++) {
+            const uint32_t leaf = e[2 + s];
+            if (leaf == kNone) break;
+            const float4 b0 = lbox[2 * (size_t)(leaf >> 3) + 0];
+            const float4 b1 = lbox[2 * (size_t)(leaf >> 3) + 1];
+            const float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
+            float tn;
+            c.v[kBoxTests]++;
+            c.v[kPredBoxTests]++;
+            if (!slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, r, tcur, tn)) continue;
+            c.v[kNodesVisited]++;
+            c.v[kLeafVisited]++;
+            c.v[kPredLeafVisited]++;
+            const uint32_t before = c.v[kTriTests];
+            const bool h = test_leaf<ANY>((const float4 *)a.tris, leaf, r, b, c);
+            c.v[kPredTriTests] += c.v[kTriTests] - before;
+            if (h) {
+                hit = true;
+                if (ANY) break;
+            }
+        }
+    }
+    if (EXACT) {
+        // every valid ray traverses; the best predicted hit seeds its interval
+        if (!ANY) {
+            float4 h;
+            h.x = b.t; h.y = b.u; h.z = b.v; h.w = __uint_as_float(b.prim);
+            ((float4 *)a.hits)[rid] = h;
+        }
+        seed_leaf = b.leaf;
+        return true;
+    }
+    if (positive && hit) {
+        c.v[kPredHits]++;
+        c.v[kHits]++;
+        // the leaf's interior-ancestor count is stored with its box
+        const float4 b1 = ((const float4 *)a.leafbox)[2 * (size_t)(b.leaf >> 3) + 1];
+        c.v[kNodesSkipped] += __float_as_uint(b1.z);
+        write_result<ANY>(a, rid, true, b);
+        return false;
+    }
+    if (positive) c.v[kFalsePos]++;
+    return true;   // "re-added to the ray pool" (section "Precision and Recall")
+}
+
+// Full traversal of ray `rid`.  HRPP: the ray came from the fallback queue
+// (already validated and counted); emit its update record and claim the
+// entry.  PLAIN: validate and count here.
+template <bool ANY, bool EXACT, bool HRPP>
+__device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, uint32_t rid, uint32_t seed_leaf,
+                                             Counters &c, uint32_t *stk_node, float *stk_t, uint32_t stride,
+                                             uint32_t cap) {
+    float4 ra, rb;
+    RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
+    if (!HRPP) {
+        c.v[kRays]++;
+        if (!ray_is_valid(ra, rb)) {
+            c.v[kInvalid]++;
+            write_result<ANY>(a, rid, false, Best{});
+            return;
+        }
+    }
+    set_inverse(r);
+    Best b;
+    b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
+    if (!ANY && EXACT && HRPP) {
+        const float4 s = ((const float4 *)a.hits)[rid];
+        b.t = s.x; b.u = s.y; b.v = s.z; b.prim = __float_as_uint(s.w); b.leaf = seed_leaf;
+    }
+    const bool hit = traverse<ANY>(a, r, b, c, stk_node, stk_t, stride, cap);
+    write_result<ANY>(a, rid, hit, b);
+    if (hit) c.v[kHits]++;
+    if (HRPP) {
+        uint64_t key;
+        uint32_t idx;
+        hash_ray(a.hash, r, key, idx);
+        if (!ANY && EXACT) {
+            const uint32_t *e = entry_ptr(a, idx);
+            const bool positive = (*(const uint64_t *)e == key) && (e[2] != kNone);
+            if (positive) {
+                bool in_pred = false;
+                for (uint32_t s = 0; s < a.ways; s++) {
+                    const uint32_t l = e[2 + s];
+                    if (l == kNone) break;
+                    if (hit && l == b.leaf) in_pred = true;
+                }
+                if (in_pred) c.v[kPredHits]++;
+                else c.v[kFalsePos]++;
+            }
+        }
+        if (hit) {
+            const uint32_t slot = rid - base;
+            a.rec_key[slot] = key;
+            a.rec_idx[slot] = idx;
+            a.rec_leaf[slot] = b.leaf;
+            uint32_t *e = (uint32_t *)entry_ptr(a, idx);
+            atomicMin(&e[2 + a.ways], rid);   // the smallest ray id claims the entry
+            c.v[kRecords]++;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain traversal: every ray of [0, count), persistent grid-stride loop.
+// ---------------------------------------------------------------------------
+template <bool ANY, bool STATS>
+__global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t count) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t stride = blockDim.x;
+    const uint32_t cap = a.stack_cap;
+    uint32_t *stk_node = lds + threadIdx.x;
+    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    Counters c;
+    c.zero();
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step)
+        traverse_one<ANY, false, false>(a, 0, i, kNone, c, stk_node, stk_t, stride, cap);
+    flush_counters<STATS>(c, a.stats);
+}
+
+// ---------------------------------------------------------------------------
+// Prediction for one epoch: one lane per ray.  Rays that must still traverse
+// are appended to the epoch's fallback queue with one atomic per wave.
 // ---------------------------------------------------------------------------
 template <bool ANY, bool EXACT, bool STATS>
 __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uint32_t count) {
@@ -287,66 +451,8 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
     c.zero();
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     bool enq = false;
-    uint32_t rid = base + i;
     uint32_t seed_leaf = kNone;
-    if (i < count) {
-        float4 ra, rb;
-        RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
-        c.v[kRays]++;
-        if (!ray_is_valid(ra, rb)) {
-            c.v[kInvalid]++;
-            write_result<ANY>(a, rid, false, Best{});
-        } else {
-            uint64_t key;
-            uint32_t idx;
-            hash_ray(a.hash, r, key, idx);
-            c.v[kLookups]++;
-            const uint32_t *e = entry_ptr(a, idx);
-            const uint64_t tag = *(const uint64_t *)e;
-            const uint32_t W = a.ways;
-            Best b;
-            b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
-            bool positive = (tag == key) && (e[2] != kNone);
-            bool hit = false;
-            if (positive) {
-                c.v[kPositives]++;
-                for (uint32_t s = 0; s < W; s++) {
-                    const uint32_t leaf = e[2 + s];
-                    if (leaf == kNone) break;
-                    c.v[kNodesVisited]++;
-                    c.v[kLeafVisited]++;
-                    if (test_leaf<ANY>((const float4 *)a.tris, leaf, r, b, c)) {
-                        hit = true;
-                        if (ANY) break;
-                    }
-                }
-            }
-            if (EXACT) {
-                // every valid ray traverses; the best predicted hit seeds it
-                if (!ANY) {
-                    float4 h;
-                    h.x = b.t; h.y = b.u; h.z = b.v; h.w = __uint_as_float(b.prim);
-                    ((float4 *)a.hits)[rid] = h;
-                }
-                seed_leaf = b.leaf;
-                enq = true;
-            } else if (positive && hit) {
-                c.v[kPredHits]++;
-                c.v[kHits]++;
-                // depth of the leaf is stored with its first triangle
-                const float4 B0 = ((const float4 *)a.tris)[3 * (size_t)(b.leaf >> 3) + 1];
-                c.v[kNodesSkipped] += __float_as_uint(B0.w);
-                write_result<ANY>(a, rid, true, b);
-            } else {
-                if (positive) c.v[kFalsePos]++;
-                enq = true;
-            }
-        }
-    }
-    // every leaf and triangle test of this kernel is on a predicted leaf
-    c.v[kPredLeafVisited] = c.v[kLeafVisited];
-    c.v[kPredTriTests] = c.v[kTriTests];
-    // wave-aggregated append to the fallback queue
+    if (i < count) enq = predict_one<ANY, EXACT>(a, base + i, c, seed_leaf);
     const uint64_t mask = __ballot(enq);
     if (mask) {
         const uint32_t lane = __lane_id();
@@ -356,17 +462,18 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
         qbase = __shfl(qbase, leader);
         if (enq) {
             const uint32_t pos = qbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            a.queue[pos] = (uint64_t)rid | ((uint64_t)seed_leaf << 32);
+            a.queue[pos] = (uint64_t)(base + i) | ((uint64_t)seed_leaf << 32);
         }
     }
     flush_counters<STATS>(c, a.stats);
 }
 
 // ---------------------------------------------------------------------------
-// K2: traverse (PLAIN: all rays of [base, base+count); HRPP: the queue)
+// Traversal of the epoch's fallback queue (its length is read on the device;
+// the grid covers the epoch, lanes past the queue's end exit at once).
 // ---------------------------------------------------------------------------
-template <bool ANY, bool EXACT, bool HRPP, bool STATS>
-__global__ __launch_bounds__(128) void k_traverse(TraceArgs a, uint32_t base, uint32_t count) {
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t base, uint32_t count) {
     extern __shared__ uint32_t lds[];
     const uint32_t stride = blockDim.x;
     const uint32_t cap = a.stack_cap;
@@ -374,64 +481,11 @@ __global__ __launch_bounds__(128) void k_traverse(TraceArgs a, uint32_t base, ui
     float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
     Counters c;
     c.zero();
-    const uint32_t total = HRPP ? *(volatile uint32_t *)&a.ctrl[0] : count;
+    const uint32_t total = *(volatile uint32_t *)&a.ctrl[0];
     const uint32_t step = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
-        uint32_t rid, seed_leaf = kNone;
-        if (HRPP) {
-            const uint64_t q = a.queue[i];
-            rid = (uint32_t)q;
-            seed_leaf = (uint32_t)(q >> 32);
-        } else {
-            rid = base + i;
-        }
-        float4 ra, rb;
-        RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
-        if (!HRPP) {
-            c.v[kRays]++;
-            if (!ray_is_valid(ra, rb)) {
-                c.v[kInvalid]++;
-                write_result<ANY>(a, rid, false, Best{});
-                continue;
-            }
-        }
-        Best b;
-        b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
-        if (!ANY && EXACT && HRPP) {
-            const float4 s = ((const float4 *)a.hits)[rid];
-            b.t = s.x; b.u = s.y; b.v = s.z; b.prim = __float_as_uint(s.w); b.leaf = seed_leaf;
-        }
-        const bool hit = traverse<ANY>(a, r, b, c, stk_node, stk_t, stride, cap);
-        write_result<ANY>(a, rid, hit, b);
-        if (hit) c.v[kHits]++;
-        if (HRPP) {
-            uint64_t key;
-            uint32_t idx;
-            hash_ray(a.hash, r, key, idx);
-            if (!ANY && EXACT) {
-                const uint32_t *e = entry_ptr(a, idx);
-                const bool positive = (*(const uint64_t *)e == key) && (e[2] != kNone);
-                if (positive) {
-                    bool in_pred = false;
-                    for (uint32_t s = 0; s < a.ways; s++) {
-                        const uint32_t l = e[2 + s];
-                        if (l == kNone) break;
-                        if (hit && l == b.leaf) in_pred = true;
-                    }
-                    if (in_pred) c.v[kPredHits]++;
-                    else c.v[kFalsePos]++;
-                }
-            }
-            if (hit) {
-                const uint32_t slot = rid - base;
-                a.rec_key[slot] = key;
-                a.rec_idx[slot] = idx;
-                a.rec_leaf[slot] = b.leaf;
-                uint32_t *e = (uint32_t *)entry_ptr(a, idx);
-                atomicMin(&e[2 + a.ways], rid);
-                c.v[kRecords]++;
-            }
-        }
+        const uint64_t q = a.queue[i];
+        traverse_one<ANY, EXACT, true>(a, base, (uint32_t)q, (uint32_t)(q >> 32), c, stk_node, stk_t, stride, cap);
     }
     flush_counters<STATS>(c, a.stats);
 }
@@ -480,13 +534,26 @@ __global__ __launch_bounds__(256) void k_update_classify(TraceArgs a, uint32_t b
                 status = kRecPresent;
             } else {
                 status = kRecFresh;
-                // sorted insertion of `leaf` into the owner's list of W smallest
+                // free slots of the entry after this epoch's claim
+                uint32_t free_slots = W;
+                if (*(const uint64_t *)e == kstar) {
+                    uint32_t used = 0;
+                    while (used < W && e[2 + used] != kNone) used++;
+                    free_slots = W - used;
+                }
+                // sorted insertion of `leaf` into the owner's list of the
+                // free_slots smallest fresh leaves; list values only ever
+                // decrease, so a plain read that is already <= x lets us skip
+                // the atomic at that position
                 uint32_t *list = a.topw + (size_t)(owner - base) * W;
                 uint32_t x = leaf;
-                for (uint32_t s = 0; s < W && x != kNone; s++) {
+                for (uint32_t s = 0; s < free_slots && x != kNone; s++) {
+                    const uint32_t seen = __hip_atomic_load(&list[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (seen == x) break;            // already listed
+                    if (seen < x) continue;          // x cannot go here
                     const uint32_t old = atomicMin(&list[s], x);
-                    if (old == x) break;           // already listed
-                    if (old > x) x = old;          // x took this place; carry the old value on
+                    if (old == x) break;
+                    if (old > x) x = old;            // x took this place; carry the old value on
                 }
             }
         }
@@ -525,7 +592,9 @@ __global__ __launch_bounds__(256) void k_update_apply(TraceArgs a, uint32_t base
             }
             e[2 + W] = kNone;                          // release the claim
         }
+        if (!STATS) a.rec_idx[i] = kNone;            // no drop count to take: retire the record now
     }
+    if (!STATS && i == 0) a.ctrl[0] = 0;
     flush_counters<STATS>(c, a.stats);
 }
 
@@ -534,7 +603,7 @@ __global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t bas
     Counters c;
     c.zero();
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) a.ctrl[0] = 0;
+    if (i == 0) a.ctrl[0] = 0;   // queue length of the next epoch
     if (i < count && a.rec_idx[i] != kNone) {
         if (a.rec_status[i] == kRecFresh) {
             const uint32_t *e = entry_ptr(a, a.rec_idx[i]);
@@ -631,18 +700,19 @@ int profile_stop(double *ms, uint64_t *launches) {
 // ---------------------------------------------------------------------------
 static inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b; }
 
+
 template <bool ANY, bool EXACT, bool STATS>
 static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipStream_t s) {
     const uint32_t g256 = ceil_div(count, 256);
+    const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     {
         ProfScope p(kKindPredict, s);
         hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
     }
-    const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     {
         ProfScope p(kKindTraverseQueue, s);
-        hipLaunchKernelGGL((k_traverse<ANY, EXACT, true, STATS>), dim3(ceil_div(count, 128)), dim3(128), lds, s, a,
-                           base, count);
+        const uint32_t blocks = std::min<uint32_t>(ceil_div(count, 128), a.max_blocks);
+        hipLaunchKernelGGL((k_traverse_queue<ANY, EXACT, STATS>), dim3(blocks), dim3(128), lds, s, a, base, count);
     }
     {
         ProfScope p(kKindUpdateClassify, s);
@@ -652,7 +722,8 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipS
         ProfScope p(kKindUpdateApply, s);
         hipLaunchKernelGGL((k_update_apply<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
     }
-    {
+    if (STATS) {
+        // counts records whose leaf did not fit, then retires the records
         ProfScope p(kKindUpdateFinish, s);
         hipLaunchKernelGGL((k_update_finish<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
     }
@@ -663,7 +734,7 @@ static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
     const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     const uint32_t blocks = std::min<uint32_t>(ceil_div(n, 128), a.max_blocks);
     ProfScope p(kKindTraversePlain, s);
-    hipLaunchKernelGGL((k_traverse<ANY, false, false, STATS>), dim3(blocks), dim3(128), lds, s, a, 0u, n);
+    hipLaunchKernelGGL((k_traverse_plain<ANY, STATS>), dim3(blocks), dim3(128), lds, s, a, n);
 }
 
 void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, hipStream_t s) {

@@ -570,13 +570,16 @@ def test_exact_closest_with_predictor_is_exact():
 
 def _sequential_model(tris, rays, bvh, qo, qd):
     """The paper's sequential predictor (an unbounded dict, no replacement):
-    a hit-all ray looks up its hash; if present, all stored leaves are
-    tested and the best hit there is accepted; otherwise (or on a miss there)
-    the ray traverses and its result leaf is appended if absent."""
+    a hit-all ray looks up its hash; if present, the stored leaves are
+    tested (each leaf's box first, against the best hit so far) and the best
+    hit there is accepted; otherwise (or on a miss there) the ray traverses
+    and its result leaf is appended if absent."""
     keys, _ = oracle.hash_rays(bvh.box[0], qo, qd, 31, rays)
     leaf_of_pos = {}
+    box_of_leaf = {}
     for i in np.nonzero(bvh.right == NONE32)[0]:
         lid = (int(bvh.first[i]) << 3) | (int(bvh.count[i]) - 1)
+        box_of_leaf[lid] = bvh.box[i]
         for k in range(int(bvh.first[i]), int(bvh.first[i] + bvh.count[i])):
             leaf_of_pos[k] = lid
     pos_of_prim = {int(p): k for k, p in enumerate(bvh.perm)}
@@ -586,6 +589,8 @@ def _sequential_model(tris, rays, bvh, qo, qd):
         k = int(keys[i])
         best = None
         for lid in table.get(k, []):
+            if not oracle.slab(box_of_leaf[lid], rays[i], best[0] if best is not None else float(rays[i, 7]))[0]:
+                continue
             f, c = lid >> 3, (lid & 7) + 1
             for pos in range(f, f + c):
                 prim = int(bvh.perm[pos])
