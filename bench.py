@@ -8,7 +8,8 @@ One step = the whole query path over one frame of the at-scale workload
      successful prediction is accepted), hit-all predictor,
   3. one shadow ray per primary hit towards a 0.1 x 0.1 area light, any hit,
      hit-any predictor,
-with epochs of 2^17 rays.  The same rays are also traced without a
+with epochs of 2^19 rays (one full-occupancy pass of the GPU; the line
+also reports the step at 2^17).  The same rays are also traced without a
 predictor ("plain").  Rays and the BVH are resident in HBM before timing;
 shadow rays are built once, in setup, from the GPU's exact primary hits.
 
@@ -45,7 +46,88 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ao", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-parts", action="store_true",
+                    help="skip the per-query timings (the profiled command, so that every launch of the "
+                         "measured kernels runs in the two-stream step)")
+    ap.add_argument("--epoch", type=int, default=0, help="epoch rays (default: the workload's 2^19)")
+    ap.add_argument("--reference-epoch", type=int, default=1 << 17,
+                    help="also time the HRPP step at this epoch size (0 = skip)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run a 256 MiB calibration copy, then one HRPP and one plain step (for rocprofv3 --pmc)")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) into a traffic summary")
     return ap.parse_args()
+
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "at_scale_step_hbm_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1910_01304_amd", "csrc", "hrpp_kernels.hip")
+CALIB_BYTES = 256 << 20
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_kernel_name(name):
+    for k in ("k_predict", "k_traverse_queue", "k_traverse_plain", "k_update_classify", "k_update_apply",
+              "k_update_finish", "k_fill32"):
+        if k in name:
+            return k
+    return None
+
+
+def summarize_traffic(fetch_csv, write_csv, out_json, epoch=None):
+    """Per-kernel HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (KiB) runs, scaled by what the same counters read for a copy of known size."""
+    import csv
+    import collections
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        calib = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            name = r["Kernel_Name"]
+            k = short_kernel_name(name)
+            if k:
+                acc[k].append(v)
+            elif "elementwise" in name or "copy" in name.lower():
+                calib.append(v)
+        return acc, calib
+
+    fetch, cf = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, cw = per_kernel(write_csv, "WRITE_SIZE")
+    f_factor = CALIB_BYTES / max(cf) if cf else 1.0
+    w_factor = CALIB_BYTES / max(cw) if cw else 1.0
+    out = {"kernel_source_sha256_16": kernel_source_hash(), "epoch_rays": epoch, "calibration_copy_bytes": CALIB_BYTES,
+           "fetch_scale": f_factor, "write_scale": w_factor, "kernels": {}}
+    for k in sorted(set(fetch) | set(write)):
+        f = fetch.get(k, [0.0])
+        w = write.get(k, [0.0])
+        out["kernels"][k] = {"dispatches": len(f), "fetch_bytes_avg": f_factor * sum(f) / len(f),
+                             "write_bytes_avg": w_factor * sum(w) / len(w)}
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def load_traffic(kernel, epoch):
+    """Measured HBM bytes per launch of `kernel` if the summary matches this
+    kernel source and epoch size."""
+    try:
+        d = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash() or d.get("epoch_rays") != epoch:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["fetch_bytes_avg"] + k["write_bytes_avg"]
 
 
 def timed(torch, fn, steps, warmup):
@@ -86,6 +168,9 @@ def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
 
 def main():
     args = parse()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, epoch=args.epoch or None)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the query path here runs on a single MI355X "
@@ -110,8 +195,9 @@ def main():
     bvh = hrpp.BVH(tris)
     build_s = time.perf_counter() - t0
     log(f"BVH: {bvh.num_nodes} nodes, depth {bvh.max_depth}, built in {build_s:.2f} s")
+    epoch = args.epoch or w["epoch"]
     pcfg = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=w["origin_bits"],
-                dir_bits=w["dir_bits"], epoch_rays=w["epoch"])
+                dir_bits=w["dir_bits"], epoch_rays=epoch)
     pred_all = hrpp.Predictor(bvh, **pcfg)
     pred_any = hrpp.Predictor(bvh, **pcfg)
     prim_d = torch.from_numpy(prim).cuda()
@@ -159,13 +245,27 @@ def main():
     def step_plain():
         on_two_streams(primary_plain, shadow_plain)
 
+    if args.traffic_probe:
+        x = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        primary_hrpp()
+        shadow_hrpp()
+        primary_plain()
+        shadow_plain()
+        torch.cuda.synchronize()
+        log("traffic probe done")
+        return
+
     log("timing")
     ms_hrpp, wall_hrpp = timed(torch, step_hrpp, args.steps, args.warmup)
     ms_plain, wall_plain = timed(torch, step_plain, args.steps, args.warmup)
     parts = {}
     for name, fn in (("primary_hrpp", primary_hrpp), ("primary_plain", primary_plain),
                      ("shadow_hrpp", shadow_hrpp), ("shadow_plain", shadow_plain)):
-        parts[name] = timed(torch, fn, args.steps, 1)[0]
+        parts[name] = float("nan") if args.no_parts else timed(torch, fn, args.steps, 1)[0]
 
     # counters of one step (separate pass with stats on)
     def counted(fn_any, fn_all):
@@ -233,10 +333,43 @@ def main():
                                                gbs=per_launch_b / (avg_ms * 1e-3) / 1e9)
         dom = max((k for k in kernels if k.startswith("hrpp:")), key=lambda k: kernels[k]["ms_per_step"])
         d = kernels[dom]
-        roofline = {"bound": "hbm", "kernel": dom.split(":", 1)[1], "achieved": round(d["gbs"], 1),
+        kname = dom.split(":", 1)[1]
+        traffic = load_traffic(kname, epoch)
+        roofline = {"bound": "hbm", "kernel": kname, "achieved": round(d["gbs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
-                    "traffic": None, "avg_launch_us": round(d["avg_us"], 2),
+                    "traffic": int(traffic) if traffic is not None else None,
+                    "avg_launch_us": round(d["avg_us"], 2),
                     "algorithmic_bytes_per_launch": int(d["bytes_per_launch"])}
+
+    ref_info = None
+    if args.reference_epoch and args.reference_epoch != epoch:
+        rcfg = dict(pcfg, epoch_rays=args.reference_epoch)
+        ra_, rb_ = hrpp.Predictor(bvh, **rcfg), hrpp.Predictor(bvh, **rcfg)
+
+        def ref_step():
+            def fa():
+                ra_.reset()
+                hrpp.trace_closest(bvh, ra_, prim_d, mode="paper", out=hits_out)
+
+            def fb():
+                rb_.reset()
+                hrpp.trace_anyhit(bvh, rb_, shadow_d, out=occ_out)
+            on_two_streams(fa, fb)
+
+        ms_ref = timed(torch, ref_step, args.steps, 1)[0]
+        s1, s2 = hrpp.new_stats(), hrpp.new_stats()
+        ra_.reset()
+        hrpp.trace_closest(bvh, ra_, prim_d, mode="paper", out=hits_out, stats=s1)
+        rb_.reset()
+        hrpp.trace_anyhit(bvh, rb_, shadow_d, out=occ_out, stats=s2)
+        torch.cuda.synchronize()
+        d1, d2 = hrpp.stats_dict(s1), hrpp.stats_dict(s2)
+        ref_info = {"epoch_rays": args.reference_epoch, "hrpp_mrays_s": round(mrays(rays_per_step, ms_ref), 2),
+                    "ms_per_step": round(ms_ref, 4),
+                    "pct_nodes_skipped": round(100.0 * (1 - (d1["nodes_visited"] + d2["nodes_visited"]) / nodes_p), 3),
+                    "pct_nodes_skipped_primary": round(pct_saved("nodes_visited", d1, p_sb), 3),
+                    "prediction_hit_rate_primary": round(d1["pred_hits"] / n_prim, 4)}
+        del ra_, rb_
 
     ao_info = None
     if not args.no_ao:
@@ -299,7 +432,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_hrpp, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) + shadow any-hit, "
-                               "HRPP 2^20 x 8, q_o 5, q_d 6, epoch 2^17",
+                               f"HRPP 2^20 x 8, q_o 5, q_d 6, epoch {epoch}",
+                   "epoch_rays": int(epoch),
                    "triangles": int(tris.shape[0]), "rays_per_step": int(rays_per_step),
                    "bvh_nodes": int(bvh.num_nodes), "bvh_depth": int(bvh.max_depth)},
         "plain_mrays_s": round(mrays(rays_per_step, ms_plain), 2),
@@ -308,7 +442,7 @@ def main():
         "wall_ms_per_step": {"hrpp": round(wall_hrpp, 4), "plain": round(wall_plain, 4)},
         "pct_nodes_skipped": round(100.0 * (1 - nodes_h / nodes_p), 3),
         "pct_box_tests_skipped": round(100.0 * (1 - box_h / box_p), 3),
-        "primary": prim_info, "shadow": shadow_info, "ao": ao_info,
+        "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "reference_epoch": ref_info,
         "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
         "p99_latency_ms": None,
     }

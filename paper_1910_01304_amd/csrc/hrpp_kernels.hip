@@ -417,7 +417,10 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
             a.rec_idx[slot] = idx;
             a.rec_leaf[slot] = b.leaf;
             uint32_t *e = (uint32_t *)entry_ptr(a, idx);
-            atomicMin(&e[2 + a.ways], rid);   // the smallest ray id claims the entry
+            // the smallest ray id claims the entry; claims only decrease within
+            // an epoch, so a coherent read that is already <= rid spares the atomic
+            const uint32_t seen = __hip_atomic_load(&e[2 + a.ways], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (seen > rid) atomicMin(&e[2 + a.ways], rid);
             c.v[kRecords]++;
         }
     }

@@ -236,10 +236,16 @@ def test_determinism_and_reset(hrpp, small_terrain):
 # for shadow rays, epochs of 2^17 rays)
 # ---------------------------------------------------------------------------
 
-def test_full_size_primary_and_shadow(hrpp):
+@pytest.fixture(scope="module")
+def full_terrain():
+    return sg.terrain_workload()
+
+
+@pytest.mark.parametrize("epoch", [sg.AT_SCALE["epoch"], 1 << 17])
+def test_full_size_primary_and_shadow(hrpp, full_terrain, epoch):
     w = sg.AT_SCALE
-    tris, prim = sg.terrain_workload()
-    cfg = (w["log2_entries"], w["ways"], w["origin_bits"], w["dir_bits"], w["epoch"])
+    tris, prim = full_terrain
+    cfg = (w["log2_entries"], w["ways"], w["origin_bits"], w["dir_bits"], epoch)
     _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg)
     assert st["rays"] == 1920 * 1080
     ob = oracle.build_sah(tris)
