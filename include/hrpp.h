@@ -209,6 +209,47 @@ hrpp_status hrpp_trace_anyhit(const hrpp_bvh *bvh, hrpp_predictor *pred, const h
 hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
                                uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent jobs (each its own BVH, predictor or none, rays
+ * and outputs) executed together.  Round r runs epoch r of every job in one
+ * launch per kernel, so scenes of uneven size fill the GPU together; the
+ * whole sequence can be captured once into a hipGraph and replayed.  Each
+ * job computes exactly what its own hrpp_trace_* call would (results,
+ * counters and table), because jobs share nothing and each job's epochs
+ * stay in order.  Predictors must be distinct across the jobs of a batch.
+ * The device pointers of the jobs are baked into the batch: to trace new
+ * rays, write them into the same buffers and launch again.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const hrpp_bvh *bvh;
+    hrpp_predictor *pred;      /* NULL = plain traversal */
+    const hrpp_ray *d_rays;
+    uint32_t n;
+    uint32_t query;            /* 0 any-hit, 1 closest-hit */
+    uint32_t mode;             /* closest-hit: HRPP_CLOSEST_PAPER or HRPP_CLOSEST_EXACT */
+    void *d_out;               /* uint8_t[n] occlusion flags or hrpp_hit[n] */
+    hrpp_stats *d_stats;       /* may be NULL */
+} hrpp_batch_job;
+
+typedef struct hrpp_batch hrpp_batch;
+
+/* Device bytes of the job table of a batch of njobs jobs. */
+size_t hrpp_batch_required_bytes(uint32_t njobs);
+
+/* Validate the jobs (as the trace calls do; EINVAL also for a predictor used
+ * twice) and upload the job table into d_buf (256-byte aligned).
+ * Synchronises `stream`. */
+hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *d_buf, size_t bytes,
+                              void *stream, hrpp_batch **out);
+
+/* Enqueue every job of the batch on `stream`.  use_graph != 0 captures the
+ * launch sequence into a hipGraph on the first call and replays it later
+ * (the kernels contain no memset, so the graph is replay-safe); 0 issues
+ * the launches directly.  Predictors are not reset by the batch. */
+hrpp_status hrpp_batch_launch(hrpp_batch *batch, uint32_t use_graph, void *stream);
+
+void hrpp_batch_destroy(hrpp_batch *batch);
+
 /* Per-kernel timing for measurement.  Between hrpp_profile_start() and
  * hrpp_profile_stop(), every kernel the library launches is bracketed by two
  * HIP events recorded on the launch stream.  Stop waits for those events and

@@ -303,15 +303,9 @@ hrpp_status hrpp_predictor_import(hrpp_predictor *p, const void *h_src, size_t b
 
 void hrpp_predictor_destroy(hrpp_predictor *p) { delete p; }
 
-static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
-                                bool any, bool exact, uint8_t *d_occ, hrpp_hit *d_hits, hrpp_stats *d_stats,
-                                void *stream) {
-    if (!bvh || !bvh->d_nodes) return HRPP_EINVAL;
-    if (n == 0) return HRPP_OK;
-    if (n >= (1u << 31) || !d_rays || (any ? !d_occ : !d_hits)) return HRPP_EINVAL;
-    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || (!any && reinterpret_cast<uintptr_t>(d_hits) % 16))
-        return HRPP_EINVAL;
-    if (pred && pred->bvh_uid != bvh->uid) return HRPP_EINVAL;
+// Kernel arguments of one trace (shared by single calls and batches).
+static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint8_t *d_occ,
+                           hrpp_hit *d_hits, hrpp_stats *d_stats) {
     TraceArgs a{};
     a.nodes = bvh->d_nodes;
     a.tris = bvh->d_tris;
@@ -325,7 +319,6 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
     a.hits = d_hits;
     a.stats = reinterpret_cast<unsigned long long *>(d_stats);
     a.error = reinterpret_cast<uint32_t *>(static_cast<char *>(const_cast<void *>(bvh->d_nodes)) - kHeaderBytes);
-    uint32_t epoch = n;
     if (pred) {
         const hrpp_predictor_desc &d = pred->desc;
         a.table = pred->d_table;
@@ -345,9 +338,29 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
         a.rec_leaf = pred->d_rec_leaf;
         a.rec_status = pred->d_rec_status;
         a.topw = pred->d_topw;
-        epoch = d.epoch_rays;
     }
-    launch_trace(a, n, any, exact, pred != nullptr, epoch, static_cast<hipStream_t>(stream));
+    return a;
+}
+
+static hrpp_status check_trace_args(const hrpp_bvh *bvh, const hrpp_predictor *pred, const void *d_rays, uint32_t n,
+                                    bool any, const void *d_out) {
+    if (!bvh || !bvh->d_nodes) return HRPP_EINVAL;
+    if (n == 0) return HRPP_OK;
+    if (n >= (1u << 31) || !d_rays || !d_out) return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || (!any && reinterpret_cast<uintptr_t>(d_out) % 16))
+        return HRPP_EINVAL;
+    if (pred && pred->bvh_uid != bvh->uid) return HRPP_EINVAL;
+    return HRPP_OK;
+}
+
+static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
+                                bool any, bool exact, uint8_t *d_occ, hrpp_hit *d_hits, hrpp_stats *d_stats,
+                                void *stream) {
+    const hrpp_status st = check_trace_args(bvh, pred, d_rays, n, any, any ? (const void *)d_occ : d_hits);
+    if (st != HRPP_OK || n == 0) return st;
+    const TraceArgs a = make_args(bvh, pred, d_rays, d_occ, d_hits, d_stats);
+    launch_trace(a, n, any, exact, pred != nullptr, pred ? pred->desc.epoch_rays : n,
+                 static_cast<hipStream_t>(stream));
     return check(hipGetLastError());
 }
 
@@ -360,6 +373,123 @@ hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const 
                                uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream) {
     if (mode != HRPP_CLOSEST_PAPER && mode != HRPP_CLOSEST_EXACT) return HRPP_EINVAL;
     return trace_common(bvh, pred, d_rays, n, false, mode == HRPP_CLOSEST_EXACT, nullptr, d_hits, d_stats, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct hrpp_batch {
+    std::vector<BatchJob> jobs;
+    std::vector<uint32_t> ids;
+    std::vector<BatchGroup> groups;
+    uint32_t max_rounds = 0;
+    BatchJob *d_jobs = nullptr;
+    uint32_t *d_ids = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;   // the legacy default stream cannot be captured
+};
+
+size_t hrpp_batch_required_bytes(uint32_t njobs) {
+    return align256((size_t)njobs * sizeof(BatchJob)) + align256((size_t)njobs * sizeof(uint32_t));
+}
+
+hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *d_buf, size_t bytes, void *stream,
+                              hrpp_batch **out) {
+    if (!jobs || njobs == 0 || !d_buf || !out) return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_buf) % 256) return HRPP_EINVAL;
+    if (bytes < hrpp_batch_required_bytes(njobs)) return HRPP_ENOMEM;
+    *out = nullptr;
+    hrpp_batch *b = new (std::nothrow) hrpp_batch();
+    if (!b) return HRPP_ENOMEM;
+    std::vector<uint32_t> kind_of(njobs);
+    for (uint32_t j = 0; j < njobs; j++) {
+        const hrpp_batch_job &J = jobs[j];
+        const bool any = (J.query == 0);
+        if (J.query > 1 || (!any && J.mode != HRPP_CLOSEST_PAPER && J.mode != HRPP_CLOSEST_EXACT)) {
+            delete b;
+            return HRPP_EINVAL;
+        }
+        hrpp_status st = check_trace_args(J.bvh, J.pred, J.d_rays, J.n, any, J.d_out);
+        if (st != HRPP_OK) { delete b; return st; }
+        for (uint32_t k = 0; k < j; k++)
+            if (J.pred && jobs[k].pred == J.pred) { delete b; return HRPP_EINVAL; }   // predictors must be distinct
+        BatchJob bj{};
+        bj.a = make_args(J.bvh, J.pred, J.d_rays, any ? static_cast<uint8_t *>(J.d_out) : nullptr,
+                         any ? nullptr : static_cast<hrpp_hit *>(J.d_out), J.d_stats);
+        bj.n = J.n;
+        bj.epoch = J.pred ? J.pred->desc.epoch_rays : std::max(1u, J.n);
+        b->jobs.push_back(bj);
+        if (J.pred) kind_of[j] = any ? kBatchAnyHrpp : (J.mode == HRPP_CLOSEST_EXACT ? kBatchExactHrpp : kBatchPaperHrpp);
+        else kind_of[j] = any ? kBatchAnyPlain : kBatchClosestPlain;
+    }
+    for (int kind = kBatchAnyHrpp; kind <= kBatchClosestPlain; kind++) {
+        BatchGroup g{};
+        g.kind = kind;
+        g.first_id = (uint32_t)b->ids.size();
+        for (uint32_t j = 0; j < njobs; j++) {
+            if ((int)kind_of[j] != kind || jobs[j].n == 0) continue;
+            const BatchJob &bj = b->jobs[j];
+            b->ids.push_back(j);
+            g.count++;
+            g.max_epoch = std::max(g.max_epoch, std::min(bj.epoch, bj.n));
+            g.max_cap = std::max(g.max_cap, bj.a.stack_cap);
+            g.max_n = std::max(g.max_n, bj.n);
+            g.rounds = std::max(g.rounds, (bj.n + bj.epoch - 1) / bj.epoch);
+            if (bj.a.stats) g.stats = true;
+        }
+        if (g.count == 0) continue;
+        if (kind == kBatchAnyPlain || kind == kBatchClosestPlain) g.rounds = 0;
+        b->max_rounds = std::max(b->max_rounds, g.rounds);
+        b->groups.push_back(g);
+    }
+    char *base = static_cast<char *>(d_buf);
+    b->d_jobs = reinterpret_cast<BatchJob *>(base);
+    b->d_ids = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(b->d_jobs, b->jobs.data(), b->jobs.size() * sizeof(BatchJob),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !b->ids.empty())
+        e = hipMemcpyAsync(b->d_ids, b->ids.data(), b->ids.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { delete b; return HRPP_EDEVICE; }
+    *out = b;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_batch_launch(hrpp_batch *b, uint32_t use_graph, void *stream) {
+    if (!b) return HRPP_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!use_graph) {
+        launch_batch(b->d_jobs, b->d_ids, b->groups, b->max_rounds, max_persistent_blocks(), s);
+        return check(hipGetLastError());
+    }
+    if (!b->exec) {
+        const uint32_t max_blocks = max_persistent_blocks();   // query outside the capture
+        if (!b->capture_stream && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return HRPP_EDEVICE;
+        hipStream_t cs = b->capture_stream;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return HRPP_EDEVICE;
+        launch_batch(b->d_jobs, b->d_ids, b->groups, b->max_rounds, max_blocks, cs);
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(cs, &g) != hipSuccess || !g) return HRPP_EDEVICE;
+        hipGraphExec_t x = nullptr;
+        if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return HRPP_EDEVICE;
+        }
+        b->graph = g;
+        b->exec = x;
+    }
+    return check(hipGraphLaunch(b->exec, s));
+}
+
+void hrpp_batch_destroy(hrpp_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    delete b;
 }
 
 hrpp_status hrpp_profile_start(void) {

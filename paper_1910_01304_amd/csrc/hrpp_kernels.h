@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace hrpp {
 
@@ -45,6 +46,24 @@ struct TraceArgs {
     uint32_t *rec_status;
     uint32_t *topw;
 };
+
+// One job of a batch (see hrpp_batch_create): its arguments, ray count and epoch size.
+struct BatchJob {
+    TraceArgs a;
+    uint32_t n, epoch, pad0, pad1;
+};
+
+enum BatchKind : int { kBatchAnyHrpp, kBatchPaperHrpp, kBatchExactHrpp, kBatchAnyPlain, kBatchClosestPlain };
+
+// Jobs of one kind, listed in ids[first_id .. first_id + count).
+struct BatchGroup {
+    int kind;
+    uint32_t first_id, count, max_epoch, max_cap, rounds, max_n;
+    bool stats;
+};
+
+void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<BatchGroup> &groups,
+                  uint32_t max_rounds, uint32_t max_blocks, hipStream_t s);
 
 enum KernelKind : int {
     kKindPredict, kKindTraverseQueue, kKindTraversePlain, kKindUpdateClassify, kKindUpdateApply,

@@ -133,6 +133,7 @@ struct Counters {
 template <bool STATS>
 __device__ __forceinline__ void flush_counters(Counters &c, unsigned long long *stats) {
     if constexpr (STATS) {
+        if (stats == nullptr) return;   // uniform per block: one block serves one job
         __shared__ unsigned long long red[kNumStats];
         if (threadIdx.x < kNumStats) red[threadIdx.x] = 0;
         __syncthreads();
@@ -430,7 +431,7 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
 // Plain traversal: every ray of [0, count), persistent grid-stride loop.
 // ---------------------------------------------------------------------------
 template <bool ANY, bool STATS>
-__global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t count) {
+__device__ __forceinline__ void body_traverse_plain(const TraceArgs &a, uint32_t count, uint32_t bx, uint32_t gx) {
     extern __shared__ uint32_t lds[];
     const uint32_t stride = blockDim.x;
     const uint32_t cap = a.stack_cap;
@@ -438,10 +439,15 @@ __global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t co
     float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
     Counters c;
     c.zero();
-    const uint32_t step = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step)
+    const uint32_t step = gx * blockDim.x;
+    for (uint32_t i = bx * blockDim.x + threadIdx.x; i < count; i += step)
         traverse_one<ANY, false, false>(a, 0, i, kNone, c, stk_node, stk_t, stride, cap);
     flush_counters<STATS>(c, a.stats);
+}
+
+template <bool ANY, bool STATS>
+__global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t count) {
+    body_traverse_plain<ANY, STATS>(a, count, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,10 +455,10 @@ __global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t co
 // are appended to the epoch's fallback queue with one atomic per wave.
 // ---------------------------------------------------------------------------
 template <bool ANY, bool EXACT, bool STATS>
-__global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uint32_t count) {
+__device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     Counters c;
     c.zero();
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = bx * blockDim.x + threadIdx.x;
     bool enq = false;
     uint32_t seed_leaf = kNone;
     if (i < count) enq = predict_one<ANY, EXACT>(a, base + i, c, seed_leaf);
@@ -471,12 +477,17 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
     flush_counters<STATS>(c, a.stats);
 }
 
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uint32_t count) {
+    body_predict<ANY, EXACT, STATS>(a, base, count, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Traversal of the epoch's fallback queue (its length is read on the device;
 // the grid covers the epoch, lanes past the queue's end exit at once).
 // ---------------------------------------------------------------------------
 template <bool ANY, bool EXACT, bool STATS>
-__global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t base, uint32_t count) {
+__device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     extern __shared__ uint32_t lds[];
     const uint32_t stride = blockDim.x;
     const uint32_t cap = a.stack_cap;
@@ -485,12 +496,17 @@ __global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t ba
     Counters c;
     c.zero();
     const uint32_t total = *(volatile uint32_t *)&a.ctrl[0];
-    const uint32_t step = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += step) {
+    const uint32_t step = gx * blockDim.x;
+    for (uint32_t i = bx * blockDim.x + threadIdx.x; i < total; i += step) {
         const uint64_t q = a.queue[i];
         traverse_one<ANY, EXACT, true>(a, base, (uint32_t)q, (uint32_t)(q >> 32), c, stk_node, stk_t, stride, cap);
     }
     flush_counters<STATS>(c, a.stats);
+}
+
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t base, uint32_t count) {
+    body_traverse_queue<ANY, EXACT, STATS>(a, base, count, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,10 +525,10 @@ __global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t ba
 enum : uint32_t { kRecConflict = 1, kRecPresent = 2, kRecFresh = 3 };
 
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_update_classify(TraceArgs a, uint32_t base, uint32_t count) {
+__device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     Counters c;
     c.zero();
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = bx * blockDim.x + threadIdx.x;
     if (i < count && a.rec_idx[i] != kNone) {
         const uint32_t idx = a.rec_idx[i];
         const uint32_t W = a.ways;
@@ -566,10 +582,15 @@ __global__ __launch_bounds__(256) void k_update_classify(TraceArgs a, uint32_t b
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_update_apply(TraceArgs a, uint32_t base, uint32_t count) {
+__global__ __launch_bounds__(256) void k_update_classify(TraceArgs a, uint32_t base, uint32_t count) {
+    body_update_classify<STATS>(a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool STATS>
+__device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     Counters c;
     c.zero();
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = bx * blockDim.x + threadIdx.x;
     if (i < count && a.rec_idx[i] != kNone) {
         const uint32_t idx = a.rec_idx[i];
         const uint32_t W = a.ways;
@@ -602,10 +623,15 @@ __global__ __launch_bounds__(256) void k_update_apply(TraceArgs a, uint32_t base
 }
 
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t base, uint32_t count) {
+__global__ __launch_bounds__(256) void k_update_apply(TraceArgs a, uint32_t base, uint32_t count) {
+    body_update_apply<STATS>(a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool STATS>
+__device__ __forceinline__ void body_update_finish(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     Counters c;
     c.zero();
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = bx * blockDim.x + threadIdx.x;
     if (i == 0) a.ctrl[0] = 0;   // queue length of the next epoch
     if (i < count && a.rec_idx[i] != kNone) {
         if (a.rec_status[i] == kRecFresh) {
@@ -619,6 +645,77 @@ __global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t bas
         a.rec_idx[i] = kNone;
     }
     flush_counters<STATS>(c, a.stats);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t base, uint32_t count) {
+    body_update_finish<STATS>(a, base, count, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched execution: many independent (BVH, predictor, rays) jobs.  Round r
+// runs epoch r of every job of a group in one launch per kernel, with
+// blockIdx.y selecting the job; each job's epochs stay in order, and jobs
+// share nothing, so every job computes exactly what its own call computes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool batch_epoch(const BatchJob &J, uint32_t round, uint32_t &base, uint32_t &count) {
+    const uint64_t b = (uint64_t)round * J.epoch;
+    if (b >= J.n) return false;
+    base = (uint32_t)b;
+    count = min(J.epoch, J.n - base);
+    return true;
+}
+
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(256) void kb_predict(const BatchJob *__restrict__ jobs, const uint32_t *__restrict__ ids,
+                                                  uint32_t round) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    uint32_t base, count;
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
+    body_predict<ANY, EXACT, STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(128) void kb_traverse_queue(const BatchJob *__restrict__ jobs,
+                                                         const uint32_t *__restrict__ ids, uint32_t round) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    uint32_t base, count;
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * 128u >= count) return;
+    body_traverse_queue<ANY, EXACT, STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void kb_update_classify(const BatchJob *__restrict__ jobs,
+                                                          const uint32_t *__restrict__ ids, uint32_t round) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    uint32_t base, count;
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
+    body_update_classify<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void kb_update_apply(const BatchJob *__restrict__ jobs,
+                                                       const uint32_t *__restrict__ ids, uint32_t round) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    uint32_t base, count;
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
+    body_update_apply<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void kb_update_finish(const BatchJob *__restrict__ jobs,
+                                                        const uint32_t *__restrict__ ids, uint32_t round) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    uint32_t base, count;
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
+    body_update_finish<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+}
+
+template <bool ANY, bool STATS>
+__global__ __launch_bounds__(128) void kb_traverse_plain(const BatchJob *__restrict__ jobs,
+                                                         const uint32_t *__restrict__ ids) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    body_traverse_plain<ANY, STATS>(J.a, J.n, blockIdx.x, gridDim.x);
 }
 
 // Fill a region with a 32-bit pattern (predictor reset; a kernel rather than
@@ -767,6 +864,66 @@ void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s) {
     const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
     ProfScope prof(kKindFill, s);
     hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, s, p, n, value);
+}
+
+}  // namespace hrpp
+
+namespace hrpp {
+
+template <bool ANY, bool EXACT, bool STATS>
+static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, uint32_t r,
+                               hipStream_t s) {
+    const dim3 g256(ceil_div(g.max_epoch, 256), g.count), g128(std::min(ceil_div(g.max_epoch, 128), 4096u), g.count);
+    const uint32_t *gid = ids + g.first_id;
+    const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
+    hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+    hipLaunchKernelGGL((kb_traverse_queue<ANY, EXACT, STATS>), g128, dim3(128), lds, s, jobs, gid, r);
+    hipLaunchKernelGGL((kb_update_classify<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+    hipLaunchKernelGGL((kb_update_apply<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+    if (STATS) hipLaunchKernelGGL((kb_update_finish<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+}
+
+template <bool ANY, bool STATS>
+static void launch_batch_plain(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, uint32_t max_blocks,
+                               hipStream_t s) {
+    const uint32_t per_job = std::max(1u, std::min(ceil_div(g.max_n, 128), max_blocks / std::max(1u, g.count)));
+    const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
+    hipLaunchKernelGGL((kb_traverse_plain<ANY, STATS>), dim3(per_job, g.count), dim3(128), lds, s, jobs,
+                       ids + g.first_id);
+}
+
+void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<BatchGroup> &groups,
+                  uint32_t max_rounds, uint32_t max_blocks, hipStream_t s) {
+    for (const BatchGroup &g : groups) {
+        if (g.kind == kBatchAnyPlain) {
+            if (g.stats) launch_batch_plain<true, true>(jobs, ids, g, max_blocks, s);
+            else launch_batch_plain<true, false>(jobs, ids, g, max_blocks, s);
+        } else if (g.kind == kBatchClosestPlain) {
+            if (g.stats) launch_batch_plain<false, true>(jobs, ids, g, max_blocks, s);
+            else launch_batch_plain<false, false>(jobs, ids, g, max_blocks, s);
+        }
+    }
+    for (uint32_t r = 0; r < max_rounds; r++) {
+        for (const BatchGroup &g : groups) {
+            if (r >= g.rounds) continue;
+            switch (g.kind) {
+                case kBatchAnyHrpp:
+                    if (g.stats) launch_batch_round<true, false, true>(jobs, ids, g, r, s);
+                    else launch_batch_round<true, false, false>(jobs, ids, g, r, s);
+                    break;
+                case kBatchPaperHrpp:
+                    if (g.stats) launch_batch_round<false, false, true>(jobs, ids, g, r, s);
+                    else launch_batch_round<false, false, false>(jobs, ids, g, r, s);
+                    break;
+                case kBatchExactHrpp:
+                    if (g.stats) launch_batch_round<false, true, true>(jobs, ids, g, r, s);
+                    else launch_batch_round<false, true, false>(jobs, ids, g, r, s);
+                    break;
+                default:
+                    break;
+            }
+        }
+    }
 }
 
 }  // namespace hrpp

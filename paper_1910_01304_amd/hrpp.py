@@ -30,7 +30,8 @@ EXPORTED = [
     "hrpp_predictor_required_bytes", "hrpp_predictor_table_bytes", "hrpp_predictor_create",
     "hrpp_predictor_reset", "hrpp_predictor_export", "hrpp_predictor_import", "hrpp_predictor_destroy",
     "hrpp_trace_anyhit", "hrpp_trace_closest", "hrpp_get_error", "hrpp_status_string",
-    "hrpp_profile_start", "hrpp_profile_stop",
+    "hrpp_profile_start", "hrpp_profile_stop", "hrpp_batch_required_bytes", "hrpp_batch_create",
+    "hrpp_batch_launch", "hrpp_batch_destroy",
 ]
 
 
@@ -50,6 +51,11 @@ class _PredDesc(C.Structure):
 
 class _KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_uint64), ("total_ms", C.c_double)]
+
+
+class _BatchJob(C.Structure):
+    _fields_ = [("bvh", C.c_void_p), ("pred", C.c_void_p), ("rays", C.c_void_p), ("n", C.c_uint32),
+                ("query", C.c_uint32), ("mode", C.c_uint32), ("out", C.c_void_p), ("stats", C.c_void_p)]
 
 
 class _Canon(C.Structure):
@@ -94,6 +100,12 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_trace_closest.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
     lib.hrpp_get_error.argtypes = [vp, vp]
     lib.hrpp_profile_stop.argtypes = [vp, u32, C.POINTER(u32)]
+    lib.hrpp_batch_required_bytes.restype = sz
+    lib.hrpp_batch_required_bytes.argtypes = [u32]
+    lib.hrpp_batch_create.argtypes = [vp, u32, vp, sz, vp, C.POINTER(vp)]
+    lib.hrpp_batch_launch.argtypes = [vp, u32, vp]
+    lib.hrpp_batch_destroy.argtypes = [vp]
+    lib.hrpp_batch_destroy.restype = None
     lib.hrpp_status_string.restype = C.c_char_p
     lib.hrpp_status_string.argtypes = [C.c_int]
     _lib = lib
@@ -280,3 +292,55 @@ def profile_stop() -> dict:
     n = C.c_uint32()
     _check(load_library().hrpp_profile_stop(arr, 16, C.byref(n)), "hrpp_profile_stop")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, 16))}
+
+
+class Batch:
+    """Many independent traces launched together (optionally as one hipGraph).
+
+    ``jobs``: dicts with keys bvh, pred (or None), rays (cuda float32 [n, 8]),
+    query ("any" | "closest"), mode ("paper" | "exact"), out (optional), stats
+    (optional int64 [24] cuda tensor).  Outputs are allocated if not given and
+    are available as ``batch.outputs[i]``.
+    """
+
+    def __init__(self, jobs, device: str = "cuda"):
+        lib = load_library()
+        self._keep = []
+        arr = (_BatchJob * len(jobs))()
+        self.outputs = []
+        for i, j in enumerate(jobs):
+            rays = j["rays"]
+            _rays_ok(rays)
+            n = rays.shape[0]
+            query = j.get("query", "any")
+            out = j.get("out")
+            if out is None:
+                out = (torch.empty(n, dtype=torch.uint8, device=rays.device) if query == "any"
+                       else torch.empty((n, 4), dtype=torch.float32, device=rays.device))
+            st = j.get("stats")
+            pred = j.get("pred")
+            arr[i] = _BatchJob(j["bvh"].handle, pred.handle if pred is not None else None, rays.data_ptr(), n,
+                               0 if query == "any" else 1, CLOSEST_MODES[j.get("mode", "paper")], out.data_ptr(),
+                               st.data_ptr() if st is not None else None)
+            self._keep += [rays, out, st, j["bvh"], pred]
+            self.outputs.append(out)
+        need = lib.hrpp_batch_required_bytes(len(jobs))
+        self._raw, self.buffer = _aligned(need, device)
+        h = C.c_void_p()
+        _check(lib.hrpp_batch_create(arr, len(jobs), self.buffer.data_ptr(), need, _stream(), C.byref(h)),
+               "hrpp_batch_create")
+        self.handle = h
+
+    def launch(self, use_graph: bool = True):
+        _check(load_library().hrpp_batch_launch(self.handle, 1 if use_graph else 0, _stream()), "hrpp_batch_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hrpp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

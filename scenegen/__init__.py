@@ -395,3 +395,56 @@ def terrain_workload(total: int = 1 << 20, width: int = 1920, height: int = 1080
     rays, pid = cam.rays(order)
     cam.assert_all_hit_terrain(rays, hf.amplitude)
     return tris, rays
+
+
+# ---------------------------------------------------------------------------
+# Many scenes (batching and serving workloads)
+# ---------------------------------------------------------------------------
+
+def soup_scene(seed: int, n: int) -> np.ndarray:
+    """A random-triangle soup of n triangles with edge ~0.8 n^(-1/3) in the unit cube."""
+    return triangle_soup(seed, n, edge=0.8 * n ** (-1.0 / 3.0))
+
+
+def heightfield_scene(seed: int, n: int) -> np.ndarray:
+    """A noise heightfield on a (floor(sqrt(n/2)) + 2)^2 vertex grid, trimmed to exactly n triangles."""
+    side = int(math.floor(math.sqrt(n / 2.0))) + 2
+    t = Heightfield(seed).triangles(side)
+    return np.ascontiguousarray(t[:n])
+
+
+def mixed_scene(seed: int, n: int) -> np.ndarray:
+    """Soup or heightfield with probability 1/2 each (decided by the seed)."""
+    return soup_scene(seed, n) if rng(seed).random() < 0.5 else heightfield_scene(seed, n)
+
+
+def secondary_rays_on_surface(tris: np.ndarray, count: int, seed: int, shadow_fraction: float = 0.6,
+                              ao_tmax_frac: float = 0.05, light_center=None, light_size: float = 0.2):
+    """Shadow (to an area light above the scene) and AO (cosine hemisphere)
+    rays from points sampled uniformly by area on the scene's triangles."""
+    p, n = surface_points(tris, count, seed)
+    g = rng(seed + 17)
+    v = tris.reshape(-1, 3).astype(np.float64)
+    lo, hi = v.min(0), v.max(0)
+    diag = float(np.linalg.norm(hi - lo))
+    ns = int(round(shadow_fraction * count))
+    # face the normal towards +y (the light) for shadow rays; random side for AO
+    up = np.where((n[:, 1] < 0)[:, None], -n, n)
+    o = p + 1e-4 * diag * up
+    lc = np.asarray(light_center if light_center is not None else [(lo[0] + hi[0]) / 2, hi[1] + 0.5 * diag,
+                                                                    (lo[2] + hi[2]) / 2])
+    s = np.stack([lc[0] + light_size * diag * g.uniform(-0.5, 0.5, ns), np.full(ns, lc[1]),
+                  lc[2] + light_size * diag * g.uniform(-0.5, 0.5, ns)], 1)
+    shadow = pack_rays(o[:ns].astype(np.float32), (s.astype(np.float32) - o[:ns].astype(np.float32)), 0.0, 1.0)
+    m = count - ns
+    t1, t2 = _onb(up[ns:])
+    x, y = _concentric_disk(g.random(m), g.random(m))
+    z = np.sqrt(np.maximum(0.0, 1 - x * x - y * y))
+    d = x[:, None] * t1 + y[:, None] * t2 + z[:, None] * up[ns:]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    ao = pack_rays(o[ns:].astype(np.float32), d.astype(np.float32), 0.0, ao_tmax_frac * diag)
+    return shadow, ao
+
+
+def log_uniform_int(g: np.random.Generator, lo: float, hi: float) -> int:
+    return int(round(math.exp(g.uniform(math.log(lo), math.log(hi)))))

@@ -1,0 +1,128 @@
+"""Batched execution: every job of a batch computes exactly what its own
+trace call computes (results, counters, table), with direct launches and
+with a captured hipGraph replayed several times."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hrpp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_01304_amd as h
+    h.load_library()
+    return h
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _jobs_spec():
+    # (scene seed, triangles, rays, query, mode, predictor (T, W, qo, qd, E) or None)
+    return [
+        (11, 3000, 20000, "any", "paper", (12, 4, 5, 6, 4096)),
+        (12, 20000, 9000, "any", "paper", (14, 8, 4, 5, 1000)),
+        (13, 700, 30000, "closest", "paper", (13, 8, 5, 6, 2048)),
+        (14, 15000, 12345, "closest", "exact", (12, 4, 5, 6, 3000)),
+        (15, 5000, 7000, "any", "paper", None),
+        (16, 9000, 5000, "closest", "paper", None),
+        (17, 1, 100, "any", "paper", (4, 2, 3, 3, 16)),
+        (18, 4000, 1, "closest", "paper", (8, 4, 5, 6, 64)),
+    ]
+
+
+def _build(hrpp, torch):
+    jobs = []
+    for seed, ntri, nray, query, mode, pc in _jobs_spec():
+        tris = sg.mixed_scene(seed, ntri)
+        sh, ao = sg.secondary_rays_on_surface(tris, nray, seed + 100)
+        rays = np.concatenate([sh, ao]) if query == "any" else np.concatenate([sh, ao])
+        if query == "closest":
+            rays[:, 7] = np.inf
+        bvh = hrpp.BVH(tris)
+        jobs.append(dict(tris=tris, rays_np=rays, bvh=bvh, query=query, mode=mode, pc=pc,
+                         rays=torch.from_numpy(rays).cuda()))
+    return jobs
+
+
+def _new_pred(hrpp, job):
+    if job["pc"] is None:
+        return None
+    T, W, qo, qd, E = job["pc"]
+    return hrpp.Predictor(job["bvh"], T, W, qo, qd, E)
+
+
+def _single(hrpp, torch, job, pred):
+    st = hrpp.new_stats()
+    if job["query"] == "any":
+        out = hrpp.trace_anyhit(job["bvh"], pred, job["rays"], stats=st)
+    else:
+        out = hrpp.trace_closest(job["bvh"], pred, job["rays"], mode=job["mode"], stats=st)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().tobytes(), hrpp.stats_dict(st), (pred.export_raw().tobytes() if pred else b"")
+
+
+def test_batch_equals_single_calls(hrpp):
+    import torch
+    _say("batch: building scenes")
+    jobs = _build(hrpp, torch)
+    ref = []
+    for j in jobs:
+        pred = _new_pred(hrpp, j)
+        ref.append(_single(hrpp, torch, j, pred))
+    # the oracle agrees with the single calls for two of the jobs
+    for k in (0, 2):
+        j = jobs[k]
+        ob = oracle.build_sah(j["tris"])
+        T, W, qo, qd, E = j["pc"]
+        tb = oracle.Table(T, W, qo, qd)
+        want, ws = oracle.trace(ob, j["tris"], j["rays_np"], query=j["query"], mode=j["mode"], table=tb, epoch=E)
+        assert want.tobytes() == ref[k][0] and ws == ref[k][1]
+    for use_graph in (False, True):
+        _say(f"batch: graph={use_graph}")
+        preds = [_new_pred(hrpp, j) for j in jobs]
+        stats = [hrpp.new_stats() for _ in jobs]
+        b = hrpp.Batch([dict(bvh=j["bvh"], pred=p, rays=j["rays"], query=j["query"], mode=j["mode"], stats=s)
+                        for j, p, s in zip(jobs, preds, stats)])
+        replays = 3 if use_graph else 1
+        for rep in range(replays):
+            for p in preds:
+                if p is not None:
+                    p.reset()
+            for s in stats:
+                s.zero_()
+            torch.cuda.synchronize()
+            b.launch(use_graph=use_graph)
+            torch.cuda.synchronize()
+            hrpp.get_error()
+            for k, j in enumerate(jobs):
+                got = (b.outputs[k].cpu().numpy().tobytes(), hrpp.stats_dict(stats[k]),
+                       preds[k].export_raw().tobytes() if preds[k] else b"")
+                assert got[0] == ref[k][0], f"job {k} results differ (graph={use_graph}, replay {rep})"
+                assert got[1] == ref[k][1], f"job {k} counters differ (graph={use_graph}, replay {rep})"
+                assert got[2] == ref[k][2], f"job {k} table differs (graph={use_graph}, replay {rep})"
+            # eager work between replays
+            _ = _single(hrpp, torch, jobs[0], None)
+        b.close()
+
+
+def test_batch_rejects_shared_predictor(hrpp):
+    import torch
+    tris = sg.soup_scene(5, 500)
+    bvh = hrpp.BVH(tris)
+    p = hrpp.Predictor(bvh, 10, 4, 4, 4, 256)
+    r = torch.from_numpy(sg.tiny_shadow_rays(5, 300)).cuda()
+    with pytest.raises(hrpp.HrppError):
+        hrpp.Batch([dict(bvh=bvh, pred=p, rays=r), dict(bvh=bvh, pred=p, rays=r)])
