@@ -52,6 +52,11 @@ def parse():
     ap.add_argument("--epoch", type=int, default=0, help="epoch rays (default: the workload's 2^19)")
     ap.add_argument("--reference-epoch", type=int, default=1 << 17,
                     help="also time the HRPP step at this epoch size (0 = skip)")
+    ap.add_argument("--workload", default="at_scale", choices=["at_scale", "batched", "autotune"],
+                    help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
+                         "graph-captured batch")
+    ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--batch-epoch", type=int, default=1 << 17)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 256 MiB calibration copy, then one HRPP and one plain step (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -187,6 +192,12 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        run_batched(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "autotune":
+        run_autotune(args, np, torch, hrpp, sg)
+        return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
     tris, prim = sg.terrain_workload()
@@ -445,6 +456,113 @@ def main():
         "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "reference_epoch": ref_info,
         "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
         "p99_latency_ms": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_autotune(args, np, torch, hrpp, sg):
+    """Tune the hit-all (primary) and hit-any (shadow) predictors of the
+    at-scale workload by measured time; prints the chosen configurations and
+    every trial as one JSON line."""
+    from paper_1910_01304_amd import autotune
+
+    tris, prim = sg.terrain_workload()
+    w = sg.AT_SCALE
+    bvh = hrpp.BVH(tris)
+    prim_d = torch.from_numpy(prim).cuda()
+    he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
+                                      light_center=w["light_center"], light_size=w["light_size"])
+    shadow_d = torch.from_numpy(shadow).cuda()
+    res = {}
+    for name, rays, query in (("primary", prim_d, "closest"), ("shadow", shadow_d, "any")):
+        r = autotune.tune(bvh, rays, query=query, mode="paper", rounds=2, reps=3, log=log)
+        res[name] = {"best": r.best, "best_ms": round(r.best_ms, 4),
+                     "best_mrays_s": round(rays.shape[0] / (r.best_ms * 1e-3) / 1e6, 1),
+                     "best_pct_nodes_skipped": round(r.best_stats["pct_nodes_skipped"], 3),
+                     "trials": [dict(t, ms=round(t["ms"], 4), pct_nodes_skipped=round(t["pct_nodes_skipped"], 3))
+                                for t in r.trials]}
+    print(json.dumps({"metric": "autotuned predictor configuration (min trace time)", "config": {
+        "workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) / shadow any-hit"}, "results": res}),
+        flush=True)
+
+
+def run_batched(args, np, torch, hrpp, sg):
+    """Many scenes of uneven size traced together: one any-hit job per scene
+    (60% shadow, 40% AO rays from points on the scene's surface), each with
+    its own BVH and predictor, in one graph-captured batch; compared with the
+    same jobs issued one call after another and with plain batched traversal."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    g = sg.rng(4)
+    specs = []
+    for k in range(args.batch_scenes):
+        specs.append(dict(seed=4000 + k, tris=sg.log_uniform_int(g, 1e4, 2e6),
+                          rays=sg.log_uniform_int(g, 1 << 16, 1 << 22), log2_entries=int(g.integers(16, 21))))
+    log(f"batched: generating {len(specs)} scenes, {sum(s['tris'] for s in specs)} triangles, "
+        f"{sum(s['rays'] for s in specs)} rays")
+    with ThreadPoolExecutor(8) as ex:
+        tris = list(ex.map(lambda sp: sg.mixed_scene(sp["seed"], sp["tris"]), specs))
+        t0 = time.perf_counter()
+        bvhs = list(ex.map(lambda t: hrpp.BVH(t, device=None), tris))
+        build_s = time.perf_counter() - t0
+        rays = list(ex.map(lambda it: np.concatenate(sg.secondary_rays_on_surface(it[1], it[0]["rays"],
+                                                                                   it[0]["seed"] + 1)),
+                           zip(specs, tris)))
+    for b in bvhs:
+        b.upload()
+    rays_d = [torch.from_numpy(r).cuda() for r in rays]
+    total = int(sum(r.shape[0] for r in rays))
+    del rays
+    E = args.batch_epoch
+    preds = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6, epoch_rays=E)
+             for b, sp in zip(bvhs, specs)]
+    outs = [torch.empty(r.shape[0], dtype=torch.uint8, device="cuda") for r in rays_d]
+    batch = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o) for b, p, r, o in zip(bvhs, preds, rays_d, outs)])
+    plain = hrpp.Batch([dict(bvh=b, pred=None, rays=r, out=o) for b, r, o in zip(bvhs, rays_d, outs)])
+
+    def reset_all():
+        for p in preds:
+            p.reset()
+
+    def step_batch():
+        reset_all()
+        batch.launch(use_graph=True)
+
+    def step_sequential():
+        reset_all()
+        for b, p, r, o in zip(bvhs, preds, rays_d, outs):
+            hrpp.trace_anyhit(b, p, r, out=o)
+
+    steps = max(1, args.steps // 2)
+    ms_batch = timed(torch, step_batch, steps, 1)[0]
+    ms_seq = timed(torch, step_sequential, steps, 1)[0]
+    ms_plain = timed(torch, lambda: plain.launch(use_graph=True), steps, 1)[0]
+    ms_reset = timed(torch, reset_all, steps, 1)[0]
+    sh, sp_ = hrpp.new_stats(), hrpp.new_stats()
+    reset_all()
+    for b, p, r, o in zip(bvhs, preds, rays_d, outs):
+        hrpp.trace_anyhit(b, p, r, out=o, stats=sh)
+        hrpp.trace_anyhit(b, None, r, out=o, stats=sp_)
+    torch.cuda.synchronize()
+    h, pl = hrpp.stats_dict(sh), hrpp.stats_dict(sp_)
+    out = {
+        "metric": "Mrays/s HRPP batched (64 scenes, one graph launch) vs sequential calls and plain",
+        "value": round(total / (ms_batch * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": steps,
+        "ms_per_step": round(ms_batch, 3), "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(specs)} scenes (soup/heightfield 50/50, 1e4-2e6 tris log-uniform), "
+                               "rays 2^16-2^22 log-uniform per scene (60% shadow, 40% AO), any-hit, "
+                               f"tables 2^16-2^20 x 8, q 5/6, epoch {E}",
+                   "scenes": len(specs), "triangles": int(sum(sp["tris"] for sp in specs)), "rays": total},
+        "sequential_calls_mrays_s": round(total / (ms_seq * 1e-3) / 1e6, 2),
+        "plain_batched_mrays_s": round(total / (ms_plain * 1e-3) / 1e6, 2),
+        "batch_speedup_vs_sequential": round(ms_seq / ms_batch, 3),
+        "predictor_reset_ms": round(ms_reset, 3),
+        "host_bvh_build_s": round(build_s, 2),
+        "pct_nodes_skipped": round(100.0 * (1 - h["nodes_visited"] / pl["nodes_visited"]), 3),
+        "prediction_hit_rate": round(h["pred_hits"] / total, 4),
+        "false_positive_rate": round(h["false_pos"] / total, 4),
+        "occluded_fraction": round(h["hits"] / total, 4),
     }
     print(json.dumps(out), flush=True)
 

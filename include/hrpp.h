@@ -250,6 +250,64 @@ hrpp_status hrpp_batch_launch(hrpp_batch *batch, uint32_t use_graph, void *strea
 
 void hrpp_batch_destroy(hrpp_batch *batch);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of ray-query requests against resident
+ * scenes.  A scheduler thread admits queued requests (arrival order; a
+ * request waiting only for a busy predictor does not hold back the requests
+ * behind it, one waiting for pool space does) when
+ *   - its rays and results fit in the device pool (the HBM budget for
+ *     in-flight requests, caller-owned, 256-byte aligned),
+ *   - one of `slots` streams is free, and
+ *   - one of the scene's predictor replicas for the query kind is free;
+ * it then copies the rays in, traces them and copies the results back on
+ * the slot's stream.  Requests on different slots run concurrently, and new
+ * requests are admitted as slots and pool space free up.  Predictors keep
+ * their tables across requests.  Only any-hit and EXACT closest-hit are
+ * served, whose results do not depend on the tables: a request's results
+ * are the same alone and in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const hrpp_bvh *bvh;
+    hrpp_predictor *const *any_preds;      /* replicas for any-hit requests (>= 1) */
+    uint32_t n_any;
+    hrpp_predictor *const *closest_preds;  /* replicas for closest-hit requests (>= 1) */
+    uint32_t n_closest;
+} hrpp_serve_scene;
+
+typedef struct {
+    uint32_t state;          /* 0 queued, 1 running, 2 done */
+    hrpp_status status;
+    double queue_ms;         /* submit -> admission */
+    double service_ms;       /* admission -> results in host memory */
+    double latency_ms;       /* submit -> results in host memory */
+} hrpp_request_info;
+
+typedef struct hrpp_server hrpp_server;
+
+/* Start a server over `nscenes` scenes (each predictor may appear once). */
+hrpp_status hrpp_serve_create(const hrpp_serve_scene *scenes, uint32_t nscenes, uint32_t slots, void *d_pool,
+                              size_t pool_bytes, hrpp_server **out);
+
+/* Queue a request: n rays in host memory (pinned memory lets the copies run
+ * asynchronously), results to h_out (uint8_t[n] for query 0 = any-hit,
+ * hrpp_hit[n] for query 1 = EXACT closest-hit).  Both buffers must stay
+ * valid until the request is done.  EBUSY if the request can never fit
+ * the pool. */
+hrpp_status hrpp_serve_submit(hrpp_server *server, uint32_t scene, uint32_t query, const hrpp_ray *h_rays,
+                              uint32_t n, void *h_out, uint64_t *request_id);
+
+/* Non-blocking state and timings of a request. */
+hrpp_status hrpp_serve_poll(hrpp_server *server, uint64_t request_id, hrpp_request_info *info);
+
+/* Block until every submitted request is done; the first failed status, if any. */
+hrpp_status hrpp_serve_wait_all(hrpp_server *server);
+
+/* Largest pool occupancy seen so far (never above pool_bytes). */
+hrpp_status hrpp_serve_pool_peak(hrpp_server *server, size_t *peak_bytes);
+
+/* Drain the queue, stop the scheduler, free the handle. */
+void hrpp_serve_destroy(hrpp_server *server);
+
 /* Per-kernel timing for measurement.  Between hrpp_profile_start() and
  * hrpp_profile_stop(), every kernel the library launches is bracketed by two
  * HIP events recorded on the launch stream.  Stop waits for those events and

@@ -1,0 +1,114 @@
+"""Autotuner for the predictor's knobs, by measured throughput on the GPU.
+
+Knobs: epoch size (the unit of batch-synchronous work, a "chunk"), table size
+(log2 entries), ways, and origin / direction quantisation bits.  The traversal
+stack depth is not a knob: the LDS stack is sized to the deepest leaf of the
+tree, which is what makes overflow impossible.  Every configuration the tuner
+can pick is an ordinary predictor configuration, traced by the same kernels
+that the parity tests check against the oracle.
+
+Search: coordinate descent from a start point, one knob at a time over its
+candidate list, for `rounds` passes; each point is timed with HIP events
+(median of `reps` runs, each run = predictor reset + trace).  Optionally a
+minimum fraction of skipped nodes can be imposed, so that the tuner does not
+trade all prediction away for speed.
+"""
+from __future__ import annotations
+
+import statistics
+from dataclasses import dataclass, field
+
+import torch
+
+from . import hrpp
+
+DEFAULT_SPACE = {
+    "epoch_rays": [1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20],
+    "log2_entries": [16, 18, 20, 22],
+    "ways": [4, 8],
+    "origin_bits": [3, 4, 5, 6, 7],
+    "dir_bits": [3, 4, 5, 6, 7],
+}
+
+
+@dataclass
+class TuneResult:
+    best: dict
+    best_ms: float
+    best_stats: dict
+    trials: list = field(default_factory=list)
+
+
+def _time_config(bvh, rays, query, mode, cfg, reps, plain_nodes):
+    pred = hrpp.Predictor(bvh, **cfg)
+    out = (torch.empty(rays.shape[0], dtype=torch.uint8, device=rays.device) if query == "any"
+           else torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device))
+
+    def run(stats=None):
+        pred.reset()
+        if query == "any":
+            hrpp.trace_anyhit(bvh, pred, rays, out=out, stats=stats)
+        else:
+            hrpp.trace_closest(bvh, pred, rays, mode=mode, out=out, stats=stats)
+
+    run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    st = hrpp.new_stats()
+    run(st)
+    torch.cuda.synchronize()
+    s = hrpp.stats_dict(st)
+    s["pct_nodes_skipped"] = 100.0 * (1.0 - s["nodes_visited"] / plain_nodes) if plain_nodes else 0.0
+    del pred
+    return statistics.median(times), s
+
+
+def tune(bvh, rays, query: str = "any", mode: str = "paper", start: dict | None = None,
+         space: dict | None = None, rounds: int = 2, reps: int = 3, min_skip_pct: float | None = None,
+         knobs=("epoch_rays", "log2_entries", "ways", "origin_bits", "dir_bits"), log=None) -> TuneResult:
+    """Coordinate-descent search of the predictor configuration minimising trace time."""
+    space = dict(DEFAULT_SPACE, **(space or {}))
+    cfg = dict(log2_entries=20, ways=8, origin_bits=5, dir_bits=6, epoch_rays=1 << 19)
+    if start:
+        cfg.update(start)
+    # plain node count, for the skip constraint and the report
+    st = hrpp.new_stats()
+    if query == "any":
+        hrpp.trace_anyhit(bvh, None, rays, stats=st)
+    else:
+        hrpp.trace_closest(bvh, None, rays, mode=mode, stats=st)
+    torch.cuda.synchronize()
+    plain_nodes = hrpp.stats_dict(st)["nodes_visited"]
+    seen = {}
+    trials = []
+
+    def evaluate(c):
+        key = tuple(sorted(c.items()))
+        if key not in seen:
+            ms, s = _time_config(bvh, rays, query, mode, c, reps, plain_nodes)
+            ok = min_skip_pct is None or s["pct_nodes_skipped"] >= min_skip_pct
+            seen[key] = (ms, s, ok)
+            trials.append(dict(config=dict(c), ms=ms, pct_nodes_skipped=s["pct_nodes_skipped"], feasible=ok))
+            if log:
+                log(f"autotune {c} -> {ms:.3f} ms, {s['pct_nodes_skipped']:.1f}% skipped{'' if ok else ' (rejected)'}")
+        return seen[key]
+
+    best_ms, best_s, best_ok = evaluate(cfg)
+    for _ in range(rounds):
+        changed = False
+        for knob in knobs:
+            for v in space[knob]:
+                c = dict(cfg, **{knob: v})
+                ms, s, ok = evaluate(c)
+                if ok and (not best_ok or ms < best_ms):
+                    cfg, best_ms, best_s, best_ok, changed = c, ms, s, True, True
+        if not changed:
+            break
+    return TuneResult(best=cfg, best_ms=best_ms, best_stats=best_s, trials=trials)

@@ -391,7 +391,9 @@ struct hrpp_batch {
 };
 
 size_t hrpp_batch_required_bytes(uint32_t njobs) {
-    return align256((size_t)njobs * sizeof(BatchJob)) + align256((size_t)njobs * sizeof(uint32_t));
+    // job table, job ids, and block offsets of the two plain groups
+    return align256((size_t)njobs * sizeof(BatchJob)) + align256((size_t)njobs * sizeof(uint32_t)) +
+           align256(2 * ((size_t)njobs + 2) * sizeof(uint32_t));
 }
 
 hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *d_buf, size_t bytes, void *stream,
@@ -446,11 +448,28 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
     char *base = static_cast<char *>(d_buf);
     b->d_jobs = reinterpret_cast<BatchJob *>(base);
     b->d_ids = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)));
+    uint32_t *d_off = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)) +
+                                                   align256((size_t)njobs * sizeof(uint32_t)));
+    // plain groups: blocks in proportion to each job's rays (about 8 rays per lane)
+    std::vector<uint32_t> offs;
+    for (BatchGroup &g : b->groups) {
+        if (g.kind != kBatchAnyPlain && g.kind != kBatchClosestPlain) continue;
+        g.d_block_off = d_off + offs.size();
+        uint32_t acc = 0;
+        for (uint32_t k = 0; k < g.count; k++) {
+            offs.push_back(acc);
+            acc += std::max(1u, (b->jobs[b->ids[g.first_id + k]].n + 1023u) / 1024u);
+        }
+        offs.push_back(acc);
+        g.total_blocks = acc;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(b->d_jobs, b->jobs.data(), b->jobs.size() * sizeof(BatchJob),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !b->ids.empty())
         e = hipMemcpyAsync(b->d_ids, b->ids.data(), b->ids.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !offs.empty())
+        e = hipMemcpyAsync(d_off, offs.data(), offs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete b; return HRPP_EDEVICE; }
     *out = b;

@@ -60,6 +60,9 @@ struct BatchGroup {
     int kind;
     uint32_t first_id, count, max_epoch, max_cap, rounds, max_n;
     bool stats;
+    // plain groups: flat grid of total_blocks, job k owns blocks [off[k], off[k+1])
+    uint32_t total_blocks;
+    const uint32_t *d_block_off;
 };
 
 void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<BatchGroup> &groups,

@@ -711,11 +711,21 @@ __global__ __launch_bounds__(256) void kb_update_finish(const BatchJob *__restri
     body_update_finish<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
 }
 
+// Plain jobs: one flat grid, each job getting blocks in proportion to its
+// rays; block_off[k] is the first block of the group's k-th job (count + 1
+// entries), found by binary search.
 template <bool ANY, bool STATS>
 __global__ __launch_bounds__(128) void kb_traverse_plain(const BatchJob *__restrict__ jobs,
-                                                         const uint32_t *__restrict__ ids) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    body_traverse_plain<ANY, STATS>(J.a, J.n, blockIdx.x, gridDim.x);
+                                                         const uint32_t *__restrict__ ids,
+                                                         const uint32_t *__restrict__ block_off, uint32_t count) {
+    uint32_t lo = 0, hi = count;   // find k with block_off[k] <= blockIdx.x < block_off[k + 1]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (block_off[mid] <= blockIdx.x) lo = mid;
+        else hi = mid;
+    }
+    const BatchJob &J = jobs[ids[lo]];
+    body_traverse_plain<ANY, STATS>(J.a, J.n, blockIdx.x - block_off[lo], block_off[lo + 1] - block_off[lo]);
 }
 
 // Fill a region with a 32-bit pattern (predictor reset; a kernel rather than
@@ -884,23 +894,21 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
 }
 
 template <bool ANY, bool STATS>
-static void launch_batch_plain(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, uint32_t max_blocks,
-                               hipStream_t s) {
-    const uint32_t per_job = std::max(1u, std::min(ceil_div(g.max_n, 128), max_blocks / std::max(1u, g.count)));
+static void launch_batch_plain(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, hipStream_t s) {
     const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
-    hipLaunchKernelGGL((kb_traverse_plain<ANY, STATS>), dim3(per_job, g.count), dim3(128), lds, s, jobs,
-                       ids + g.first_id);
+    hipLaunchKernelGGL((kb_traverse_plain<ANY, STATS>), dim3(g.total_blocks), dim3(128), lds, s, jobs,
+                       ids + g.first_id, g.d_block_off, g.count);
 }
 
 void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<BatchGroup> &groups,
                   uint32_t max_rounds, uint32_t max_blocks, hipStream_t s) {
     for (const BatchGroup &g : groups) {
         if (g.kind == kBatchAnyPlain) {
-            if (g.stats) launch_batch_plain<true, true>(jobs, ids, g, max_blocks, s);
-            else launch_batch_plain<true, false>(jobs, ids, g, max_blocks, s);
+            if (g.stats) launch_batch_plain<true, true>(jobs, ids, g, s);
+            else launch_batch_plain<true, false>(jobs, ids, g, s);
         } else if (g.kind == kBatchClosestPlain) {
-            if (g.stats) launch_batch_plain<false, true>(jobs, ids, g, max_blocks, s);
-            else launch_batch_plain<false, false>(jobs, ids, g, max_blocks, s);
+            if (g.stats) launch_batch_plain<false, true>(jobs, ids, g, s);
+            else launch_batch_plain<false, false>(jobs, ids, g, s);
         }
     }
     for (uint32_t r = 0; r < max_rounds; r++) {

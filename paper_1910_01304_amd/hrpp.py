@@ -31,7 +31,8 @@ EXPORTED = [
     "hrpp_predictor_reset", "hrpp_predictor_export", "hrpp_predictor_import", "hrpp_predictor_destroy",
     "hrpp_trace_anyhit", "hrpp_trace_closest", "hrpp_get_error", "hrpp_status_string",
     "hrpp_profile_start", "hrpp_profile_stop", "hrpp_batch_required_bytes", "hrpp_batch_create",
-    "hrpp_batch_launch", "hrpp_batch_destroy",
+    "hrpp_batch_launch", "hrpp_batch_destroy", "hrpp_serve_create", "hrpp_serve_submit", "hrpp_serve_poll",
+    "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy",
 ]
 
 
@@ -56,6 +57,16 @@ class _KernelTime(C.Structure):
 class _BatchJob(C.Structure):
     _fields_ = [("bvh", C.c_void_p), ("pred", C.c_void_p), ("rays", C.c_void_p), ("n", C.c_uint32),
                 ("query", C.c_uint32), ("mode", C.c_uint32), ("out", C.c_void_p), ("stats", C.c_void_p)]
+
+
+class _ServeScene(C.Structure):
+    _fields_ = [("bvh", C.c_void_p), ("any_preds", C.c_void_p), ("n_any", C.c_uint32),
+                ("closest_preds", C.c_void_p), ("n_closest", C.c_uint32)]
+
+
+class _RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_uint32), ("status", C.c_int), ("queue_ms", C.c_double), ("service_ms", C.c_double),
+                ("latency_ms", C.c_double)]
 
 
 class _Canon(C.Structure):
@@ -106,6 +117,13 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_batch_launch.argtypes = [vp, u32, vp]
     lib.hrpp_batch_destroy.argtypes = [vp]
     lib.hrpp_batch_destroy.restype = None
+    lib.hrpp_serve_create.argtypes = [vp, u32, u32, vp, sz, C.POINTER(vp)]
+    lib.hrpp_serve_submit.argtypes = [vp, u32, u32, vp, u32, vp, C.POINTER(C.c_uint64)]
+    lib.hrpp_serve_poll.argtypes = [vp, C.c_uint64, vp]
+    lib.hrpp_serve_wait_all.argtypes = [vp]
+    lib.hrpp_serve_pool_peak.argtypes = [vp, C.POINTER(sz)]
+    lib.hrpp_serve_destroy.argtypes = [vp]
+    lib.hrpp_serve_destroy.restype = None
     lib.hrpp_status_string.restype = C.c_char_p
     lib.hrpp_status_string.argtypes = [C.c_int]
     _lib = lib
@@ -337,6 +355,68 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             load_library().hrpp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over resident scenes.
+
+    ``scenes``: list of (bvh, [any-hit predictors], [closest-hit predictors]).
+    ``pool_bytes``: device budget for in-flight request rays and results.
+    Requests carry host tensors (pinned for asynchronous copies): rays
+    float32 [n, 8]; results uint8 [n] (query "any") or float32 [n, 4]
+    (query "closest", exact closest hit).
+    """
+
+    def __init__(self, scenes, slots: int = 8, pool_bytes: int = 1 << 30, device: str = "cuda"):
+        lib = load_library()
+        self._keep = []
+        arr = (_ServeScene * len(scenes))()
+        for i, (bvh, anyp, clp) in enumerate(scenes):
+            a = (C.c_void_p * len(anyp))(*[p.handle.value for p in anyp])
+            c = (C.c_void_p * len(clp))(*[p.handle.value for p in clp])
+            self._keep += [a, c, bvh, list(anyp), list(clp)]
+            arr[i] = _ServeScene(bvh.handle, C.cast(a, C.c_void_p), len(anyp), C.cast(c, C.c_void_p), len(clp))
+        self._raw, self.pool = _aligned(pool_bytes, device)
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib.hrpp_serve_create(arr, len(scenes), slots, self.pool.data_ptr(), pool_bytes, C.byref(h)),
+               "hrpp_serve_create")
+        self.handle = h
+        self._reqs = {}
+
+    def submit(self, scene: int, query: str, rays: torch.Tensor, out: torch.Tensor) -> int:
+        if rays.is_cuda or out.is_cuda or not rays.is_contiguous() or not out.is_contiguous():
+            raise HrppError("serving requests use contiguous host tensors")
+        rid = C.c_uint64()
+        _check(load_library().hrpp_serve_submit(self.handle, scene, 0 if query == "any" else 1, rays.data_ptr(),
+                                                rays.shape[0], out.data_ptr(), C.byref(rid)), "hrpp_serve_submit")
+        self._reqs[rid.value] = (rays, out)
+        return rid.value
+
+    def poll(self, rid: int) -> dict:
+        info = _RequestInfo()
+        _check(load_library().hrpp_serve_poll(self.handle, rid, C.byref(info)), "hrpp_serve_poll")
+        return dict(state=info.state, status=info.status, queue_ms=info.queue_ms, service_ms=info.service_ms,
+                    latency_ms=info.latency_ms)
+
+    def wait_all(self):
+        _check(load_library().hrpp_serve_wait_all(self.handle), "hrpp_serve_wait_all")
+
+    def pool_peak(self) -> int:
+        v = C.c_size_t()
+        _check(load_library().hrpp_serve_pool_peak(self.handle, C.byref(v)), "hrpp_serve_pool_peak")
+        return v.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hrpp_serve_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
