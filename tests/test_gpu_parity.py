@@ -241,12 +241,16 @@ def full_terrain():
     return sg.terrain_workload()
 
 
-@pytest.mark.parametrize("epoch", [sg.AT_SCALE["epoch"], 1 << 17])
-def test_full_size_primary_and_shadow(hrpp, full_terrain, epoch):
+@pytest.mark.parametrize("tuned", [True, False])
+def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
+    # the benchmark's launch configuration (autotuned quantisation and epochs),
+    # and the untuned reference (q_o 5, q_d 6, epochs of 2^17)
     w = sg.AT_SCALE
     tris, prim = full_terrain
-    cfg = (w["log2_entries"], w["ways"], w["origin_bits"], w["dir_bits"], epoch)
-    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg)
+    pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17), (5, 6, 1 << 17))
+    cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2])
+    cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2])
+    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all)
     assert st["rays"] == 1920 * 1080
     ob = oracle.build_sah(tris)
     he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
@@ -254,7 +258,7 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, epoch):
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
     check_case(hrpp, "full shadow plain", tris, shadow)
-    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg)
+    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any)
 
 
 def test_results_do_not_depend_on_stats(hrpp, small_terrain):
