@@ -56,7 +56,7 @@ PredLayout pred_layout(const hrpp_predictor_desc *d) {
     L.rec_idx = off; off += align256(E * 4);
     L.rec_leaf = off; off += align256(E * 4);
     L.rec_status = off; off += align256(E * 4);
-    L.queue = off; off += align256(E * 8);
+    L.queue = off; off += align256((size_t)kSubQueues * queue_subcap_for((uint32_t)E) * 8);
     L.ctrl = off; off += 256;
     L.total = off;
     return L;
@@ -333,6 +333,7 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.hash.log2n = d.log2_entries;
         a.ctrl = pred->d_ctrl;
         a.queue = pred->d_queue;
+        a.queue_subcap = queue_subcap_for(d.epoch_rays);
         a.rec_key = pred->d_rec_key;
         a.rec_idx = pred->d_rec_idx;
         a.rec_leaf = pred->d_rec_leaf;

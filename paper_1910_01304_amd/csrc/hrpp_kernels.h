@@ -18,6 +18,15 @@ struct HashArgs {
     uint32_t qo, qd, log2n;
 };
 
+constexpr uint32_t kSubQueues = 8;     // striped fallback sub-queues per epoch
+
+// Capacity of one sub-queue: prediction blocks of 256 rays go to sub-queue
+// (block % kSubQueues), so each receives at most ceil(blocks / kSubQueues) blocks.
+inline uint32_t queue_subcap_for(uint32_t epoch) {
+    const uint32_t blocks = (epoch + 255u) / 256u;
+    return ((blocks + kSubQueues - 1u) / kSubQueues) * 256u;
+}
+
 struct TraceArgs {
     // scene
     const void *nodes;            // interior nodes, 64 B each
@@ -38,8 +47,9 @@ struct TraceArgs {
     uint32_t entry_bytes;
     uint32_t ways;
     HashArgs hash;
-    uint32_t *ctrl;               // [0] queue count
-    uint64_t *queue;
+    uint32_t *ctrl;               // [0 .. kSubQueues) sub-queue counts
+    uint64_t *queue;              // kSubQueues sub-queues of queue_subcap entries
+    uint32_t queue_subcap;
     uint64_t *rec_key;
     uint32_t *rec_idx;
     uint32_t *rec_leaf;

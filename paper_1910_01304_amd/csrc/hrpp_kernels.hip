@@ -462,17 +462,25 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
     bool enq = false;
     uint32_t seed_leaf = kNone;
     if (i < count) enq = predict_one<ANY, EXACT>(a, base + i, c, seed_leaf);
+    // append to the fallback queue: lanes are counted per wave (ballot), waves
+    // per block (LDS atomic), and each block takes its range with one global
+    // atomic on one of kSubQueues striped counters, so no single counter sees
+    // more than one atomic per kSubQueues blocks
+    __shared__ uint32_t s_count, s_base;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
     const uint64_t mask = __ballot(enq);
-    if (mask) {
-        const uint32_t lane = __lane_id();
-        const uint32_t leader = __ffsll((unsigned long long)mask) - 1;
-        uint32_t qbase = 0;
-        if (lane == leader) qbase = atomicAdd(&a.ctrl[0], (uint32_t)__popcll(mask));
-        qbase = __shfl(qbase, leader);
-        if (enq) {
-            const uint32_t pos = qbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            a.queue[pos] = (uint64_t)(base + i) | ((uint64_t)seed_leaf << 32);
-        }
+    const uint32_t lane = __lane_id();
+    uint32_t wave_off = 0;
+    if (lane == 0 && mask) wave_off = atomicAdd(&s_count, (uint32_t)__popcll(mask));
+    wave_off = __shfl(wave_off, 0);
+    __syncthreads();
+    const uint32_t sub = bx % kSubQueues;
+    if (threadIdx.x == 0 && s_count) s_base = atomicAdd(&a.ctrl[sub], s_count);
+    __syncthreads();
+    if (enq) {
+        const uint32_t pos = s_base + wave_off + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        a.queue[(size_t)sub * a.queue_subcap + pos] = (uint64_t)(base + i) | ((uint64_t)seed_leaf << 32);
     }
     flush_counters<STATS>(c, a.stats);
 }
@@ -495,10 +503,26 @@ __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t
     float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
     Counters c;
     c.zero();
-    const uint32_t total = *(volatile uint32_t *)&a.ctrl[0];
+    uint32_t cnt[kSubQueues];
+    uint32_t total = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kSubQueues; k++) {
+        cnt[k] = *(volatile uint32_t *)&a.ctrl[k];
+        total += cnt[k];
+    }
     const uint32_t step = gx * blockDim.x;
     for (uint32_t i = bx * blockDim.x + threadIdx.x; i < total; i += step) {
-        const uint64_t q = a.queue[i];
+        // work item i -> (sub-queue, offset)
+        uint32_t sub = 0, off = i;
+        bool found = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kSubQueues; k++) {
+            if (!found) {
+                if (off < cnt[k]) found = true;
+                else { off -= cnt[k]; sub++; }
+            }
+        }
+        const uint64_t q = a.queue[(size_t)sub * a.queue_subcap + off];
         traverse_one<ANY, EXACT, true>(a, base, (uint32_t)q, (uint32_t)(q >> 32), c, stk_node, stk_t, stride, cap);
     }
     flush_counters<STATS>(c, a.stats);
@@ -618,7 +642,7 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
         }
         if (!STATS) a.rec_idx[i] = kNone;            // no drop count to take: retire the record now
     }
-    if (!STATS && i == 0) a.ctrl[0] = 0;
+    if (!STATS && i < kSubQueues) a.ctrl[i] = 0;   // queue counters of the next epoch
     flush_counters<STATS>(c, a.stats);
 }
 
@@ -632,7 +656,7 @@ __device__ __forceinline__ void body_update_finish(const TraceArgs &a, uint32_t 
     Counters c;
     c.zero();
     const uint32_t i = bx * blockDim.x + threadIdx.x;
-    if (i == 0) a.ctrl[0] = 0;   // queue length of the next epoch
+    if (i < kSubQueues) a.ctrl[i] = 0;   // queue counters of the next epoch
     if (i < count && a.rec_idx[i] != kNone) {
         if (a.rec_status[i] == kRecFresh) {
             const uint32_t *e = entry_ptr(a, a.rec_idx[i]);
