@@ -129,10 +129,14 @@ def bvh_vertices(tris: np.ndarray, bvh: CanonBVH) -> np.ndarray:
 
 
 class Table:
-    """Predictor table: ``tags[N]`` (uint64, all-ones = empty) and ``slots[N, W]``."""
+    """Predictor table: ``tags[N]`` (uint64, all-ones = empty) and ``slots[N, W]``.
 
-    def __init__(self, log2n: int, ways: int, qo: int, qd: int):
-        self.log2n, self.W, self.qo, self.qd = log2n, ways, qo, qd
+    ``hash_mode`` 0: grid origin + octahedral direction (qo, qd bits);
+    1: the paper's IEEE-754 bit hash with precision qo in 1..7 (qd must equal qo).
+    """
+
+    def __init__(self, log2n: int, ways: int, qo: int, qd: int, hash_mode: int = 0):
+        self.log2n, self.W, self.qo, self.qd, self.hash_mode = log2n, ways, qo, qd, hash_mode
         self.tags = np.full(1 << log2n, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64)
         self.slots = np.full((1 << log2n, ways), NONE32, np.uint32)
 
@@ -141,7 +145,7 @@ class Table:
         self.slots[:] = NONE32
 
     def copy(self) -> "Table":
-        t = Table(self.log2n, self.W, self.qo, self.qd)
+        t = Table(self.log2n, self.W, self.qo, self.qd, self.hash_mode)
         t.tags[:] = self.tags
         t.slots[:] = self.slots
         return t
@@ -172,13 +176,14 @@ def trace(bvh: CanonBVH, tris: np.ndarray, rays: np.ndarray, query: str = "any",
     s = bvh._struct()
     if table is not None:
         tg, sl, l2, W, qo, qd = table.tags, table.slots, table.log2n, table.W, table.qo, table.qd
+        hm = table.hash_mode
     else:
         tg = sl = None
-        l2 = W = qo = qd = 0
+        l2 = W = qo = qd = hm = 0
     rc = _L().orc_trace(C.byref(s), _p(vtx), _p(rays), C.c_uint32(n), C.c_int(1 if closest else 0),
                         C.c_int(1 if mode == "exact" else 0), _p(tg), _p(sl), C.c_uint32(l2), C.c_uint32(W),
                         C.c_uint32(qo), C.c_uint32(qd), C.c_uint32(epoch), _p(occ), _p(hits), _p(stats),
-                        _p(outcome), C.c_int(nthreads))
+                        _p(outcome), C.c_int(nthreads), C.c_uint32(hm))
     if rc != 0:
         raise ValueError("oracle trace rejected its arguments")
     return (hits if closest else occ), stats_dict(stats)
@@ -196,14 +201,14 @@ def brute_force(tris: np.ndarray, rays: np.ndarray, closest: bool = False, nthre
     return hits if closest else occ
 
 
-def hash_rays(root_box: np.ndarray, qo: int, qd: int, log2n: int, rays: np.ndarray):
+def hash_rays(root_box: np.ndarray, qo: int, qd: int, log2n: int, rays: np.ndarray, hash_mode: int = 0):
     rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
     box = np.ascontiguousarray(root_box, np.float32).reshape(6)
     n = rays.shape[0]
     keys = np.zeros(n, np.uint64)
     idx = np.zeros(n, np.uint32)
     _L().orc_hash(_p(box), C.c_uint32(qo), C.c_uint32(qd), C.c_uint32(log2n), _p(rays), C.c_uint32(n),
-                  _p(keys), _p(idx))
+                  _p(keys), _p(idx), C.c_uint32(hash_mode))
     return keys, idx
 
 

@@ -393,10 +393,12 @@ typedef struct {
     float bmin[3];
     float scale[3];
     uint32_t qo, qd, log2n;
+    uint32_t mode;       /* 0 grid + octahedral, 1 the paper's IEEE-754 bit hash (precision qo) */
 } hash_params;
 
 static void hash_setup(hash_params *h, const float *root_box, uint32_t qo, uint32_t qd, uint32_t log2n)
 {
+    h->mode = 0;
     for (int a = 0; a < 3; a++) {
         float ext = root_box[3 + a] - root_box[a];
         float s = (float)(1u << qo) / ext;
@@ -417,8 +419,38 @@ static uint32_t quantize(float x, float maxcell)
 
 static float sign_not_neg(float x) { return x >= 0.0f ? 1.0f : -1.0f; }
 
+/* The paper's hash ("HRPP Hash Function"): from each binary32 value keep
+   the sign bit, the p most significant exponent bits and the p most
+   significant mantissa bits, sign highest (2p+1 bits). */
+static uint32_t ieee_hash(float x, uint32_t p)
+{
+    uint32_t u = float_to_bits(x);
+    uint32_t sign = u >> 31, expo = (u >> 23) & 0xFFu, mant = u & 0x7FFFFFu;
+    return (sign << (2 * p)) | ((expo >> (8 - p)) << p) | (mant >> (23 - p));
+}
+
+/* Swizzle origin with direction by XOR (o.x^d.z, o.y^d.y, o.z^d.x) and
+   concatenate the three values at a stride of 8 bits (p <= 3, 2p+1 <= 7
+   bits fit a byte) or 16 bits (4 <= p <= 7, at most 15 bits a field), at
+   most 48 bits in all.  p is limited to 7 so that a field never exceeds
+   the 16 bits the paper extracts per value. */
+static uint64_t paper_key(const float *o, const float *d, uint32_t p)
+{
+    uint64_t h0 = ieee_hash(o[0], p) ^ ieee_hash(d[2], p);
+    uint64_t h1 = ieee_hash(o[1], p) ^ ieee_hash(d[1], p);
+    uint64_t h2 = ieee_hash(o[2], p) ^ ieee_hash(d[0], p);
+    uint32_t stride = p <= 3 ? 8u : 16u;
+    return h0 | (h1 << stride) | (h2 << (2 * stride));
+}
+
 static void hash_ray(const hash_params *h, const float *o, const float *d, uint64_t *key, uint32_t *idx)
 {
+    if (h->mode == 1) {
+        uint64_t k = paper_key(o, d, h->qo);
+        *key = k;
+        *idx = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> (64u - h->log2n));
+        return;
+    }
     uint32_t cell[3];
     float maxo = (float)((1u << h->qo) - 1u);
     for (int a = 0; a < 3; a++) cell[a] = quantize((o[a] - h->bmin[a]) * h->scale[a], maxo);
@@ -443,10 +475,11 @@ static void hash_ray(const hash_params *h, const float *o, const float *d, uint6
 
 /* Exported for the hash pins. */
 void orc_hash(const float *root_box, uint32_t qo, uint32_t qd, uint32_t log2n, const float *rays,
-              uint32_t n, uint64_t *keys, uint32_t *idxs)
+              uint32_t n, uint64_t *keys, uint32_t *idxs, uint32_t mode)
 {
     hash_params h;
     hash_setup(&h, root_box, qo, qd, log2n);
+    h.mode = mode;
     for (uint32_t i = 0; i < n; i++) hash_ray(&h, rays + 8 * (size_t)i, rays + 8 * (size_t)i + 4, keys + i, idxs + i);
 }
 
@@ -764,10 +797,12 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
    on bad arguments. */
 int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t n, int query, int cmode,
               uint64_t *tags, uint32_t *slots, uint32_t log2n, uint32_t W, uint32_t qo, uint32_t qd,
-              uint32_t epoch, uint8_t *occ, float *hits, uint64_t *stats, uint8_t *outcome, int nthreads)
+              uint32_t epoch, uint8_t *occ, float *hits, uint64_t *stats, uint8_t *outcome, int nthreads,
+              uint32_t hash_mode)
 {
     if (!bvh || bvh->num_nodes == 0) return -1;
     if (tags && (W < 1 || log2n < 1 || log2n > 31 || qo < 1 || qo > 10 || qd < 1 || qd > 10 || epoch < 1)) return -1;
+    if (tags && (hash_mode > 1 || (hash_mode == 1 && (qo > 7 || qd != qo)))) return -1;
     scene sc;
     sc.bvh = bvh;
     sc.vtx = vtx;
@@ -781,6 +816,7 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
     if (tags) {
         tb.tag = tags; tb.slot = slots; tb.W = W;
         hash_setup(&tb.h, bvh->box, qo, qd, log2n);
+        tb.h.mode = hash_mode;
         ptb = &tb;
     }
     if (nthreads > 0) omp_set_num_threads(nthreads);

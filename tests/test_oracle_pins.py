@@ -700,3 +700,69 @@ def test_update_rule_smallest_ray_id_owns_the_entry():
         assert st["conflicts"] == 25 - n_owner and st["tag_claims"] == 1
         want = [sq_leaf[1]] if owner == 24 else sorted([sq_leaf[0], sq_leaf[2]])
         assert [x for x in tb.slots[1].tolist() if x != NONE32] == want
+
+
+# ---------------------------------------------------------------------------
+# The paper's IEEE-754 bit hash (hash_mode 1)
+# ---------------------------------------------------------------------------
+
+def test_paper_hash_hand_cases():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_hash_cases.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append(line.split())
+    assert len(rows) == 2
+    for row in rows:
+        p = int(row[0])
+        o = [float(x) for x in row[1:4]]
+        d = [float(x) for x in row[4:7]]
+        key = int(row[13])
+        keys, idx = oracle.hash_rays(np.zeros(6, np.float32), p, p, 20, _ray(o, d), hash_mode=1)
+        assert int(keys[0]) == key
+        # the fold into the table is the same multiplicative hash as for the grid key
+        k0, i0 = int(keys[0]), int(idx[0])
+        assert i0 == ((k0 * 0x9E3779B97F4A7C15) % (1 << 64)) >> (64 - 20)
+
+
+def test_paper_hash_bit_fields_and_width():
+    g = np.random.default_rng(77)
+    for p in range(1, 8):
+        o = g.normal(size=(200, 3)).astype(np.float32) * 10
+        d = g.normal(size=(200, 3)).astype(np.float32)
+        rays = np.concatenate([o, np.zeros((200, 1)), d, np.ones((200, 1))], 1).astype(np.float32)
+        keys, _ = oracle.hash_rays(np.zeros(6, np.float32), p, p, 16, rays, hash_mode=1)
+        stride = 8 if p <= 3 else 16
+        mask = (1 << (2 * p + 1)) - 1
+        for k in keys[:50]:
+            k = int(k)
+            assert k < (1 << (3 * stride)) and k < (1 << 48)
+            for f in range(3):
+                assert (k >> (f * stride)) & ~mask & ((1 << stride) - 1) == 0   # 2p+1 bits per field
+        # a sign flip of o.x flips exactly the top bit of field 0
+        r2 = rays.copy()
+        r2[:, 0] = -r2[:, 0]
+        k2, _ = oracle.hash_rays(np.zeros(6, np.float32), p, p, 16, r2, hash_mode=1)
+        assert all(int(a) ^ int(b) == (1 << (2 * p)) for a, b in zip(keys, k2))
+        # similar rays (same exponent and leading mantissa bits) share a key
+        r3 = rays.copy()
+        r3[:, 0] = np.nextafter(r3[:, 0], np.float32(np.inf), dtype=np.float32)
+        k3, _ = oracle.hash_rays(np.zeros(6, np.float32), p, p, 16, r3, hash_mode=1)
+        same = np.count_nonzero(keys == k3)
+        assert same >= 190
+
+
+def test_paper_hash_trace_runs_and_keeps_invariants():
+    tris = sg.triangle_soup(1, 256)
+    rays = sg.tiny_shadow_rays(1, 4096)
+    b = oracle.build_sah(tris)
+    for p in (2, 4, 6):
+        tb = oracle.Table(12, 4, p, p, hash_mode=1)
+        out = np.zeros(4096, np.uint8)
+        occ, st = oracle.trace(b, tris, rays, table=tb, epoch=256, outcome=out)
+        _allowed_mismatch(tris, rays, occ != oracle.brute_force(tris, rays))
+        _check_table_invariants(tb, set(int(x) for x in b.leaf_ids()))
+        assert np.all(oracle.brute_force(tris, rays)[out == 2] == 1)
+    with pytest.raises(ValueError):
+        oracle.trace(b, tris, rays, table=oracle.Table(12, 4, 8, 8, hash_mode=1), epoch=256)
