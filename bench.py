@@ -58,9 +58,13 @@ def parse():
                     help="epoch rays of both predictors (default: the autotuned values of the workload)")
     ap.add_argument("--reference-epoch", type=int, default=1 << 17,
                     help="also time the HRPP step at this epoch size (0 = skip)")
-    ap.add_argument("--workload", default="at_scale", choices=["at_scale", "batched", "autotune", "serving"],
+    ap.add_argument("--workload", default="at_scale",
+                    choices=["at_scale", "batched", "autotune", "serving", "sweep"],
                     help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
                          "graph-captured batch")
+    ap.add_argument("--sweep-epoch", type=int, default=1 << 17,
+                    help="epoch of the table-size x precision sweep (incoherent AO rays)")
+    ap.add_argument("--sweep-modes", default="0,1", help="hash modes of the sweep (0 grid+octahedral, 1 IEEE bits)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
     ap.add_argument("--tune-knobs", default="epoch_rays,log2_entries,ways,origin_bits,dir_bits",
@@ -214,6 +218,9 @@ def main():
         return
     if args.workload == "serving":
         run_serving(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "sweep":
+        run_sweep(args, np, torch, hrpp, sg)
         return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
@@ -535,6 +542,93 @@ def run_autotune(args, np, torch, hrpp, sg):
     print(json.dumps({"metric": "autotuned predictor configuration (min trace time)", "config": {
         "workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) / shadow any-hit", "knobs": list(knobs)},
         "results": res}), flush=True)
+
+
+def run_sweep(args, np, torch, hrpp, sg):
+    """Loose versus tight hashing on incoherent rays: the 1280x720 x 8 AO rays
+    of the terrain scene traced with a hit-any predictor of 2^T entries x 8
+    leaves, T in 16..22, at precision q in 3..7 (q_o = q_d = q for the grid +
+    octahedral hash, p = q for the IEEE-754 bit hash), epoch 2^17.  Each point:
+    median time of 3 (reset + trace), counters of one more run, and the table
+    afterwards (entries in use, leaves per used entry).  The oracle is timed at
+    the corner and default points of each mode as the CPU baseline."""
+    wi = sg.INCOHERENT
+    log("generating the incoherent AO workload")
+    tris, _ = sg.terrain_scene(sg.AT_SCALE["seed"])
+    bvh = hrpp.BVH(tris)
+    cam_rays, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+    cam_d = torch.from_numpy(cam_rays).cuda()
+    hh = hrpp.trace_closest(bvh, None, cam_d, mode="exact").cpu().numpy()
+    ao = sg.ao_rays_from_hits(tris, cam_rays, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                              samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+    n = ao.shape[0]
+    ao_d = torch.from_numpy(ao).cuda()
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = hrpp.new_stats()
+    ms_plain = timed(torch, lambda: hrpp.trace_anyhit(bvh, None, ao_d, out=out), 5, 1)[0]
+    hrpp.trace_anyhit(bvh, None, ao_d, out=out, stats=st)
+    torch.cuda.synchronize()
+    plain = hrpp.stats_dict(st)
+    modes = [int(m) for m in args.sweep_modes.split(",") if m]
+    points = []
+    for mode in modes:
+        for T in range(16, 23):
+            for q in range(3, 8):
+                cfg = dict(log2_entries=T, ways=8, origin_bits=q, dir_bits=q, epoch_rays=args.sweep_epoch,
+                           hash_mode=mode)
+                pred = hrpp.Predictor(bvh, **cfg)
+
+                def run(stats=None):
+                    pred.reset()
+                    hrpp.trace_anyhit(bvh, pred, ao_d, out=out, stats=stats)
+
+                ms = timed(torch, run, 3, 1)[0]
+                st = hrpp.new_stats()
+                run(st)
+                torch.cuda.synchronize()
+                d = hrpp.stats_dict(st)
+                tags, slots = pred.export()
+                used = tags != np.uint64(0xFFFFFFFFFFFFFFFF)
+                n_used = int(np.count_nonzero(used))
+                leaves = int(np.count_nonzero(slots[used] != np.uint32(0xFFFFFFFF)))
+                points.append(dict(
+                    hash_mode=mode, log2_entries=T, q=q, ms=round(ms, 4), mrays_s=round(n / (ms * 1e-3) / 1e6, 1),
+                    pct_nodes_skipped=round(100.0 * (1 - d["nodes_visited"] / plain["nodes_visited"]), 3),
+                    pct_box_tests_skipped=round(100.0 * (1 - d["box_tests"] / plain["box_tests"]), 3),
+                    prediction_hit_rate=round(d["pred_hits"] / n, 4),
+                    false_positive_rate=round(d["false_pos"] / n, 4),
+                    entries_used=n_used, leaves_per_used_entry=round(leaves / max(n_used, 1), 3),
+                    table_mb=round(pred.table_bytes / 2**20, 1), conflicts=d["conflicts"],
+                    dropped_leaves=d["dropped"]))
+                log(f"sweep mode {mode} T {T} q {q}: {points[-1]['mrays_s']} Mrays/s, "
+                    f"{points[-1]['pct_nodes_skipped']}% skipped, {n_used} entries")
+                del pred
+    hrpp.get_error(bvh)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ob = oracle.build_sah(tris)
+        vtx = oracle.bvh_vertices(tris, ob)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        sample_pts = [(m, T, q) for m in modes for (T, q) in ((16, 3), (16, 7), (22, 3), (22, 7), (20, 5))]
+        tot = 0.0
+        for m, T, q in sample_pts:
+            tb = oracle.Table(T, 8, q, q, hash_mode=m)
+            c0 = time.perf_counter()
+            oracle.trace(ob, tris, ao, query="any", table=tb, epoch=args.sweep_epoch, vtx=vtx, nthreads=threads)
+            tot += time.perf_counter() - c0
+        cpu = {"value": round(n * len(sample_pts) / tot / 1e6, 3), "unit": "Mrays/s", "cores": threads,
+               "kind": "oracle", "sample": f"{len(sample_pts)} sweep points (corners and T 20 / q 5 of each hash mode), "
+                                           f"{n} AO rays each, {tot:.1f} s in all"}
+    print(json.dumps({
+        "metric": "incoherent AO: Mrays/s and % nodes skipped versus table size and hash precision",
+        "unit": "Mrays/s", "dtype": "f32", "data": "synthetic", "higher_is_better": True,
+        "config": {"workload": f"terrain 1M tris, 1280x720 x 8 AO rays ({n}), any hit, tmax 0.05 x diagonal, "
+                               f"hit-any predictor W 8, epoch {args.sweep_epoch}",
+                   "hash_modes": {"0": "grid origin + octahedral direction, q_o = q_d = q",
+                                  "1": "IEEE-754 sign / exponent / mantissa bits, precision q"}},
+        "plain_mrays_s": round(n / (ms_plain * 1e-3) / 1e6, 1), "plain_nodes_visited": plain["nodes_visited"],
+        "points": points, "cpu_baseline": cpu}), flush=True)
 
 
 def run_serving(args, np, torch, hrpp, sg):

@@ -68,7 +68,17 @@ typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
  *  dir_bits      q_d: octahedral direction bins per axis = 2^q_d, 1..10
  *  epoch_rays    E: rays per epoch; rays of epoch k see the table as it stood
  *                after epoch k-1 (batch-synchronous update), 1..2^22
- *  hash_mode     0 = grid origin + octahedral direction (the only mode built)
+ *  hash_mode     0 = grid origin cells (q_o bits per axis over the scene bounds)
+ *                    + octahedral direction bins (q_d bits per axis);
+ *                1 = the bit-field hash of section "HRPP Hash Function": per
+ *                    binary32 value of origin and direction the sign, the p
+ *                    leading exponent and p leading mantissa bits, fields
+ *                    o.x^d.z, o.y^d.y, o.z^d.x packed at a stride of 8 bits
+ *                    (p <= 3) or 16 bits (p >= 4); p = origin_bits in 1..7
+ *                    and dir_bits must equal origin_bits.  The scene bounds
+ *                    play no part in this mode.
+ *                Both modes fold the key into the index with
+ *                (key * 0x9E3779B97F4A7C15) >> (64 - T) and store it as the tag.
  *  go_up_level   0 = predict leaves (the only level built) */
 typedef struct {
     uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level;
@@ -167,7 +177,8 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc);
 
 /* Create a predictor bound to `bvh` (its hash grid spans the BVH's root
  * box) in d_buf (256-byte aligned), and enqueue its reset on `stream`.
- * Errors: EINVAL (bad desc, hash_mode or go_up_level other than 0),
+ * Errors: EINVAL (bad desc, hash_mode above 1 or a mode-1 precision out of
+ * range, go_up_level other than 0),
  * ENOMEM (bytes too small). */
 hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf,
                                   size_t bytes, void *stream, hrpp_predictor **out);

@@ -37,7 +37,8 @@ uint32_t max_persistent_blocks() {
 bool desc_ok(const hrpp_predictor_desc *d) {
     return d && d->log2_entries >= 1 && d->log2_entries <= 26 && d->ways >= 1 && d->ways <= 8 &&
            d->origin_bits >= 1 && d->origin_bits <= 10 && d->dir_bits >= 1 && d->dir_bits <= 10 &&
-           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->hash_mode == 0 && d->go_up_level == 0;
+           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level == 0 &&
+           (d->hash_mode == 0 || (d->hash_mode == 1 && d->origin_bits <= 7 && d->dir_bits == d->origin_bits));
 }
 
 uint32_t entry_bytes_for(uint32_t ways) { return ways <= 4 ? 32u : 64u; }
@@ -331,6 +332,8 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.hash.qo = d.origin_bits;
         a.hash.qd = d.dir_bits;
         a.hash.log2n = d.log2_entries;
+        a.hash.mode = d.hash_mode;
+        a.hash.stride = d.origin_bits <= 3 ? 8u : 16u;
         a.ctrl = pred->d_ctrl;
         a.queue = pred->d_queue;
         a.queue_subcap = queue_subcap_for(d.epoch_rays);

@@ -16,6 +16,8 @@ struct HashArgs {
     float maxd;         // 2^qd - 1
     float half;         // 2^(qd - 1)
     uint32_t qo, qd, log2n;
+    uint32_t mode;      // 0 grid + octahedral; 1 IEEE-754 bit fields at precision qo
+    uint32_t stride;    // mode 1: field stride of the key, 8 or 16 bits
 };
 
 constexpr uint32_t kSubQueues = 8;     // striped fallback sub-queues per epoch

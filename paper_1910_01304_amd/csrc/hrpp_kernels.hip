@@ -96,7 +96,25 @@ __device__ __forceinline__ uint32_t quantize(float x, float maxcell) {
 // 2^qd x 2^qd octahedral map, packed into a key and folded into the table
 // index by Fibonacci hashing (the section "HRPP Hash Function" asks for a
 // hash that sends similar rays to the same entry).
+// Mode 1 is the section's own encoding: per binary32 value the sign, the p
+// leading exponent bits and the p leading mantissa bits (2p+1 bits, sign
+// highest); origin and direction values are paired by XOR as (o.x, d.z),
+// (o.y, d.y), (o.z, d.x) and the three fields packed at a stride of 8 or 16.
+__device__ __forceinline__ uint32_t ieee_bits(float x, uint32_t p) {
+    const uint32_t u = __float_as_uint(x);
+    return ((u >> 31) << (2 * p)) | ((((u >> 23) & 0xFFu) >> (8 - p)) << p) | ((u & 0x7FFFFFu) >> (23 - p));
+}
+
 __device__ __forceinline__ void hash_ray(const HashArgs &h, const RayState &r, uint64_t &key, uint32_t &idx) {
+    if (h.mode == 1) {
+        const uint32_t p = h.qo;
+        const uint64_t f0 = ieee_bits(r.ox, p) ^ ieee_bits(r.dz, p);
+        const uint64_t f1 = ieee_bits(r.oy, p) ^ ieee_bits(r.dy, p);
+        const uint64_t f2 = ieee_bits(r.oz, p) ^ ieee_bits(r.dx, p);
+        key = f0 | (f1 << h.stride) | (f2 << (2 * h.stride));
+        idx = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64u - h.log2n));
+        return;
+    }
     const float maxo = h.maxo, maxd = h.maxd, half = h.half;
     uint32_t cx = quantize((r.ox - h.bmin[0]) * h.scale[0], maxo);
     uint32_t cy = quantize((r.oy - h.bmin[1]) * h.scale[1], maxo);

@@ -81,8 +81,13 @@ def test_host_argument_validation():
     assert lib.hrpp_predictor_required_bytes(C.byref(pd)) > (1 << 12) * 32
     assert lib.hrpp_predictor_table_bytes(C.byref(pd)) == (1 << 12) * 32
     for badp in (hrpp.hrpp._PredDesc(0, 4, 5, 6, 256, 0, 0), hrpp.hrpp._PredDesc(12, 9, 5, 6, 256, 0, 0),
-                 hrpp.hrpp._PredDesc(12, 4, 5, 6, 0, 0, 0), hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 2, 0)):
+                 hrpp.hrpp._PredDesc(12, 4, 5, 6, 0, 0, 0), hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 2, 0),
+                 # the bit-field hash: precision 1..7 and dir_bits equal to origin_bits
+                 hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 1, 0), hrpp.hrpp._PredDesc(12, 4, 8, 8, 256, 1, 0),
+                 hrpp.hrpp._PredDesc(12, 4, 0, 0, 256, 1, 0)):
         assert lib.hrpp_predictor_required_bytes(C.byref(badp)) == 0
+    for p in range(1, 8):
+        assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, p, p, 256, 1, 0))) > 0
     assert lib.hrpp_status_string(4) == b"BVH deeper than max_depth"
 
 

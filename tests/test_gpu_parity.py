@@ -76,9 +76,11 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
     vtx = oracle.bvh_vertices(tris, ob)
     pred = tb = None
     if pred_cfg is not None:
-        T, W, qo, qd, E = pred_cfg
-        pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E)
-        tb = oracle.Table(T, W, qo, qd)
+        T, W, qo, qd, E = pred_cfg[:5]
+        hm = pred_cfg[5] if len(pred_cfg) > 5 else 0
+        pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E,
+                              hash_mode=hm)
+        tb = oracle.Table(T, W, qo, qd, hash_mode=hm)
     gst = hrpp.new_stats()
     for c in range(calls):
         got, gs = gpu_run(hrpp, bvh, rays, query, mode, pred, gst)
@@ -165,6 +167,29 @@ def test_terrain_table_shapes(hrpp, small_terrain, cfg):
     tris, prim = small_terrain
     check_case(hrpp, f"terrain table {cfg}", tris, prim[:20000], query="closest", mode="paper", pred_cfg=cfg)
     check_case(hrpp, f"terrain table {cfg} exact", tris, prim[:20000], query="closest", mode="exact", pred_cfg=cfg)
+
+
+# ---------------------------------------------------------------------------
+# The paper's IEEE-754 bit hash (hash mode 1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 7])
+def test_tiny_paper_hash(hrpp, p):
+    tris, rays = sg.tiny_workload()
+    check_case(hrpp, f"tiny paper hash p={p}", tris, rays, pred_cfg=(12, 4, p, p, 300, 1), calls=2)
+
+
+def test_terrain_paper_hash(hrpp, small_terrain):
+    tris, prim = small_terrain
+    _, st = check_case(hrpp, "terrain primary paper hash p=6", tris, prim, query="closest", mode="paper",
+                       pred_cfg=(14, 8, 6, 6, 4096, 1))
+    assert st["pred_hits"] > 0
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=2)
+    check_case(hrpp, "terrain shadow paper hash p=5", tris, shadow, pred_cfg=(14, 8, 5, 5, 4096, 1))
+    check_case(hrpp, "terrain closest exact paper hash p=3", tris, prim[:20000], query="closest",
+               mode="exact", pred_cfg=(10, 2, 3, 3, 1000, 1))
 
 
 # ---------------------------------------------------------------------------
@@ -259,6 +284,25 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
                                       light_center=w["light_center"], light_size=w["light_size"])
     check_case(hrpp, "full shadow plain", tris, shadow)
     check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any)
+
+
+@pytest.mark.parametrize("cfg", [
+    (20, 8, 5, 6, 1 << 19, 0),     # the benchmark's AO predictor
+    (16, 8, 3, 3, 1 << 17, 1),     # sweep corners, the IEEE-754 bit hash
+    (22, 8, 7, 7, 1 << 17, 1),
+])
+def test_full_size_ao(hrpp, full_terrain, cfg):
+    # the incoherent workload: 1280x720 primaries x 8 AO rays (7,372,800)
+    wi = sg.INCOHERENT
+    tris, _ = full_terrain
+    cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+    ob = oracle.build_sah(tris)
+    hh, _ = oracle.trace(ob, tris, cam, query="closest", mode="exact")
+    ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                              samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+    assert ao.shape[0] == 7372800
+    _, st = check_case(hrpp, f"full AO {cfg}", tris, ao, pred_cfg=cfg)
+    assert st["rays"] == 7372800
 
 
 def test_results_do_not_depend_on_stats(hrpp, small_terrain):
