@@ -133,10 +133,13 @@ class Table:
 
     ``hash_mode`` 0: grid origin + octahedral direction (qo, qd bits);
     1: the paper's IEEE-754 bit hash with precision qo in 1..7 (qd must equal qo).
+    ``go_up`` 0: slots hold leaf ids; g >= 1: canonical node indices of the
+    node g levels above the result leaf (the root if the leaf is shallower).
     """
 
-    def __init__(self, log2n: int, ways: int, qo: int, qd: int, hash_mode: int = 0):
+    def __init__(self, log2n: int, ways: int, qo: int, qd: int, hash_mode: int = 0, go_up: int = 0):
         self.log2n, self.W, self.qo, self.qd, self.hash_mode = log2n, ways, qo, qd, hash_mode
+        self.go_up = go_up
         self.tags = np.full(1 << log2n, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64)
         self.slots = np.full((1 << log2n, ways), NONE32, np.uint32)
 
@@ -145,7 +148,7 @@ class Table:
         self.slots[:] = NONE32
 
     def copy(self) -> "Table":
-        t = Table(self.log2n, self.W, self.qo, self.qd, self.hash_mode)
+        t = Table(self.log2n, self.W, self.qo, self.qd, self.hash_mode, self.go_up)
         t.tags[:] = self.tags
         t.slots[:] = self.slots
         return t
@@ -176,14 +179,14 @@ def trace(bvh: CanonBVH, tris: np.ndarray, rays: np.ndarray, query: str = "any",
     s = bvh._struct()
     if table is not None:
         tg, sl, l2, W, qo, qd = table.tags, table.slots, table.log2n, table.W, table.qo, table.qd
-        hm = table.hash_mode
+        hm, gu = table.hash_mode, table.go_up
     else:
         tg = sl = None
-        l2 = W = qo = qd = hm = 0
+        l2 = W = qo = qd = hm = gu = 0
     rc = _L().orc_trace(C.byref(s), _p(vtx), _p(rays), C.c_uint32(n), C.c_int(1 if closest else 0),
                         C.c_int(1 if mode == "exact" else 0), _p(tg), _p(sl), C.c_uint32(l2), C.c_uint32(W),
                         C.c_uint32(qo), C.c_uint32(qd), C.c_uint32(epoch), _p(occ), _p(hits), _p(stats),
-                        _p(outcome), C.c_int(nthreads), C.c_uint32(hm))
+                        _p(outcome), C.c_int(nthreads), C.c_uint32(hm), C.c_uint32(gu))
     if rc != 0:
         raise ValueError("oracle trace rejected its arguments")
     return (hits if closest else occ), stats_dict(stats)

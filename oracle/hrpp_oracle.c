@@ -502,8 +502,10 @@ int orc_slab(const float *box6, const float *ray8, float tcur, float *tnear)
 typedef struct {
     const orc_bvh *bvh;
     const float *vtx;          /* 9 floats per BVH-ordered triangle */
-    const uint32_t *leaf_depth_by_first; /* depth of the leaf starting at triangle k */
     const uint32_t *leaf_node_by_first;  /* node index of the leaf starting at triangle k */
+    const uint32_t *parent;    /* parent node of each node (NONE32 for the root) */
+    const uint32_t *sub_lo;    /* BVH-ordered triangle range [sub_lo, sub_end) */
+    const uint32_t *sub_end;   /*   of each node's subtree */
 } scene;
 
 typedef struct {
@@ -540,16 +542,11 @@ static int test_leaf(const scene *sc, uint32_t first, uint32_t count, const floa
     return changed;
 }
 
-/* Plain stack traversal.  Order fully fixed:
-   root box tested first (one box test); at an interior node both child
-   boxes are tested against [tmin, tcur] (two box tests); with both hit,
-   the child with the smaller entry distance is visited first (left on a
-   tie) and the other is pushed with its entry distance; a popped node is
-   visited only if its stored entry distance still passes the slab
-   criterion against the current tcur (tnear <= tcur * (1 + 3*2^-23), which
-   is exactly the slab test re-run with the shrunken interval).  Leaves test
-   their triangles in BVH order.  Any-hit stops at the first hit. */
-static int traverse(const scene *sc, const float *r, const float *inv, int closest, best_hit *b, uint64_t *st)
+/* Walk the subtree of `node`, whose own box the caller has already tested
+   against [tmin, tcur].  With node = root this is the whole traversal; a
+   predicted node ("Go Up Level") is walked the same way. */
+static int walk(const scene *sc, uint32_t node, const float *r, const float *inv, int closest, best_hit *b,
+                uint64_t *st)
 {
     const orc_bvh *bvh = sc->bvh;
     uint32_t stack_node[128];
@@ -557,14 +554,8 @@ static int traverse(const scene *sc, const float *r, const float *inv, int close
     int sp = 0;
     float tmin = r[3];
     float tcur = closest ? (b->prim != NONE32 ? b->t : r[7]) : r[7];
-    float tn;
     int found = (b->prim != NONE32);
     const float pad = bits_to_float(0x3F800003u);
-
-    st[S_TRAVERSALS]++;
-    st[S_BOX_TESTS]++;
-    if (!slab(bvh->box, r, inv, tmin, tcur, &tn)) return found;
-    uint32_t node = 0;
     for (;;) {
         st[S_NODES_VISITED]++;
         if (bvh->right[node] != NONE32) {
@@ -599,6 +590,34 @@ static int traverse(const scene *sc, const float *r, const float *inv, int close
     }
 }
 
+/* Plain stack traversal.  Order fully fixed:
+   root box tested first (one box test); at an interior node both child
+   boxes are tested against [tmin, tcur] (two box tests); with both hit,
+   the child with the smaller entry distance is visited first (left on a
+   tie) and the other is pushed with its entry distance; a popped node is
+   visited only if its stored entry distance still passes the slab
+   criterion against the current tcur (tnear <= tcur * (1 + 3*2^-23), which
+   is exactly the slab test re-run with the shrunken interval).  Leaves test
+   their triangles in BVH order.  Any-hit stops at the first hit. */
+static int traverse(const scene *sc, const float *r, const float *inv, int closest, best_hit *b, uint64_t *st)
+{
+    float tcur = closest ? (b->prim != NONE32 ? b->t : r[7]) : r[7];
+    float tn;
+    st[S_TRAVERSALS]++;
+    st[S_BOX_TESTS]++;
+    if (!slab(sc->bvh->box, r, inv, r[3], tcur, &tn)) return b->prim != NONE32;
+    return walk(sc, 0, r, inv, closest, b, st);
+}
+
+/* The node a record names at go-up level g: the leaf holding the result, or
+   its ancestor g levels up (the root if the leaf has fewer ancestors). */
+static uint32_t predicted_node_of(const scene *sc, uint32_t leaf, uint32_t go_up)
+{
+    uint32_t node = sc->leaf_node_by_first[leaf >> 3];
+    for (uint32_t k = 0; k < go_up && sc->parent[node] != NONE32; k++) node = sc->parent[node];
+    return node;
+}
+
 /* ======================================================================== */
 /* HRPP per ray ("Overview" direct flow; "Precision and Recall")            */
 /* ======================================================================== */
@@ -609,6 +628,7 @@ typedef struct {
     uint64_t *tag;      /* [N] */
     uint32_t *slot;     /* [N * W] */
     uint32_t W;
+    uint32_t go_up;     /* 0: slots hold leaf ids; g >= 1: node indices g levels above the leaf */
     hash_params h;
 } table;
 
@@ -642,33 +662,38 @@ static void trace_one(const scene *sc, const table *tb, const float *r, int quer
         st[S_LOOKUPS]++;
         const uint32_t *slots = tb->slot + (size_t)idx * tb->W;
         int positive = (tb->tag[idx] == key && slots[0] != NONE32);
+        uint32_t skip_depth = 0;
         if (positive) {
             st[S_POSITIVES]++;
-            uint64_t tri_before = st[S_TRI_TESTS];
-            /* evaluate the predicted leaves in slot order: a leaf's box is
+            uint64_t box_before = st[S_BOX_TESTS], leaf_before = st[S_LEAF_VISITED], tri_before = st[S_TRI_TESTS];
+            /* evaluate the predicted nodes in slot order: a node's box is
                tested against [tmin, tcur] (tcur = tmax, or the best hit so
-               far for closest hit) and its triangles only if the box is hit */
+               far for closest hit) and, if hit, its subtree is walked (a
+               predicted leaf: its triangles).  The interior nodes above the
+               node that produced the result count as skipped. */
             for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) {
-                uint32_t first = slots[s] >> 3, count = (slots[s] & 7u) + 1u;
+                uint32_t node = tb->go_up ? slots[s] : sc->leaf_node_by_first[slots[s] >> 3];
                 float tn;
                 float tcur = (closest && b.prim != NONE32) ? b.t : r[7];
                 st[S_BOX_TESTS]++;
-                st[S_PRED_BOX_TESTS]++;
-                if (!slab(sc->bvh->box + 6 * (size_t)sc->leaf_node_by_first[first], r, inv, r[3], tcur, &tn)) continue;
-                st[S_NODES_VISITED]++;
-                st[S_LEAF_VISITED]++;
-                st[S_PRED_LEAF_VISITED]++;
-                if (test_leaf(sc, first, count, r, closest, &b, st)) {
+                if (!slab(sc->bvh->box + 6 * (size_t)node, r, inv, r[3], tcur, &tn)) continue;
+                float bt = b.t;
+                uint32_t bp = b.prim;
+                int f = walk(sc, node, r, inv, closest, &b, st);
+                if (b.prim != bp || b.t != bt) skip_depth = sc->bvh->depth[node];
+                if (f) {
                     hit = 1;
                     if (!closest) break;
                 }
             }
+            st[S_PRED_BOX_TESTS] += st[S_BOX_TESTS] - box_before;
+            st[S_PRED_LEAF_VISITED] += st[S_LEAF_VISITED] - leaf_before;
             st[S_PRED_TRI_TESTS] += st[S_TRI_TESTS] - tri_before;
         }
         if (positive && hit && !(closest && cmode == C_EXACT)) {
             /* true positive: interior traversal skipped */
             st[S_PRED_HITS]++;
-            st[S_NODES_SKIPPED] += sc->leaf_depth_by_first[b.leaf >> 3];
+            st[S_NODES_SKIPPED] += skip_depth;
             if (outcome) *outcome = OUT_PRED_HIT;
         } else {
             if (positive && !(closest && cmode == C_EXACT)) st[S_FALSE_POS]++;
@@ -682,16 +707,21 @@ static void trace_one(const scene *sc, const table *tb, const float *r, int quer
                 found = traverse(sc, r, inv, closest, &b, st);
             }
             if (closest && cmode == C_EXACT && positive) {
-                /* success iff the final best lies in a predicted leaf */
+                /* success iff the final best lies in a predicted leaf, or in
+                   the subtree of a predicted node */
                 int in_pred = 0;
-                for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) if (found && slots[s] == b.leaf) in_pred = 1;
+                for (uint32_t s = 0; s < tb->W && slots[s] != NONE32; s++) {
+                    uint32_t node = tb->go_up ? slots[s] : sc->leaf_node_by_first[slots[s] >> 3];
+                    if (found && sc->sub_lo[node] <= (b.leaf >> 3) && (b.leaf >> 3) < sc->sub_end[node]) in_pred = 1;
+                }
                 if (in_pred) st[S_PRED_HITS]++; else st[S_FALSE_POS]++;
                 if (outcome) *outcome = in_pred ? OUT_PRED_HIT : OUT_FALSE_POS;
                 (void)seed_leaf;
             }
             hit = found;
             if (found) {
-                rec->has = 1; rec->idx = idx; rec->key = key; rec->leaf = b.leaf;
+                rec->has = 1; rec->idx = idx; rec->key = key;
+                rec->leaf = tb->go_up ? predicted_node_of(sc, b.leaf, tb->go_up) : b.leaf;
                 st[S_RECORDS]++;
             }
         }
@@ -798,23 +828,41 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
 int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t n, int query, int cmode,
               uint64_t *tags, uint32_t *slots, uint32_t log2n, uint32_t W, uint32_t qo, uint32_t qd,
               uint32_t epoch, uint8_t *occ, float *hits, uint64_t *stats, uint8_t *outcome, int nthreads,
-              uint32_t hash_mode)
+              uint32_t hash_mode, uint32_t go_up)
 {
     if (!bvh || bvh->num_nodes == 0) return -1;
     if (tags && (W < 1 || log2n < 1 || log2n > 31 || qo < 1 || qo > 10 || qd < 1 || qd > 10 || epoch < 1)) return -1;
     if (tags && (hash_mode > 1 || (hash_mode == 1 && (qo > 7 || qd != qo)))) return -1;
+    if (tags && go_up > 64) return -1;
     scene sc;
     sc.bvh = bvh;
     sc.vtx = vtx;
-    uint32_t *ldepth = (uint32_t *)malloc(sizeof(uint32_t) * (bvh->num_tris + 1));
+    uint32_t m = bvh->num_nodes;
     uint32_t *lnode = (uint32_t *)malloc(sizeof(uint32_t) * (bvh->num_tris + 1));
-    for (uint32_t i = 0; i < bvh->num_nodes; i++)
-        if (bvh->right[i] == NONE32) { ldepth[bvh->first[i]] = bvh->depth[i]; lnode[bvh->first[i]] = i; }
-    sc.leaf_depth_by_first = ldepth;
+    uint32_t *parent = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    uint32_t *sub_lo = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    uint32_t *sub_end = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    for (uint32_t i = 0; i < m; i++) parent[i] = NONE32;
+    for (uint32_t i = 0; i < m; i++) {
+        if (bvh->right[i] == NONE32) lnode[bvh->first[i]] = i;
+        else { parent[i + 1] = i; parent[bvh->right[i]] = i; }
+    }
+    /* children follow their parent in pre-order: a reverse sweep sees them first */
+    for (uint32_t i = m; i-- > 0;) {
+        if (bvh->right[i] == NONE32) { sub_lo[i] = bvh->first[i]; sub_end[i] = bvh->first[i] + bvh->count[i]; }
+        else {
+            uint32_t L = i + 1, R = bvh->right[i];
+            sub_lo[i] = sub_lo[L] < sub_lo[R] ? sub_lo[L] : sub_lo[R];
+            sub_end[i] = sub_end[L] > sub_end[R] ? sub_end[L] : sub_end[R];
+        }
+    }
     sc.leaf_node_by_first = lnode;
+    sc.parent = parent;
+    sc.sub_lo = sub_lo;
+    sc.sub_end = sub_end;
     table tb, *ptb = NULL;
     if (tags) {
-        tb.tag = tags; tb.slot = slots; tb.W = W;
+        tb.tag = tags; tb.slot = slots; tb.W = W; tb.go_up = go_up;
         hash_setup(&tb.h, bvh->box, qo, qd, log2n);
         tb.h.mode = hash_mode;
         ptb = &tb;
@@ -843,8 +891,10 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
         for (int s = 0; s < STATS_SLOTS; s++) stats[s] += acc[s];
     }
     free(recs);
-    free(ldepth);
     free(lnode);
+    free(parent);
+    free(sub_lo);
+    free(sub_end);
     return 0;
 }
 

@@ -766,3 +766,210 @@ def test_paper_hash_trace_runs_and_keeps_invariants():
         assert np.all(oracle.brute_force(tris, rays)[out == 2] == 1)
     with pytest.raises(ValueError):
         oracle.trace(b, tris, rays, table=oracle.Table(12, 4, 8, 8, hash_mode=1), epoch=256)
+
+
+# ---------------------------------------------------------------------------
+# Go Up Level (slots name the node g levels above the result leaf)
+# ---------------------------------------------------------------------------
+
+def _parents(b):
+    par = np.full(b.num_nodes, NONE32, np.int64)
+    for i in range(b.num_nodes):
+        if b.right[i] != NONE32:
+            par[i + 1] = i
+            par[int(b.right[i])] = i
+    return par
+
+
+def _ancestor(par, node, g):
+    for _ in range(g):
+        if par[node] == NONE32:
+            break
+        node = int(par[node])
+    return node
+
+
+def test_go_up_hand_tree_slots_and_counters():
+    # root(0) -> [inner(1) -> leaf A(2), leaf C(3)], leaf B(4); two identical
+    # rays down onto A, one epoch per ray: ray 0 traverses and records, ray 1
+    # is predicted
+    tris = np.concatenate([_square(0, 0, 0), _square(0, 0, -1), _square(2, 0, 0)])
+    b = _hand_bvh(tris, [(4, 0, 0, 0), (3, 0, 0, 1), (NONE32, 0, 2, 2), (NONE32, 2, 2, 2), (NONE32, 4, 2, 1)])
+    down = _ray([0.75, 1, 0.25], [0, -1, 0])
+    rays = np.stack([down, down])
+    plain = dict(box_tests=5, nodes_visited=3, interior_visited=2, leaf_visited=1, tri_tests=1)
+    for g, slot, pred in ((0, 0 << 3 | 1, dict(box_tests=1, nodes_visited=1, interior_visited=0, leaf_visited=1,
+                                                 tri_tests=1, skipped=2)),
+                          # parent of A: test node 1's box, then node 1 (A and C both hit, A nearer), A
+                          (1, 1, dict(box_tests=3, nodes_visited=2, interior_visited=1, leaf_visited=1,
+                                      tri_tests=1, skipped=1)),
+                          # the root: the walk is the whole traversal, nothing skipped
+                          (2, 0, dict(box_tests=5, nodes_visited=3, interior_visited=2, leaf_visited=1,
+                                      tri_tests=1, skipped=0)),
+                          (9, 0, dict(box_tests=5, nodes_visited=3, interior_visited=2, leaf_visited=1,
+                                      tri_tests=1, skipped=0))):
+        tb = oracle.Table(4, 2, 3, 3, go_up=g)
+        out = np.zeros(2, np.uint8)
+        occ, st = oracle.trace(b, tris, rays, table=tb, epoch=1, outcome=out)
+        assert occ.tolist() == [1, 1] and out.tolist() == [1, 2]
+        used = np.nonzero(tb.tags != EMPTY_TAG)[0]
+        assert len(used) == 1 and tb.slots[used[0]].tolist() == [slot, NONE32]
+        for k in ("box_tests", "nodes_visited", "interior_visited", "leaf_visited", "tri_tests"):
+            assert st[k] == plain[k] + pred[k], (g, k)
+        assert st["nodes_skipped"] == pred["skipped"] and st["traversals"] == 1 and st["pred_hits"] == 1
+        assert st["pred_box_tests"] == pred["box_tests"] and st["pred_leaf_visited"] == 1
+        assert st["pred_tri_tests"] == 1
+    # a ray onto B (depth 1): at go-up 1 its parent is the root
+    onto_b = _ray([2.75, 1, 0.25], [0, -1, 0])
+    tb = oracle.Table(4, 2, 3, 3, go_up=1)
+    oracle.trace(b, tris, onto_b[None], table=tb, epoch=1)
+    assert tb.slots[tb.tags != EMPTY_TAG][0].tolist() == [0, NONE32]
+
+
+def test_go_up_records_name_ancestors_of_exact_hits():
+    # one epoch, EXACT closest: every hitting ray records the leaf of its exact
+    # closest triangle (brute force), mapped g levels up; the table must be
+    # what the update rule makes of those records, rebuilt here from scratch
+    tris = sg.triangle_soup(5, 300, edge=0.12)
+    g0 = np.random.default_rng(5)
+    o = np.tile([[0.5, -0.5, 0.5]], (3000, 1)) + g0.uniform(-0.1, 0.1, (3000, 3))
+    d = np.tile([[0.0, 1.0, 0.0]], (3000, 1)) + g0.uniform(-0.4, 0.4, (3000, 3))
+    rays = sg.pack_rays(o.astype(np.float32), d.astype(np.float32), 0.0, np.inf)
+    b = oracle.build_sah(tris)
+    par = _parents(b)
+    leaf_node_of_pos = {}
+    for i in np.nonzero(b.right == NONE32)[0]:
+        for k in range(int(b.first[i]), int(b.first[i] + b.count[i])):
+            leaf_node_of_pos[k] = int(i)
+    pos_of_prim = {int(p): k for k, p in enumerate(b.perm)}
+    exact = oracle.brute_force(tris, rays, closest=True)
+    T, W = 6, 3
+    keys, idx = oracle.hash_rays(b.box[0], 3, 3, T, rays)
+    for g in (1, 2, 3, 40):
+        tb = oracle.Table(T, W, 3, 3, go_up=g)
+        _, st = oracle.trace(b, tris, rays, query="closest", mode="exact", table=tb, epoch=rays.shape[0])
+        want_tags = np.full(1 << T, EMPTY_TAG, np.uint64)
+        want_slots = np.full((1 << T, W), NONE32, np.uint32)
+        groups = {}
+        for r in range(rays.shape[0]):
+            prim = int(exact[r, 3].view(np.uint32))
+            if prim != NONE32:
+                node = _ancestor(par, leaf_node_of_pos[pos_of_prim[prim]], g)
+                groups.setdefault(int(idx[r]), []).append((r, int(keys[r]), node))
+        drops = conflicts = 0
+        for i, recs in groups.items():
+            kstar = recs[0][1]
+            fresh = sorted({n for _, k, n in recs if k == kstar})
+            want_tags[i] = kstar
+            want_slots[i, :min(W, len(fresh))] = fresh[:W]
+            drops += sum(1 for _, k, n in recs if k == kstar and n not in fresh[:W])
+            conflicts += sum(1 for _, k, _n in recs if k != kstar)
+        assert np.array_equal(tb.tags, want_tags), g
+        assert np.array_equal(tb.slots, want_slots), g
+        assert st["dropped"] == drops and st["conflicts"] == conflicts and st["tag_claims"] == len(groups)
+        if g == 40:
+            assert set(tb.slots[tb.tags != EMPTY_TAG][:, 0].tolist()) == {0}
+
+
+def test_go_up_root_walk_equals_plain_traversal():
+    # with every slot naming the root, a positive ray's walk is exactly the
+    # plain traversal: its counts are the plain ones (without the traversal
+    # count); a false positive then traverses again
+    tris, rays, b, tb, _, _, _ = _config1(4096, table=oracle.Table(12, 4, 5, 6, go_up=64))
+    assert set(tb.slots[tb.tags != EMPTY_TAG][:, 0].tolist()) == {0}
+    out = np.zeros(rays.shape[0], np.uint8)
+    occ, st = oracle.trace(b, tris, rays, table=tb, epoch=4096, outcome=out)
+    assert np.array_equal(occ, oracle.brute_force(tris, rays))
+    _, p_all = oracle.trace(b, tris, rays)
+    _, p_fp = oracle.trace(b, tris, rays[out == 3])
+    _, p_pos = oracle.trace(b, tris, rays[(out == 2) | (out == 3)])
+    for k in ("box_tests", "nodes_visited", "interior_visited", "leaf_visited", "tri_tests"):
+        assert st[k] == p_all[k] + p_fp[k], k
+    assert st["pred_box_tests"] == p_pos["box_tests"]
+    assert st["pred_leaf_visited"] == p_pos["leaf_visited"] and st["pred_tri_tests"] == p_pos["tri_tests"]
+    assert st["pred_hits"] == np.count_nonzero(out == 2) > 100 and st["nodes_skipped"] == 0
+    assert np.all(occ[out == 2] == 1) and np.all(occ[out == 3] == 0)
+    assert st["traversals"] == np.count_nonzero((out == 1) | (out == 3))
+
+
+@pytest.mark.parametrize("g", [1, 2, 3])
+def test_go_up_results_and_invariants(g):
+    tris = sg.triangle_soup(1, 256)
+    rays = sg.tiny_shadow_rays(1, 4096)
+    b = oracle.build_sah(tris)
+    par = _parents(b)
+    valid = {_ancestor(par, int(i), g) for i in np.nonzero(b.right == NONE32)[0]}
+    tb = oracle.Table(12, 4, 5, 6, go_up=g)
+    occ, st = oracle.trace(b, tris, rays, table=tb, epoch=256)
+    _allowed_mismatch(tris, rays, occ != oracle.brute_force(tris, rays))
+    _check_table_invariants(tb, valid)
+    assert st["pred_hits"] > 0
+    # closest: EXACT equals brute force; PAPER accepts only real hits
+    rc = rays.copy()
+    rc[:, 7] = np.inf
+    he = oracle.brute_force(tris, rc, closest=True)
+    hx, _ = oracle.trace(b, tris, rc, query="closest", mode="exact", table=oracle.Table(12, 4, 5, 6, go_up=g),
+                         epoch=256)
+    assert np.array_equal(hx[:, 3].view(np.uint32), he[:, 3].view(np.uint32))
+    hp, sp = oracle.trace(b, tris, rc, query="closest", mode="paper", table=oracle.Table(12, 4, 5, 6, go_up=g),
+                          epoch=256)
+    hit = hp[:, 3].view(np.uint32) != NONE32
+    assert np.array_equal(hit, he[:, 3].view(np.uint32) != NONE32)
+    for r in np.nonzero(hit)[0][:300]:
+        h, t, _, _ = oracle.mt(tris[hp[r, 3].view(np.uint32)], rc[r])
+        assert h and t == hp[r, 0]
+    with pytest.raises(ValueError):
+        oracle.trace(b, tris, rays, table=oracle.Table(12, 4, 5, 6, go_up=65), epoch=256)
+
+
+def _subtree_ranges(b):
+    lo = np.zeros(b.num_nodes, np.int64)
+    hi = np.zeros(b.num_nodes, np.int64)
+
+    def rec(i):
+        if b.right[i] == NONE32:
+            lo[i], hi[i] = int(b.first[i]), int(b.first[i] + b.count[i])
+        else:
+            rec(i + 1)
+            rec(int(b.right[i]))
+            lo[i] = min(lo[i + 1], lo[int(b.right[i])])
+            hi[i] = max(hi[i + 1], hi[int(b.right[i])])
+    rec(0)
+    return lo, hi
+
+
+@pytest.mark.parametrize("g", [1, 3])
+def test_go_up_exact_prediction_hits_by_subtree_membership(g):
+    # EXACT closest: a positive ray counts a prediction hit iff its exact
+    # closest triangle lies in the subtree of one of the entry's nodes; the
+    # table is frozen for the second call (one epoch), so every decision can
+    # be recomputed here from the snapshot
+    tris = sg.triangle_soup(7, 300, edge=0.12)
+    g0 = np.random.default_rng(7)
+    o = np.tile([[0.5, -0.5, 0.5]], (3000, 1)) + g0.uniform(-0.1, 0.1, (3000, 3))
+    d = np.tile([[0.0, 1.0, 0.0]], (3000, 1)) + g0.uniform(-0.4, 0.4, (3000, 3))
+    rays = sg.pack_rays(o.astype(np.float32), d.astype(np.float32), 0.0, np.inf)
+    b = oracle.build_sah(tris)
+    lo, hi = _subtree_ranges(b)
+    pos_of_prim = {int(p): k for k, p in enumerate(b.perm)}
+    T = 8
+    tb = oracle.Table(T, 4, 4, 4, go_up=g)
+    oracle.trace(b, tris, rays, query="closest", mode="exact", table=tb, epoch=rays.shape[0])
+    snap = tb.copy()
+    out = np.zeros(rays.shape[0], np.uint8)
+    _, st = oracle.trace(b, tris, rays, query="closest", mode="exact", table=tb, epoch=rays.shape[0], outcome=out)
+    exact = oracle.brute_force(tris, rays, closest=True)
+    keys, idx = oracle.hash_rays(b.box[0], 4, 4, T, rays)
+    want_hits = want_fp = 0
+    for r in range(rays.shape[0]):
+        i = int(idx[r])
+        slots = [int(x) for x in snap.slots[i] if x != NONE32]
+        if not (snap.tags[i] == keys[r] and slots):
+            assert out[r] == 1
+            continue
+        prim = int(exact[r, 3].view(np.uint32))
+        inside = prim != NONE32 and any(lo[n] <= pos_of_prim[prim] < hi[n] for n in slots)
+        want_hits += inside
+        want_fp += not inside
+        assert out[r] == (2 if inside else 3)
+    assert st["pred_hits"] == want_hits > 50 and st["false_pos"] == want_fp > 0
