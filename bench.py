@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--reference-epoch", type=int, default=1 << 17,
                     help="also time the HRPP step at this epoch size (0 = skip)")
     ap.add_argument("--workload", default="at_scale",
-                    choices=["at_scale", "batched", "autotune", "serving", "sweep"],
+                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup"],
                     help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
                          "graph-captured batch")
     ap.add_argument("--sweep-epoch", type=int, default=1 << 17,
@@ -221,6 +221,9 @@ def main():
         return
     if args.workload == "sweep":
         run_sweep(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "goup":
+        run_goup(args, np, torch, hrpp, sg)
         return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
@@ -629,6 +632,79 @@ def run_sweep(args, np, torch, hrpp, sg):
                                   "1": "IEEE-754 sign / exponent / mantissa bits, precision q"}},
         "plain_mrays_s": round(n / (ms_plain * 1e-3) / 1e6, 1), "plain_nodes_visited": plain["nodes_visited"],
         "points": points, "cpu_baseline": cpu}), flush=True)
+
+
+def run_goup(args, np, torch, hrpp, sg):
+    """Go-up level versus table memory and skipped work: the at-scale primary
+    (closest, paper semantics) and shadow (any hit) rays with predictors that
+    name the leaf (g = 0) or the node g levels above it, g in 0..4, at the
+    benchmark's predictor configurations.  Each point: median time of 3
+    (reset + trace), counters of one more run, the table afterwards (entries
+    in use, distinct nodes per used entry)."""
+    w = sg.AT_SCALE
+    log("generating the at-scale workload")
+    tris, prim = sg.terrain_workload()
+    bvh = hrpp.BVH(tris)
+    prim_d = torch.from_numpy(prim).cuda()
+    he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
+                                      light_center=w["light_center"], light_size=w["light_size"])
+    shadow_d = torch.from_numpy(shadow).cuda()
+    res = {}
+    for name, rays, query, q in (("primary", prim_d, "closest", w["primary_q"]),
+                                 ("shadow", shadow_d, "any", w["shadow_q"])):
+        n = rays.shape[0]
+        out = (torch.empty((n, 4), dtype=torch.float32, device="cuda") if query == "closest"
+               else torch.empty(n, dtype=torch.uint8, device="cuda"))
+
+        def trace(pred, st=None):
+            if query == "closest":
+                hrpp.trace_closest(bvh, pred, rays, mode="paper", out=out, stats=st)
+            else:
+                hrpp.trace_anyhit(bvh, pred, rays, out=out, stats=st)
+
+        ms_plain = timed(torch, lambda: trace(None), 5, 1)[0]
+        st = hrpp.new_stats()
+        trace(None, st)
+        torch.cuda.synchronize()
+        plain = hrpp.stats_dict(st)
+        pts = []
+        for g in range(0, 5):
+            pred = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0],
+                                  dir_bits=q[1], epoch_rays=q[2], go_up_level=g)
+
+            def run(st=None):
+                pred.reset()
+                trace(pred, st)
+
+            ms = timed(torch, run, 3, 1)[0]
+            st = hrpp.new_stats()
+            run(st)
+            torch.cuda.synchronize()
+            d = hrpp.stats_dict(st)
+            tags, slots = pred.export()
+            used = tags != np.uint64(0xFFFFFFFFFFFFFFFF)
+            n_used = int(np.count_nonzero(used))
+            ids = int(np.count_nonzero(slots[used] != np.uint32(0xFFFFFFFF)))
+            pts.append(dict(go_up=g, ms=round(ms, 4), mrays_s=round(n / (ms * 1e-3) / 1e6, 1),
+                            pct_nodes_skipped=round(100.0 * (1 - d["nodes_visited"] / plain["nodes_visited"]), 3),
+                            pct_box_tests_skipped=round(100.0 * (1 - d["box_tests"] / plain["box_tests"]), 3),
+                            prediction_hit_rate=round(d["pred_hits"] / n, 4),
+                            false_positive_rate=round(d["false_pos"] / n, 4),
+                            entries_used=n_used, ids_per_used_entry=round(ids / max(n_used, 1), 3),
+                            slots_in_use=ids, occupied_mb=round(n_used * pred.entry_bytes / 2**20, 2),
+                            dropped=d["dropped"]))
+            log(f"go-up {name} g {g}: {pts[-1]}")
+            del pred
+        res[name] = dict(rays=n, query=query, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
+                         plain_mrays_s=round(n / (ms_plain * 1e-3) / 1e6, 1), points=pts)
+    hrpp.get_error(bvh)
+    print(json.dumps({
+        "metric": "go-up level versus table use and skipped work", "unit": "Mrays/s", "dtype": "f32",
+        "data": "synthetic", "higher_is_better": True,
+        "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) and shadow any-hit, "
+                               f"tables 2^{w['log2_entries']} x {w['ways']}"},
+        "results": res}), flush=True)
 
 
 def run_serving(args, np, torch, hrpp, sg):

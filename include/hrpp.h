@@ -79,7 +79,11 @@ typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
  *                    play no part in this mode.
  *                Both modes fold the key into the index with
  *                (key * 0x9E3779B97F4A7C15) >> (64 - T) and store it as the tag.
- *  go_up_level   0 = predict leaves (the only level built) */
+ *  go_up_level   g in [0, 64] (section "Go Up Level"): 0 predicts leaves;
+ *                g >= 1 predicts the node g levels above the leaf a ray
+ *                reached (the root if the leaf is shallower), and a
+ *                positive ray walks that node's subtree with the ordinary
+ *                traversal rules after testing its box */
 typedef struct {
     uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level;
 } hrpp_predictor_desc;
@@ -90,21 +94,24 @@ typedef struct {
  *  rays, invalid, hits          rays seen / invalid / with a hit
  *  lookups, positives           table probes / probes whose entry holds the key
  *  pred_hits, false_pos         positives that did / did not succeed in the
- *                               predicted leaves (EXACT: final hit in a
- *                               predicted leaf or not)
- *  traversals                   full stack traversals run
- *  nodes_visited                interior + leaf visits (predicted leaves included)
+ *                               predicted leaves or subtrees (EXACT: final hit
+ *                               in one of them or not)
+ *  traversals                   full stack traversals run (subtree walks of
+ *                               predicted nodes are not counted here)
+ *  nodes_visited                interior + leaf visits (predicted ones included)
  *  interior_visited, leaf_visited, box_tests, tri_tests
  *  nodes_skipped                sum over prediction successes of the
- *                               predicted leaf's interior-ancestor count
+ *                               interior-ancestor count of the predicted leaf
+ *                               or node that produced the result
  *  records                      update records emitted (traversed rays with a hit)
  *  tag_claims, leaf_inserts     entries (re)claimed / leaves written
  *  dropped                      owner-key records whose leaf did not fit
  *  conflicts                    records discarded because another key owns the entry
  *  pred_leaf_visited, pred_tri_tests, pred_box_tests
  *                               the part of leaf_visited / tri_tests / box_tests
- *                               spent on predicted leaves (a predicted leaf's box
- *                               is tested first; its triangles only if it is hit) */
+ *                               spent on predictions (a predicted leaf's or
+ *                               node's box is tested first; its triangles or
+ *                               subtree only if it is hit) */
 #define HRPP_STATS_SLOTS 24
 typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
@@ -178,7 +185,7 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc);
 /* Create a predictor bound to `bvh` (its hash grid spans the BVH's root
  * box) in d_buf (256-byte aligned), and enqueue its reset on `stream`.
  * Errors: EINVAL (bad desc, hash_mode above 1 or a mode-1 precision out of
- * range, go_up_level other than 0),
+ * range, go_up_level above 64),
  * ENOMEM (bytes too small). */
 hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf,
                                   size_t bytes, void *stream, hrpp_predictor **out);
@@ -188,14 +195,18 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *pred, void *stream);
 
 /* Copy the table to host memory after the work on `stream` (synchronises
  * the stream).  Layout per entry: uint64 tag (all-ones = empty), then
- * `ways` uint32 slots (0xFFFFFFFF = empty; a leaf id is
- * (first_tri << 3) | (count - 1)), then a uint32 claim word (0xFFFFFFFF
- * between calls) and 0xFF padding up to the entry size (32 B for
- * ways <= 4, else 64 B). */
+ * `ways` uint32 slots (0xFFFFFFFF = empty; at go-up level 0 a leaf id
+ * (first_tri << 3) | (count - 1), at level g >= 1 the canonical depth-first
+ * index of the node g levels above the leaf), then a uint32 claim word
+ * (0xFFFFFFFF between calls) and 0xFF padding up to the entry size (32 B
+ * for ways <= 4, else 64 B). */
 hrpp_status hrpp_predictor_export(const hrpp_predictor *pred, void *h_dst, size_t bytes, void *stream);
 
 /* Overwrite the table from host memory (same layout as export); for
- * checkpoint/restore.  Synchronises the stream. */
+ * checkpoint/restore.  Synchronises the stream.  EINVAL if a claim word is
+ * not 0xFFFFFFFF or a slot lies outside the predictor's BVH (a leaf id whose
+ * triangle range passes the triangle count, or a node index >= the node
+ * count); nothing is copied then. */
 hrpp_status hrpp_predictor_import(hrpp_predictor *pred, const void *h_src, size_t bytes, void *stream);
 
 void hrpp_predictor_destroy(hrpp_predictor *pred);

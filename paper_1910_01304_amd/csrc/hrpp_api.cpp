@@ -37,7 +37,7 @@ uint32_t max_persistent_blocks() {
 bool desc_ok(const hrpp_predictor_desc *d) {
     return d && d->log2_entries >= 1 && d->log2_entries <= 26 && d->ways >= 1 && d->ways <= 8 &&
            d->origin_bits >= 1 && d->origin_bits <= 10 && d->dir_bits >= 1 && d->dir_bits <= 10 &&
-           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level == 0 &&
+           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level <= 64 &&
            (d->hash_mode == 0 || (d->hash_mode == 1 && d->origin_bits <= 7 && d->dir_bits == d->origin_bits));
 }
 
@@ -84,8 +84,9 @@ const char *hrpp_status_string(hrpp_status s) {
 size_t hrpp_bvh_required_bytes(uint32_t num_tris, const hrpp_bvh_desc *desc) {
     if (num_tris == 0 || !desc) return 0;
     const size_t interior = num_tris > 1 ? (size_t)num_tris - 1 : 0;   // at most n - 1 interior nodes
+    const size_t nodes = 2 * (size_t)num_tris - 1;                      // at most 2n - 1 nodes
     return kHeaderBytes + align256(interior * kNodeBytes) + align256((size_t)num_tris * kTriBytes) +
-           align256((size_t)num_tris * kLeafBoxBytes);
+           align256((size_t)num_tris * kLeafBoxBytes) + align256(nodes * kCNodeBytes);
 }
 
 hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
@@ -111,6 +112,7 @@ hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const h
     b->d_nodes = nullptr;
     b->d_tris = nullptr;
     b->d_leafbox = nullptr;
+    b->d_cnode = nullptr;
     *out = b;
     return HRPP_OK;
 }
@@ -118,7 +120,8 @@ hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const h
 size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh) {
     if (!bvh) return 0;
     return kHeaderBytes + align256((size_t)bvh->num_interior * kNodeBytes) +
-           align256((size_t)bvh->num_tris * kTriBytes) + align256((size_t)bvh->num_tris * kLeafBoxBytes);
+           align256((size_t)bvh->num_tris * kTriBytes) + align256((size_t)bvh->num_tris * kLeafBoxBytes) +
+           align256((size_t)bvh->num_nodes * kCNodeBytes);
 }
 
 hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream) {
@@ -165,29 +168,52 @@ hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream
         p[8] = v[6] - v[0]; p[9] = v[7] - v[1]; p[10] = v[8] - v[2];
         p[11] = 0.0f;
     }
-    // leaf boxes, indexed by the leaf's first triangle: min xyz, max x | max yz, depth, count
+    // leaf boxes, indexed by the leaf's first triangle: min xyz, max x | max yz, depth, canonical node
     std::vector<float> hl((size_t)n * 8, 0.0f);
     for (uint32_t i = 0; i < m; i++) {
         if (t.right[i] != kNone) continue;
         float *p = &hl[(size_t)t.first[i] * 8];
         for (int a = 0; a < 6; a++) p[a] = t.box[6 * (size_t)i + a];
         std::memcpy(&p[6], &t.depth[i], 4);
-        std::memcpy(&p[7], &t.count[i], 4);
+        std::memcpy(&p[7], &i, 4);
+    }
+    // canonical node records (go-up levels >= 1 name nodes by canonical index):
+    // min xyz, max x | max yz, reference, depth | parent, subtree triangle range
+    std::vector<uint32_t> parent(m, kNone), lo(m), hi(m);
+    for (uint32_t i = 0; i < m; i++)
+        if (t.right[i] != kNone) { parent[i + 1] = i; parent[t.right[i]] = i; }
+    for (uint32_t i = m; i-- > 0;) {
+        if (t.right[i] == kNone) { lo[i] = t.first[i]; hi[i] = t.first[i] + t.count[i]; continue; }
+        lo[i] = std::min(lo[i + 1], lo[t.right[i]]);
+        hi[i] = std::max(hi[i + 1], hi[t.right[i]]);
+    }
+    std::vector<uint32_t> hc((size_t)m * 12, 0u);
+    for (uint32_t i = 0; i < m; i++) {
+        uint32_t *p = &hc[(size_t)i * 12];
+        std::memcpy(p, &t.box[6 * (size_t)i], 6 * sizeof(float));
+        p[6] = ref_of(i);
+        p[7] = t.depth[i];
+        p[8] = parent[i];
+        p[9] = lo[i];
+        p[10] = hi[i];
     }
     char *base = static_cast<char *>(d_buf);
     char *d_nodes = base + kHeaderBytes;
     char *d_tris = d_nodes + align256((size_t)ni * kNodeBytes);
     char *d_leafbox = d_tris + align256((size_t)n * kTriBytes);
+    char *d_cnode = d_leafbox + align256((size_t)n * kLeafBoxBytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemsetAsync(base, 0, kHeaderBytes, s);
     if (e == hipSuccess && ni) e = hipMemcpyAsync(d_nodes, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_tris, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_leafbox, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cnode, hc.data(), hc.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host staging buffers die here
     if (e != hipSuccess) return HRPP_EDEVICE;
     b->d_nodes = d_nodes;
     b->d_tris = d_tris;
     b->d_leafbox = d_leafbox;
+    b->d_cnode = d_cnode;
     return HRPP_OK;
 }
 
@@ -260,6 +286,8 @@ hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc
     if (!p) return HRPP_ENOMEM;
     char *base = static_cast<char *>(d_buf);
     p->bvh_uid = bvh->uid;
+    p->bvh_tris = bvh->num_tris;
+    p->bvh_nodes = bvh->num_nodes;
     p->desc = *desc;
     p->entry_bytes = entry_bytes_for(desc->ways);
     p->table_bytes = (size_t(1) << desc->log2_entries) * p->entry_bytes;
@@ -296,6 +324,26 @@ hrpp_status hrpp_predictor_export(const hrpp_predictor *p, void *h_dst, size_t b
 
 hrpp_status hrpp_predictor_import(hrpp_predictor *p, const void *h_src, size_t bytes, void *stream) {
     if (!p || !h_src || bytes < p->table_bytes) return HRPP_EINVAL;
+    // every slot must stay inside this predictor's BVH (a leaf id's triangle
+    // range, or a node index at go-up levels >= 1) and no claim may be held,
+    // so that the kernels never index outside the scene arrays
+    const char *src = static_cast<const char *>(h_src);
+    const size_t entries = size_t(1) << p->desc.log2_entries;
+    for (size_t i = 0; i < entries; i++) {
+        const char *e = src + i * p->entry_bytes;
+        uint32_t w[9];
+        std::memcpy(w, e + 8, 4 * (p->desc.ways + 1));
+        if (w[p->desc.ways] != kNone) return HRPP_EINVAL;
+        for (uint32_t k = 0; k < p->desc.ways; k++) {
+            const uint32_t v = w[k];
+            if (v == kNone) continue;
+            if (p->desc.go_up_level > 0) {
+                if (v >= p->bvh_nodes) return HRPP_EINVAL;
+            } else if ((v >> 3) + (v & 7u) + 1u > p->bvh_tris) {
+                return HRPP_EINVAL;
+            }
+        }
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->d_table, h_src, p->table_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -311,6 +359,7 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
     a.nodes = bvh->d_nodes;
     a.tris = bvh->d_tris;
     a.leafbox = bvh->d_leafbox;
+    a.cnode = bvh->d_cnode;
     for (int i = 0; i < 6; i++) a.root_box[i] = bvh->root_box[i];
     a.root_ref = bvh->root_ref;
     a.stack_cap = std::max<uint32_t>(1u, bvh->max_depth);
@@ -333,6 +382,7 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.hash.qd = d.dir_bits;
         a.hash.log2n = d.log2_entries;
         a.hash.mode = d.hash_mode;
+        a.go_up = d.go_up_level;
         a.hash.stride = d.origin_bits <= 3 ? 8u : 16u;
         a.ctrl = pred->d_ctrl;
         a.queue = pred->d_queue;
@@ -429,12 +479,17 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
         if (J.pred) kind_of[j] = any ? kBatchAnyHrpp : (J.mode == HRPP_CLOSEST_EXACT ? kBatchExactHrpp : kBatchPaperHrpp);
         else kind_of[j] = any ? kBatchAnyPlain : kBatchClosestPlain;
     }
-    for (int kind = kBatchAnyHrpp; kind <= kBatchClosestPlain; kind++) {
+    for (int kind = kBatchAnyHrpp; kind <= kBatchClosestPlain; kind++)
+    for (int sub = 0; sub < 2; sub++) {
+        const bool hrpp_kind = (kind == kBatchAnyHrpp || kind == kBatchPaperHrpp || kind == kBatchExactHrpp);
+        if (sub && !hrpp_kind) continue;
         BatchGroup g{};
         g.kind = kind;
+        g.subtree = (sub == 1);
         g.first_id = (uint32_t)b->ids.size();
         for (uint32_t j = 0; j < njobs; j++) {
             if ((int)kind_of[j] != kind || jobs[j].n == 0) continue;
+            if (hrpp_kind && (jobs[j].pred->desc.go_up_level > 0) != g.subtree) continue;
             const BatchJob &bj = b->jobs[j];
             b->ids.push_back(j);
             g.count++;

@@ -39,7 +39,8 @@ hrpp_status build_sah_tree(const float *verts, uint32_t n, const hrpp_bvh_desc &
 // GPU layout sizes.
 constexpr size_t kNodeBytes = 64;   // two child boxes + two references
 constexpr size_t kTriBytes = 48;    // v0+prim | e1+leaf depth | e2+pad
-constexpr size_t kLeafBoxBytes = 32;  // per BVH triangle position: box of the leaf starting there + depth
+constexpr size_t kLeafBoxBytes = 32;  // per BVH triangle position: box of the leaf starting there, depth, node
+constexpr size_t kCNodeBytes = 48;    // per canonical node: box, reference, depth, parent, triangle range
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace hrpp
@@ -53,12 +54,14 @@ struct hrpp_bvh {
     const void *d_nodes;        // num_interior * 64 B
     const void *d_tris;         // num_tris * 48 B
     const void *d_leafbox;      // num_tris * 32 B (valid at leaf start positions)
+    const void *d_cnode;        // num_nodes * 48 B, canonical (depth-first pre-order) node records
     hrpp::CanonTree canon;
     std::vector<float> verts;   // host copy of the input, used by the upload
 };
 
 struct hrpp_predictor {
     uint64_t bvh_uid;
+    uint32_t bvh_tris, bvh_nodes;  // sizes of the BVH the table indexes (import checks slots against them)
     hrpp_predictor_desc desc;
     uint32_t entry_bytes;       // 32 or 64
     float bmin[3], scale[3];    // hash grid over the BVH root box

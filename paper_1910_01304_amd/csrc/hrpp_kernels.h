@@ -34,6 +34,7 @@ struct TraceArgs {
     const void *nodes;            // interior nodes, 64 B each
     const void *tris;             // triangles, 48 B each
     const void *leafbox;          // leaf boxes by first triangle, 32 B each
+    const void *cnode;            // canonical node records, 48 B each (predicted interior nodes)
     float root_box[6];
     uint32_t root_ref;
     uint32_t stack_cap;           // LDS stack slots per lane (>= deepest leaf)
@@ -48,6 +49,7 @@ struct TraceArgs {
     void *table;
     uint32_t entry_bytes;
     uint32_t ways;
+    uint32_t go_up;               // 0: slots hold leaf ids; g: canonical node g levels above the leaf
     HashArgs hash;
     uint32_t *ctrl;               // [0 .. kSubQueues) sub-queue counts
     uint64_t *queue;              // kSubQueues sub-queues of queue_subcap entries
@@ -72,6 +74,7 @@ struct BatchGroup {
     int kind;
     uint32_t first_id, count, max_epoch, max_cap, rounds, max_n;
     bool stats;
+    bool subtree;                 // predictors of go-up level >= 1
     // plain groups: flat grid of total_blocks, job k owns blocks [off[k], off[k+1])
     uint32_t total_blocks;
     const uint32_t *d_block_off;

@@ -213,19 +213,16 @@ __device__ __forceinline__ bool test_leaf(const float4 *__restrict__ tris, uint3
 // The per-lane stack lives in LDS, lane-interleaved (slot * blockDim + lane)
 // so that the 64 lanes of a wave touch 64 consecutive dwords.
 // ---------------------------------------------------------------------------
+// walk(): the subtree of `ref`, whose own box the caller has tested; from
+// the root this is the whole traversal, from a predicted node (go-up level
+// >= 1) the evaluation of that prediction.
 template <bool ANY>
-__device__ __forceinline__ bool traverse(const TraceArgs &a, const RayState &r, Best &b, Counters &c,
-                                         uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
+__device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best &b, Counters &c, uint32_t ref,
+                                     uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     const float4 *__restrict__ nodes = (const float4 *)a.nodes;
     const float4 *__restrict__ tris = (const float4 *)a.tris;
     float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
     bool found = (b.prim != kNone);
-    float tn;
-    c.v[kTraversals]++;
-    c.v[kBoxTests]++;
-    if (!slab(a.root_box[0], a.root_box[1], a.root_box[2], a.root_box[3], a.root_box[4], a.root_box[5], r, tcur, tn))
-        return found;
-    uint32_t ref = a.root_ref;
     uint32_t sp = 0;
     for (;;) {
         c.v[kNodesVisited]++;
@@ -271,6 +268,38 @@ __device__ __forceinline__ bool traverse(const TraceArgs &a, const RayState &r, 
     }
 }
 
+template <bool ANY>
+__device__ __forceinline__ bool traverse(const TraceArgs &a, const RayState &r, Best &b, Counters &c,
+                                         uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
+    const float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
+    float tn;
+    c.v[kTraversals]++;
+    c.v[kBoxTests]++;
+    if (!slab(a.root_box[0], a.root_box[1], a.root_box[2], a.root_box[3], a.root_box[4], a.root_box[5], r, tcur, tn))
+        return b.prim != kNone;
+    return walk<ANY>(a, r, b, c, a.root_ref, stk_node, stk_t, stride, cap);
+}
+
+// Canonical node record: min xyz, max x | max yz, reference, depth | parent,
+// subtree triangle range [lo, hi), 0.
+__device__ __forceinline__ const uint32_t *cnode_ptr(const TraceArgs &a, uint32_t node) {
+    return (const uint32_t *)a.cnode + 12 * (size_t)node;
+}
+
+// The node a record names: the result leaf (go-up level 0), or its ancestor
+// go_up levels up, stopping at the root.
+__device__ __forceinline__ uint32_t record_node(const TraceArgs &a, uint32_t leaf) {
+    if (a.go_up == 0) return leaf;
+    const float4 b1 = ((const float4 *)a.leafbox)[2 * (size_t)(leaf >> 3) + 1];
+    uint32_t node = __float_as_uint(b1.w);
+    for (uint32_t k = 0; k < a.go_up; k++) {
+        const uint32_t p = cnode_ptr(a, node)[8];
+        if (p == kNone) break;
+        node = p;
+    }
+    return node;
+}
+
 __device__ __forceinline__ RayState load_ray(const float4 *rays, uint32_t rid, float4 &a, float4 &b) {
     a = rays[2 * (size_t)rid + 0];
     b = rays[2 * (size_t)rid + 1];
@@ -311,8 +340,9 @@ __device__ __forceinline__ const uint32_t *entry_ptr(const TraceArgs &a, uint32_
 // Prediction for ray `rid` ("Overview": hash, look up, evaluate the predicted
 // leaves).  Returns true if the ray must still traverse; then *seed_leaf is
 // the leaf of the best predicted hit (EXACT) or kNone.
-template <bool ANY, bool EXACT>
-__device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Counters &c, uint32_t &seed_leaf) {
+template <bool ANY, bool EXACT, bool SUBTREE>
+__device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Counters &c, uint32_t &seed_leaf,
+                                            uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     float4 ra, rb;
     RayState r = load_ray((const float4 *)a.rays, rid, ra, rb);
     seed_leaf = kNone;
@@ -333,7 +363,36 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
     b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
     const bool positive = (tag == key) && (e[2] != kNone);
     bool hit = false;
-    if (positive) {
+    uint32_t skip_depth = 0;
+    if (SUBTREE && positive) {
+        c.v[kPositives]++;
+        set_inverse(r);
+        const uint32_t box0 = c.v[kBoxTests], leaf0 = c.v[kLeafVisited], tri0 = c.v[kTriTests];
+        // predicted nodes in slot order: the node's box against [tmin, tcur],
+        // then a walk of its subtree; the interior nodes above the node that
+        // produced the result are the ones skipped
+        for (uint32_t s = 0; s < W; s++) {
+            const uint32_t node = e[2 + s];
+            if (node == kNone) break;
+            const float4 *nb = (const float4 *)cnode_ptr(a, node);
+            const float4 n0 = nb[0], n1 = nb[1];
+            const float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
+            float tn;
+            c.v[kBoxTests]++;
+            if (!slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, r, tcur, tn)) continue;
+            const float bt = b.t;
+            const uint32_t bp = b.prim;
+            const bool f = walk<ANY>(a, r, b, c, __float_as_uint(n1.z), stk_node, stk_t, stride, cap);
+            if (b.prim != bp || b.t != bt) skip_depth = __float_as_uint(n1.w);
+            if (f) {
+                hit = true;
+                if (ANY) break;
+            }
+        }
+        c.v[kPredBoxTests] += c.v[kBoxTests] - box0;
+        c.v[kPredLeafVisited] += c.v[kLeafVisited] - leaf0;
+        c.v[kPredTriTests] += c.v[kTriTests] - tri0;
+    } else if (positive) {
         c.v[kPositives]++;
         set_inverse(r);
         const float4 *__restrict__ lbox = (const float4 *)a.leafbox;
@@ -375,9 +434,13 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
     if (positive && hit) {
         c.v[kPredHits]++;
         c.v[kHits]++;
-        // the leaf's interior-ancestor count is stored with its box
-        const float4 b1 = ((const float4 *)a.leafbox)[2 * (size_t)(b.leaf >> 3) + 1];
-        c.v[kNodesSkipped] += __float_as_uint(b1.z);
+        if (SUBTREE) {
+            c.v[kNodesSkipped] += skip_depth;
+        } else {
+            // the leaf's interior-ancestor count is stored with its box
+            const float4 b1 = ((const float4 *)a.leafbox)[2 * (size_t)(b.leaf >> 3) + 1];
+            c.v[kNodesSkipped] += __float_as_uint(b1.z);
+        }
         write_result<ANY>(a, rid, true, b);
         return false;
     }
@@ -420,11 +483,20 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
             const uint32_t *e = entry_ptr(a, idx);
             const bool positive = (*(const uint64_t *)e == key) && (e[2] != kNone);
             if (positive) {
+                // the final best lies in a predicted leaf, or in the
+                // subtree of a predicted node
                 bool in_pred = false;
                 for (uint32_t s = 0; s < a.ways; s++) {
                     const uint32_t l = e[2 + s];
                     if (l == kNone) break;
-                    if (hit && l == b.leaf) in_pred = true;
+                    if (!hit) continue;
+                    if (a.go_up == 0) {
+                        if (l == b.leaf) in_pred = true;
+                    } else {
+                        const uint32_t *cn = cnode_ptr(a, l);
+                        const uint32_t first = b.leaf >> 3;
+                        if (cn[9] <= first && first < cn[10]) in_pred = true;
+                    }
                 }
                 if (in_pred) c.v[kPredHits]++;
                 else c.v[kFalsePos]++;
@@ -434,7 +506,7 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
             const uint32_t slot = rid - base;
             a.rec_key[slot] = key;
             a.rec_idx[slot] = idx;
-            a.rec_leaf[slot] = b.leaf;
+            a.rec_leaf[slot] = record_node(a, b.leaf);
             uint32_t *e = (uint32_t *)entry_ptr(a, idx);
             // the smallest ray id claims the entry; claims only decrease within
             // an epoch, so a coherent read that is already <= rid spares the atomic
@@ -472,14 +544,21 @@ __global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t co
 // Prediction for one epoch: one lane per ray.  Rays that must still traverse
 // are appended to the epoch's fallback queue with one atomic per wave.
 // ---------------------------------------------------------------------------
-template <bool ANY, bool EXACT, bool STATS>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
 __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
+    // SUBTREE (go-up level >= 1): predicted nodes are walked with the LDS
+    // stack of the traversal kernels
+    extern __shared__ uint32_t lds[];
+    const uint32_t stride = blockDim.x;
+    const uint32_t cap = a.stack_cap;
+    uint32_t *stk_node = lds + threadIdx.x;
+    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
     Counters c;
     c.zero();
     const uint32_t i = bx * blockDim.x + threadIdx.x;
     bool enq = false;
     uint32_t seed_leaf = kNone;
-    if (i < count) enq = predict_one<ANY, EXACT>(a, base + i, c, seed_leaf);
+    if (i < count) enq = predict_one<ANY, EXACT, SUBTREE>(a, base + i, c, seed_leaf, stk_node, stk_t, stride, cap);
     // append to the fallback queue: lanes are counted per wave (ballot), waves
     // per block (LDS atomic), and each block takes its range with one global
     // atomic on one of kSubQueues striped counters, so no single counter sees
@@ -503,9 +582,9 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
     flush_counters<STATS>(c, a.stats);
 }
 
-template <bool ANY, bool EXACT, bool STATS>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
 __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uint32_t count) {
-    body_predict<ANY, EXACT, STATS>(a, base, count, blockIdx.x, gridDim.x);
+    body_predict<ANY, EXACT, STATS, SUBTREE>(a, base, count, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -708,13 +787,13 @@ __device__ __forceinline__ bool batch_epoch(const BatchJob &J, uint32_t round, u
     return true;
 }
 
-template <bool ANY, bool EXACT, bool STATS>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
 __global__ __launch_bounds__(256) void kb_predict(const BatchJob *__restrict__ jobs, const uint32_t *__restrict__ ids,
                                                   uint32_t round) {
     const BatchJob &J = jobs[ids[blockIdx.y]];
     uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
-    body_predict<ANY, EXACT, STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * blockDim.x >= count) return;
+    body_predict<ANY, EXACT, STATS, SUBTREE>(J.a, base, count, blockIdx.x, gridDim.x);
 }
 
 template <bool ANY, bool EXACT, bool STATS>
@@ -859,7 +938,11 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipS
     const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     {
         ProfScope p(kKindPredict, s);
-        hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+        if (a.go_up == 0)
+            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false>), dim3(g256), dim3(256), 0, s, a, base, count);
+        else   // predicted subtrees are walked with the traversal's LDS stack
+            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true>), dim3(ceil_div(count, 128)), dim3(128), lds, s,
+                               a, base, count);
     }
     {
         ProfScope p(kKindTraverseQueue, s);
@@ -928,7 +1011,11 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
     const dim3 g256(ceil_div(g.max_epoch, 256), g.count), g128(std::min(ceil_div(g.max_epoch, 128), 4096u), g.count);
     const uint32_t *gid = ids + g.first_id;
     const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
-    hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+    if (!g.subtree)
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false>), g256, dim3(256), 0, s, jobs, gid, r);
+    else
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, true>), dim3(ceil_div(g.max_epoch, 128), g.count),
+                           dim3(128), lds, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_traverse_queue<ANY, EXACT, STATS>), g128, dim3(128), lds, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_update_classify<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_update_apply<STATS>), g256, dim3(256), 0, s, jobs, gid, r);

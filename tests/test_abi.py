@@ -88,6 +88,9 @@ def test_host_argument_validation():
         assert lib.hrpp_predictor_required_bytes(C.byref(badp)) == 0
     for p in range(1, 8):
         assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, p, p, 256, 1, 0))) > 0
+    # go-up levels 0..64
+    assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 64))) > 0
+    assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 65))) == 0
     assert lib.hrpp_status_string(4) == b"BVH deeper than max_depth"
 
 

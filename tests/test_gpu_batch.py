@@ -40,6 +40,10 @@ def _jobs_spec():
         (16, 9000, 5000, "closest", "paper", None),
         (17, 1, 100, "any", "paper", (4, 2, 3, 3, 16)),
         (18, 4000, 1, "closest", "paper", (8, 4, 5, 6, 64)),
+        # go-up levels >= 1 (predicted subtrees) run as groups of their own
+        (19, 6000, 15000, "any", "paper", (12, 4, 5, 6, 2048, 0, 1)),
+        (20, 8000, 11000, "closest", "paper", (13, 8, 5, 6, 4096, 0, 2)),
+        (21, 3000, 6000, "closest", "exact", (12, 4, 4, 4, 1500, 1, 3)),
     ]
 
 
@@ -60,8 +64,9 @@ def _build(hrpp, torch):
 def _new_pred(hrpp, job):
     if job["pc"] is None:
         return None
-    T, W, qo, qd, E = job["pc"]
-    return hrpp.Predictor(job["bvh"], T, W, qo, qd, E)
+    T, W, qo, qd, E = job["pc"][:5]
+    hm, gu = (job["pc"][5], job["pc"][6]) if len(job["pc"]) > 5 else (0, 0)
+    return hrpp.Predictor(job["bvh"], T, W, qo, qd, E, hash_mode=hm, go_up_level=gu)
 
 
 def _single(hrpp, torch, job, pred):

@@ -78,9 +78,10 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
     if pred_cfg is not None:
         T, W, qo, qd, E = pred_cfg[:5]
         hm = pred_cfg[5] if len(pred_cfg) > 5 else 0
+        gu = pred_cfg[6] if len(pred_cfg) > 6 else 0
         pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E,
-                              hash_mode=hm)
-        tb = oracle.Table(T, W, qo, qd, hash_mode=hm)
+                              hash_mode=hm, go_up_level=gu)
+        tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu)
     gst = hrpp.new_stats()
     for c in range(calls):
         got, gs = gpu_run(hrpp, bvh, rays, query, mode, pred, gst)
@@ -190,6 +191,74 @@ def test_terrain_paper_hash(hrpp, small_terrain):
     check_case(hrpp, "terrain shadow paper hash p=5", tris, shadow, pred_cfg=(14, 8, 5, 5, 4096, 1))
     check_case(hrpp, "terrain closest exact paper hash p=3", tris, prim[:20000], query="closest",
                mode="exact", pred_cfg=(10, 2, 3, 3, 1000, 1))
+
+
+# ---------------------------------------------------------------------------
+# Go Up Level >= 1: predicted interior nodes, walked as subtrees
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("g", [1, 2, 3, 64])
+def test_tiny_go_up(hrpp, g):
+    tris, rays = sg.tiny_workload()
+    _, st = check_case(hrpp, f"tiny go-up {g}", tris, rays, pred_cfg=(12, 4, 5, 6, 256, 0, g), calls=2)
+    assert st["pred_hits"] > 0
+    rc = rays.copy()
+    rc[:, 7] = np.inf
+    for mode in ("paper", "exact"):
+        check_case(hrpp, f"tiny closest {mode} go-up {g}", tris, rc, query="closest", mode=mode,
+                   pred_cfg=(12, 4, 5, 6, 256, 0, g), calls=2)
+
+
+@pytest.mark.parametrize("g", [1, 2])
+def test_terrain_go_up(hrpp, small_terrain, g):
+    tris, prim = small_terrain
+    _, st = check_case(hrpp, f"terrain primary paper go-up {g}", tris, prim, query="closest", mode="paper",
+                       pred_cfg=(14, 8, 5, 6, 4096, 0, g))
+    assert st["pred_hits"] > 1000
+    check_case(hrpp, f"terrain primary exact go-up {g}", tris, prim[:20000], query="closest", mode="exact",
+               pred_cfg=(12, 2, 4, 4, 1000, 0, g))
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=2)
+    check_case(hrpp, f"terrain shadow go-up {g}", tris, shadow, pred_cfg=(14, 8, 5, 6, 4096, 0, g))
+    check_case(hrpp, f"terrain shadow go-up {g}, one way, paper hash", tris, shadow,
+               pred_cfg=(6, 1, 5, 5, 777, 1, g))
+
+
+def test_full_size_go_up(hrpp, full_terrain):
+    w = sg.AT_SCALE
+    tris, prim = full_terrain
+    pq = w["primary_q"]
+    check_case(hrpp, "full primary paper go-up 1", tris, prim, query="closest", mode="paper",
+               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1))
+
+
+def test_import_validates_slots(hrpp, small_terrain):
+    tris, prim = small_terrain
+    _say("import validation")
+    bvh = hrpp.BVH(tris)
+    import torch
+    r = torch.from_numpy(prim[:20000]).cuda()
+    for g in (0, 2):
+        p = hrpp.Predictor(bvh, 12, 4, 5, 6, 4096, go_up_level=g)
+        hrpp.trace_closest(bvh, p, r, mode="paper")
+        raw = p.export_raw()
+        q = hrpp.Predictor(bvh, 12, 4, 5, 6, 4096, go_up_level=g)
+        q.import_raw(raw)                                   # round trip
+        assert np.array_equal(q.export_raw(), raw)
+        tags, slots = p.export()
+        used = np.nonzero(tags != np.uint64(0xFFFFFFFFFFFFFFFF))[0]
+        assert used.size
+        e = int(used[0]) * p.entry_bytes
+        bad = raw.copy()
+        bad[e + 8:e + 12] = np.frombuffer(np.uint32(0x7FFFFFF0).tobytes(), np.uint8)   # slot out of range
+        with pytest.raises(RuntimeError):
+            q.import_raw(bad)
+        bad = raw.copy()
+        bad[e + 8 + 4 * 4:e + 12 + 4 * 4] = 0                 # claim word held
+        with pytest.raises(RuntimeError):
+            q.import_raw(bad)
+        assert np.array_equal(q.export_raw(), raw)           # a refused import copies nothing
 
 
 # ---------------------------------------------------------------------------
