@@ -8,9 +8,12 @@ One step = the whole query path over one frame of the at-scale workload
      successful prediction is accepted), hit-all predictor,
   3. one shadow ray per primary hit towards a 0.1 x 0.1 area light, any hit,
      hit-any predictor,
-with the predictor quantisation and epoch sizes chosen by the autotuner
-(hit-all: q_o 5, q_d 7, 2^19 rays; hit-any: q_o 7, q_d 5, 2^20 rays; the
-line also reports the untuned q_o 5 / q_d 6 step at epochs of 2^17).  The
+with the predictor quantisation, epoch sizes and fallback split chosen by the
+autotuner and a sweep of the two-stream step (hit-all: q_o 5, q_d 7, 2^19
+rays, failing rays always compacted into the fallback queue; hit-any: q_o 6,
+q_d 3, 2^20 rays, waves with >= 48 failing lanes traverse at once; the first
+epoch after a reset always traverses in place; the line also reports the
+untuned q_o 5 / q_d 6 step at epochs of 2^17).  The
 same rays are also traced without a
 predictor ("plain").  Rays and the BVH are resident in HBM before timing;
 shadow rays are built once, in setup, from the GPU's exact primary hits.
@@ -67,7 +70,8 @@ def parse():
     ap.add_argument("--sweep-modes", default="0,1", help="hash modes of the sweep (0 grid+octahedral, 1 IEEE bits)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
-    ap.add_argument("--tune-knobs", default="epoch_rays,log2_entries,ways,origin_bits,dir_bits",
+    ap.add_argument("--tune-queries", default="", help="comma list of primary,shadow,ao (default all)")
+    ap.add_argument("--tune-knobs", default="epoch_rays,log2_entries,ways,origin_bits,dir_bits,inline_lanes",
                     help="autotune: comma-separated knobs to search (the others stay at the workload's values)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=500)
@@ -170,16 +174,20 @@ def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
     tot = 0
     for st, n, out_b in ((st_any, n_any, 1), (st_all, n_all, 16)):
         trav_tri = st["tri_tests"] - st["pred_tri_tests"]
+        q_trav, q_int, q_tri, q_rec = (st["queue_traversals"], st["queue_interior_visited"], st["queue_tri_tests"],
+                                       st["queue_records"])
         if kind == "k_traverse_plain":
             tot += n * (RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * st["tri_tests"]
         elif kind == "k_predict":
-            # ray, table entry, predicted leaf boxes and triangles, results of successes, queue append
+            # ray, table entry, predicted leaf boxes and triangles, results of successes, queue appends,
+            # and the fallback traversals run in place (nodes, triangles, result, record + claim)
             tot += (n * RAY_B + st["lookups"] * entry_b + LEAFBOX_B * st["pred_box_tests"]
-                    + TRI_B * st["pred_tri_tests"] + st["pred_hits"] * out_b + st["traversals"] * 8)
+                    + TRI_B * st["pred_tri_tests"] + st["pred_hits"] * out_b + q_trav * 8
+                    + (st["traversals"] - q_trav) * out_b + NODE_B * (st["interior_visited"] - q_int)
+                    + TRI_B * (trav_tri - q_tri) + (st["records"] - q_rec) * (16 + 4))
         elif kind == "k_traverse_queue":
             # queue entry, ray, nodes, triangles, result, record + claim
-            tot += (st["traversals"] * (8 + RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * trav_tri
-                    + st["records"] * (16 + 4))
+            tot += q_trav * (8 + RAY_B + out_b) + NODE_B * q_int + TRI_B * q_tri + q_rec * (16 + 4)
         elif kind.startswith("k_update"):
             tot += st["records"] * (16 + 4 + 4 + entry_b)
     return tot
@@ -190,8 +198,8 @@ def main():
     if args.summarize_traffic:
         import scenegen as sg
         w = sg.AT_SCALE
-        cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2])
-                for q in (w["primary_q"], w["shadow_q"])]
+        cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
+                     inline_lanes=q[3]) for q in (w["primary_q"], w["shadow_q"])]
         summarize_traffic(*args.summarize_traffic, configs=cfgs)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,10 +243,12 @@ def main():
     log(f"BVH: {bvh.num_nodes} nodes, depth {bvh.max_depth}, built in {build_s:.2f} s")
     pq, sq = w["primary_q"], w["shadow_q"]
     if args.epoch:
-        pq, sq = (pq[0], pq[1], args.epoch), (sq[0], sq[1], args.epoch)
+        pq, sq = (pq[0], pq[1], args.epoch, pq[3]), (sq[0], sq[1], args.epoch, sq[3])
     epoch = pq[2]
-    cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2])
-    cfg_any = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1], epoch_rays=sq[2])
+    cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2],
+                   inline_lanes=pq[3])
+    cfg_any = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1], epoch_rays=sq[2],
+                   inline_lanes=sq[3])
     pcfg = cfg_all
     pred_all = hrpp.Predictor(bvh, **cfg_all)
     pred_any = hrpp.Predictor(bvh, **cfg_any)
@@ -407,7 +417,7 @@ def main():
     ref_info = None
     if args.reference_epoch:
         # the untuned reference: both predictors at q_o 5, q_d 6 and the reference epoch
-        rcfg = dict(pcfg, origin_bits=5, dir_bits=6, epoch_rays=args.reference_epoch)
+        rcfg = dict(pcfg, origin_bits=5, dir_bits=6, epoch_rays=args.reference_epoch, inline_lanes=0)
         ra_, rb_ = hrpp.Predictor(bvh, **rcfg), hrpp.Predictor(bvh, **rcfg)
 
         def ref_step():
@@ -448,7 +458,7 @@ def main():
         ao_d = torch.from_numpy(ao).cuda()
         ao_out = torch.empty(ao.shape[0], dtype=torch.uint8, device="cuda")
         pred_ao = hrpp.Predictor(bvh, log2_entries=wi["log2_entries"], ways=wi["ways"], origin_bits=wi["origin_bits"],
-                                 dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"])
+                                 dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"], inline_lanes=wi["inline_lanes"])
 
         def ao_hrpp():
             pred_ao.reset()
@@ -498,8 +508,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_hrpp, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) + shadow any-hit, "
-                               f"HRPP tables 2^20 x 8; hit-all q_o {pq[0]} q_d {pq[1]} epoch {pq[2]}; "
-                               f"hit-any q_o {sq[0]} q_d {sq[1]} epoch {sq[2]} (autotuned)",
+                               f"HRPP tables 2^20 x 8; hit-all q_o {pq[0]} q_d {pq[1]} epoch {pq[2]} "
+                               f"inline lanes {pq[3]}; hit-any q_o {sq[0]} q_d {sq[1]} epoch {sq[2]} "
+                               f"inline lanes {sq[3]} (autotuned)",
                    "hit_all_predictor": cfg_all, "hit_any_predictor": cfg_any,
                    "triangles": int(tris.shape[0]), "rays_per_step": int(rays_per_step),
                    "bvh_nodes": int(bvh.num_nodes), "bvh_depth": int(bvh.max_depth)},
@@ -530,12 +541,22 @@ def run_autotune(args, np, torch, hrpp, sg):
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
     shadow_d = torch.from_numpy(shadow).cuda()
+    wi = sg.INCOHERENT
+    cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+    hh = hrpp.trace_closest(bvh, None, torch.from_numpy(cam).cuda(), mode="exact").cpu().numpy()
+    ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                              samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+    ao_d = torch.from_numpy(ao).cuda()
     res = {}
     knobs = tuple(k for k in args.tune_knobs.split(",") if k)
+    ao_q = (wi["origin_bits"], wi["dir_bits"], wi["epoch"], wi["inline_lanes"])
     for name, rays, query, q in (("primary", prim_d, "closest", w["primary_q"]),
-                                 ("shadow", shadow_d, "any", w["shadow_q"])):
+                                 ("shadow", shadow_d, "any", w["shadow_q"]),
+                                 ("ao", ao_d, "any", ao_q)):
+        if args.tune_queries and name not in args.tune_queries.split(","):
+            continue
         start = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1],
-                     epoch_rays=q[2])
+                     epoch_rays=q[2], inline_lanes=q[3])
         r = autotune.tune(bvh, rays, query=query, mode="paper", start=start, rounds=2, reps=3, knobs=knobs, log=log)
         res[name] = {"best": r.best, "best_ms": round(r.best_ms, 4),
                      "best_mrays_s": round(rays.shape[0] / (r.best_ms * 1e-3) / 1e6, 1),
@@ -578,7 +599,7 @@ def run_sweep(args, np, torch, hrpp, sg):
         for T in range(16, 23):
             for q in range(3, 8):
                 cfg = dict(log2_entries=T, ways=8, origin_bits=q, dir_bits=q, epoch_rays=args.sweep_epoch,
-                           hash_mode=mode)
+                           hash_mode=mode, inline_lanes=wi["inline_lanes"])
                 pred = hrpp.Predictor(bvh, **cfg)
 
                 def run(stats=None):
@@ -671,7 +692,7 @@ def run_goup(args, np, torch, hrpp, sg):
         pts = []
         for g in range(0, 5):
             pred = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0],
-                                  dir_bits=q[1], epoch_rays=q[2], go_up_level=g)
+                                  dir_bits=q[1], epoch_rays=q[2], inline_lanes=q[3], go_up_level=g)
 
             def run(st=None):
                 pred.reset()

@@ -83,9 +83,14 @@ typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
  *                g >= 1 predicts the node g levels above the leaf a ray
  *                reached (the root if the leaf is shallower), and a
  *                positive ray walks that node's subtree with the ordinary
- *                traversal rules after testing its box */
+ *                traversal rules after testing its box
+ *  inline_lanes  scheduling only (results do not depend on it): a 64-lane
+ *                wave of the prediction kernel in which at least this many
+ *                rays must still traverse traverses them at once; other
+ *                waves append theirs to the epoch's compacted fallback
+ *                queue.  1..64; 65 = always queue; 0 = the default (48). */
 typedef struct {
-    uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level;
+    uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level, inline_lanes;
 } hrpp_predictor_desc;
 
 /* Work counters, accumulated (added to) by every trace call that is given
@@ -111,13 +116,21 @@ typedef struct {
  *                               the part of leaf_visited / tri_tests / box_tests
  *                               spent on predictions (a predicted leaf's or
  *                               node's box is tested first; its triangles or
- *                               subtree only if it is hit) */
-#define HRPP_STATS_SLOTS 24
+ *                               subtree only if it is hit)
+ *  queue_traversals, queue_interior_visited, queue_tri_tests, queue_records
+ *                               schedule counters, not part of the method: the
+ *                               part of traversals / interior_visited /
+ *                               tri_tests / records done by the fallback-queue
+ *                               kernel (the rest of the fallback work runs
+ *                               inside the prediction kernel; the split
+ *                               follows inline_lanes) */
+#define HRPP_STATS_SLOTS 32
 typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
              nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
              records, tag_claims, leaf_inserts, dropped, conflicts, pred_leaf_visited, pred_tri_tests,
-             pred_box_tests, reserved[2];
+             pred_box_tests, queue_traversals, queue_interior_visited, queue_tri_tests, queue_records,
+             reserved[6];
 } hrpp_stats;
 
 enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };

@@ -1,7 +1,9 @@
 """Autotuner for the predictor's knobs, by measured throughput on the GPU.
 
 Knobs: epoch size (the unit of batch-synchronous work, a "chunk"), table size
-(log2 entries), ways, and origin / direction quantisation bits.  The traversal
+(log2 entries), ways, origin / direction quantisation bits, and the number of
+failing lanes at which a prediction wave traverses at once instead of
+queueing (a pure scheduling knob: results do not depend on it).  The traversal
 stack depth is not a knob: the LDS stack is sized to the deepest leaf of the
 tree, which is what makes overflow impossible.  Every configuration the tuner
 can pick is an ordinary predictor configuration, traced by the same kernels
@@ -28,6 +30,7 @@ DEFAULT_SPACE = {
     "ways": [4, 8],
     "origin_bits": [3, 4, 5, 6, 7],
     "dir_bits": [3, 4, 5, 6, 7],
+    "inline_lanes": [16, 32, 48, 56, 64, 65],
 }
 
 

@@ -37,7 +37,7 @@ uint32_t max_persistent_blocks() {
 bool desc_ok(const hrpp_predictor_desc *d) {
     return d && d->log2_entries >= 1 && d->log2_entries <= 26 && d->ways >= 1 && d->ways <= 8 &&
            d->origin_bits >= 1 && d->origin_bits <= 10 && d->dir_bits >= 1 && d->dir_bits <= 10 &&
-           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level <= 64 &&
+           d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level <= 64 && d->inline_lanes <= 65 &&
            (d->hash_mode == 0 || (d->hash_mode == 1 && d->origin_bits <= 7 && d->dir_bits == d->origin_bits));
 }
 
@@ -272,6 +272,7 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
     launch_fill32(p->d_topw, E * p->desc.ways, kNone, s);
     launch_fill32(p->d_rec_idx, E, kNone, s);
     launch_fill32(p->d_ctrl, 64, 0u, s);
+    p->empty = true;
     return check(hipGetLastError());
 }
 
@@ -347,6 +348,7 @@ hrpp_status hrpp_predictor_import(hrpp_predictor *p, const void *h_src, size_t b
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->d_table, h_src, p->table_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    p->empty = false;
     return check(e);
 }
 
@@ -383,6 +385,7 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.hash.log2n = d.log2_entries;
         a.hash.mode = d.hash_mode;
         a.go_up = d.go_up_level;
+        a.inline_min = d.inline_lanes ? d.inline_lanes : kDefaultInlineLanes;
         a.hash.stride = d.origin_bits <= 3 ? 8u : 16u;
         a.ctrl = pred->d_ctrl;
         a.queue = pred->d_queue;
@@ -413,8 +416,9 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
     const hrpp_status st = check_trace_args(bvh, pred, d_rays, n, any, any ? (const void *)d_occ : d_hits);
     if (st != HRPP_OK || n == 0) return st;
     const TraceArgs a = make_args(bvh, pred, d_rays, d_occ, d_hits, d_stats);
-    launch_trace(a, n, any, exact, pred != nullptr, pred ? pred->desc.epoch_rays : n,
+    launch_trace(a, n, any, exact, pred != nullptr, pred ? pred->desc.epoch_rays : n, pred && pred->empty,
                  static_cast<hipStream_t>(stream));
+    if (pred) pred->empty = false;
     return check(hipGetLastError());
 }
 
@@ -443,6 +447,11 @@ struct hrpp_batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;   // the legacy default stream cannot be captured
 };
+
+static bool bj_inline(const hrpp_predictor *p) {
+    const uint32_t v = p->desc.inline_lanes ? p->desc.inline_lanes : kDefaultInlineLanes;
+    return v <= 64;
+}
 
 size_t hrpp_batch_required_bytes(uint32_t njobs) {
     // job table, job ids, and block offsets of the two plain groups
@@ -490,6 +499,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
         for (uint32_t j = 0; j < njobs; j++) {
             if ((int)kind_of[j] != kind || jobs[j].n == 0) continue;
             if (hrpp_kind && (jobs[j].pred->desc.go_up_level > 0) != g.subtree) continue;
+            if (hrpp_kind && bj_inline(jobs[j].pred)) g.inline_any = true;
             const BatchJob &bj = b->jobs[j];
             b->ids.push_back(j);
             g.count++;

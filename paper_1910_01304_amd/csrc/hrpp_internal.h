@@ -19,8 +19,11 @@ constexpr int kMaxDepth = 64;                  // deepest leaf the kernels accep
 enum Stat : int {
     kRays, kInvalid, kHits, kLookups, kPositives, kPredHits, kFalsePos, kTraversals,
     kNodesVisited, kInteriorVisited, kLeafVisited, kBoxTests, kTriTests, kNodesSkipped,
-    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kPredLeafVisited, kPredTriTests, kPredBoxTests, kNumStats
+    kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kPredLeafVisited, kPredTriTests, kPredBoxTests,
+    kQueueTraversals, kQueueInteriorVisited, kQueueTriTests, kQueueRecords, kNumStats
 };
+
+static_assert(kNumStats <= HRPP_STATS_SLOTS, "hrpp_stats has a slot for every counter");
 
 // Canonical depth-first pre-order tree, as produced by the builder.
 struct CanonTree {
@@ -62,6 +65,7 @@ struct hrpp_bvh {
 struct hrpp_predictor {
     uint64_t bvh_uid;
     uint32_t bvh_tris, bvh_nodes;  // sizes of the BVH the table indexes (import checks slots against them)
+    bool empty = true;             // reset and not traced or imported since (scheduling hint only)
     hrpp_predictor_desc desc;
     uint32_t entry_bytes;       // 32 or 64
     float bmin[3], scale[3];    // hash grid over the BVH root box

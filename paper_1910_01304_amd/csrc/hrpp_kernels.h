@@ -21,9 +21,12 @@ struct HashArgs {
 };
 
 constexpr uint32_t kSubQueues = 8;     // striped fallback sub-queues per epoch
+constexpr uint32_t kDefaultInlineLanes = 48;   // failing lanes of a wave that traverse at once
 
-// Capacity of one sub-queue: prediction blocks of 256 rays go to sub-queue
-// (block % kSubQueues), so each receives at most ceil(blocks / kSubQueues) blocks.
+// Capacity of one sub-queue, sized as if prediction blocks held 256 rays:
+// block b appends to sub-queue (b % kSubQueues), so with blocks of 128 rays a
+// sub-queue receives at most ceil(ceil(E/128) / kSubQueues) * 128 rays, which
+// never exceeds ceil(ceil(E/256) / kSubQueues) * 256.
 inline uint32_t queue_subcap_for(uint32_t epoch) {
     const uint32_t blocks = (epoch + 255u) / 256u;
     return ((blocks + kSubQueues - 1u) / kSubQueues) * 256u;
@@ -50,6 +53,7 @@ struct TraceArgs {
     uint32_t entry_bytes;
     uint32_t ways;
     uint32_t go_up;               // 0: slots hold leaf ids; g: canonical node g levels above the leaf
+    uint32_t inline_min;          // failing lanes of a wave that traverse at once (65 = never)
     HashArgs hash;
     uint32_t *ctrl;               // [0 .. kSubQueues) sub-queue counts
     uint64_t *queue;              // kSubQueues sub-queues of queue_subcap entries
@@ -75,6 +79,7 @@ struct BatchGroup {
     uint32_t first_id, count, max_epoch, max_cap, rounds, max_n;
     bool stats;
     bool subtree;                 // predictors of go-up level >= 1
+    bool inline_any;              // some job traverses failing waves in place
     // plain groups: flat grid of total_blocks, job k owns blocks [off[k], off[k+1])
     uint32_t total_blocks;
     const uint32_t *d_block_off;
@@ -91,7 +96,10 @@ const char *kernel_kind_name(int k);
 void profile_start();
 int profile_stop(double *ms, uint64_t *launches);   // synchronises the recorded events
 
-void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, hipStream_t s);
+// empty_table: the predictor was reset and not traced since (its first epoch
+// then traverses in place).
+void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, bool empty_table,
+                  hipStream_t s);
 void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
 
 }  // namespace hrpp

@@ -541,13 +541,17 @@ __global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t co
 }
 
 // ---------------------------------------------------------------------------
-// Prediction for one epoch: one lane per ray.  Rays that must still traverse
-// are appended to the epoch's fallback queue with one atomic per wave.
+// Prediction for one epoch: one lane per ray.  A wave in which at least
+// inline_min rays must still traverse traverses them at once (their lanes
+// would mostly be busy anyway); other waves append theirs to the epoch's
+// compacted fallback queue.  Either way a ray runs the same traversal and
+// emits the same record, so results do not depend on the split.
 // ---------------------------------------------------------------------------
-template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
 __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
-    // SUBTREE (go-up level >= 1): predicted nodes are walked with the LDS
-    // stack of the traversal kernels
+    // SUBTREE (go-up level >= 1) walks predicted nodes and INLINE traverses
+    // failing rays in place, both with the LDS stack of the traversal
+    // kernels; without either the kernel needs no LDS
     extern __shared__ uint32_t lds[];
     const uint32_t stride = blockDim.x;
     const uint32_t cap = a.stack_cap;
@@ -559,6 +563,9 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
     bool enq = false;
     uint32_t seed_leaf = kNone;
     if (i < count) enq = predict_one<ANY, EXACT, SUBTREE>(a, base + i, c, seed_leaf, stk_node, stk_t, stride, cap);
+    const bool inline_wave = INLINE && (uint32_t)__popcll(__ballot(enq)) >= a.inline_min;   // uniform per wave
+    const bool now = enq && inline_wave;
+    enq = enq && !inline_wave;
     // append to the fallback queue: lanes are counted per wave (ballot), waves
     // per block (LDS atomic), and each block takes its range with one global
     // atomic on one of kSubQueues striped counters, so no single counter sees
@@ -579,12 +586,13 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
         const uint32_t pos = s_base + wave_off + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
         a.queue[(size_t)sub * a.queue_subcap + pos] = (uint64_t)(base + i) | ((uint64_t)seed_leaf << 32);
     }
+    if (INLINE && now) traverse_one<ANY, EXACT, true>(a, base, base + i, seed_leaf, c, stk_node, stk_t, stride, cap);
     flush_counters<STATS>(c, a.stats);
 }
 
-template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
 __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uint32_t count) {
-    body_predict<ANY, EXACT, STATS, SUBTREE>(a, base, count, blockIdx.x, gridDim.x);
+    body_predict<ANY, EXACT, STATS, SUBTREE, INLINE>(a, base, count, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,6 +630,11 @@ __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t
         const uint64_t q = a.queue[(size_t)sub * a.queue_subcap + off];
         traverse_one<ANY, EXACT, true>(a, base, (uint32_t)q, (uint32_t)(q >> 32), c, stk_node, stk_t, stride, cap);
     }
+    // schedule counters: all of this kernel's work is queued fallback work
+    c.v[kQueueTraversals] = c.v[kTraversals];
+    c.v[kQueueInteriorVisited] = c.v[kInteriorVisited];
+    c.v[kQueueTriTests] = c.v[kTriTests];
+    c.v[kQueueRecords] = c.v[kRecords];
     flush_counters<STATS>(c, a.stats);
 }
 
@@ -787,13 +800,13 @@ __device__ __forceinline__ bool batch_epoch(const BatchJob &J, uint32_t round, u
     return true;
 }
 
-template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
 __global__ __launch_bounds__(256) void kb_predict(const BatchJob *__restrict__ jobs, const uint32_t *__restrict__ ids,
                                                   uint32_t round) {
     const BatchJob &J = jobs[ids[blockIdx.y]];
     uint32_t base, count;
     if (!batch_epoch(J, round, base, count) || blockIdx.x * blockDim.x >= count) return;
-    body_predict<ANY, EXACT, STATS, SUBTREE>(J.a, base, count, blockIdx.x, gridDim.x);
+    body_predict<ANY, EXACT, STATS, SUBTREE, INLINE>(J.a, base, count, blockIdx.x, gridDim.x);
 }
 
 template <bool ANY, bool EXACT, bool STATS>
@@ -937,12 +950,20 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipS
     const uint32_t g256 = ceil_div(count, 256);
     const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     {
+        // with in-place traversal or predicted subtrees: blocks of 128 lanes
+        // with the traversal's LDS stack; otherwise 256 lanes and no LDS
         ProfScope p(kKindPredict, s);
-        if (a.go_up == 0)
-            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false>), dim3(g256), dim3(256), 0, s, a, base, count);
-        else   // predicted subtrees are walked with the traversal's LDS stack
-            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true>), dim3(ceil_div(count, 128)), dim3(128), lds, s,
-                               a, base, count);
+        const bool inl = a.inline_min <= 64;
+        const dim3 g128(ceil_div(count, 128)), b128(128);
+        if (a.go_up != 0) {
+            if (inl) hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true, true>), g128, b128, lds, s, a, base, count);
+            else     hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true, false>), g128, b128, lds, s, a, base, count);
+        } else if (inl) {
+            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false, true>), g128, b128, lds, s, a, base, count);
+        } else {
+            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false, false>), dim3(g256), dim3(256), 0, s, a, base,
+                               count);
+        }
     }
     {
         ProfScope p(kKindTraverseQueue, s);
@@ -972,15 +993,20 @@ static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL((k_traverse_plain<ANY, STATS>), dim3(blocks), dim3(128), lds, s, a, n);
 }
 
-void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, hipStream_t s) {
-    const bool st = a.stats != nullptr;
+void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, bool empty_table,
+                  hipStream_t s) {
+    const bool st = args.stats != nullptr;
     if (!hrpp) {
-        if (any) { if (st) launch_plain<true, true>(a, n, s); else launch_plain<true, false>(a, n, s); }
-        else     { if (st) launch_plain<false, true>(a, n, s); else launch_plain<false, false>(a, n, s); }
+        if (any) { if (st) launch_plain<true, true>(args, n, s); else launch_plain<true, false>(args, n, s); }
+        else     { if (st) launch_plain<false, true>(args, n, s); else launch_plain<false, false>(args, n, s); }
         return;
     }
     for (uint32_t base = 0; base < n; base += epoch) {
         const uint32_t cnt = std::min(epoch, n - base);
+        // an empty table predicts nothing: the first epoch after a reset
+        // traverses every ray in place
+        TraceArgs a = args;
+        if (base == 0 && empty_table) a.inline_min = 1;
         if (any) {
             if (st) launch_epoch<true, false, true>(a, base, cnt, s);
             else    launch_epoch<true, false, false>(a, base, cnt, s);
@@ -1011,11 +1037,13 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
     const dim3 g256(ceil_div(g.max_epoch, 256), g.count), g128(std::min(ceil_div(g.max_epoch, 128), 4096u), g.count);
     const uint32_t *gid = ids + g.first_id;
     const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
-    if (!g.subtree)
-        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false>), g256, dim3(256), 0, s, jobs, gid, r);
+    const dim3 gp(ceil_div(g.max_epoch, 128), g.count);
+    if (g.subtree)
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, true, true>), gp, dim3(128), lds, s, jobs, gid, r);
+    else if (g.inline_any)
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, true>), gp, dim3(128), lds, s, jobs, gid, r);
     else
-        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, true>), dim3(ceil_div(g.max_epoch, 128), g.count),
-                           dim3(128), lds, s, jobs, gid, r);
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, false>), g256, dim3(256), 0, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_traverse_queue<ANY, EXACT, STATS>), g128, dim3(128), lds, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_update_classify<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_update_apply<STATS>), g256, dim3(256), 0, s, jobs, gid, r);

@@ -21,8 +21,11 @@ STAT_NAMES = [
     "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
     "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
     "pred_box_tests",
+    # schedule counters (how much fallback work ran in the queue kernel), not part of the method
+    "queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records",
 ]
-STATS_SLOTS = 24
+SCHEDULE_STATS = ("queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records")
+STATS_SLOTS = 32
 CLOSEST_MODES = {"paper": 0, "exact": 1}
 EXPORTED = [
     "hrpp_bvh_required_bytes", "hrpp_build_bvh", "hrpp_bvh_build_host", "hrpp_bvh_device_bytes",
@@ -47,7 +50,7 @@ class _BvhDesc(C.Structure):
 class _PredDesc(C.Structure):
     _fields_ = [("log2_entries", C.c_uint32), ("ways", C.c_uint32), ("origin_bits", C.c_uint32),
                 ("dir_bits", C.c_uint32), ("epoch_rays", C.c_uint32), ("hash_mode", C.c_uint32),
-                ("go_up_level", C.c_uint32)]
+                ("go_up_level", C.c_uint32), ("inline_lanes", C.c_uint32)]
 
 
 class _KernelTime(C.Structure):
@@ -200,9 +203,11 @@ class Predictor:
     """A predictor table bound to one BVH (one per query type, hit-any / hit-all)."""
 
     def __init__(self, bvh: BVH, log2_entries: int = 12, ways: int = 4, origin_bits: int = 5, dir_bits: int = 6,
-                 epoch_rays: int = 1 << 17, hash_mode: int = 0, go_up_level: int = 0, device: str = "cuda"):
+                 epoch_rays: int = 1 << 17, hash_mode: int = 0, go_up_level: int = 0, inline_lanes: int = 0,
+                 device: str = "cuda"):
         lib = load_library()
-        self.desc = _PredDesc(log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level)
+        self.desc = _PredDesc(log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level,
+                              inline_lanes)
         need = lib.hrpp_predictor_required_bytes(C.byref(self.desc))
         if need == 0:
             raise HrppError("hrpp_predictor_required_bytes: invalid descriptor")
@@ -317,7 +322,7 @@ class Batch:
 
     ``jobs``: dicts with keys bvh, pred (or None), rays (cuda float32 [n, 8]),
     query ("any" | "closest"), mode ("paper" | "exact"), out (optional), stats
-    (optional int64 [24] cuda tensor).  Outputs are allocated if not given and
+    (optional int64 [32] cuda tensor).  Outputs are allocated if not given and
     are available as ``batch.outputs[i]``.
     """
 

@@ -370,11 +370,14 @@ def scene_diagonal(tris: np.ndarray) -> float:
 TINY = dict(seed=1, n_tris=256, n_rays=4096, log2_entries=12, ways=4, origin_bits=5, dir_bits=6, epoch=256)
 AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin_bits=5, dir_bits=6,
                 epoch=1 << 19, light_center=(0.5, 1.0, 0.5), light_size=0.1,
-                # (origin bits, direction bits, epoch rays) of the hit-all and hit-any
-                # predictors, chosen by the autotuner with the table fixed at 2^20 x 8
-                primary_q=(5, 7, 1 << 19), shadow_q=(7, 5, 1 << 20))
+                # (origin bits, direction bits, epoch rays, inline lanes) of the hit-all
+                # and hit-any predictors, chosen by the autotuner (table fixed at
+                # 2^20 x 8) and a sweep of the two-stream step over the inline split;
+                # the hit-all predictor keeps epochs of 2^19, where about 70% of the
+                # nodes are skipped (46% at 2^20)
+                primary_q=(5, 7, 1 << 19, 65), shadow_q=(6, 3, 1 << 20, 48))
 INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=20, ways=8, origin_bits=5,
-                  dir_bits=6, epoch=1 << 19, tmax_frac=0.05)
+                  dir_bits=6, epoch=1 << 20, inline_lanes=16, tmax_frac=0.05)
 
 
 def tiny_workload():

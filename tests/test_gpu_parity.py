@@ -79,8 +79,9 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
         T, W, qo, qd, E = pred_cfg[:5]
         hm = pred_cfg[5] if len(pred_cfg) > 5 else 0
         gu = pred_cfg[6] if len(pred_cfg) > 6 else 0
+        il = pred_cfg[7] if len(pred_cfg) > 7 else 0
         pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E,
-                              hash_mode=hm, go_up_level=gu)
+                              hash_mode=hm, go_up_level=gu, inline_lanes=il)
         tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu)
     gst = hrpp.new_stats()
     for c in range(calls):
@@ -92,7 +93,8 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
             acc = dict(ws)
         else:
             acc = {k: acc[k] + ws[k] for k in acc}
-        assert gs == acc, {k: (gs[k], acc[k]) for k in acc if gs[k] != acc[k]}
+        # every counter the method defines (the schedule counters are not among them)
+        assert {k: gs[k] for k in acc} == acc, {k: (gs[k], acc[k]) for k in acc if gs[k] != acc[k]}
         if pred is not None:
             assert_same_table(pred, tb)
     return got, gs
@@ -170,6 +172,22 @@ def test_terrain_table_shapes(hrpp, small_terrain, cfg):
     check_case(hrpp, f"terrain table {cfg} exact", tris, prim[:20000], query="closest", mode="exact", pred_cfg=cfg)
 
 
+@pytest.mark.parametrize("inline", [1, 32, 64, 65])
+def test_inline_or_queued_fallback_same_results(hrpp, small_terrain, inline):
+    # a wave's failing rays traverse at once or through the queue: the
+    # schedule must not change results, counters or the table
+    tris, prim = small_terrain
+    check_case(hrpp, f"terrain primary paper inline {inline}", tris, prim, query="closest", mode="paper",
+               pred_cfg=(14, 8, 5, 6, 4096, 0, 0, inline))
+    check_case(hrpp, f"terrain primary exact inline {inline}", tris, prim[:30000], query="closest", mode="exact",
+               pred_cfg=(13, 4, 4, 5, 3000, 0, 0, inline))
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=2)
+    check_case(hrpp, f"terrain shadow inline {inline} go-up 1", tris, shadow,
+               pred_cfg=(14, 8, 5, 6, 4096, 0, 1, inline))
+
+
 # ---------------------------------------------------------------------------
 # The paper's IEEE-754 bit hash (hash mode 1)
 # ---------------------------------------------------------------------------
@@ -230,7 +248,7 @@ def test_full_size_go_up(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     check_case(hrpp, "full primary paper go-up 1", tris, prim, query="closest", mode="paper",
-               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1))
+               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3]))
 
 
 def test_import_validates_slots(hrpp, small_terrain):
@@ -341,9 +359,9 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
     # and the untuned reference (q_o 5, q_d 6, epochs of 2^17)
     w = sg.AT_SCALE
     tris, prim = full_terrain
-    pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17), (5, 6, 1 << 17))
-    cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2])
-    cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2])
+    pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17, 0), (5, 6, 1 << 17, 0))
+    cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3])
+    cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3])
     _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all)
     assert st["rays"] == 1920 * 1080
     ob = oracle.build_sah(tris)
@@ -356,7 +374,7 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
 
 
 @pytest.mark.parametrize("cfg", [
-    (20, 8, 5, 6, 1 << 19, 0),     # the benchmark's AO predictor
+    (20, 8, 5, 6, 1 << 19, 0, 0, sg.INCOHERENT["inline_lanes"]),     # the benchmark's AO predictor
     (16, 8, 3, 3, 1 << 17, 1),     # sweep corners, the IEEE-754 bit hash
     (22, 8, 7, 7, 1 << 17, 1),
 ])
