@@ -16,7 +16,7 @@ STAT_NAMES = [
     "rays", "invalid", "hits", "lookups", "positives", "pred_hits", "false_pos", "traversals",
     "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
     "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
-    "pred_box_tests",
+    "pred_box_tests", "evictions",
 ]
 STATS_SLOTS = 24
 NONE32 = 0xFFFFFFFF
@@ -135,11 +135,14 @@ class Table:
     1: the paper's IEEE-754 bit hash with precision qo in 1..7 (qd must equal qo).
     ``go_up`` 0: slots hold leaf ids; g >= 1: canonical node indices of the
     node g levels above the result leaf (the root if the leaf is shallower).
+    ``policy`` bit 0: FIFO eviction within an entry; bit 1: an entry's
+    resident tag keeps the entry (0 = the paper's: no eviction).
     """
 
-    def __init__(self, log2n: int, ways: int, qo: int, qd: int, hash_mode: int = 0, go_up: int = 0):
+    def __init__(self, log2n: int, ways: int, qo: int, qd: int, hash_mode: int = 0, go_up: int = 0,
+                 policy: int = 0):
         self.log2n, self.W, self.qo, self.qd, self.hash_mode = log2n, ways, qo, qd, hash_mode
-        self.go_up = go_up
+        self.go_up, self.policy = go_up, policy
         self.tags = np.full(1 << log2n, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64)
         self.slots = np.full((1 << log2n, ways), NONE32, np.uint32)
 
@@ -148,7 +151,7 @@ class Table:
         self.slots[:] = NONE32
 
     def copy(self) -> "Table":
-        t = Table(self.log2n, self.W, self.qo, self.qd, self.hash_mode, self.go_up)
+        t = Table(self.log2n, self.W, self.qo, self.qd, self.hash_mode, self.go_up, self.policy)
         t.tags[:] = self.tags
         t.slots[:] = self.slots
         return t
@@ -179,14 +182,15 @@ def trace(bvh: CanonBVH, tris: np.ndarray, rays: np.ndarray, query: str = "any",
     s = bvh._struct()
     if table is not None:
         tg, sl, l2, W, qo, qd = table.tags, table.slots, table.log2n, table.W, table.qo, table.qd
-        hm, gu = table.hash_mode, table.go_up
+        hm, gu, pol = table.hash_mode, table.go_up, table.policy
     else:
         tg = sl = None
-        l2 = W = qo = qd = hm = gu = 0
+        l2 = W = qo = qd = hm = gu = pol = 0
     rc = _L().orc_trace(C.byref(s), _p(vtx), _p(rays), C.c_uint32(n), C.c_int(1 if closest else 0),
                         C.c_int(1 if mode == "exact" else 0), _p(tg), _p(sl), C.c_uint32(l2), C.c_uint32(W),
                         C.c_uint32(qo), C.c_uint32(qd), C.c_uint32(epoch), _p(occ), _p(hits), _p(stats),
-                        _p(outcome), C.c_int(nthreads), C.c_uint32(hm), C.c_uint32(gu))
+                        _p(outcome), C.c_int(nthreads), C.c_uint32(hm), C.c_uint32(gu),
+                        C.c_uint32(pol))
     if rc != 0:
         raise ValueError("oracle trace rejected its arguments")
     return (hits if closest else occ), stats_dict(stats)

@@ -34,7 +34,7 @@ enum {
     S_RAYS, S_INVALID, S_HITS, S_LOOKUPS, S_POSITIVES, S_PRED_HITS, S_FALSE_POS,
     S_TRAVERSALS, S_NODES_VISITED, S_INTERIOR_VISITED, S_LEAF_VISITED, S_BOX_TESTS,
     S_TRI_TESTS, S_NODES_SKIPPED, S_RECORDS, S_TAG_CLAIMS, S_LEAF_INSERTS, S_DROPPED,
-    S_CONFLICTS, S_PRED_LEAF_VISITED, S_PRED_TRI_TESTS, S_PRED_BOX_TESTS, S_COUNT
+    S_CONFLICTS, S_PRED_LEAF_VISITED, S_PRED_TRI_TESTS, S_PRED_BOX_TESTS, S_EVICTIONS, S_COUNT
 };
 #define STATS_SLOTS 24
 
@@ -629,6 +629,7 @@ typedef struct {
     uint32_t *slot;     /* [N * W] */
     uint32_t W;
     uint32_t go_up;     /* 0: slots hold leaf ids; g >= 1: node indices g levels above the leaf */
+    uint32_t policy;    /* bit 0: FIFO eviction within an entry; bit 1: the resident tag keeps its entry */
     hash_params h;
 } table;
 
@@ -740,18 +741,23 @@ write:
 }
 
 /* ======================================================================== */
-/* Epoch-end update (our batch-synchronous reading of the paper's insertion */
-/* rule: "the leaf node of the conflicting ray is inserted into the        */
-/* existing predictor entry ... only if it is not already present";        */
-/* entries have W slots and there is no eviction, as the paper has no      */
-/* replacement policy).  For every entry touched by this epoch's records:  */
-/*  1. the key of the record with the smallest ray id owns the entry; if   */
-/*     the stored tag differs, the tag is replaced and all slots emptied;   */
+/* Epoch-end update: our batch-synchronous reading of the insertion rule   */
+/* of section "HRPP Hash Function" (a conflicting ray's leaf joins the      */
+/* existing entry unless already present).  Entries have W slots.  For     */
+/* every entry touched by this epoch's records:                            */
+/*  1. the owner key: the key of the record with the smallest ray id; with */
+/*     the resident policy (bit 1) an entry that holds a tag keeps it, and  */
+/*     only its own key's records count.  If the stored tag differs from    */
+/*     the owner key, the tag is replaced and all slots emptied;            */
 /*  2. records with another key are discarded (conflicts);                 */
-/*  3. the owner key's leaves not yet present are inserted, in increasing  */
-/*     leaf-id order, into the empty slots (front to back); leaves that do  */
-/*     not fit are dropped (every record whose leaf is absent from the      */
-/*     final entry counts one drop).                                        */
+/*  3. the owner key's ids not yet present are taken in increasing order.  */
+/*     Without eviction (the paper: no replacement policy, section          */
+/*     "Precision and Recall") they fill the empty slots front to back and */
+/*     the rest are dropped.  With FIFO eviction (bit 0) the W smallest     */
+/*     enter at the back and the oldest slots at the front make room.       */
+/*     Every record whose id is absent from the final entry counts a drop.  */
+/* The future-work sections ask for a replacement policy; bits 0 and 1 are  */
+/* two simple, deterministic ones.                                          */
 /* ======================================================================== */
 typedef struct { uint32_t idx; uint32_t rid; } rec_ref;
 static int rec_ref_cmp(const void *pa, const void *pb)
@@ -780,6 +786,10 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
         uint32_t idx = refs[g].idx;
         uint64_t kstar = recs[refs[g].rid - base].key;
         uint32_t *slots = tb->slot + (size_t)idx * W;
+        if ((tb->policy & 2u) && tb->tag[idx] != EMPTY_TAG) {
+            /* the resident key keeps the entry; other keys' records are conflicts */
+            kstar = tb->tag[idx];
+        }
         if (tb->tag[idx] != kstar) {
             tb->tag[idx] = kstar;
             for (uint32_t s = 0; s < W; s++) slots[s] = NONE32;
@@ -798,7 +808,18 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
             if (!present) fresh[nf++] = r->leaf;
         }
         qsort(fresh, nf, sizeof(uint32_t), u32_cmp);
-        for (uint32_t f = 0; f < nf && used < W; f++) { slots[used++] = fresh[f]; st[S_LEAF_INSERTS]++; }
+        if (tb->policy & 1u) {
+            /* FIFO: the oldest (front) slots make room for up to W new ids */
+            uint32_t take = nf < W ? nf : W;
+            uint32_t evict = used + take > W ? used + take - W : 0;
+            for (uint32_t s = 0; s + evict < used; s++) slots[s] = slots[s + evict];
+            used -= evict;
+            st[S_EVICTIONS] += evict;
+            for (uint32_t f = 0; f < take; f++) { slots[used++] = fresh[f]; st[S_LEAF_INSERTS]++; }
+            for (uint32_t s = used; s < W; s++) slots[s] = NONE32;
+        } else {
+            for (uint32_t f = 0; f < nf && used < W; f++) { slots[used++] = fresh[f]; st[S_LEAF_INSERTS]++; }
+        }
         for (uint32_t j = g; j < e; j++) {
             const record *r = &recs[refs[j].rid - base];
             if (r->key != kstar) continue;
@@ -828,12 +849,12 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
 int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t n, int query, int cmode,
               uint64_t *tags, uint32_t *slots, uint32_t log2n, uint32_t W, uint32_t qo, uint32_t qd,
               uint32_t epoch, uint8_t *occ, float *hits, uint64_t *stats, uint8_t *outcome, int nthreads,
-              uint32_t hash_mode, uint32_t go_up)
+              uint32_t hash_mode, uint32_t go_up, uint32_t policy)
 {
     if (!bvh || bvh->num_nodes == 0) return -1;
     if (tags && (W < 1 || log2n < 1 || log2n > 31 || qo < 1 || qo > 10 || qd < 1 || qd > 10 || epoch < 1)) return -1;
     if (tags && (hash_mode > 1 || (hash_mode == 1 && (qo > 7 || qd != qo)))) return -1;
-    if (tags && go_up > 64) return -1;
+    if (tags && (go_up > 64 || policy > 3)) return -1;
     scene sc;
     sc.bvh = bvh;
     sc.vtx = vtx;
@@ -862,7 +883,7 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
     sc.sub_end = sub_end;
     table tb, *ptb = NULL;
     if (tags) {
-        tb.tag = tags; tb.slot = slots; tb.W = W; tb.go_up = go_up;
+        tb.tag = tags; tb.slot = slots; tb.W = W; tb.go_up = go_up; tb.policy = policy;
         hash_setup(&tb.h, bvh->box, qo, qd, log2n);
         tb.h.mode = hash_mode;
         ptb = &tb;

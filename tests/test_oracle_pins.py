@@ -973,3 +973,95 @@ def test_go_up_exact_prediction_hits_by_subtree_membership(g):
         want_fp += not inside
         assert out[r] == (2 if inside else 3)
     assert st["pred_hits"] == want_hits > 50 and st["false_pos"] == want_fp > 0
+
+
+# ---------------------------------------------------------------------------
+# Replacement policies (bit 0: FIFO eviction within an entry; bit 1: the
+# resident tag keeps its entry)
+# ---------------------------------------------------------------------------
+
+def test_fifo_eviction_hand_case():
+    # one key (8), W = 2; epoch 1 reaches square 0, epoch 2 squares 1 and 2,
+    # epoch 3 square 0 again (each call is one epoch)
+    tris, b, sq_leaf = _three_squares()
+    r0 = _rays_to_squares([-0.5, 1.0, 0.1], np.array([0] * 6), 60)
+    r12 = _rays_to_squares([-0.5, 1.0, 0.1], np.array([1, 2] * 5), 61)
+    lo, hi = sorted(sq_leaf[1:])
+    for policy in (0, 1):
+        tb = oracle.Table(4, 2, 1, 1, policy=policy)
+        oracle.trace(b, tris, r0, query="closest", mode="exact", table=tb, epoch=1000)
+        e = int(np.nonzero(tb.tags != EMPTY_TAG)[0][0])
+        assert tb.slots[e].tolist() == [sq_leaf[0], NONE32]
+        _, st = oracle.trace(b, tris, r12, query="closest", mode="exact", table=tb, epoch=1000)
+        if policy == 0:
+            # no eviction: one free slot takes the smaller new leaf, the other is dropped
+            assert tb.slots[e].tolist() == [sq_leaf[0], lo]
+            assert (st["leaf_inserts"], st["evictions"], st["dropped"]) == (1, 0, 5)
+        else:
+            # FIFO: the oldest leaf (square 0) leaves, both new leaves enter in id order
+            assert tb.slots[e].tolist() == [lo, hi]
+            assert (st["leaf_inserts"], st["evictions"], st["dropped"]) == (2, 1, 0)
+        _, st = oracle.trace(b, tris, r0, query="closest", mode="exact", table=tb, epoch=1000)
+        if policy == 1:
+            assert tb.slots[e].tolist() == [hi, sq_leaf[0]]
+            assert (st["leaf_inserts"], st["evictions"]) == (1, 1)
+        else:
+            assert tb.slots[e].tolist() == [sq_leaf[0], lo] and st["leaf_inserts"] == 0
+
+
+def test_resident_tag_keeps_its_entry_hand_case():
+    # keys 8 (rays from above) and 24 (from below) share index 1 of a 2-entry table
+    tris, b, sq_leaf = _three_squares()
+    below = _rays_to_squares([-0.5, -1.0, 0.1], np.array([1] * 5), 53)
+    above = _rays_to_squares([-0.5, 1.0, 0.1], np.array([0, 2] * 10), 54)
+    for policy in (0, 2):
+        tb = oracle.Table(1, 4, 1, 1, policy=policy)
+        oracle.trace(b, tris, above, query="closest", mode="exact", table=tb, epoch=100)
+        assert int(tb.tags[1]) == 8
+        resident = tb.slots[1].copy()
+        _, st = oracle.trace(b, tris, below, query="closest", mode="exact", table=tb, epoch=100)
+        if policy == 0:
+            # the smallest ray id's key (24) takes the entry over
+            assert int(tb.tags[1]) == 24 and tb.slots[1].tolist() == [sq_leaf[1], NONE32, NONE32, NONE32]
+            assert (st["tag_claims"], st["conflicts"]) == (1, 0)
+        else:
+            # the resident key 8 keeps it; key 24's records are conflicts
+            assert int(tb.tags[1]) == 8 and np.array_equal(tb.slots[1], resident)
+            assert (st["tag_claims"], st["conflicts"], st["leaf_inserts"]) == (0, 5, 0)
+    # an empty entry is still claimed by the smallest ray id's key
+    tb = oracle.Table(1, 4, 1, 1, policy=2)
+    oracle.trace(b, tris, np.concatenate([below, above]), query="closest", mode="exact", table=tb, epoch=100)
+    assert int(tb.tags[1]) == 24
+
+
+@pytest.mark.parametrize("policy", [1, 2, 3])
+def test_policies_results_invariants_and_special_cases(policy):
+    tris = sg.triangle_soup(1, 256)
+    rays = sg.tiny_shadow_rays(1, 4096)
+    b = oracle.build_sah(tris)
+    valid = set(int(x) for x in b.leaf_ids())
+    for T, W in ((4, 2), (8, 1), (12, 4)):
+        tb = oracle.Table(T, W, 5, 6, policy=policy)
+        out = np.zeros(4096, np.uint8)
+        occ, st = oracle.trace(b, tris, rays, table=tb, epoch=256, outcome=out)
+        _allowed_mismatch(tris, rays, occ != oracle.brute_force(tris, rays))
+        _check_table_invariants(tb, valid)
+        assert np.all(oracle.brute_force(tris, rays)[out == 2] == 1)
+        if policy & 1:
+            assert st["evictions"] <= st["leaf_inserts"]
+        else:
+            assert st["evictions"] == 0
+        if policy == 3:
+            # no tag is ever replaced, so every slot in use is an insert not yet evicted
+            assert np.count_nonzero(tb.slots != NONE32) == st["leaf_inserts"] - st["evictions"]
+    # special cases that reduce to the rule without eviction: FIFO never evicts
+    # when entries are wide enough, and the resident rule never differs when no
+    # two keys share an index
+    base = oracle.Table(20, 8, 5, 6)
+    _, s0 = oracle.trace(b, tris, rays, table=base, epoch=256)
+    assert s0["dropped"] == 0 and s0["conflicts"] == 0
+    tb = oracle.Table(20, 8, 5, 6, policy=policy)
+    _, s1 = oracle.trace(b, tris, rays, table=tb, epoch=256)
+    assert s1 == s0 and np.array_equal(tb.slots, base.slots) and np.array_equal(tb.tags, base.tags)
+    with pytest.raises(ValueError):
+        oracle.trace(b, tris, rays, table=oracle.Table(12, 4, 5, 6, policy=4), epoch=256)
