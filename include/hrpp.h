@@ -88,9 +88,17 @@ typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
  *                wave of the prediction kernel in which at least this many
  *                rays must still traverse traverses them at once; other
  *                waves append theirs to the epoch's compacted fallback
- *                queue.  1..64; 65 = always queue; 0 = the default (48). */
+ *                queue.  1..64; 65 = always queue; 0 = the default (48).
+ *  replace_policy  0 = no eviction (the paper has no replacement policy,
+ *                section "Precision and Recall": ids that do not fit a full
+ *                entry are dropped; a new owner key replaces the tag);
+ *                bit 0 = FIFO within an entry: the oldest slots make room for
+ *                up to `ways` new ids; bit 1 = the resident tag keeps its
+ *                entry: records of another key are conflicts and only empty
+ *                entries are claimed.  0..3. */
 typedef struct {
-    uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level, inline_lanes;
+    uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level, inline_lanes,
+             replace_policy;
 } hrpp_predictor_desc;
 
 /* Work counters, accumulated (added to) by every trace call that is given
@@ -109,14 +117,15 @@ typedef struct {
  *                               interior-ancestor count of the predicted leaf
  *                               or node that produced the result
  *  records                      update records emitted (traversed rays with a hit)
- *  tag_claims, leaf_inserts     entries (re)claimed / leaves written
- *  dropped                      owner-key records whose leaf did not fit
+ *  tag_claims, leaf_inserts     entries (re)claimed / ids written
+ *  dropped                      owner-key records whose id is not in the final entry
  *  conflicts                    records discarded because another key owns the entry
  *  pred_leaf_visited, pred_tri_tests, pred_box_tests
  *                               the part of leaf_visited / tri_tests / box_tests
  *                               spent on predictions (a predicted leaf's or
  *                               node's box is tested first; its triangles or
  *                               subtree only if it is hit)
+ *  evictions                    ids evicted by FIFO replacement
  *  queue_traversals, queue_interior_visited, queue_tri_tests, queue_records
  *                               schedule counters, not part of the method: the
  *                               part of traversals / interior_visited /
@@ -129,8 +138,8 @@ typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
              nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
              records, tag_claims, leaf_inserts, dropped, conflicts, pred_leaf_visited, pred_tri_tests,
-             pred_box_tests, queue_traversals, queue_interior_visited, queue_tri_tests, queue_records,
-             reserved[6];
+             pred_box_tests, evictions, queue_traversals, queue_interior_visited, queue_tri_tests,
+             queue_records, reserved[5];
 } hrpp_stats;
 
 enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };

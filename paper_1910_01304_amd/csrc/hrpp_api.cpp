@@ -38,6 +38,7 @@ bool desc_ok(const hrpp_predictor_desc *d) {
     return d && d->log2_entries >= 1 && d->log2_entries <= 26 && d->ways >= 1 && d->ways <= 8 &&
            d->origin_bits >= 1 && d->origin_bits <= 10 && d->dir_bits >= 1 && d->dir_bits <= 10 &&
            d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level <= 64 && d->inline_lanes <= 65 &&
+           d->replace_policy <= 3 &&
            (d->hash_mode == 0 || (d->hash_mode == 1 && d->origin_bits <= 7 && d->dir_bits == d->origin_bits));
 }
 
@@ -386,6 +387,7 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.hash.mode = d.hash_mode;
         a.go_up = d.go_up_level;
         a.inline_min = d.inline_lanes ? d.inline_lanes : kDefaultInlineLanes;
+        a.policy = d.replace_policy;
         a.hash.stride = d.origin_bits <= 3 ? 8u : 16u;
         a.ctrl = pred->d_ctrl;
         a.queue = pred->d_queue;

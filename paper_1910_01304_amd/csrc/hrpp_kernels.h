@@ -54,6 +54,7 @@ struct TraceArgs {
     uint32_t ways;
     uint32_t go_up;               // 0: slots hold leaf ids; g: canonical node g levels above the leaf
     uint32_t inline_min;          // failing lanes of a wave that traverse at once (65 = never)
+    uint32_t policy;              // bit 0: FIFO eviction; bit 1: the resident tag keeps its entry
     HashArgs hash;
     uint32_t *ctrl;               // [0 .. kSubQueues) sub-queue counts
     uint64_t *queue;              // kSubQueues sub-queues of queue_subcap entries

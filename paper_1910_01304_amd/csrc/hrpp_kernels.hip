@@ -508,10 +508,16 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
             a.rec_idx[slot] = idx;
             a.rec_leaf[slot] = record_node(a, b.leaf);
             uint32_t *e = (uint32_t *)entry_ptr(a, idx);
-            // the smallest ray id claims the entry; claims only decrease within
-            // an epoch, so a coherent read that is already <= rid spares the atomic
-            const uint32_t seen = __hip_atomic_load(&e[2 + a.ways], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (seen > rid) atomicMin(&e[2 + a.ways], rid);
+            // the smallest ray id claims the entry (with the resident policy only
+            // a record of the resident key, or any record for an empty entry;
+            // the table does not change during an epoch); claims only decrease
+            // within an epoch, so a coherent read that is already <= rid spares
+            // the atomic
+            const uint64_t tag = *(const uint64_t *)e;
+            if (!(a.policy & 2u) || tag == kEmptyTag || tag == key) {
+                const uint32_t seen = __hip_atomic_load(&e[2 + a.ways], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (seen > rid) atomicMin(&e[2 + a.ways], rid);
+            }
             c.v[kRecords]++;
         }
     }
@@ -645,14 +651,17 @@ __global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t ba
 
 // ---------------------------------------------------------------------------
 // K3: epoch-end update (section "HRPP Hash Function": a conflicting ray's
-// leaf is inserted into the existing entry unless already present; there is
-// no replacement policy, section "Precision and Recall").  Deterministic
-// batch form: the key of the smallest ray id owns an entry touched this
-// epoch; the owner's new leaves go into the free slots in increasing leaf-id
-// order; the rest are dropped.
+// leaf is inserted into the existing entry unless already present; the paper
+// has no replacement policy, section "Precision and Recall").  Deterministic
+// batch form: the key of the smallest claiming ray id owns an entry touched
+// this epoch (with the resident policy only the resident key's records, or
+// any record for an empty entry, claim); the owner's new ids go into the free
+// slots in increasing id order and the rest are dropped, or, with FIFO
+// eviction, the W smallest enter at the back and the oldest slots make room.
 //   U1 (records): classify each record against the claim winner; collect the
-//       owner's fresh leaves in a sorted, duplicate-free list of W (atomicMin
-//       insertion cascade) kept per claiming ray.
+//       owner's fresh ids in a sorted, duplicate-free list (atomicMin
+//       insertion cascade, bounded by the room the entry has) kept per
+//       claiming ray.
 //   U2 (winning records): rewrite the entry, release the claim.
 //   U3 (records): count drops, clear the record slot, reset the queue count.
 // ---------------------------------------------------------------------------
@@ -668,7 +677,9 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
         const uint32_t W = a.ways;
         const uint32_t *e = entry_ptr(a, idx);
         const uint32_t owner = e[2 + W];                // smallest ray id (claim)
-        const uint64_t kstar = a.rec_key[owner - base];
+        // with the resident policy an entry may have no claim: every record
+        // of the epoch had another key than the resident tag
+        const uint64_t kstar = owner == kNone ? ~a.rec_key[i] : a.rec_key[owner - base];
         const uint32_t leaf = a.rec_leaf[i];
         uint32_t status;
         if (a.rec_key[i] != kstar) {
@@ -687,9 +698,10 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
                 status = kRecPresent;
             } else {
                 status = kRecFresh;
-                // free slots of the entry after this epoch's claim
+                // room for new ids after this epoch's claim: the free slots,
+                // or every slot with FIFO eviction
                 uint32_t free_slots = W;
-                if (*(const uint64_t *)e == kstar) {
+                if (*(const uint64_t *)e == kstar && !(a.policy & 1u)) {
                     uint32_t used = 0;
                     while (used < W && e[2 + used] != kNone) used++;
                     free_slots = W - used;
@@ -740,6 +752,15 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
                 while (used < W && e[2 + used] != kNone) used++;
             }
             uint32_t *list = a.topw + (size_t)i * W;
+            if (a.policy & 1u) {
+                // FIFO: the oldest (front) slots make room for the new ids
+                uint32_t nf = 0;
+                while (nf < W && list[nf] != kNone) nf++;
+                const uint32_t evict = used + nf > W ? used + nf - W : 0;
+                for (uint32_t s = 0; s + evict < used; s++) e[2 + s] = e[2 + s + evict];
+                used -= evict;
+                c.v[kEvictions] += evict;
+            }
             for (uint32_t s = 0; s < W; s++) {
                 const uint32_t l = list[s];
                 if (l != kNone && used < W) {
@@ -768,7 +789,9 @@ __device__ __forceinline__ void body_update_finish(const TraceArgs &a, uint32_t 
     const uint32_t i = bx * blockDim.x + threadIdx.x;
     if (i < kSubQueues) a.ctrl[i] = 0;   // queue counters of the next epoch
     if (i < count && a.rec_idx[i] != kNone) {
-        if (a.rec_status[i] == kRecFresh) {
+        // a record of the owner key counts a drop if its id is not in the
+        // final entry (with FIFO eviction this includes ids present before)
+        if (a.rec_status[i] != kRecConflict) {
             const uint32_t *e = entry_ptr(a, a.rec_idx[i]);
             const uint32_t leaf = a.rec_leaf[i];
             bool present = false;

@@ -20,7 +20,7 @@ STAT_NAMES = [
     "rays", "invalid", "hits", "lookups", "positives", "pred_hits", "false_pos", "traversals",
     "nodes_visited", "interior_visited", "leaf_visited", "box_tests", "tri_tests", "nodes_skipped",
     "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
-    "pred_box_tests",
+    "pred_box_tests", "evictions",
     # schedule counters (how much fallback work ran in the queue kernel), not part of the method
     "queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records",
 ]
@@ -50,7 +50,7 @@ class _BvhDesc(C.Structure):
 class _PredDesc(C.Structure):
     _fields_ = [("log2_entries", C.c_uint32), ("ways", C.c_uint32), ("origin_bits", C.c_uint32),
                 ("dir_bits", C.c_uint32), ("epoch_rays", C.c_uint32), ("hash_mode", C.c_uint32),
-                ("go_up_level", C.c_uint32), ("inline_lanes", C.c_uint32)]
+                ("go_up_level", C.c_uint32), ("inline_lanes", C.c_uint32), ("replace_policy", C.c_uint32)]
 
 
 class _KernelTime(C.Structure):
@@ -204,10 +204,10 @@ class Predictor:
 
     def __init__(self, bvh: BVH, log2_entries: int = 12, ways: int = 4, origin_bits: int = 5, dir_bits: int = 6,
                  epoch_rays: int = 1 << 17, hash_mode: int = 0, go_up_level: int = 0, inline_lanes: int = 0,
-                 device: str = "cuda"):
+                 replace_policy: int = 0, device: str = "cuda"):
         lib = load_library()
         self.desc = _PredDesc(log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level,
-                              inline_lanes)
+                              inline_lanes, replace_policy)
         need = lib.hrpp_predictor_required_bytes(C.byref(self.desc))
         if need == 0:
             raise HrppError("hrpp_predictor_required_bytes: invalid descriptor")

@@ -94,6 +94,9 @@ def test_host_argument_validation():
     # inline_lanes: 0 (default) .. 65 (always queue)
     assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 65))) > 0
     assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 66))) == 0
+    # replacement policies 0..3
+    assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 0, 3))) > 0
+    assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 0, 4))) == 0
     assert lib.hrpp_status_string(4) == b"BVH deeper than max_depth"
 
 

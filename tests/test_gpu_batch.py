@@ -44,6 +44,9 @@ def _jobs_spec():
         (19, 6000, 15000, "any", "paper", (12, 4, 5, 6, 2048, 0, 1)),
         (20, 8000, 11000, "closest", "paper", (13, 8, 5, 6, 4096, 0, 2)),
         (21, 3000, 6000, "closest", "exact", (12, 4, 4, 4, 1500, 1, 3)),
+        # replacement policies
+        (22, 5000, 12000, "any", "paper", (6, 2, 5, 6, 3000, 0, 0, 1, 3)),
+        (23, 7000, 9000, "closest", "paper", (7, 4, 5, 6, 2500, 0, 2, 65, 1)),
     ]
 
 
@@ -66,7 +69,9 @@ def _new_pred(hrpp, job):
         return None
     T, W, qo, qd, E = job["pc"][:5]
     hm, gu = (job["pc"][5], job["pc"][6]) if len(job["pc"]) > 5 else (0, 0)
-    return hrpp.Predictor(job["bvh"], T, W, qo, qd, E, hash_mode=hm, go_up_level=gu)
+    il, rp = (job["pc"][7], job["pc"][8]) if len(job["pc"]) > 7 else (0, 0)
+    return hrpp.Predictor(job["bvh"], T, W, qo, qd, E, hash_mode=hm, go_up_level=gu, inline_lanes=il,
+                          replace_policy=rp)
 
 
 def _method_stats(hrpp, st):

@@ -80,9 +80,10 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
         hm = pred_cfg[5] if len(pred_cfg) > 5 else 0
         gu = pred_cfg[6] if len(pred_cfg) > 6 else 0
         il = pred_cfg[7] if len(pred_cfg) > 7 else 0
+        rp = pred_cfg[8] if len(pred_cfg) > 8 else 0
         pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E,
-                              hash_mode=hm, go_up_level=gu, inline_lanes=il)
-        tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu)
+                              hash_mode=hm, go_up_level=gu, inline_lanes=il, replace_policy=rp)
+        tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu, policy=rp)
     gst = hrpp.new_stats()
     for c in range(calls):
         got, gs = gpu_run(hrpp, bvh, rays, query, mode, pred, gst)
@@ -170,6 +171,45 @@ def test_terrain_table_shapes(hrpp, small_terrain, cfg):
     tris, prim = small_terrain
     check_case(hrpp, f"terrain table {cfg}", tris, prim[:20000], query="closest", mode="paper", pred_cfg=cfg)
     check_case(hrpp, f"terrain table {cfg} exact", tris, prim[:20000], query="closest", mode="exact", pred_cfg=cfg)
+
+
+# ---------------------------------------------------------------------------
+# Replacement policies (FIFO eviction, resident-tag priority)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("policy", [1, 2, 3])
+def test_tiny_policies(hrpp, policy):
+    tris, rays = sg.tiny_workload()
+    for T, W in ((4, 2), (8, 1), (12, 4)):
+        _, st = check_case(hrpp, f"tiny policy {policy} T {T} W {W}", tris, rays,
+                           pred_cfg=(T, W, 5, 6, 256, 0, 0, 0, policy), calls=2)
+
+
+@pytest.mark.parametrize("policy", [1, 2, 3])
+def test_terrain_policies(hrpp, small_terrain, policy):
+    tris, prim = small_terrain
+    _, st = check_case(hrpp, f"terrain primary paper policy {policy}", tris, prim, query="closest", mode="paper",
+                       pred_cfg=(8, 2, 5, 6, 4096, 0, 0, 0, policy))
+    if policy & 1:
+        assert st["evictions"] > 0
+    if policy & 2:
+        assert st["conflicts"] > 0
+    check_case(hrpp, f"terrain exact policy {policy}, go-up 1, inline", tris, prim[:30000], query="closest",
+               mode="exact", pred_cfg=(6, 3, 4, 4, 2000, 0, 1, 1, policy))
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=2)
+    check_case(hrpp, f"terrain shadow policy {policy}, paper hash", tris, shadow,
+               pred_cfg=(7, 4, 5, 5, 4096, 1, 0, 48, policy))
+
+
+def test_full_size_policy(hrpp, full_terrain):
+    w = sg.AT_SCALE
+    tris, prim = full_terrain
+    pq = w["primary_q"]
+    _, st = check_case(hrpp, "full primary paper, FIFO + resident, 2^12 x 4", tris, prim, query="closest",
+                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3))
+    assert st["evictions"] > 0
 
 
 @pytest.mark.parametrize("inline", [1, 32, 64, 65])
