@@ -37,6 +37,11 @@ if ROOT not in sys.path:
 METRIC = "Mrays/s HRPP vs plain BVH traversal (shadow/AO), % nodes skipped, p99 lat"
 HBM_PEAK_GBS = 8000.0
 NODE_B, TRI_B, RAY_B, LEAFBOX_B = 64, 48, 32, 32
+# inline_lanes of the serving and batched predictors, from an A/B of 65 / 1 / 48:
+# queue-only fallback gave serving the lowest p99 (4.1 ms at 80% load against
+# 4.8 and 6.1), in-place fallback gave the batched any-hit scenes the highest rate
+SERVE_INLINE = 65
+BATCH_INLINE = 1
 
 
 def log(msg):
@@ -62,12 +67,14 @@ def parse():
     ap.add_argument("--reference-epoch", type=int, default=1 << 17,
                     help="also time the HRPP step at this epoch size (0 = skip)")
     ap.add_argument("--workload", default="at_scale",
-                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup"],
+                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup", "policy"],
                     help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
                          "graph-captured batch")
     ap.add_argument("--sweep-epoch", type=int, default=1 << 17,
                     help="epoch of the table-size x precision sweep (incoherent AO rays)")
     ap.add_argument("--sweep-modes", default="0,1", help="hash modes of the sweep (0 grid+octahedral, 1 IEEE bits)")
+    ap.add_argument("--inline-lanes", type=int, default=-1,
+                    help="inline_lanes of the batched and serving predictors (-1: the workload's default)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
     ap.add_argument("--tune-queries", default="", help="comma list of primary,shadow,ao (default all)")
@@ -232,6 +239,9 @@ def main():
         return
     if args.workload == "goup":
         run_goup(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "policy":
+        run_policy(args, np, torch, hrpp, sg)
         return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
@@ -728,6 +738,79 @@ def run_goup(args, np, torch, hrpp, sg):
         "results": res}), flush=True)
 
 
+def run_policy(args, np, torch, hrpp, sg):
+    """Table memory versus skipped work under the replacement policies: the
+    at-scale primary rays (closest, paper semantics, the benchmark's hit-all
+    quantisation and epoch) and the incoherent AO rays (any hit), with tables
+    of 2^T entries x 8 ways (64 B entries), T from 6 to 20, and policies 0
+    (no eviction), 1 (FIFO), 2 (resident tag keeps its entry), 3 (both)."""
+    w, wi = sg.AT_SCALE, sg.INCOHERENT
+    log("generating the at-scale and AO workloads")
+    tris, prim = sg.terrain_workload()
+    bvh = hrpp.BVH(tris)
+    prim_d = torch.from_numpy(prim).cuda()
+    cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+    hh = hrpp.trace_closest(bvh, None, torch.from_numpy(cam).cuda(), mode="exact").cpu().numpy()
+    ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                              samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+    ao_d = torch.from_numpy(ao).cuda()
+    pq = w["primary_q"]
+    res = {}
+    for name, rays, query, q in (("primary", prim_d, "closest", pq),
+                                 ("ao", ao_d, "any", (wi["origin_bits"], wi["dir_bits"], wi["epoch"],
+                                                      wi["inline_lanes"]))):
+        n = rays.shape[0]
+        out = (torch.empty((n, 4), dtype=torch.float32, device="cuda") if query == "closest"
+               else torch.empty(n, dtype=torch.uint8, device="cuda"))
+
+        def trace(pred, st=None):
+            if query == "closest":
+                hrpp.trace_closest(bvh, pred, rays, mode="paper", out=out, stats=st)
+            else:
+                hrpp.trace_anyhit(bvh, pred, rays, out=out, stats=st)
+
+        ms_plain = timed(torch, lambda: trace(None), 5, 1)[0]
+        st = hrpp.new_stats()
+        trace(None, st)
+        torch.cuda.synchronize()
+        plain = hrpp.stats_dict(st)
+        pts = []
+        for T in (6, 8, 10, 12, 14, 16, 20):
+            for pol in (0, 1, 2, 3):
+                pred = hrpp.Predictor(bvh, log2_entries=T, ways=8, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
+                                      inline_lanes=q[3], replace_policy=pol)
+
+                def run(st=None):
+                    pred.reset()
+                    trace(pred, st)
+
+                ms = timed(torch, run, 3, 1)[0]
+                st = hrpp.new_stats()
+                run(st)
+                torch.cuda.synchronize()
+                d = hrpp.stats_dict(st)
+                tags, _ = pred.export()
+                pts.append(dict(log2_entries=T, policy=pol, table_kb=pred.table_bytes // 1024, ms=round(ms, 4),
+                                mrays_s=round(n / (ms * 1e-3) / 1e6, 1),
+                                pct_nodes_skipped=round(100.0 * (1 - d["nodes_visited"] / plain["nodes_visited"]), 3),
+                                prediction_hit_rate=round(d["pred_hits"] / n, 4),
+                                false_positive_rate=round(d["false_pos"] / n, 4),
+                                entries_used=int(np.count_nonzero(tags != np.uint64(0xFFFFFFFFFFFFFFFF))),
+                                tag_claims=d["tag_claims"], conflicts=d["conflicts"], dropped=d["dropped"],
+                                evictions=d["evictions"]))
+                log(f"policy {name} T {T} p {pol}: {pts[-1]}")
+                del pred
+        res[name] = dict(rays=n, query=query, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
+                         plain_mrays_s=round(n / (ms_plain * 1e-3) / 1e6, 1), points=pts)
+    hrpp.get_error(bvh)
+    print(json.dumps({
+        "metric": "table memory versus skipped work under replacement policies", "unit": "Mrays/s",
+        "dtype": "f32", "data": "synthetic", "higher_is_better": True,
+        "config": {"workload": "terrain 1M tris; 1920x1080 primary closest (PAPER); 1280x720 x 8 AO any-hit; "
+                               "tables 2^T x 8, T 6..20; policy bit 0 FIFO, bit 1 resident tag"},
+        "results": res}), flush=True)
+
+
 def run_serving(args, np, torch, hrpp, sg):
     """Continuous batching under Poisson arrivals: 8 resident scenes, requests
     of 1e3-1e6 rays (20% primary exact closest-hit, 40% shadow, 40% AO),
@@ -759,7 +842,8 @@ def run_serving(args, np, torch, hrpp, sg):
         pools.append({"closest": torch.from_numpy(cam_rays).pin_memory(),
                       "shadow": torch.from_numpy(sh).pin_memory(), "ao": torch.from_numpy(ao).pin_memory()})
     del made
-    pc = dict(log2_entries=18, ways=8, origin_bits=5, dir_bits=6, epoch_rays=1 << 19)
+    pc = dict(log2_entries=18, ways=8, origin_bits=5, dir_bits=6, epoch_rays=1 << 19,
+              inline_lanes=args.inline_lanes if args.inline_lanes >= 0 else SERVE_INLINE)
     scenes = [(b, [hrpp.Predictor(b, **pc) for _ in range(2)], [hrpp.Predictor(b, **pc) for _ in range(2)])
               for b in bvhs]
     pool_bytes = 8 << 30
@@ -869,7 +953,9 @@ def run_batched(args, np, torch, hrpp, sg):
     total = int(sum(r.shape[0] for r in rays))
     del rays
     E = args.batch_epoch
-    preds = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6, epoch_rays=E)
+    il = args.inline_lanes if args.inline_lanes >= 0 else BATCH_INLINE
+    preds = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6, epoch_rays=E,
+                            inline_lanes=il)
              for b, sp in zip(bvhs, specs)]
     outs = [torch.empty(r.shape[0], dtype=torch.uint8, device="cuda") for r in rays_d]
     batch = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o) for b, p, r, o in zip(bvhs, preds, rays_d, outs)])
