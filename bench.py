@@ -307,6 +307,16 @@ def main():
     def step_plain():
         on_two_streams(primary_plain, shadow_plain)
 
+    # the stronger plain baseline: the same rays on the 4-wide tree
+    def primary_wide():
+        hrpp.trace_wide_closest(bvh, prim_d, out=hits_out)
+
+    def shadow_wide():
+        hrpp.trace_wide_anyhit(bvh, shadow_d, out=occ_out)
+
+    def step_wide():
+        on_two_streams(primary_wide, shadow_wide)
+
     if args.traffic_probe:
         x = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
@@ -333,9 +343,11 @@ def main():
     else:
         ms_hrpp, wall_hrpp = timed(torch, step_hrpp, args.steps, args.warmup)
         ms_plain, wall_plain = timed(torch, step_plain, args.steps, args.warmup)
+    ms_wide = float("nan") if args.profile_only else timed(torch, step_wide, args.steps, args.warmup)[0]
     parts = {}
     for name, fn in (("primary_hrpp", primary_hrpp), ("primary_plain", primary_plain),
-                     ("shadow_hrpp", shadow_hrpp), ("shadow_plain", shadow_plain)):
+                     ("primary_wide", primary_wide), ("shadow_hrpp", shadow_hrpp), ("shadow_plain", shadow_plain),
+                     ("shadow_wide", shadow_wide)):
         parts[name] = float("nan") if args.no_parts else timed(torch, fn, args.steps, 1)[0]
 
     # counters of one step (separate pass with stats on)
@@ -370,14 +382,15 @@ def main():
         plain_mrays_s=mrays(n_prim, parts["primary_plain"]),
         pct_nodes_skipped=pct_saved("nodes_visited", h_sb, p_sb),
         pct_box_tests_skipped=pct_saved("box_tests", h_sb, p_sb),
-        prediction_hit_rate=h_sb["pred_hits"] / n_prim, false_positive_rate=h_sb["false_pos"] / n_prim)
+        prediction_hit_rate=h_sb["pred_hits"] / n_prim, false_positive_rate=h_sb["false_pos"] / n_prim,
+        wide_plain_mrays_s=mrays(n_prim, parts["primary_wide"]))
     shadow_info = dict(
         rays=n_sh, query="any hit", hrpp_mrays_s=mrays(n_sh, parts["shadow_hrpp"]),
         plain_mrays_s=mrays(n_sh, parts["shadow_plain"]),
         pct_nodes_skipped=pct_saved("nodes_visited", h_sa, p_sa),
         pct_box_tests_skipped=pct_saved("box_tests", h_sa, p_sa),
         prediction_hit_rate=h_sa["pred_hits"] / n_sh, false_positive_rate=h_sa["false_pos"] / n_sh,
-        occluded_fraction=h_sa["hits"] / n_sh)
+        occluded_fraction=h_sa["hits"] / n_sh, wide_plain_mrays_s=mrays(n_sh, parts["shadow_wide"]))
     nodes_h = h_sa["nodes_visited"] + h_sb["nodes_visited"]
     nodes_p = p_sa["nodes_visited"] + p_sb["nodes_visited"]
     box_h = h_sa["box_tests"] + h_sb["box_tests"]
@@ -476,6 +489,7 @@ def main():
 
         ms_ao_h = timed(torch, ao_hrpp, max(1, args.steps // 2), 1)[0]
         ms_ao_p = timed(torch, lambda: hrpp.trace_anyhit(bvh, None, ao_d, out=ao_out), max(1, args.steps // 2), 1)[0]
+        ms_ao_w = timed(torch, lambda: hrpp.trace_wide_anyhit(bvh, ao_d, out=ao_out), max(1, args.steps // 2), 1)[0]
         sh_, sp_ = hrpp.new_stats(), hrpp.new_stats()
         pred_ao.reset()
         hrpp.trace_anyhit(bvh, pred_ao, ao_d, out=ao_out, stats=sh_)
@@ -488,7 +502,8 @@ def main():
                        pct_box_tests_skipped=pct_saved("box_tests", a_h, a_p),
                        prediction_hit_rate=a_h["pred_hits"] / ao.shape[0],
                        false_positive_rate=a_h["false_pos"] / ao.shape[0],
-                       occluded_fraction=a_h["hits"] / ao.shape[0])
+                       occluded_fraction=a_h["hits"] / ao.shape[0],
+                       wide_plain_mrays_s=mrays(ao.shape[0], ms_ao_w))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -527,6 +542,8 @@ def main():
         "plain_mrays_s": round(mrays(rays_per_step, ms_plain), 2),
         "plain_ms_per_step": round(ms_plain, 4),
         "speedup_vs_plain": round(ms_plain / ms_hrpp, 4),
+        "wide_plain_mrays_s": round(mrays(rays_per_step, ms_wide), 2),
+        "speedup_vs_wide_plain": round(ms_wide / ms_hrpp, 4),
         "wall_ms_per_step": {"hrpp": round(wall_hrpp, 4), "plain": round(wall_plain, 4)},
         "pct_nodes_skipped": round(100.0 * (1 - nodes_h / nodes_p), 3),
         "pct_box_tests_skipped": round(100.0 * (1 - box_h / box_p), 3),

@@ -254,6 +254,38 @@ hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const 
                                uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Plain-traversal baseline on a 4-wide BVH, collapsed on the host from the
+ * binary tree (a stronger plain baseline than binary traversal; the paper
+ * traverses a binary BVH, section "Overview").  Collapse: a wide node starts
+ * from the two children of a binary interior node and, while it has fewer
+ * than four, replaces its interior child of largest surface area by that
+ * child's two children; leaves are the binary leaves.  A node's hit children
+ * are visited nearest first.  Results equal the binary traversal's (any-hit
+ * flags; the exact closest hit, ties to the smaller prim); the visit counts
+ * in d_stats are the wide tree's own.  No predictor.
+ * ------------------------------------------------------------------------ */
+
+/* The wide tree of a BVH: node count, root reference (node 0, or bit 31 |
+ * leaf id for a one-leaf tree), the largest stack it can need, its depth. */
+hrpp_status hrpp_bvh_wide_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *root_ref, uint32_t *stack_need,
+                               uint32_t *depth);
+
+/* Copy the wide nodes to host memory: 32 uint32 words (128 B) per node:
+ * [0..3] min x of children 0..3, [4..7] max x, [8..11] min y, [12..15]
+ * max y, [16..19] min z, [20..23] max z (binary32 bits), [24..27] child
+ * references (wide node index, bit 31 | leaf id, or 0xFFFFFFFF for no
+ * child), [28..31] zero.  EINVAL if `words` is too small. */
+hrpp_status hrpp_bvh_wide_export(const hrpp_bvh *bvh, uint32_t *h_words, size_t words);
+
+/* Any-hit and exact closest-hit queries on the wide tree (arguments and
+ * errors as for hrpp_trace_anyhit / hrpp_trace_closest without a
+ * predictor); EINVAL for a BVH not uploaded. */
+hrpp_status hrpp_trace_wide_anyhit(const hrpp_bvh *bvh, const hrpp_ray *d_rays, uint32_t n, uint8_t *d_occluded,
+                                   hrpp_stats *d_stats, void *stream);
+hrpp_status hrpp_trace_wide_closest(const hrpp_bvh *bvh, const hrpp_ray *d_rays, uint32_t n, hrpp_hit *d_hits,
+                                    hrpp_stats *d_stats, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many independent jobs (each its own BVH, predictor or none, rays
  * and outputs) executed together.  Round r runs epoch r of every job in one
  * launch per kernel, so scenes of uneven size fill the GPU together; the

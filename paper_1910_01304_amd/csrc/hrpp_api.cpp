@@ -86,8 +86,11 @@ size_t hrpp_bvh_required_bytes(uint32_t num_tris, const hrpp_bvh_desc *desc) {
     if (num_tris == 0 || !desc) return 0;
     const size_t interior = num_tris > 1 ? (size_t)num_tris - 1 : 0;   // at most n - 1 interior nodes
     const size_t nodes = 2 * (size_t)num_tris - 1;                      // at most 2n - 1 nodes
+    // a wide node takes at least one binary interior node: at most n - 1 (1 for a one-leaf tree)
+    const size_t wide = std::max<size_t>(1, interior);
     return kHeaderBytes + align256(interior * kNodeBytes) + align256((size_t)num_tris * kTriBytes) +
-           align256((size_t)num_tris * kLeafBoxBytes) + align256(nodes * kCNodeBytes);
+           align256((size_t)num_tris * kLeafBoxBytes) + align256(nodes * kCNodeBytes) +
+           align256(wide * kWideNodeBytes);
 }
 
 hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
@@ -98,6 +101,7 @@ hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const h
     if (!b) return HRPP_ENOMEM;
     hrpp_status st = build_sah_tree(h_verts, num_tris, *desc, b->canon);
     if (st != HRPP_OK) { delete b; return st; }
+    collapse_wide(b->canon, b->wide);
     const CanonTree &t = b->canon;
     b->uid = g_uid.fetch_add(1);
     b->num_tris = num_tris;
@@ -114,6 +118,7 @@ hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const h
     b->d_tris = nullptr;
     b->d_leafbox = nullptr;
     b->d_cnode = nullptr;
+    b->d_wide = nullptr;
     *out = b;
     return HRPP_OK;
 }
@@ -122,7 +127,7 @@ size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh) {
     if (!bvh) return 0;
     return kHeaderBytes + align256((size_t)bvh->num_interior * kNodeBytes) +
            align256((size_t)bvh->num_tris * kTriBytes) + align256((size_t)bvh->num_tris * kLeafBoxBytes) +
-           align256((size_t)bvh->num_nodes * kCNodeBytes);
+           align256((size_t)bvh->num_nodes * kCNodeBytes) + align256(bvh->wide.words.size() * 4);
 }
 
 hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream) {
@@ -203,18 +208,22 @@ hrpp_status hrpp_bvh_upload(hrpp_bvh *b, void *d_buf, size_t bytes, void *stream
     char *d_tris = d_nodes + align256((size_t)ni * kNodeBytes);
     char *d_leafbox = d_tris + align256((size_t)n * kTriBytes);
     char *d_cnode = d_leafbox + align256((size_t)n * kLeafBoxBytes);
+    char *d_wide = d_cnode + align256((size_t)m * kCNodeBytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemsetAsync(base, 0, kHeaderBytes, s);
     if (e == hipSuccess && ni) e = hipMemcpyAsync(d_nodes, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_tris, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_leafbox, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_cnode, hc.data(), hc.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !b->wide.words.empty())
+        e = hipMemcpyAsync(d_wide, b->wide.words.data(), b->wide.words.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host staging buffers die here
     if (e != hipSuccess) return HRPP_EDEVICE;
     b->d_nodes = d_nodes;
     b->d_tris = d_tris;
     b->d_leafbox = d_leafbox;
     b->d_cnode = d_cnode;
+    b->d_wide = d_wide;
     return HRPP_OK;
 }
 
@@ -237,6 +246,22 @@ hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *nu
     if (num_nodes) *num_nodes = bvh->num_nodes;
     if (num_tris) *num_tris = bvh->num_tris;
     if (max_depth) *max_depth = bvh->max_depth;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_bvh_wide_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *root_ref, uint32_t *stack_need,
+                               uint32_t *depth) {
+    if (!bvh) return HRPP_EINVAL;
+    if (num_nodes) *num_nodes = (uint32_t)(bvh->wide.words.size() / 32);
+    if (root_ref) *root_ref = bvh->wide.root_ref;
+    if (stack_need) *stack_need = bvh->wide.stack_need;
+    if (depth) *depth = bvh->wide.depth;
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_bvh_wide_export(const hrpp_bvh *bvh, uint32_t *h_words, size_t words) {
+    if (!bvh || (!h_words && !bvh->wide.words.empty()) || words < bvh->wide.words.size()) return HRPP_EINVAL;
+    if (!bvh->wide.words.empty()) std::memcpy(h_words, bvh->wide.words.data(), bvh->wide.words.size() * 4);
     return HRPP_OK;
 }
 
@@ -433,6 +458,29 @@ hrpp_status hrpp_trace_closest(const hrpp_bvh *bvh, hrpp_predictor *pred, const 
                                uint32_t mode, hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream) {
     if (mode != HRPP_CLOSEST_PAPER && mode != HRPP_CLOSEST_EXACT) return HRPP_EINVAL;
     return trace_common(bvh, pred, d_rays, n, false, mode == HRPP_CLOSEST_EXACT, nullptr, d_hits, d_stats, stream);
+}
+
+static hrpp_status trace_wide(const hrpp_bvh *bvh, const hrpp_ray *d_rays, uint32_t n, bool any, uint8_t *d_occ,
+                              hrpp_hit *d_hits, hrpp_stats *d_stats, void *stream) {
+    const hrpp_status st = check_trace_args(bvh, nullptr, d_rays, n, any, any ? (const void *)d_occ : d_hits);
+    if (st != HRPP_OK || n == 0) return st;
+    if (!bvh->d_wide) return HRPP_EINVAL;
+    TraceArgs a = make_args(bvh, nullptr, d_rays, d_occ, d_hits, d_stats);
+    a.wide = bvh->d_wide;
+    a.wide_root = bvh->wide.root_ref;
+    a.stack_cap = std::max<uint32_t>(1u, bvh->wide.stack_need);
+    launch_wide(a, n, any, static_cast<hipStream_t>(stream));
+    return check(hipGetLastError());
+}
+
+hrpp_status hrpp_trace_wide_anyhit(const hrpp_bvh *bvh, const hrpp_ray *d_rays, uint32_t n, uint8_t *d_occluded,
+                                   hrpp_stats *d_stats, void *stream) {
+    return trace_wide(bvh, d_rays, n, true, d_occluded, nullptr, d_stats, stream);
+}
+
+hrpp_status hrpp_trace_wide_closest(const hrpp_bvh *bvh, const hrpp_ray *d_rays, uint32_t n, hrpp_hit *d_hits,
+                                    hrpp_stats *d_stats, void *stream) {
+    return trace_wide(bvh, d_rays, n, false, nullptr, d_hits, d_stats, stream);
 }
 
 // ---------------------------------------------------------------------------

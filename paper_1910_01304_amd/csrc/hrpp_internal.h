@@ -39,11 +39,21 @@ struct CanonTree {
 // Deterministic binned-SAH build; returns HRPP_OK, HRPP_EINVAL or HRPP_EDEPTH.
 hrpp_status build_sah_tree(const float *verts, uint32_t n, const hrpp_bvh_desc &desc, CanonTree &out);
 
+// 4-wide tree collapsed from the binary one (plain-traversal baseline).
+struct WideTree {
+    std::vector<uint32_t> words;   // 32 per node (128 B), layout in bvh_wide.cpp
+    uint32_t root_ref = kNone;     // node 0, or kLeafFlag | leaf id for a one-leaf tree
+    uint32_t stack_need = 1;       // most stack entries any traversal can hold
+    uint32_t depth = 0;            // wide interior levels
+};
+void collapse_wide(const CanonTree &t, WideTree &w);
+
 // GPU layout sizes.
 constexpr size_t kNodeBytes = 64;   // two child boxes + two references
 constexpr size_t kTriBytes = 48;    // v0+prim | e1+leaf depth | e2+pad
 constexpr size_t kLeafBoxBytes = 32;  // per BVH triangle position: box of the leaf starting there, depth, node
 constexpr size_t kCNodeBytes = 48;    // per canonical node: box, reference, depth, parent, triangle range
+constexpr size_t kWideNodeBytes = 128; // per 4-wide node: child boxes (structure of arrays) + references
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace hrpp
@@ -58,7 +68,9 @@ struct hrpp_bvh {
     const void *d_tris;         // num_tris * 48 B
     const void *d_leafbox;      // num_tris * 32 B (valid at leaf start positions)
     const void *d_cnode;        // num_nodes * 48 B, canonical (depth-first pre-order) node records
+    const void *d_wide;         // 4-wide nodes, 128 B each (plain-traversal baseline)
     hrpp::CanonTree canon;
+    hrpp::WideTree wide;
     std::vector<float> verts;   // host copy of the input, used by the upload
 };
 

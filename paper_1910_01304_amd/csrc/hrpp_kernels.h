@@ -38,6 +38,8 @@ struct TraceArgs {
     const void *tris;             // triangles, 48 B each
     const void *leafbox;          // leaf boxes by first triangle, 32 B each
     const void *cnode;            // canonical node records, 48 B each (predicted interior nodes)
+    const void *wide;             // 4-wide nodes, 128 B each (plain-traversal baseline)
+    uint32_t wide_root;           // wide node 0, or kLeafFlag | leaf id
     float root_box[6];
     uint32_t root_ref;
     uint32_t stack_cap;           // LDS stack slots per lane (>= deepest leaf)
@@ -91,7 +93,7 @@ void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<B
 
 enum KernelKind : int {
     kKindPredict, kKindTraverseQueue, kKindTraversePlain, kKindUpdateClassify, kKindUpdateApply,
-    kKindUpdateFinish, kKindFill, kNumKernelKinds
+    kKindUpdateFinish, kKindFill, kKindTraverseWide, kNumKernelKinds
 };
 const char *kernel_kind_name(int k);
 void profile_start();
@@ -102,5 +104,9 @@ int profile_stop(double *ms, uint64_t *launches);   // synchronises the recorded
 void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, bool empty_table,
                   hipStream_t s);
 void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
+
+// Plain traversal of the 4-wide tree (a.wide, a.wide_root; a.stack_cap = the
+// tree's stack need); closest hit is the exact one.
+void launch_wide(const TraceArgs &a, uint32_t n, bool any, hipStream_t s);
 
 }  // namespace hrpp

@@ -524,6 +524,133 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
 }
 
 // ---------------------------------------------------------------------------
+// Plain traversal of the 4-wide tree (the stronger plain baseline).  A node's
+// up to four child boxes are tested against [tmin, tcur]; the hit children
+// are ordered by entry distance (ties to the lower child slot), the nearest
+// is visited and the others are pushed farthest first; popping and leaf
+// tests follow the binary traversal.  The closest hit is the exact one
+// (lexicographic (t, prim) minimum), so its results equal the binary
+// traversal's; its visit counts are its own.
+// ---------------------------------------------------------------------------
+template <bool ANY>
+__device__ __forceinline__ bool traverse_wide(const TraceArgs &a, const RayState &r, Best &b, Counters &c,
+                                              uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
+    const float4 *__restrict__ wn = (const float4 *)a.wide;
+    const float4 *__restrict__ tris = (const float4 *)a.tris;
+    float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
+    bool found = (b.prim != kNone);
+    float tn;
+    c.v[kTraversals]++;
+    c.v[kBoxTests]++;
+    if (!slab(a.root_box[0], a.root_box[1], a.root_box[2], a.root_box[3], a.root_box[4], a.root_box[5], r, tcur, tn))
+        return found;
+    uint32_t ref = a.wide_root;
+    uint32_t sp = 0;
+    for (;;) {
+        c.v[kNodesVisited]++;
+        if (!(ref & kLeafFlag)) {
+            c.v[kInteriorVisited]++;
+            const float4 *q = wn + 8 * (size_t)ref;
+            const float4 x0 = q[0], x1 = q[1], y0 = q[2], y1 = q[3], z0 = q[4], z1 = q[5];
+            const uint4 rf = ((const uint4 *)q)[6];
+            // one sort key per child slot: miss flag, entry distance in an
+            // order-preserving encoding, slot index (ties keep slot order);
+            // sorted by a 5-comparator network, all in registers
+            uint64_t key[4];
+            float tk[4];
+            uint32_t nh = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const float mnx = k == 0 ? x0.x : k == 1 ? x0.y : k == 2 ? x0.z : x0.w;
+                const float mxx = k == 0 ? x1.x : k == 1 ? x1.y : k == 2 ? x1.z : x1.w;
+                const float mny = k == 0 ? y0.x : k == 1 ? y0.y : k == 2 ? y0.z : y0.w;
+                const float mxy = k == 0 ? y1.x : k == 1 ? y1.y : k == 2 ? y1.z : y1.w;
+                const float mnz = k == 0 ? z0.x : k == 1 ? z0.y : k == 2 ? z0.z : z0.w;
+                const float mxz = k == 0 ? z1.x : k == 1 ? z1.y : k == 2 ? z1.z : z1.w;
+                const uint32_t rk = k == 0 ? rf.x : k == 1 ? rf.y : k == 2 ? rf.z : rf.w;
+                bool h = false;
+                float t = 0.0f;
+                if (rk != kNone) {
+                    c.v[kBoxTests]++;
+                    h = slab(mnx, mny, mnz, mxx, mxy, mxz, r, tcur, t);
+                }
+                const uint32_t u = __float_as_uint(t);
+                const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+                key[k] = ((uint64_t)(h ? 0u : 1u) << 40) | ((uint64_t)ord << 2) | (uint64_t)k;
+                tk[k] = t;
+                nh += h ? 1u : 0u;
+            }
+#define HRPP_CSWAP(i, j) { const uint64_t lo_ = key[i] < key[j] ? key[i] : key[j]; \
+                           const uint64_t hi_ = key[i] < key[j] ? key[j] : key[i]; key[i] = lo_; key[j] = hi_; }
+            HRPP_CSWAP(0, 1) HRPP_CSWAP(2, 3) HRPP_CSWAP(0, 2) HRPP_CSWAP(1, 3) HRPP_CSWAP(1, 2)
+#undef HRPP_CSWAP
+            if (nh > 0) {
+                if (sp + nh - 1 > cap) { atomicOr(a.error, 1u); return found; }
+                // push the hit children farthest first; visit the nearest
+#pragma unroll
+                for (int j = 3; j >= 0; j--) {
+                    const uint32_t k = (uint32_t)(key[j] & 3u);
+                    const uint32_t rk = k == 0 ? rf.x : k == 1 ? rf.y : k == 2 ? rf.z : rf.w;
+                    const float t = k == 0 ? tk[0] : k == 1 ? tk[1] : k == 2 ? tk[2] : tk[3];
+                    if ((uint32_t)j >= nh) continue;
+                    if (j == 0) {
+                        ref = rk;
+                    } else {
+                        stk_node[sp * stride] = rk;
+                        if constexpr (!ANY) stk_t[sp * stride] = t;
+                        sp++;
+                    }
+                }
+                continue;
+            }
+        } else {
+            c.v[kLeafVisited]++;
+            if (test_leaf<ANY>(tris, ref & ~kLeafFlag, r, b, c)) {
+                found = true;
+                if constexpr (ANY) return true;
+                tcur = b.t;
+            }
+        }
+        for (;;) {
+            if (sp == 0) return found;
+            sp--;
+            if constexpr (ANY) break;
+            else if (stk_t[sp * stride] <= tcur * far_pad()) break;
+        }
+        ref = stk_node[sp * stride];
+    }
+}
+
+template <bool ANY, bool STATS>
+__global__ __launch_bounds__(128) void k_traverse_wide(TraceArgs a, uint32_t count) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t stride = blockDim.x;
+    const uint32_t cap = a.stack_cap;
+    uint32_t *stk_node = lds + threadIdx.x;
+    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    Counters c;
+    c.zero();
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step) {
+        float4 ra, rb;
+        RayState r = load_ray((const float4 *)a.rays, i, ra, rb);
+        c.v[kRays]++;
+        if (!ray_is_valid(ra, rb)) {
+            c.v[kInvalid]++;
+            write_result<ANY>(a, i, false, Best{});
+            continue;
+        }
+        set_inverse(r);
+        Best b;
+        b.t = __builtin_inff(); b.u = 0.0f; b.v = 0.0f; b.prim = kNone; b.leaf = kNone;
+        const bool hit = traverse_wide<ANY>(a, r, b, c, stk_node, stk_t, stride, cap);
+        write_result<ANY>(a, i, hit, b);
+        if (hit) c.v[kHits]++;
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+// ---------------------------------------------------------------------------
 // Plain traversal: every ray of [0, count), persistent grid-stride loop.
 // ---------------------------------------------------------------------------
 template <bool ANY, bool STATS>
@@ -937,7 +1064,7 @@ struct ProfScope {
 const char *kernel_kind_name(int k) {
     static const char *names[kNumKernelKinds] = {"k_predict", "k_traverse_queue", "k_traverse_plain",
                                                  "k_update_classify", "k_update_apply", "k_update_finish",
-                                                 "k_fill32"};
+                                                 "k_fill32", "k_traverse_wide"};
     return (k >= 0 && k < kNumKernelKinds) ? names[k] : "unknown";
 }
 
@@ -1040,6 +1167,20 @@ void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool 
             if (st) launch_epoch<false, false, true>(a, base, cnt, s);
             else    launch_epoch<false, false, false>(a, base, cnt, s);
         }
+    }
+}
+
+void launch_wide(const TraceArgs &a, uint32_t n, bool any, hipStream_t s) {
+    const size_t lds = (size_t)(any ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
+    const uint32_t blocks = std::min<uint32_t>(ceil_div(n, 128), a.max_blocks);
+    const bool st = a.stats != nullptr;
+    ProfScope p(kKindTraverseWide, s);
+    if (any) {
+        if (st) hipLaunchKernelGGL((k_traverse_wide<true, true>), dim3(blocks), dim3(128), lds, s, a, n);
+        else    hipLaunchKernelGGL((k_traverse_wide<true, false>), dim3(blocks), dim3(128), lds, s, a, n);
+    } else {
+        if (st) hipLaunchKernelGGL((k_traverse_wide<false, true>), dim3(blocks), dim3(128), lds, s, a, n);
+        else    hipLaunchKernelGGL((k_traverse_wide<false, false>), dim3(blocks), dim3(128), lds, s, a, n);
     }
 }
 

@@ -35,7 +35,8 @@ EXPORTED = [
     "hrpp_trace_anyhit", "hrpp_trace_closest", "hrpp_get_error", "hrpp_status_string",
     "hrpp_profile_start", "hrpp_profile_stop", "hrpp_batch_required_bytes", "hrpp_batch_create",
     "hrpp_batch_launch", "hrpp_batch_destroy", "hrpp_serve_create", "hrpp_serve_submit", "hrpp_serve_poll",
-    "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy",
+    "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy", "hrpp_bvh_wide_info",
+    "hrpp_bvh_wide_export", "hrpp_trace_wide_anyhit", "hrpp_trace_wide_closest",
 ]
 
 
@@ -113,6 +114,10 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_trace_anyhit.argtypes = [vp, vp, vp, u32, vp, vp, vp]
     lib.hrpp_trace_closest.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
     lib.hrpp_get_error.argtypes = [vp, vp]
+    lib.hrpp_bvh_wide_info.argtypes = [vp, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
+    lib.hrpp_bvh_wide_export.argtypes = [vp, vp, sz]
+    lib.hrpp_trace_wide_anyhit.argtypes = [vp, vp, u32, vp, vp, vp]
+    lib.hrpp_trace_wide_closest.argtypes = [vp, vp, u32, vp, vp, vp]
     lib.hrpp_profile_stop.argtypes = [vp, u32, C.POINTER(u32)]
     lib.hrpp_batch_required_bytes.restype = sz
     lib.hrpp_batch_required_bytes.argtypes = [u32]
@@ -171,6 +176,21 @@ class BVH:
         self.buffer = None
         if device is not None:
             self.upload(device)
+
+    def wide_info(self) -> dict:
+        """The 4-wide tree of the plain-traversal baseline: nodes, root reference, stack need, depth."""
+        n, r, k, d = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(load_library().hrpp_bvh_wide_info(self.handle, C.byref(n), C.byref(r), C.byref(k), C.byref(d)),
+               "hrpp_bvh_wide_info")
+        return dict(num_nodes=n.value, root_ref=r.value, stack_need=k.value, depth=d.value)
+
+    def wide_export(self) -> np.ndarray:
+        """The wide nodes as uint32 [nodes, 32] (layout in include/hrpp.h)."""
+        m = self.wide_info()["num_nodes"]
+        out = np.zeros((m, 32), np.uint32)
+        _check(load_library().hrpp_bvh_wide_export(self.handle, out.ctypes.data if m else None, out.size),
+               "hrpp_bvh_wide_export")
+        return out
 
     def upload(self, device: str = "cuda"):
         self._raw, self.buffer = _aligned(self.device_bytes, device)
@@ -297,6 +317,32 @@ def trace_closest(bvh: BVH, pred: Predictor | None, rays: torch.Tensor, mode: st
                                              rays.data_ptr(), n, CLOSEST_MODES[mode], out.data_ptr(),
                                              stats.data_ptr() if stats is not None else None, _stream()),
            "hrpp_trace_closest")
+    return out
+
+
+def trace_wide_anyhit(bvh: BVH, rays: torch.Tensor, out: torch.Tensor | None = None,
+                      stats: torch.Tensor | None = None) -> torch.Tensor:
+    """Any-hit flags from plain traversal of the 4-wide tree (the baseline)."""
+    _rays_ok(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=rays.device)
+    _check(load_library().hrpp_trace_wide_anyhit(bvh.handle, rays.data_ptr(), n, out.data_ptr(),
+                                                 stats.data_ptr() if stats is not None else None, _stream()),
+           "hrpp_trace_wide_anyhit")
+    return out
+
+
+def trace_wide_closest(bvh: BVH, rays: torch.Tensor, out: torch.Tensor | None = None,
+                       stats: torch.Tensor | None = None) -> torch.Tensor:
+    """Exact closest hits from plain traversal of the 4-wide tree (the baseline)."""
+    _rays_ok(rays)
+    n = rays.shape[0]
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    _check(load_library().hrpp_trace_wide_closest(bvh.handle, rays.data_ptr(), n, out.data_ptr(),
+                                                  stats.data_ptr() if stats is not None else None, _stream()),
+           "hrpp_trace_wide_closest")
     return out
 
 

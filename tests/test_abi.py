@@ -108,3 +108,92 @@ def test_no_cpu_fallback_in_product_package():
             src = open(os.path.join(pkg, fn)).read()
             assert "oracle" not in src.replace("# ", "").split("\n", 0)[0] or True
             assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+def _python_wide(e):
+    """The 4-wide collapse written out from its definition (include/hrpp.h):
+    start from a binary node's two children; while fewer than four, replace the
+    interior child of largest half area (double; ties to the earlier child) by
+    its two children, in place; number wide nodes in depth-first pre-order."""
+    NONE = 0xFFFFFFFF
+    box, right, first, count = e["box"], e["right"], e["first"], e["count"]
+    words = []
+
+    def area(i):
+        b = box[i].astype(np.float64)
+        dx, dy, dz = b[3] - b[0], b[4] - b[1], b[5] - b[2]
+        return dx * dy + dy * dz + dz * dx
+
+    def leaf_ref(i):
+        return 0x80000000 | (int(first[i]) << 3) | (int(count[i]) - 1)
+
+    def emit(i):
+        ch = [i + 1, int(right[i])]
+        while len(ch) < 4:
+            inner = [k for k, c in enumerate(ch) if right[c] != NONE]
+            if not inner:
+                break
+            k = max(inner, key=lambda k: (area(ch[k]), -k))
+            c = ch[k]
+            ch[k:k + 1] = [c + 1, int(right[c])]
+        wid = len(words)
+        words.append(np.zeros(32, np.uint32))
+        for k in range(4):
+            if k < len(ch):
+                b = box[ch[k]].view(np.uint32)
+                for a, comp in enumerate((0, 3, 1, 4, 2, 5)):
+                    words[wid][4 * a + k] = b[comp]
+                words[wid][24 + k] = leaf_ref(ch[k]) if right[ch[k]] == NONE else emit(ch[k])
+            else:
+                words[wid][24 + k] = NONE
+        return wid
+
+    if right[0] == NONE:
+        return np.zeros((0, 32), np.uint32), leaf_ref(0)
+    emit(0)
+    return np.stack(words), 0
+
+
+def test_wide_tree_matches_its_definition_and_is_valid():
+    hrpp = pytest.importorskip("paper_1910_01304_amd")
+    for tris in (sg.triangle_soup(1, 256), sg.triangle_soup(3, 1), sg.triangle_soup(2, 7),
+                 sg.scaled_terrain_scene(5, 20000)[0]):
+        for leaf_max in (1, 4):
+            b = hrpp.BVH(tris, leaf_max=leaf_max, device=None)
+            e = b.export()
+            info = b.wide_info()
+            words = b.wide_export()
+            want, root = _python_wide(e)
+            assert info["root_ref"] == root and np.array_equal(words, want)
+            if root & 0x80000000:
+                continue
+            # every binary leaf exactly once; each node's box is the exact union of
+            # its children's boxes; stack need and depth bound every traversal
+            leaves = {(int(e["first"][i]) << 3) | (int(e["count"][i]) - 1)
+                      for i in np.nonzero(e["right"] == 0xFFFFFFFF)[0]}
+            seen = []
+
+            def walk(n):
+                refs = words[n, 24:28]
+                nch = int(np.count_nonzero(refs != 0xFFFFFFFF))
+                assert 2 <= nch <= 4 and np.all(refs[nch:] == 0xFFFFFFFF)
+                need, depth = 0, 0
+                for k in range(nch):
+                    ref = int(refs[k])
+                    if ref & 0x80000000:
+                        seen.append(ref & 0x7FFFFFFF)
+                    else:
+                        cb = words[ref, 24:28]
+                        m = cb != 0xFFFFFFFF
+                        lo = [words[ref, 4 * a:4 * a + 4].view(np.float32)[m].min() for a in (0, 2, 4)]
+                        hi = [words[ref, 4 * a:4 * a + 4].view(np.float32)[m].max() for a in (1, 3, 5)]
+                        assert np.array_equal(np.array(lo + hi, np.float32),
+                                              np.array([words[n, 4 * a + k].view(np.float32)
+                                                        for a in (0, 2, 4, 1, 3, 5)], np.float32))
+                        cn, cd = walk(ref)
+                        need, depth = max(need, cn), max(depth, cd)
+                return nch - 1 + need, depth + 1
+
+            need, depth = walk(0)
+            assert sorted(seen) == sorted(leaves)
+            assert info["stack_need"] == need and info["depth"] == depth

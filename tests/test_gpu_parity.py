@@ -174,6 +174,86 @@ def test_terrain_table_shapes(hrpp, small_terrain, cfg):
 
 
 # ---------------------------------------------------------------------------
+# Plain-traversal baseline on the 4-wide tree: results equal the oracle's
+# plain traversal (any-hit flags, exact closest hits); the per-ray counts
+# (rays, invalid, hits, traversals) match, the visit counts are its own
+# ---------------------------------------------------------------------------
+
+def wide_case(hrpp, name, tris, rays, query="any", leaf_max=4):
+    import torch
+    _say(f"{name}: wide {query}, {tris.shape[0]} tris, {rays.shape[0]} rays")
+    bvh = hrpp.BVH(tris, leaf_max=leaf_max)
+    ob = oracle.build_sah(tris, leaf_max=leaf_max)
+    vtx = oracle.bvh_vertices(tris, ob)
+    r = torch.from_numpy(np.ascontiguousarray(rays)).cuda()
+    st = hrpp.new_stats()
+    if query == "any":
+        got = hrpp.trace_wide_anyhit(bvh, r, stats=st)
+        want, ws = oracle.trace(ob, tris, rays, query="any", vtx=vtx)
+    else:
+        got = hrpp.trace_wide_closest(bvh, r, stats=st)
+        want, ws = oracle.trace(ob, tris, rays, query="closest", mode="exact", vtx=vtx)
+    torch.cuda.synchronize()
+    hrpp.get_error(bvh)
+    assert_same_result(query, got.cpu().numpy(), want)
+    gs = hrpp.stats_dict(st)
+    for k in ("rays", "invalid", "hits", "traversals"):
+        assert gs[k] == ws[k], (k, gs[k], ws[k])
+    return gs, ws
+
+
+def test_wide_tiny_and_edges(hrpp):
+    tris, rays = sg.tiny_workload()
+    wide_case(hrpp, "tiny", tris, rays)
+    rc = rays.copy()
+    rc[:, 7] = np.inf
+    wide_case(hrpp, "tiny", tris, rc, "closest")
+    for lm in (1, 8):
+        wide_case(hrpp, f"tiny leaf_max {lm}", tris, rc, "closest", leaf_max=lm)
+    # one triangle (the root is a leaf), invalid rays
+    one = sg.triangle_soup(3, 1)
+    bad = rays[:64].copy()
+    bad[::4, 4:7] = 0.0
+    bad[1::4, 0] = np.nan
+    bad[2::4, 3] = 2.0
+    wide_case(hrpp, "one triangle, invalid rays", one, bad)
+    wide_case(hrpp, "one triangle, invalid rays", one, bad, "closest")
+    import torch
+    bvh = hrpp.BVH(tris)
+    st = hrpp.new_stats()
+    empty = torch.empty((0, 8), dtype=torch.float32, device="cuda")
+    hrpp.trace_wide_anyhit(bvh, empty, stats=st)
+    hrpp.trace_wide_closest(bvh, empty, stats=st)
+    torch.cuda.synchronize()
+    assert all(v == 0 for v in hrpp.stats_dict(st).values())
+
+
+def test_wide_terrain(hrpp, small_terrain):
+    tris, prim = small_terrain
+    gs, ws = wide_case(hrpp, "terrain primary", tris, prim, "closest")
+    assert gs["interior_visited"] < ws["interior_visited"]
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    t, p = he[:, 0], he[:, 3].view(np.uint32)
+    shadow = sg.shadow_rays_from_hits(tris, prim, t, p, seed=2)
+    wide_case(hrpp, "terrain shadow", tris, shadow)
+    ao = sg.ao_rays_from_hits(tris, prim[:4000], t[:4000], p[:4000], seed=3, samples=8,
+                              tmax=0.05 * sg.scene_diagonal(tris))
+    wide_case(hrpp, "terrain ao", tris, ao)
+
+
+def test_wide_full_size(hrpp, full_terrain):
+    w = sg.AT_SCALE
+    tris, prim = full_terrain
+    wide_case(hrpp, "full primary", tris, prim, "closest")
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
+                                      light_center=w["light_center"], light_size=w["light_size"])
+    wide_case(hrpp, "full shadow", tris, shadow)
+
+
+# ---------------------------------------------------------------------------
 # Replacement policies (FIFO eviction, resident-tag priority)
 # ---------------------------------------------------------------------------
 
