@@ -212,7 +212,9 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc);
 hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf,
                                   size_t bytes, void *stream, hrpp_predictor **out);
 
-/* Enqueue a reset: every entry empty (all bytes 0xFF), scratch cleared. */
+/* Enqueue a reset: every entry empty (all bytes 0xFF).  The per-epoch
+ * scratch (fallback queue, records, fresh-id lists) is left cleared by every
+ * epoch, so it is cleared here only after creation or a failed launch. */
 hrpp_status hrpp_predictor_reset(hrpp_predictor *pred, void *stream);
 
 /* Copy the table to host memory after the work on `stream` (synchronises

@@ -293,11 +293,16 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc) {
 hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
     if (!p) return HRPP_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t E = p->desc.epoch_rays;
     launch_fill32(static_cast<uint32_t *>(p->d_table), p->table_bytes / 4, kNone, s);
-    launch_fill32(p->d_topw, E * p->desc.ways, kNone, s);
-    launch_fill32(p->d_rec_idx, E, kNone, s);
     launch_fill32(p->d_ctrl, 64, 0u, s);
+    if (p->scratch_dirty) {
+        // every epoch leaves the fresh-id lists and record slots cleared; they
+        // are cleared here only at creation and after a failed launch
+        const size_t E = p->desc.epoch_rays;
+        launch_fill32(p->d_topw, E * p->desc.ways, kNone, s);
+        launch_fill32(p->d_rec_idx, E, kNone, s);
+        p->scratch_dirty = false;
+    }
     p->empty = true;
     return check(hipGetLastError());
 }
@@ -445,8 +450,12 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
     const TraceArgs a = make_args(bvh, pred, d_rays, d_occ, d_hits, d_stats);
     launch_trace(a, n, any, exact, pred != nullptr, pred ? pred->desc.epoch_rays : n, pred && pred->empty,
                  static_cast<hipStream_t>(stream));
-    if (pred) pred->empty = false;
-    return check(hipGetLastError());
+    const hrpp_status ls = check(hipGetLastError());
+    if (pred) {
+        pred->empty = false;
+        if (ls != HRPP_OK) pred->scratch_dirty = true;
+    }
+    return ls;
 }
 
 hrpp_status hrpp_trace_anyhit(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
@@ -488,6 +497,7 @@ hrpp_status hrpp_trace_wide_closest(const hrpp_bvh *bvh, const hrpp_ray *d_rays,
 // ---------------------------------------------------------------------------
 struct hrpp_batch {
     std::vector<BatchJob> jobs;
+    std::vector<hrpp_predictor *> preds;    // the jobs' predictors (host state: scheduling hints, scratch)
     std::vector<uint32_t> ids;
     std::vector<BatchGroup> groups;
     uint32_t max_rounds = 0;
@@ -535,6 +545,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
         bj.n = J.n;
         bj.epoch = J.pred ? J.pred->desc.epoch_rays : std::max(1u, J.n);
         b->jobs.push_back(bj);
+        if (J.pred) b->preds.push_back(J.pred);
         if (J.pred) kind_of[j] = any ? kBatchAnyHrpp : (J.mode == HRPP_CLOSEST_EXACT ? kBatchExactHrpp : kBatchPaperHrpp);
         else kind_of[j] = any ? kBatchAnyPlain : kBatchClosestPlain;
     }
@@ -595,9 +606,19 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
     return HRPP_OK;
 }
 
+static hrpp_status batch_launch(hrpp_batch *b, uint32_t use_graph, hipStream_t s);
+
 hrpp_status hrpp_batch_launch(hrpp_batch *b, uint32_t use_graph, void *stream) {
     if (!b) return HRPP_EINVAL;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hrpp_status st = batch_launch(b, use_graph, static_cast<hipStream_t>(stream));
+    for (hrpp_predictor *p : b->preds) {
+        p->empty = false;
+        if (st != HRPP_OK) p->scratch_dirty = true;
+    }
+    return st;
+}
+
+static hrpp_status batch_launch(hrpp_batch *b, uint32_t use_graph, hipStream_t s) {
     if (!use_graph) {
         launch_batch(b->d_jobs, b->d_ids, b->groups, b->max_rounds, max_persistent_blocks(), s);
         return check(hipGetLastError());

@@ -78,6 +78,7 @@ struct hrpp_predictor {
     uint64_t bvh_uid;
     uint32_t bvh_tris, bvh_nodes;  // sizes of the BVH the table indexes (import checks slots against them)
     bool empty = true;             // reset and not traced or imported since (scheduling hint only)
+    bool scratch_dirty = true;     // fresh-id lists / record slots need clearing (creation, failed launch)
     hrpp_predictor_desc desc;
     uint32_t entry_bytes;       // 32 or 64
     float bmin[3], scale[3];    // hash grid over the BVH root box

@@ -799,9 +799,11 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
     Counters c;
     c.zero();
     const uint32_t i = bx * blockDim.x + threadIdx.x;
+    const uint32_t W = a.ways;
+    // a fresh record's insertion: the owner's list and the id to insert
+    uint32_t ins_owner = kNone, ins_leaf = kNone, free_slots = 0;
     if (i < count && a.rec_idx[i] != kNone) {
         const uint32_t idx = a.rec_idx[i];
-        const uint32_t W = a.ways;
         const uint32_t *e = entry_ptr(a, idx);
         const uint32_t owner = e[2 + W];                // smallest ray id (claim)
         // with the resident policy an entry may have no claim: every record
@@ -827,29 +829,38 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
                 status = kRecFresh;
                 // room for new ids after this epoch's claim: the free slots,
                 // or every slot with FIFO eviction
-                uint32_t free_slots = W;
+                free_slots = W;
                 if (*(const uint64_t *)e == kstar && !(a.policy & 1u)) {
                     uint32_t used = 0;
                     while (used < W && e[2 + used] != kNone) used++;
                     free_slots = W - used;
                 }
-                // sorted insertion of `leaf` into the owner's list of the
-                // free_slots smallest fresh leaves; list values only ever
-                // decrease, so a plain read that is already <= x lets us skip
-                // the atomic at that position
-                uint32_t *list = a.topw + (size_t)(owner - base) * W;
-                uint32_t x = leaf;
-                for (uint32_t s = 0; s < free_slots && x != kNone; s++) {
-                    const uint32_t seen = __hip_atomic_load(&list[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (seen == x) break;            // already listed
-                    if (seen < x) continue;          // x cannot go here
-                    const uint32_t old = atomicMin(&list[s], x);
-                    if (old == x) break;
-                    if (old > x) x = old;            // x took this place; carry the old value on
-                }
+                ins_owner = owner;
+                ins_leaf = leaf;
             }
         }
         a.rec_status[i] = status;
+    }
+    // Coherent rays give runs of identical (owner, id) insertions; inserting
+    // an id twice into a sorted duplicate-free list changes nothing, so a
+    // record whose neighbour lane carries the same pair leaves it to that lane.
+    const uint32_t lane = __lane_id();
+    const uint32_t prev_owner = __shfl_up(ins_owner, 1), prev_leaf = __shfl_up(ins_leaf, 1);
+    const bool dup = lane > 0 && prev_owner == ins_owner && prev_leaf == ins_leaf;
+    if (ins_owner != kNone && !dup) {
+        // sorted insertion of the id into the owner's list of the free_slots
+        // smallest fresh ids; list values only ever decrease, so a plain read
+        // that is already <= x lets us skip the atomic at that position
+        uint32_t *list = a.topw + (size_t)(ins_owner - base) * W;
+        uint32_t x = ins_leaf;
+        for (uint32_t s = 0; s < free_slots && x != kNone; s++) {
+            const uint32_t seen = __hip_atomic_load(&list[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (seen == x) break;            // already listed
+            if (seen < x) continue;          // x cannot go here
+            const uint32_t old = atomicMin(&list[s], x);
+            if (old == x) break;
+            if (old > x) x = old;            // x took this place; carry the old value on
+        }
     }
     flush_counters<STATS>(c, a.stats);
 }
