@@ -186,9 +186,10 @@ def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
         if kind == "k_traverse_plain":
             tot += n * (RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * st["tri_tests"]
         elif kind == "k_predict":
-            # ray, table entry, predicted leaf boxes and triangles, results of successes, queue appends,
-            # and the fallback traversals run in place (nodes, triangles, result, record + claim)
-            tot += (n * RAY_B + st["lookups"] * entry_b + LEAFBOX_B * st["pred_box_tests"]
+            # ray, table entry (none in the first epoch after a reset, whose table is known to be
+            # empty), predicted leaf boxes and triangles, results of successes, queue appends, and the
+            # fallback traversals run in place (nodes, triangles, result, record + claim)
+            tot += (n * RAY_B + (st["lookups"] - st["empty_lookups"]) * entry_b + LEAFBOX_B * st["pred_box_tests"]
                     + TRI_B * st["pred_tri_tests"] + st["pred_hits"] * out_b + q_trav * 8
                     + (st["traversals"] - q_trav) * out_b + NODE_B * (st["interior_visited"] - q_int)
                     + TRI_B * (trav_tri - q_tri) + (st["records"] - q_rec) * (16 + 4))

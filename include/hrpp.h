@@ -132,14 +132,17 @@ typedef struct {
  *                               tri_tests / records done by the fallback-queue
  *                               kernel (the rest of the fallback work runs
  *                               inside the prediction kernel; the split
- *                               follows inline_lanes) */
+ *                               follows inline_lanes)
+ *  empty_lookups                schedule counter: lookups answered without
+ *                               reading the table, in the first epoch after a
+ *                               reset (the table is known to be empty) */
 #define HRPP_STATS_SLOTS 32
 typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
              nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
              records, tag_claims, leaf_inserts, dropped, conflicts, pred_leaf_visited, pred_tri_tests,
              pred_box_tests, evictions, queue_traversals, queue_interior_visited, queue_tri_tests,
-             queue_records, reserved[5];
+             queue_records, empty_lookups, reserved[4];
 } hrpp_stats;
 
 enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };

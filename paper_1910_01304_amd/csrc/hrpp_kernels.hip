@@ -729,6 +729,46 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
 }
 
 // ---------------------------------------------------------------------------
+// The first epoch after a reset: the table is empty, so every valid ray's
+// lookup is negative and every valid ray traverses.  Same counts, records
+// and claims as the prediction kernel followed by the queue, without the
+// entry reads and the queue; a persistent grid-stride loop like plain
+// traversal.
+// ---------------------------------------------------------------------------
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base, uint32_t count) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t stride = blockDim.x;
+    const uint32_t cap = a.stack_cap;
+    uint32_t *stk_node = lds + threadIdx.x;
+    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    Counters c;
+    c.zero();
+    const uint32_t step = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step) {
+        const uint32_t rid = base + i;
+        float4 ra, rb;
+        load_ray((const float4 *)a.rays, rid, ra, rb);
+        c.v[kRays]++;
+        if (!ray_is_valid(ra, rb)) {
+            c.v[kInvalid]++;
+            write_result<ANY>(a, rid, false, Best{});
+            continue;
+        }
+        c.v[kLookups]++;
+        c.v[kEmptyLookups]++;
+        if (!ANY && EXACT) {
+            // no predicted hit seeds the interval
+            float4 h;
+            h.x = __builtin_inff(); h.y = 0.0f; h.z = 0.0f; h.w = __uint_as_float(kNone);
+            ((float4 *)a.hits)[rid] = h;
+        }
+        traverse_one<ANY, EXACT, true>(a, base, rid, kNone, c, stk_node, stk_t, stride, cap);
+    }
+    flush_counters<STATS>(c, a.stats);
+}
+
+// ---------------------------------------------------------------------------
 // Traversal of the epoch's fallback queue (its length is read on the device;
 // the grid covers the epoch, lanes past the queue's end exit at once).
 // ---------------------------------------------------------------------------
@@ -1107,29 +1147,36 @@ static inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b
 
 
 template <bool ANY, bool EXACT, bool STATS>
-static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, hipStream_t s) {
+static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool empty_table, hipStream_t s) {
     const uint32_t g256 = ceil_div(count, 256);
     const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
-    {
-        // with in-place traversal or predicted subtrees: blocks of 128 lanes
-        // with the traversal's LDS stack; otherwise 256 lanes and no LDS
+    const uint32_t persistent = std::min<uint32_t>(ceil_div(count, 128), a.max_blocks);
+    if (empty_table) {
+        // every valid ray traverses; no queue is filled
         ProfScope p(kKindPredict, s);
-        const bool inl = a.inline_min <= 64;
-        const dim3 g128(ceil_div(count, 128)), b128(128);
-        if (a.go_up != 0) {
-            if (inl) hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true, true>), g128, b128, lds, s, a, base, count);
-            else     hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true, false>), g128, b128, lds, s, a, base, count);
-        } else if (inl) {
-            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false, true>), g128, b128, lds, s, a, base, count);
-        } else {
-            hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false, false>), dim3(g256), dim3(256), 0, s, a, base,
+        hipLaunchKernelGGL((k_epoch_empty<ANY, EXACT, STATS>), dim3(persistent), dim3(128), lds, s, a, base, count);
+    } else {
+        {
+            // with in-place traversal or predicted subtrees: blocks of 128 lanes
+            // with the traversal's LDS stack; otherwise 256 lanes and no LDS
+            ProfScope p(kKindPredict, s);
+            const bool inl = a.inline_min <= 64;
+            const dim3 g128(ceil_div(count, 128)), b128(128);
+            if (a.go_up != 0) {
+                if (inl) hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true, true>), g128, b128, lds, s, a, base, count);
+                else     hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, true, false>), g128, b128, lds, s, a, base, count);
+            } else if (inl) {
+                hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false, true>), g128, b128, lds, s, a, base, count);
+            } else {
+                hipLaunchKernelGGL((k_predict<ANY, EXACT, STATS, false, false>), dim3(g256), dim3(256), 0, s, a,
+                                   base, count);
+            }
+        }
+        {
+            ProfScope p(kKindTraverseQueue, s);
+            hipLaunchKernelGGL((k_traverse_queue<ANY, EXACT, STATS>), dim3(persistent), dim3(128), lds, s, a, base,
                                count);
         }
-    }
-    {
-        ProfScope p(kKindTraverseQueue, s);
-        const uint32_t blocks = std::min<uint32_t>(ceil_div(count, 128), a.max_blocks);
-        hipLaunchKernelGGL((k_traverse_queue<ANY, EXACT, STATS>), dim3(blocks), dim3(128), lds, s, a, base, count);
     }
     {
         ProfScope p(kKindUpdateClassify, s);
@@ -1165,18 +1212,17 @@ void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool 
     for (uint32_t base = 0; base < n; base += epoch) {
         const uint32_t cnt = std::min(epoch, n - base);
         // an empty table predicts nothing: the first epoch after a reset
-        // traverses every ray in place
-        TraceArgs a = args;
-        if (base == 0 && empty_table) a.inline_min = 1;
+        // traverses every ray, with the dedicated kernel
+        const bool e0 = (base == 0 && empty_table);
         if (any) {
-            if (st) launch_epoch<true, false, true>(a, base, cnt, s);
-            else    launch_epoch<true, false, false>(a, base, cnt, s);
+            if (st) launch_epoch<true, false, true>(args, base, cnt, e0, s);
+            else    launch_epoch<true, false, false>(args, base, cnt, e0, s);
         } else if (exact) {
-            if (st) launch_epoch<false, true, true>(a, base, cnt, s);
-            else    launch_epoch<false, true, false>(a, base, cnt, s);
+            if (st) launch_epoch<false, true, true>(args, base, cnt, e0, s);
+            else    launch_epoch<false, true, false>(args, base, cnt, e0, s);
         } else {
-            if (st) launch_epoch<false, false, true>(a, base, cnt, s);
-            else    launch_epoch<false, false, false>(a, base, cnt, s);
+            if (st) launch_epoch<false, false, true>(args, base, cnt, e0, s);
+            else    launch_epoch<false, false, false>(args, base, cnt, e0, s);
         }
     }
 }

@@ -22,9 +22,10 @@ STAT_NAMES = [
     "records", "tag_claims", "leaf_inserts", "dropped", "conflicts", "pred_leaf_visited", "pred_tri_tests",
     "pred_box_tests", "evictions",
     # schedule counters (how much fallback work ran in the queue kernel), not part of the method
-    "queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records",
+    "queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records", "empty_lookups",
 ]
-SCHEDULE_STATS = ("queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records")
+SCHEDULE_STATS = ("queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records",
+                  "empty_lookups")
 STATS_SLOTS = 32
 CLOSEST_MODES = {"paper": 0, "exact": 1}
 EXPORTED = [
