@@ -512,6 +512,47 @@ def test_full_size_ao(hrpp, full_terrain, cfg):
     assert st["rays"] == 7372800
 
 
+def test_maximum_epoch_and_large_table(hrpp, full_terrain):
+    # the largest epoch (2^22 rays) over the 7,372,800 AO rays (one full epoch
+    # and a ragged one) with a 2^24-entry table, queue-only and in-place fallback
+    wi = sg.INCOHERENT
+    tris, _ = full_terrain
+    cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+    ob = oracle.build_sah(tris)
+    hh, _ = oracle.trace(ob, tris, cam, query="closest", mode="exact")
+    ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                              samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+    for inline in (65, 1):
+        _, st = check_case(hrpp, f"AO, epoch 2^22, table 2^24 x 4, inline {inline}", tris, ao,
+                           pred_cfg=(24, 4, 5, 6, 1 << 22, 0, 0, inline))
+        assert st["rays"] == 7372800 and st["pred_hits"] > 0
+
+
+def test_random_configurations(hrpp):
+    # random predictor configurations on small random scenes, every one against
+    # the oracle: hash mode, go-up level, replacement policy, fallback split,
+    # epoch (ragged), table shape, query and closest-hit mode
+    g = np.random.default_rng(2024)
+    for case in range(40):
+        seed = int(g.integers(1, 1 << 30))
+        n_tris = int(g.integers(1, 3000))
+        tris = sg.mixed_scene(seed, n_tris) if n_tris > 50 else sg.triangle_soup(seed, n_tris)
+        sh, ao = sg.secondary_rays_on_surface(tris, int(g.integers(1, 6000)), seed + 1)
+        rays = np.concatenate([sh, ao])
+        query = ["any", "closest"][int(g.integers(0, 2))]
+        mode = ["paper", "exact"][int(g.integers(0, 2))]
+        if query == "closest" and g.random() < 0.5:
+            rays = rays.copy()
+            rays[:, 7] = np.inf
+        hm = int(g.integers(0, 2))
+        q = int(g.integers(1, 8)) if hm else None
+        qo, qd = (q, q) if hm else (int(g.integers(1, 9)), int(g.integers(1, 9)))
+        cfg = (int(g.integers(1, 15)), int(g.integers(1, 9)), qo, qd, int(g.integers(1, 3000)), hm,
+               int(g.choice([0, 0, 1, 2, 5])), int(g.choice([0, 1, 16, 48, 64, 65])), int(g.integers(0, 4)))
+        check_case(hrpp, f"random {case}", tris, rays, query=query, mode=mode, pred_cfg=cfg,
+                   calls=int(g.integers(1, 3)), leaf_max=int(g.choice([1, 2, 4, 8])))
+
+
 def test_results_do_not_depend_on_stats(hrpp, small_terrain):
     # the benchmark times the path without counters; it must compute the same
     import torch
