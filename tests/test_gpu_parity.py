@@ -553,6 +553,36 @@ def test_random_configurations(hrpp):
                    calls=int(g.integers(1, 3)), leaf_max=int(g.choice([1, 2, 4, 8])))
 
 
+def test_epoch_aligned_split_calls_equal_one_call(hrpp, small_terrain):
+    # ray ids are call-relative and each call starts an epoch, so tracing the
+    # rays in two calls split at an epoch boundary computes exactly what one
+    # call computes (results, the method's counters, the table)
+    import torch
+    tris, prim = small_terrain
+    _say("split calls")
+    bvh = hrpp.BVH(tris)
+    r = torch.from_numpy(prim).cuda()
+    E = 4096
+    for query, mode in (("closest", "paper"), ("any", "paper"), ("closest", "exact")):
+        outs = []
+        for split in (None, 3 * E):
+            pred = hrpp.Predictor(bvh, 14, 8, 5, 6, E, inline_lanes=16)
+            st = hrpp.new_stats()
+            parts = [(0, r.shape[0])] if split is None else [(0, split), (split, r.shape[0])]
+            if query == "any":
+                out = torch.empty(r.shape[0], dtype=torch.uint8, device="cuda")
+                for a, b in parts:
+                    hrpp.trace_anyhit(bvh, pred, r[a:b], out=out[a:b], stats=st)
+            else:
+                out = torch.empty((r.shape[0], 4), dtype=torch.float32, device="cuda")
+                for a, b in parts:
+                    hrpp.trace_closest(bvh, pred, r[a:b], mode=mode, out=out[a:b], stats=st)
+            torch.cuda.synchronize()
+            d = {k: v for k, v in hrpp.stats_dict(st).items() if k not in hrpp.SCHEDULE_STATS}
+            outs.append((out.cpu().numpy().tobytes(), pred.export_raw().tobytes(), d))
+        assert outs[0] == outs[1], query
+
+
 def test_results_do_not_depend_on_stats(hrpp, small_terrain):
     # the benchmark times the path without counters; it must compute the same
     import torch
