@@ -95,9 +95,14 @@ CALIB_BYTES = 256 << 20
 
 
 def kernel_source_hash():
+    """Hash of the kernel source's code (comments and blank space removed),
+    so that traffic counters stay attached to the code they measured."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    src = open(KERNEL_SRC).read()
+    src = re.sub(r"//[^\n]*", "", src)
+    src = "\n".join(" ".join(line.split()) for line in src.splitlines() if line.strip())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def short_kernel_name(name):

@@ -2,15 +2,22 @@
 //
 // Per epoch of E rays (rays of epoch k see the table after epoch k-1):
 //   k_predict    one lane per ray: validate, hash, probe the table, test the
-//                predicted leaves; successes write their result, the rest
-//                are appended to the epoch's fallback queue (one atomic per
-//                wave).
-//   k_traverse_queue  stack traversal of the queued rays; emits one update
-//                record per traversed hit and claims the record's entry with
-//                a 32-bit atomicMin on the ray id (the smallest id owns it).
-//   k_traverse_plain  stack traversal of every ray (no predictor).
+//                predicted leaves (or walk the predicted subtrees, go-up
+//                level >= 1); successes write their result; a wave with
+//                enough failing rays traverses them in place, other waves
+//                append theirs to the epoch's fallback queue (one atomic per
+//                block on one of kSubQueues striped counters).
+//   k_epoch_empty  the first epoch after a reset (empty table): every valid
+//                ray traverses, in a persistent loop.
+//   k_traverse_queue  stack traversal of the queued rays.
+//                A traversed ray with a hit emits one update record and
+//                claims the record's entry with a 32-bit atomicMin on the ray
+//                id (the smallest id owns it), wherever it traversed.
 //   k_update_*   three passes over the epoch's records that turn the table
 //                of epoch k-1 into the table of epoch k.
+// Without a predictor:
+//   k_traverse_plain  stack traversal of every ray (binary tree).
+//   k_traverse_wide   the same on the 4-wide tree collapsed from it.
 //
 // Section references are to Demoullin, Gubran and Aamodt, "Hash-Based Ray
 // Path Prediction".  Every floating-point expression below is written in
@@ -338,8 +345,9 @@ __device__ __forceinline__ const uint32_t *entry_ptr(const TraceArgs &a, uint32_
 // ---------------------------------------------------------------------------
 
 // Prediction for ray `rid` ("Overview": hash, look up, evaluate the predicted
-// leaves).  Returns true if the ray must still traverse; then *seed_leaf is
-// the leaf of the best predicted hit (EXACT) or kNone.
+// leaves or, at go-up level >= 1, walk the predicted subtrees).  Returns true
+// if the ray must still traverse; then *seed_leaf is the leaf of the best
+// predicted hit (EXACT) or kNone.
 template <bool ANY, bool EXACT, bool SUBTREE>
 __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Counters &c, uint32_t &seed_leaf,
                                             uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
@@ -448,9 +456,10 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
     return true;   // "re-added to the ray pool" (section "Precision and Recall")
 }
 
-// Full traversal of ray `rid`.  HRPP: the ray came from the fallback queue
-// (already validated and counted); emit its update record and claim the
-// entry.  PLAIN: validate and count here.
+// Full traversal of ray `rid`.  HRPP: a fallback ray (already validated and
+// counted by the prediction step, from the queue, in place, or in the first
+// epoch after a reset); emit its update record and claim the entry.  PLAIN:
+// validate and count here.
 template <bool ANY, bool EXACT, bool HRPP>
 __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, uint32_t rid, uint32_t seed_leaf,
                                              Counters &c, uint32_t *stk_node, float *stk_t, uint32_t stride,
