@@ -440,6 +440,9 @@ def main():
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(d["gbs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
                     "traffic": int(traffic) if traffic is not None else None,
+                    # the measured HBM bytes of a launch over its duration, against the same peak
+                    "traffic_frac": (round(traffic / (d["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                     if traffic is not None else None),
                     "avg_launch_us": round(d["avg_us"], 2),
                     "algorithmic_bytes_per_launch": int(d["bytes_per_launch"])}
 
@@ -552,6 +555,7 @@ def main():
         "wide_plain_mrays_s": round(mrays(rays_per_step, ms_wide), 2),
         "speedup_vs_wide_plain": round(ms_wide / ms_hrpp, 4),
         "wall_ms_per_step": {"hrpp": round(wall_hrpp, 4), "plain": round(wall_plain, 4)},
+        "table_bytes": {"hit_all": int(pred_all.table_bytes), "hit_any": int(pred_any.table_bytes)},
         "pct_nodes_skipped": round(100.0 * (1 - nodes_h / nodes_p), 3),
         "pct_box_tests_skipped": round(100.0 * (1 - box_h / box_p), 3),
         "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "reference_epoch": ref_info,
