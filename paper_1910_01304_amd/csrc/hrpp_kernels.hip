@@ -790,13 +790,18 @@ __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t
     float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
     Counters c;
     c.zero();
+    // the sub-queue counts are final when this kernel starts (the prediction
+    // kernel before it wrote them): one uniform read per wave
+    static_assert(kSubQueues == 8, "the counts are read as two uint4");
     uint32_t cnt[kSubQueues];
     uint32_t total = 0;
+    const uint4 c0 = *(const uint4 *)&a.ctrl[0], c1 = *(const uint4 *)&a.ctrl[4];
+    cnt[0] = __builtin_amdgcn_readfirstlane(c0.x); cnt[1] = __builtin_amdgcn_readfirstlane(c0.y);
+    cnt[2] = __builtin_amdgcn_readfirstlane(c0.z); cnt[3] = __builtin_amdgcn_readfirstlane(c0.w);
+    cnt[4] = __builtin_amdgcn_readfirstlane(c1.x); cnt[5] = __builtin_amdgcn_readfirstlane(c1.y);
+    cnt[6] = __builtin_amdgcn_readfirstlane(c1.z); cnt[7] = __builtin_amdgcn_readfirstlane(c1.w);
 #pragma unroll
-    for (uint32_t k = 0; k < kSubQueues; k++) {
-        cnt[k] = *(volatile uint32_t *)&a.ctrl[k];
-        total += cnt[k];
-    }
+    for (uint32_t k = 0; k < kSubQueues; k++) total += cnt[k];
     const uint32_t step = gx * blockDim.x;
     for (uint32_t i = bx * blockDim.x + threadIdx.x; i < total; i += step) {
         // work item i -> (sub-queue, offset)
