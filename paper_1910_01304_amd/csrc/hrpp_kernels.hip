@@ -217,8 +217,10 @@ __device__ __forceinline__ bool test_leaf(const float4 *__restrict__ tris, uint3
 // child (left on a tie) is taken and the other pushed with its entry
 // distance; a popped node is visited only if its entry distance still passes
 // against the current tcur; leaves test triangles in BVH order.
-// The per-lane stack lives in LDS, lane-interleaved (slot * blockDim + lane)
-// so that the 64 lanes of a wave touch 64 consecutive dwords.
+// The per-lane stack lives in private memory (the cached scratch path):
+// sized to the deepest tree the library accepts, it leaves occupancy to the
+// registers, where an LDS stack of the same size limited closest-hit kernels
+// to 3 waves per SIMD.  Callers pass (pointer, stride 1, capacity = depth).
 // ---------------------------------------------------------------------------
 // walk(): the subtree of `ref`, whose own box the caller has tested; from
 // the root this is the whole traversal, from a predicted node (go-up level
@@ -630,13 +632,20 @@ __device__ __forceinline__ bool traverse_wide(const TraceArgs &a, const RayState
     }
 }
 
-template <bool ANY, bool STATS>
+// PRIV: the stack in per-lane private memory (backed by the cached scratch
+// path) instead of LDS, so that the wide tree's deep worst-case stack does
+// not limit occupancy; used when the stack need fits kWidePrivStack.
+constexpr uint32_t kWidePrivStack = 48;
+
+template <bool ANY, bool STATS, bool PRIV>
 __global__ __launch_bounds__(128) void k_traverse_wide(TraceArgs a, uint32_t count) {
     extern __shared__ uint32_t lds[];
-    const uint32_t stride = blockDim.x;
-    const uint32_t cap = a.stack_cap;
-    uint32_t *stk_node = lds + threadIdx.x;
-    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    uint32_t pn[PRIV ? kWidePrivStack : 1];
+    float pt[PRIV ? kWidePrivStack : 1];
+    const uint32_t stride = PRIV ? 1u : blockDim.x;
+    const uint32_t cap = PRIV ? kWidePrivStack : a.stack_cap;
+    uint32_t *stk_node = PRIV ? pn : lds + threadIdx.x;
+    float *stk_t = PRIV ? pt : (float *)(lds + cap * stride + threadIdx.x);
     Counters c;
     c.zero();
     const uint32_t step = gridDim.x * blockDim.x;
@@ -664,11 +673,10 @@ __global__ __launch_bounds__(128) void k_traverse_wide(TraceArgs a, uint32_t cou
 // ---------------------------------------------------------------------------
 template <bool ANY, bool STATS>
 __device__ __forceinline__ void body_traverse_plain(const TraceArgs &a, uint32_t count, uint32_t bx, uint32_t gx) {
-    extern __shared__ uint32_t lds[];
-    const uint32_t stride = blockDim.x;
-    const uint32_t cap = a.stack_cap;
-    uint32_t *stk_node = lds + threadIdx.x;
-    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    uint32_t stk_node[kMaxDepth];                // per-lane stack in private memory
+    float stk_t[ANY ? 1 : kMaxDepth];
+    const uint32_t stride = 1;
+    const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
     const uint32_t step = gx * blockDim.x;
@@ -692,13 +700,12 @@ __global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t co
 template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
 __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     // SUBTREE (go-up level >= 1) walks predicted nodes and INLINE traverses
-    // failing rays in place, both with the LDS stack of the traversal
-    // kernels; without either the kernel needs no LDS
-    extern __shared__ uint32_t lds[];
-    const uint32_t stride = blockDim.x;
-    const uint32_t cap = a.stack_cap;
-    uint32_t *stk_node = lds + threadIdx.x;
-    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    // failing rays in place, both with a traversal stack; without either the
+    // stack is unused
+    uint32_t stk_node[kMaxDepth];                // per-lane stack in private memory
+    float stk_t[ANY ? 1 : kMaxDepth];
+    const uint32_t stride = 1;
+    const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
     const uint32_t i = bx * blockDim.x + threadIdx.x;
@@ -746,11 +753,10 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
 // ---------------------------------------------------------------------------
 template <bool ANY, bool EXACT, bool STATS>
 __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base, uint32_t count) {
-    extern __shared__ uint32_t lds[];
-    const uint32_t stride = blockDim.x;
-    const uint32_t cap = a.stack_cap;
-    uint32_t *stk_node = lds + threadIdx.x;
-    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    uint32_t stk_node[kMaxDepth];                // per-lane stack in private memory
+    float stk_t[ANY ? 1 : kMaxDepth];
+    const uint32_t stride = 1;
+    const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
     const uint32_t step = gridDim.x * blockDim.x;
@@ -783,11 +789,10 @@ __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base,
 // ---------------------------------------------------------------------------
 template <bool ANY, bool EXACT, bool STATS>
 __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
-    extern __shared__ uint32_t lds[];
-    const uint32_t stride = blockDim.x;
-    const uint32_t cap = a.stack_cap;
-    uint32_t *stk_node = lds + threadIdx.x;
-    float *stk_t = (float *)(lds + cap * stride + threadIdx.x);
+    uint32_t stk_node[kMaxDepth];                // per-lane stack in private memory
+    float stk_t[ANY ? 1 : kMaxDepth];
+    const uint32_t stride = 1;
+    const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
     // the sub-queue counts are final when this kernel starts (the prediction
@@ -1163,7 +1168,7 @@ static inline uint32_t ceil_div(uint32_t a, uint32_t b) { return (a + b - 1) / b
 template <bool ANY, bool EXACT, bool STATS>
 static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool empty_table, hipStream_t s) {
     const uint32_t g256 = ceil_div(count, 256);
-    const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
+    const size_t lds = 0;   // traversal stacks live in private memory
     const uint32_t persistent = std::min<uint32_t>(ceil_div(count, 128), a.max_blocks);
     if (empty_table) {
         // every valid ray traverses; no queue is filled
@@ -1172,7 +1177,7 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool
     } else {
         {
             // with in-place traversal or predicted subtrees: blocks of 128 lanes
-            // with the traversal's LDS stack; otherwise 256 lanes and no LDS
+            // (like the traversal kernels); otherwise 256 lanes
             ProfScope p(kKindPredict, s);
             const bool inl = a.inline_min <= 64;
             const dim3 g128(ceil_div(count, 128)), b128(128);
@@ -1186,7 +1191,9 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool
                                    base, count);
             }
         }
-        {
+        if (a.inline_min > 1) {
+            // (with inline_min 1 every wave that has a failing ray traverses
+            // in place, so the queue stays empty and is not launched)
             ProfScope p(kKindTraverseQueue, s);
             hipLaunchKernelGGL((k_traverse_queue<ANY, EXACT, STATS>), dim3(persistent), dim3(128), lds, s, a, base,
                                count);
@@ -1209,7 +1216,7 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool
 
 template <bool ANY, bool STATS>
 static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
-    const size_t lds = (size_t)(ANY ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
+    const size_t lds = 0;   // the traversal stack lives in private memory
     const uint32_t blocks = std::min<uint32_t>(ceil_div(n, 128), a.max_blocks);
     ProfScope p(kKindTraversePlain, s);
     hipLaunchKernelGGL((k_traverse_plain<ANY, STATS>), dim3(blocks), dim3(128), lds, s, a, n);
@@ -1242,16 +1249,26 @@ void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool 
 }
 
 void launch_wide(const TraceArgs &a, uint32_t n, bool any, hipStream_t s) {
-    const size_t lds = (size_t)(any ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
+    const bool priv = a.stack_cap <= kWidePrivStack;
+    const size_t lds = priv ? 0 : (size_t)(any ? 1 : 2) * a.stack_cap * 128 * sizeof(uint32_t);
     const uint32_t blocks = std::min<uint32_t>(ceil_div(n, 128), a.max_blocks);
     const bool st = a.stats != nullptr;
+    const dim3 g(blocks), b(128);
     ProfScope p(kKindTraverseWide, s);
-    if (any) {
-        if (st) hipLaunchKernelGGL((k_traverse_wide<true, true>), dim3(blocks), dim3(128), lds, s, a, n);
-        else    hipLaunchKernelGGL((k_traverse_wide<true, false>), dim3(blocks), dim3(128), lds, s, a, n);
+    if (priv) {
+        if (any) {
+            if (st) hipLaunchKernelGGL((k_traverse_wide<true, true, true>), g, b, 0, s, a, n);
+            else    hipLaunchKernelGGL((k_traverse_wide<true, false, true>), g, b, 0, s, a, n);
+        } else {
+            if (st) hipLaunchKernelGGL((k_traverse_wide<false, true, true>), g, b, 0, s, a, n);
+            else    hipLaunchKernelGGL((k_traverse_wide<false, false, true>), g, b, 0, s, a, n);
+        }
+    } else if (any) {
+        if (st) hipLaunchKernelGGL((k_traverse_wide<true, true, false>), g, b, lds, s, a, n);
+        else    hipLaunchKernelGGL((k_traverse_wide<true, false, false>), g, b, lds, s, a, n);
     } else {
-        if (st) hipLaunchKernelGGL((k_traverse_wide<false, true>), dim3(blocks), dim3(128), lds, s, a, n);
-        else    hipLaunchKernelGGL((k_traverse_wide<false, false>), dim3(blocks), dim3(128), lds, s, a, n);
+        if (st) hipLaunchKernelGGL((k_traverse_wide<false, true, false>), g, b, lds, s, a, n);
+        else    hipLaunchKernelGGL((k_traverse_wide<false, false, false>), g, b, lds, s, a, n);
     }
 }
 
@@ -1271,7 +1288,7 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
                                hipStream_t s) {
     const dim3 g256(ceil_div(g.max_epoch, 256), g.count), g128(std::min(ceil_div(g.max_epoch, 128), 4096u), g.count);
     const uint32_t *gid = ids + g.first_id;
-    const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
+    const size_t lds = 0;   // traversal stacks live in private memory
     const dim3 gp(ceil_div(g.max_epoch, 128), g.count);
     if (g.subtree)
         hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, true, true>), gp, dim3(128), lds, s, jobs, gid, r);
@@ -1287,7 +1304,7 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
 
 template <bool ANY, bool STATS>
 static void launch_batch_plain(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, hipStream_t s) {
-    const size_t lds = (size_t)(ANY ? 1 : 2) * g.max_cap * 128 * sizeof(uint32_t);
+    const size_t lds = 0;   // traversal stacks live in private memory
     hipLaunchKernelGGL((kb_traverse_plain<ANY, STATS>), dim3(g.total_blocks), dim3(128), lds, s, jobs,
                        ids + g.first_id, g.d_block_off, g.count);
 }
