@@ -200,8 +200,9 @@ hrpp_status hrpp_bvh_export(const hrpp_bvh *bvh, hrpp_bvh_canon *h_out);
 /* Release the handle (the caller's device buffer is not touched). */
 void hrpp_bvh_destroy(hrpp_bvh *bvh);
 
-/* Device bytes a predictor needs: the table (2^T entries of 32/64 B) plus
- * per-epoch scratch (fallback queue, update records, claim words). */
+/* Device bytes a predictor needs: the table (2^T entries of 32/64 B), one
+ * reset mark per 16 entries and per-epoch scratch (fallback queue, update
+ * records, fresh-id lists). */
 size_t hrpp_predictor_required_bytes(const hrpp_predictor_desc *desc);
 
 /* Bytes of the table alone (what hrpp_predictor_export copies). */
@@ -215,9 +216,12 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc);
 hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf,
                                   size_t bytes, void *stream, hrpp_predictor **out);
 
-/* Enqueue a reset: every entry empty (all bytes 0xFF).  The per-epoch
- * scratch (fallback queue, records, fresh-id lists) is left cleared by every
- * epoch, so it is cleared here only after creation or a failed launch. */
+/* Enqueue a reset: every entry empty (all bytes 0xFF).  The update marks
+ * each group of 16 entries in which it tags an empty entry, so a reset
+ * rewrites only the marked groups (the whole table after creation, an import
+ * or a failed launch).  The per-epoch scratch (fallback queue, records,
+ * fresh-id lists) is left cleared by every epoch, so it is cleared here only
+ * after creation or a failed launch. */
 hrpp_status hrpp_predictor_reset(hrpp_predictor *pred, void *stream);
 
 /* Copy the table to host memory after the work on `stream` (synchronises

@@ -45,7 +45,7 @@ bool desc_ok(const hrpp_predictor_desc *d) {
 uint32_t entry_bytes_for(uint32_t ways) { return ways <= 4 ? 32u : 64u; }
 
 struct PredLayout {
-    size_t table, topw, rec_key, rec_idx, rec_leaf, rec_status, queue, ctrl, total;
+    size_t table, topw, rec_key, rec_idx, rec_leaf, rec_status, queue, dirty, ctrl, total;
 };
 
 PredLayout pred_layout(const hrpp_predictor_desc *d) {
@@ -59,6 +59,7 @@ PredLayout pred_layout(const hrpp_predictor_desc *d) {
     L.rec_leaf = off; off += align256(E * 4);
     L.rec_status = off; off += align256(E * 4);
     L.queue = off; off += align256((size_t)kSubQueues * queue_subcap_for((uint32_t)E) * 8);
+    L.dirty = off; off += align256((N + kResetGroup - 1) / kResetGroup);
     L.ctrl = off; off += 256;
     L.total = off;
     return L;
@@ -293,7 +294,11 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc) {
 hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
     if (!p) return HRPP_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    launch_fill32(static_cast<uint32_t *>(p->d_table), p->table_bytes / 4, kNone, s);
+    // the update marks the group of every entry it tags while empty (see
+    // k_update_apply): clear the marked groups, or everything when an entry
+    // may have been written without a mark
+    launch_reset_table(p->d_table, p->entry_bytes, 1u << p->desc.log2_entries, p->d_dirty,
+                       p->table_unmarked || p->scratch_dirty, s);
     launch_fill32(p->d_ctrl, 64, 0u, s);
     if (p->scratch_dirty) {
         // every epoch leaves the fresh-id lists and record slots cleared; they
@@ -303,8 +308,10 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
         launch_fill32(p->d_rec_idx, E, kNone, s);
         p->scratch_dirty = false;
     }
+    const hrpp_status st = check(hipGetLastError());
+    if (st == HRPP_OK) p->table_unmarked = false;
     p->empty = true;
-    return check(hipGetLastError());
+    return st;
 }
 
 hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf, size_t bytes,
@@ -330,6 +337,7 @@ hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc
     p->d_rec_leaf = reinterpret_cast<uint32_t *>(base + L.rec_leaf);
     p->d_rec_status = reinterpret_cast<uint32_t *>(base + L.rec_status);
     p->d_queue = reinterpret_cast<uint64_t *>(base + L.queue);
+    p->d_dirty = reinterpret_cast<uint8_t *>(base + L.dirty);
     p->d_ctrl = reinterpret_cast<uint32_t *>(base + L.ctrl);
     // hash grid over the scene box: scale = 2^qo / extent (0 for a flat or
     // degenerate axis), computed once in binary32
@@ -380,6 +388,7 @@ hrpp_status hrpp_predictor_import(hrpp_predictor *p, const void *h_src, size_t b
     hipError_t e = hipMemcpyAsync(p->d_table, h_src, p->table_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     p->empty = false;
+    p->table_unmarked = true;      // imported entries carry no reset marks
     return check(e);
 }
 
@@ -420,6 +429,7 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.policy = d.replace_policy;
         a.hash.stride = d.origin_bits <= 3 ? 8u : 16u;
         a.ctrl = pred->d_ctrl;
+        a.dirty = pred->d_dirty;
         a.queue = pred->d_queue;
         a.queue_subcap = queue_subcap_for(d.epoch_rays);
         a.rec_key = pred->d_rec_key;
@@ -453,7 +463,7 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
     const hrpp_status ls = check(hipGetLastError());
     if (pred) {
         pred->empty = false;
-        if (ls != HRPP_OK) pred->scratch_dirty = true;
+        if (ls != HRPP_OK) pred->scratch_dirty = pred->table_unmarked = true;
     }
     return ls;
 }
@@ -613,7 +623,7 @@ hrpp_status hrpp_batch_launch(hrpp_batch *b, uint32_t use_graph, void *stream) {
     const hrpp_status st = batch_launch(b, use_graph, static_cast<hipStream_t>(stream));
     for (hrpp_predictor *p : b->preds) {
         p->empty = false;
-        if (st != HRPP_OK) p->scratch_dirty = true;
+        if (st != HRPP_OK) p->scratch_dirty = p->table_unmarked = true;
     }
     return st;
 }

@@ -79,6 +79,8 @@ struct hrpp_predictor {
     uint32_t bvh_tris, bvh_nodes;  // sizes of the BVH the table indexes (import checks slots against them)
     bool empty = true;             // reset and not traced or imported since (scheduling hint only)
     bool scratch_dirty = true;     // fresh-id lists / record slots need clearing (creation, failed launch)
+    bool table_unmarked = true;    // the table may hold entries whose reset group is not marked
+                                   // (creation, import, failed launch): the next reset clears all of it
     hrpp_predictor_desc desc;
     uint32_t entry_bytes;       // 32 or 64
     float bmin[3], scale[3];    // hash grid over the BVH root box
@@ -90,6 +92,7 @@ struct hrpp_predictor {
     uint32_t *d_rec_leaf;       // E
     uint32_t *d_rec_status;     // E
     uint64_t *d_queue;          // E fallback entries: ray id | seed leaf << 32
-    uint32_t *d_ctrl;           // [0] queue count, [1] error word
+    uint8_t *d_dirty;           // ceil(2^T / 16) reset marks
+    uint32_t *d_ctrl;           // [0, 8) sub-queue counts
     size_t table_bytes;
 };

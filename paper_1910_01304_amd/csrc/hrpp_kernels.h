@@ -21,6 +21,7 @@ struct HashArgs {
 };
 
 constexpr uint32_t kSubQueues = 8;     // striped fallback sub-queues per epoch
+constexpr uint32_t kResetGroup = 16;   // table entries per reset mark
 constexpr uint32_t kDefaultInlineLanes = 48;   // failing lanes of a wave that traverse at once
 
 // Capacity of one sub-queue, sized as if prediction blocks held 256 rays:
@@ -42,7 +43,7 @@ struct TraceArgs {
     uint32_t wide_root;           // wide node 0, or kLeafFlag | leaf id
     float root_box[6];
     uint32_t root_ref;
-    uint32_t stack_cap;           // LDS stack slots per lane (>= deepest leaf)
+    uint32_t stack_cap;           // traversal stack slots per lane (>= deepest leaf)
     uint32_t max_blocks;          // grid cap of the persistent plain traversal
     // rays and results
     const void *rays;             // hrpp_ray[n]
@@ -59,6 +60,7 @@ struct TraceArgs {
     uint32_t policy;              // bit 0: FIFO eviction; bit 1: the resident tag keeps its entry
     HashArgs hash;
     uint32_t *ctrl;               // [0 .. kSubQueues) sub-queue counts
+    uint8_t *dirty;               // reset marks, one per kResetGroup entries
     uint64_t *queue;              // kSubQueues sub-queues of queue_subcap entries
     uint32_t queue_subcap;
     uint64_t *rec_key;
@@ -104,6 +106,10 @@ int profile_stop(double *ms, uint64_t *launches);   // synchronises the recorded
 void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, bool empty_table,
                   hipStream_t s);
 void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
+// Empties every group of kResetGroup entries whose mark is set (all groups
+// when `full`) and clears the marks.
+void launch_reset_table(void *table, uint32_t entry_bytes, uint32_t n_entries, uint8_t *dirty, bool full,
+                        hipStream_t s);
 
 // Plain traversal of the 4-wide tree (a.wide, a.wide_root; a.stack_cap = the
 // tree's stack need); closest hit is the exact one.

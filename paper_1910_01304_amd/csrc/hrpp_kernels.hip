@@ -14,7 +14,8 @@
 //                claims the record's entry with a 32-bit atomicMin on the ray
 //                id (the smallest id owns it), wherever it traversed.
 //   k_update_*   three passes over the epoch's records that turn the table
-//                of epoch k-1 into the table of epoch k.
+//                of epoch k-1 into the table of epoch k; an entry tagged
+//                while empty marks its group for k_reset_table.
 // Without a predictor:
 //   k_traverse_plain  stack traversal of every ray (binary tree).
 //   k_traverse_wide   the same on the 4-wide tree collapsed from it.
@@ -848,7 +849,8 @@ __global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t ba
 //       owner's fresh ids in a sorted, duplicate-free list (atomicMin
 //       insertion cascade, bounded by the room the entry has) kept per
 //       claiming ray.
-//   U2 (winning records): rewrite the entry, release the claim.
+//   U2 (winning records): rewrite the entry, release the claim; an entry
+//       that was empty marks its group for the reset.
 //   U3 (records): count drops, clear the record slot, reset the queue count.
 // ---------------------------------------------------------------------------
 enum : uint32_t { kRecConflict = 1, kRecPresent = 2, kRecFresh = 3 };
@@ -942,6 +944,9 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
             const uint64_t kstar = a.rec_key[i];
             uint32_t used = 0;
             if (*(const uint64_t *)e != kstar) {
+                // an entry that leaves the empty state marks its group for the
+                // reset (a plain byte store: every writer stores the same 1)
+                if (*(const uint64_t *)e == kEmptyTag) a.dirty[idx / kResetGroup] = 1;
                 *(uint64_t *)e = kstar;
                 for (uint32_t s = 0; s < W; s++) e[2 + s] = kNone;
                 c.v[kTagClaims]++;
@@ -1087,6 +1092,34 @@ __global__ __launch_bounds__(128) void kb_traverse_plain(const BatchJob *__restr
 __global__ void k_fill32(uint32_t *p, size_t n, uint32_t value) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = value;
+}
+
+// Reset of a predictor table.  The update marks the group of kResetGroup
+// entries of every entry it tags while the entry is empty, so every entry that
+// is not empty lies in a marked group.  One wave per 64 groups: each lane reads
+// one mark, and the wave clears the marked groups with coalesced 16-byte
+// stores of all-ones (every group with `full`), then clears the marks.
+__global__ __launch_bounds__(256) void k_reset_table(uint4 *table, uint32_t entry_u4, uint32_t n_entries,
+                                                     uint8_t *dirty, uint32_t full) {
+    const uint32_t lane = __lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / 64u;
+    const uint32_t n_groups = (n_entries + kResetGroup - 1u) / kResetGroup;
+    const uint32_t g = wave * 64u + lane;
+    bool marked = false;
+    if (g < n_groups) {
+        marked = full || dirty[g] != 0;
+        if (marked) dirty[g] = 0;
+    }
+    uint64_t m = __ballot(marked);
+    const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
+    const size_t end_all = (size_t)n_entries * entry_u4;
+    while (m) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(m);
+        m &= m - 1ull;
+        const size_t first = (size_t)(wave * 64u + b) * kResetGroup * entry_u4;
+        const size_t end = min(end_all, first + (size_t)kResetGroup * entry_u4);
+        for (size_t j = first + lane; j < end; j += 64) table[j] = ones;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1277,6 +1310,16 @@ void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s) {
     const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255) / 256, 4096);
     ProfScope prof(kKindFill, s);
     hipLaunchKernelGGL(k_fill32, dim3(blocks), dim3(256), 0, s, p, n, value);
+}
+
+void launch_reset_table(void *table, uint32_t entry_bytes, uint32_t n_entries, uint8_t *dirty, bool full,
+                        hipStream_t s) {
+    const uint32_t n_groups = (n_entries + kResetGroup - 1u) / kResetGroup;
+    const uint32_t waves = (n_groups + 63u) / 64u;
+    const uint32_t blocks = (waves + 3u) / 4u;
+    ProfScope prof(kKindFill, s);
+    hipLaunchKernelGGL(k_reset_table, dim3(blocks), dim3(256), 0, s, (uint4 *)table, entry_bytes / 16u, n_entries,
+                       dirty, full ? 1u : 0u);
 }
 
 }  // namespace hrpp

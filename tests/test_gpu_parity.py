@@ -462,6 +462,44 @@ def test_determinism_and_reset(hrpp, small_terrain):
     assert np.array_equal(h1.view(np.uint32), h2.view(np.uint32))
 
 
+def test_reset_clears_written_entries(hrpp, small_terrain):
+    """A reset empties every entry written since the previous one: the update
+    marks the group of each entry it tags while empty and the reset clears the
+    marked groups; after an import it clears the whole table.  Tables of few
+    and of many used entries, and one smaller than a group."""
+    import torch
+    tris, prim = small_terrain
+    bvh = hrpp.BVH(tris)
+    r = torch.from_numpy(prim).cuda()
+    empty_tag = np.uint64(0xFFFFFFFFFFFFFFFF)
+    for T, W, qo, qd in ((10, 8, 3, 3), (8, 8, 5, 6), (3, 4, 5, 6), (12, 4, 5, 6)):
+        _say(f"reset, T {T} W {W} q_o {qo} q_d {qd}")
+        pred = hrpp.Predictor(bvh, T, W, qo, qd, 4096)
+        fresh = hrpp.Predictor(bvh, T, W, qo, qd, 4096)
+        for _ in range(3):
+            # two calls between resets: marks persist across calls
+            hrpp.trace_closest(bvh, pred, r[:20000], mode="paper")
+            hrpp.trace_closest(bvh, pred, r[20000:], mode="paper")
+            tags, _ = pred.export()
+            assert int((tags != empty_tag).sum()) > 0
+            pred.reset()
+            assert (pred.export_raw() == 0xFF).all()
+        # after the resets the predictor behaves as a new one
+        h1 = hrpp.trace_closest(bvh, pred, r, mode="paper").cpu().numpy()
+        h2 = hrpp.trace_closest(bvh, fresh, r, mode="paper").cpu().numpy()
+        assert np.array_equal(h1.view(np.uint32), h2.view(np.uint32))
+        raw = pred.export_raw()
+        assert np.array_equal(raw, fresh.export_raw())
+        # imported entries carry no marks: the next reset clears everything
+        pred.reset()
+        pred.import_raw(raw)
+        hrpp.trace_closest(bvh, pred, r[:1000], mode="paper")
+        pred.reset()
+        assert (pred.export_raw() == 0xFF).all()
+        pred.close()
+        fresh.close()
+
+
 # ---------------------------------------------------------------------------
 # Full size: the 1M-triangle scene at 1920x1080, in the benchmark's launch
 # configuration (hit-all predictor 2^20 x 8 for primaries, hit-any predictor
