@@ -299,11 +299,12 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
     // may have been written without a mark
     launch_reset_table(p->d_table, p->entry_bytes, 1u << p->desc.log2_entries, p->d_dirty,
                        p->table_unmarked || p->scratch_dirty, s);
-    launch_fill32(p->d_ctrl, 64, 0u, s);
     if (p->scratch_dirty) {
-        // every epoch leaves the fresh-id lists and record slots cleared; they
-        // are cleared here only at creation and after a failed launch
+        // every epoch leaves the fresh-id lists, record slots and sub-queue
+        // counts cleared; they are cleared here only at creation and after a
+        // failed launch
         const size_t E = p->desc.epoch_rays;
+        launch_fill32(p->d_ctrl, 64, 0u, s);
         launch_fill32(p->d_topw, E * p->desc.ways, kNone, s);
         launch_fill32(p->d_rec_idx, E, kNone, s);
         p->scratch_dirty = false;
