@@ -105,8 +105,8 @@ def kernel_source_hash():
 
 
 def short_kernel_name(name):
-    for k in ("k_predict", "k_traverse_queue", "k_traverse_plain", "k_update_classify", "k_update_apply",
-              "k_update_finish", "k_fill32"):
+    for k in ("k_predict", "k_epoch_empty", "k_traverse_queue", "k_traverse_plain", "k_traverse_wide",
+              "k_update_classify", "k_update_apply", "k_update_finish", "k_fill32", "k_reset_table"):
         if k in name:
             return k
     return None
@@ -187,16 +187,23 @@ def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
         trav_tri = st["tri_tests"] - st["pred_tri_tests"]
         q_trav, q_int, q_tri, q_rec = (st["queue_traversals"], st["queue_interior_visited"], st["queue_tri_tests"],
                                        st["queue_records"])
+        e_rays, e_trav, e_int, e_tri, e_rec = (st["empty_rays"], st["empty_lookups"], st["empty_interior_visited"],
+                                               st["empty_tri_tests"], st["empty_records"])
         if kind == "k_traverse_plain":
             tot += n * (RAY_B + out_b) + NODE_B * st["interior_visited"] + TRI_B * st["tri_tests"]
+        elif kind == "k_epoch_empty":
+            # the first epoch after a reset: ray, result, every valid ray's traversal (nodes,
+            # triangles), record + claim; no table entry is read
+            tot += e_rays * (RAY_B + out_b) + NODE_B * e_int + TRI_B * e_tri + e_rec * (16 + 4)
         elif kind == "k_predict":
-            # ray, table entry (none in the first epoch after a reset, whose table is known to be
-            # empty), predicted leaf boxes and triangles, results of successes, queue appends, and the
-            # fallback traversals run in place (nodes, triangles, result, record + claim)
-            tot += (n * RAY_B + (st["lookups"] - st["empty_lookups"]) * entry_b + LEAFBOX_B * st["pred_box_tests"]
-                    + TRI_B * st["pred_tri_tests"] + st["pred_hits"] * out_b + q_trav * 8
-                    + (st["traversals"] - q_trav) * out_b + NODE_B * (st["interior_visited"] - q_int)
-                    + TRI_B * (trav_tri - q_tri) + (st["records"] - q_rec) * (16 + 4))
+            # the other epochs: ray, table entry, predicted leaf boxes and triangles, results of
+            # successes, queue appends, and the fallback traversals run in place (nodes, triangles,
+            # result, record + claim)
+            tot += ((n - e_rays) * RAY_B + (st["lookups"] - st["empty_lookups"]) * entry_b
+                    + LEAFBOX_B * st["pred_box_tests"] + TRI_B * st["pred_tri_tests"] + st["pred_hits"] * out_b
+                    + q_trav * 8 + (st["traversals"] - q_trav - e_trav) * out_b
+                    + NODE_B * (st["interior_visited"] - q_int - e_int) + TRI_B * (trav_tri - q_tri - e_tri)
+                    + (st["records"] - q_rec - e_rec) * (16 + 4))
         elif kind == "k_traverse_queue":
             # queue entry, ray, nodes, triangles, result, record + claim
             tot += q_trav * (8 + RAY_B + out_b) + NODE_B * q_int + TRI_B * q_tri + q_rec * (16 + 4)

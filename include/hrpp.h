@@ -135,14 +135,19 @@ typedef struct {
  *                               follows inline_lanes)
  *  empty_lookups                schedule counter: lookups answered without
  *                               reading the table, in the first epoch after a
- *                               reset (the table is known to be empty) */
+ *                               reset (the table is known to be empty)
+ *  empty_rays, empty_interior_visited, empty_tri_tests, empty_records
+ *                               schedule counters: the part of rays /
+ *                               interior_visited / tri_tests / records in
+ *                               that first epoch (its own kernel) */
 #define HRPP_STATS_SLOTS 32
 typedef struct {
     uint64_t rays, invalid, hits, lookups, positives, pred_hits, false_pos, traversals,
              nodes_visited, interior_visited, leaf_visited, box_tests, tri_tests, nodes_skipped,
              records, tag_claims, leaf_inserts, dropped, conflicts, pred_leaf_visited, pred_tri_tests,
              pred_box_tests, evictions, queue_traversals, queue_interior_visited, queue_tri_tests,
-             queue_records, empty_lookups, reserved[4];
+             queue_records, empty_lookups, empty_rays, empty_interior_visited, empty_tri_tests,
+             empty_records;
 } hrpp_stats;
 
 enum { HRPP_CLOSEST_PAPER = 0, HRPP_CLOSEST_EXACT = 1 };

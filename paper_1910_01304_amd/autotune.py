@@ -4,8 +4,8 @@ Knobs: epoch size (the unit of batch-synchronous work, a "chunk"), table size
 (log2 entries), ways, origin / direction quantisation bits, and the number of
 failing lanes at which a prediction wave traverses at once instead of
 queueing (a pure scheduling knob: results do not depend on it).  The traversal
-stack depth is not a knob: the LDS stack is sized to the deepest leaf of the
-tree, which is what makes overflow impossible.  Every configuration the tuner
+stack depth is not a knob: the per-lane stack holds the deepest tree the
+library accepts (64 levels), which is what makes overflow impossible.  Every configuration the tuner
 can pick is an ordinary predictor configuration, traced by the same kernels
 that the parity tests check against the oracle.
 

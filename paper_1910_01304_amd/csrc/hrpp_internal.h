@@ -20,7 +20,8 @@ enum Stat : int {
     kRays, kInvalid, kHits, kLookups, kPositives, kPredHits, kFalsePos, kTraversals,
     kNodesVisited, kInteriorVisited, kLeafVisited, kBoxTests, kTriTests, kNodesSkipped,
     kRecords, kTagClaims, kLeafInserts, kDropped, kConflicts, kPredLeafVisited, kPredTriTests, kPredBoxTests,
-    kEvictions, kQueueTraversals, kQueueInteriorVisited, kQueueTriTests, kQueueRecords, kEmptyLookups, kNumStats
+    kEvictions, kQueueTraversals, kQueueInteriorVisited, kQueueTriTests, kQueueRecords, kEmptyLookups,
+    kEmptyRays, kEmptyInteriorVisited, kEmptyTriTests, kEmptyRecords, kNumStats
 };
 
 static_assert(kNumStats <= HRPP_STATS_SLOTS, "hrpp_stats has a slot for every counter");

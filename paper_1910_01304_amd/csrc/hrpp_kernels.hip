@@ -781,6 +781,11 @@ __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base,
         }
         traverse_one<ANY, EXACT, true>(a, base, rid, kNone, c, stk_node, stk_t, stride, cap);
     }
+    // schedule counters: all of this kernel's work is first-epoch work
+    c.v[kEmptyRays] = c.v[kRays];
+    c.v[kEmptyInteriorVisited] = c.v[kInteriorVisited];
+    c.v[kEmptyTriTests] = c.v[kTriTests];
+    c.v[kEmptyRecords] = c.v[kRecords];
     flush_counters<STATS>(c, a.stats);
 }
 
@@ -1167,7 +1172,7 @@ struct ProfScope {
 const char *kernel_kind_name(int k) {
     static const char *names[kNumKernelKinds] = {"k_predict", "k_traverse_queue", "k_traverse_plain",
                                                  "k_update_classify", "k_update_apply", "k_update_finish",
-                                                 "k_fill32", "k_traverse_wide"};
+                                                 "k_fill32", "k_traverse_wide", "k_epoch_empty"};
     return (k >= 0 && k < kNumKernelKinds) ? names[k] : "unknown";
 }
 
@@ -1205,7 +1210,7 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool
     const uint32_t persistent = std::min<uint32_t>(ceil_div(count, 128), a.max_blocks);
     if (empty_table) {
         // every valid ray traverses; no queue is filled
-        ProfScope p(kKindPredict, s);
+        ProfScope p(kKindEpochEmpty, s);
         hipLaunchKernelGGL((k_epoch_empty<ANY, EXACT, STATS>), dim3(persistent), dim3(128), lds, s, a, base, count);
     } else {
         {

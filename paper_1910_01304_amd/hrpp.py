@@ -23,9 +23,10 @@ STAT_NAMES = [
     "pred_box_tests", "evictions",
     # schedule counters (how much fallback work ran in the queue kernel), not part of the method
     "queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records", "empty_lookups",
+    "empty_rays", "empty_interior_visited", "empty_tri_tests", "empty_records",
 ]
 SCHEDULE_STATS = ("queue_traversals", "queue_interior_visited", "queue_tri_tests", "queue_records",
-                  "empty_lookups")
+                  "empty_lookups", "empty_rays", "empty_interior_visited", "empty_tri_tests", "empty_records")
 STATS_SLOTS = 32
 CLOSEST_MODES = {"paper": 0, "exact": 1}
 EXPORTED = [

@@ -84,6 +84,17 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
         pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E,
                               hash_mode=hm, go_up_level=gu, inline_lanes=il, replace_policy=rp)
         tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu, policy=rp)
+    first = None
+    if pred is not None and rays.shape[0] > 0:
+        # the first epoch of a new predictor sees an empty table: the GPU runs it in
+        # its own kernel, whose schedule counters equal the oracle's counts for
+        # those rays alone
+        e0 = min(pred_cfg[4], rays.shape[0])
+        _, w0 = oracle.trace(ob, tris, rays[:e0], query=query, mode=mode, table=oracle.Table(T, W, qo, qd,
+                             hash_mode=hm, go_up=gu, policy=rp), epoch=pred_cfg[4], vtx=vtx)
+        first = {"empty_rays": w0["rays"], "empty_lookups": w0["lookups"],
+                 "empty_interior_visited": w0["interior_visited"], "empty_tri_tests": w0["tri_tests"],
+                 "empty_records": w0["records"]}
     gst = hrpp.new_stats()
     for c in range(calls):
         got, gs = gpu_run(hrpp, bvh, rays, query, mode, pred, gst)
@@ -98,6 +109,16 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
         assert {k: gs[k] for k in acc} == acc, {k: (gs[k], acc[k]) for k in acc if gs[k] != acc[k]}
         if pred is not None:
             assert_same_table(pred, tb)
+            # schedule counters: the first epoch (later calls add none), and the
+            # queue split of the other epochs' fallback traversals
+            if first is not None:
+                assert {k: gs[k] for k in first} == first, ({k: gs[k] for k in first}, first)
+            later = gs["traversals"] - gs["empty_lookups"]
+            if il == 65:
+                assert gs["queue_traversals"] == later
+            elif il == 1:
+                assert gs["queue_traversals"] == 0
+            assert 0 <= gs["queue_traversals"] <= later
     return got, gs
 
 
