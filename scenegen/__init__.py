@@ -222,8 +222,9 @@ class Camera:
         self.vfov = vfov_deg
         self.width, self.height = width, height
 
-    def rays(self, order: str = "bayer"):
-        """Unit-direction primary rays through pixel centres, interval (0, inf).
+    def rays(self, order: str = "bayer", offset=(0.5, 0.5)):
+        """Unit-direction primary rays through one sample position per pixel
+        (``offset`` within the pixel, (0.5, 0.5) = the centre), interval (0, inf).
 
         Returns ``(rays, pixel_ids)`` with rays in trace order.
         """
@@ -236,8 +237,8 @@ class Camera:
         aspect = self.width / self.height
         pid = pixel_order(self.width, self.height, order)
         px, py = pid % self.width, pid // self.width
-        sx = (2 * (px + 0.5) / self.width - 1) * th * aspect
-        sy = (1 - 2 * (py + 0.5) / self.height) * th
+        sx = (2 * (px + offset[0]) / self.width - 1) * th * aspect
+        sy = (1 - 2 * (py + offset[1]) / self.height) * th
         d = w[None, :] + sx[:, None] * u[None, :] + sy[:, None] * v[None, :]
         d /= np.linalg.norm(d, axis=1, keepdims=True)
         o = np.broadcast_to(self.eye, d.shape)
@@ -391,16 +392,27 @@ def camera_for(width: int, height: int) -> Camera:
 
 
 def terrain_workload(total: int = 1 << 20, width: int = 1920, height: int = 1080, seed: int = 2,
-                     order: str = "bayer"):
-    """Scene and primary rays of the at-scale workload (optionally scaled down)."""
+                     order: str = "bayer", offset=(0.5, 0.5)):
+    """Scene and primary rays of the at-scale workload (optionally scaled
+    down; ``offset`` = sample position within each pixel)."""
     if total == 1 << 20:
         tris, hf = terrain_scene(seed)
     else:
         tris, hf = scaled_terrain_scene(seed, total)
     cam = camera_for(width, height)
-    rays, pid = cam.rays(order)
+    rays, pid = cam.rays(order, offset)
     cam.assert_all_hit_terrain(rays, hf.amplitude)
     return tris, rays
+
+
+# sample positions of the progressive frames (a 2 x 2 stratified pattern)
+PROGRESSIVE_OFFSETS = ((0.25, 0.25), (0.75, 0.25), (0.25, 0.75), (0.75, 0.75))
+
+
+def progressive_primaries(width: int = 1920, height: int = 1080, order: str = "bayer"):
+    """Primary rays of the at-scale camera for each progressive frame."""
+    cam = camera_for(width, height)
+    return [cam.rays(order, off)[0] for off in PROGRESSIVE_OFFSETS]
 
 
 # ---------------------------------------------------------------------------
