@@ -19,7 +19,8 @@ built once, in setup, from the GPU's exact primary hits.
 
 Prints one JSON line.  Options: --steps, --warmup, --no-cpu-baseline,
 --no-ao (skip the incoherent AO measurement), --no-progressive (skip the
-frames with tables kept across them), --gpus (only 1 is supported).
+frames with tables kept across them), --no-serving (skip the serving run
+that gives the line its p99 latency), --gpus (only 1 is supported).
 """
 from __future__ import annotations
 
@@ -55,6 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ao", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving measurement that gives the line its p99 latency")
     ap.add_argument("--no-progressive", action="store_true",
                     help="skip the progressive-frames measurement (tables kept across frames)")
     ap.add_argument("--no-profile", action="store_true")
@@ -84,6 +87,8 @@ def parse():
                     help="autotune: comma-separated knobs to search (the others stay at the workload's values)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=500)
+    ap.add_argument("--serve-slots", type=int, default=8, help="stream slots of the server")
+    ap.add_argument("--serve-replicas", type=int, default=2, help="predictor replicas per scene and query kind")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 256 MiB calibration copy, then one HRPP and one plain step (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -351,6 +356,7 @@ def main():
         args.no_cpu_baseline = True
         args.no_ao = True
         args.no_progressive = True
+        args.no_serving = True
         args.reference_epoch = 0
         args.steps = max(1, args.steps)
     log("timing")
@@ -593,6 +599,12 @@ def main():
                "sample": f"the full step ({rays_per_step} rays, HRPP, same tables and epochs), median of "
                          f"{len(times)} runs ({sum(times):.1f} s in all), {med:.3f} s each"}
 
+    serve = None
+    if not args.no_serving:
+        # the serving workload at 50% and 80% of saturation (as `--workload serving`)
+        log("serving")
+        serve = measure_serving(args, np, torch, hrpp, sg, (0.5, 0.8), args.serve_requests, args.serve_warmup)
+
     value = mrays(rays_per_step, ms_hrpp)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
@@ -617,7 +629,9 @@ def main():
         "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "reference_epoch": ref_info,
         "progressive": prog_info,
         "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
-        "p99_latency_ms": None,
+        "p99_latency_ms": serve["value"] if serve else None,
+        "serving": ({"p99_ms_at_80pct_load": serve["value"], "saturation_mrays_s": serve["saturation_mrays_s"],
+                     "results": serve["results"], "workload": serve["config"]["workload"]} if serve else None),
     }
     print(json.dumps(out), flush=True)
 
@@ -902,6 +916,13 @@ def run_serving(args, np, torch, hrpp, sg):
     8 GiB device pool, 8 stream slots, two predictor replicas per scene and
     query kind.  Reports saturation throughput and p50/p99 latency at 50% and
     80% of it."""
+    print(json.dumps(measure_serving(args, np, torch, hrpp, sg, (0.5, 0.8), args.serve_requests,
+                                     args.serve_warmup)), flush=True)
+
+
+def measure_serving(args, np, torch, hrpp, sg, rhos, n_requests, n_warmup):
+    """The serving measurement at the given loads (fractions of saturation),
+    n_requests timed after n_warmup; returns the result object."""
     from concurrent.futures import ThreadPoolExecutor
 
     g = sg.rng(5)
@@ -929,10 +950,11 @@ def run_serving(args, np, torch, hrpp, sg):
     del made
     pc = dict(log2_entries=18, ways=8, origin_bits=5, dir_bits=6, epoch_rays=1 << 19,
               inline_lanes=args.inline_lanes if args.inline_lanes >= 0 else SERVE_INLINE)
-    scenes = [(b, [hrpp.Predictor(b, **pc) for _ in range(2)], [hrpp.Predictor(b, **pc) for _ in range(2)])
+    nrep = args.serve_replicas
+    scenes = [(b, [hrpp.Predictor(b, **pc) for _ in range(nrep)], [hrpp.Predictor(b, **pc) for _ in range(nrep)])
               for b in bvhs]
     pool_bytes = 8 << 30
-    srv = hrpp.Server(scenes, slots=8, pool_bytes=pool_bytes)
+    srv = hrpp.Server(scenes, slots=args.serve_slots, pool_bytes=pool_bytes)
     ring_n = 1 << 26
     out_any = torch.empty(ring_n, dtype=torch.uint8).pin_memory()
     out_cl = torch.empty((ring_n // 4, 4), dtype=torch.float32).pin_memory()
@@ -957,26 +979,29 @@ def run_serving(args, np, torch, hrpp, sg):
         ring[query] += n
         return srv.submit(scene, query, rays, o)
 
-    # saturation: everything at once
+    # saturation: 1,000 requests submitted at once, median of three sets
     rg = sg.rng(55)
-    sat_reqs = [make_request(rg) for _ in range(1000)]
-    for r in sat_reqs[:100]:
+    for r in [make_request(rg) for _ in range(100)]:
         submit(r)
     srv.wait_all()
-    t0 = time.perf_counter()
-    for r in sat_reqs:
-        submit(r)
-    srv.wait_all()
-    sat_s = time.perf_counter() - t0
-    sat_rays = sum(r[2] for r in sat_reqs)
-    sat_rate = sat_rays / sat_s
-    mean_size = sat_rays / len(sat_reqs)
-    log(f"serving: saturation {sat_rate / 1e6:.1f} Mrays/s")
+    rates, sizes = [], []
+    for _ in range(3):
+        sat_reqs = [make_request(rg) for _ in range(1000)]
+        t0 = time.perf_counter()
+        for r in sat_reqs:
+            submit(r)
+        srv.wait_all()
+        sat_rays = sum(r[2] for r in sat_reqs)
+        rates.append(sat_rays / (time.perf_counter() - t0))
+        sizes.append(sat_rays / len(sat_reqs))
+    sat_rate = statistics.median(rates)
+    mean_size = statistics.mean(sizes)
+    log(f"serving: saturation {sat_rate / 1e6:.1f} Mrays/s (sets: {', '.join(f'{x / 1e6:.0f}' for x in rates)})")
     results = {}
-    for rho in (0.5, 0.8):
+    for rho in rhos:
         lam = rho * sat_rate / mean_size
         rg = sg.rng(int(rho * 100))
-        reqs = [make_request(rg) for _ in range(args.serve_warmup + args.serve_requests)]
+        reqs = [make_request(rg) for _ in range(n_warmup + n_requests)]
         gaps = rg.exponential(1.0 / lam, len(reqs))
         ids = []
         t_start = time.perf_counter()
@@ -988,26 +1013,40 @@ def run_serving(args, np, torch, hrpp, sg):
             ids.append(submit(r))
         srv.wait_all()
         wall = time.perf_counter() - t_start
-        lat = np.array([srv.poll(i)["latency_ms"] for i in ids[args.serve_warmup:]])
+        info = [srv.poll(i) for i in ids[n_warmup:]]
+        lat = np.array([x["latency_ms"] for x in info])
+        qms = np.array([x["queue_ms"] for x in info])
+        sms = np.array([x["service_ms"] for x in info])
+        size = np.array([r[2] for r in reqs[n_warmup:]])
         rays_meas = sum(r[2] for r in reqs)
         results[f"rho_{rho}"] = {"arrival_rate_req_s": round(lam, 1), "requests": len(lat),
                                  "p50_ms": round(float(np.percentile(lat, 50)), 3),
                                  "p99_ms": round(float(np.percentile(lat, 99)), 3),
                                  "mean_ms": round(float(lat.mean()), 3),
+                                 "p99_queue_ms": round(float(np.percentile(qms, 99)), 3),
+                                 "p99_service_ms": round(float(np.percentile(sms, 99)), 3),
+                                 "p99_ms_under_100k_rays": round(float(np.percentile(lat[size < 100000], 99)), 3),
+                                 "p99_ms_over_100k_rays": round(float(np.percentile(lat[size >= 100000], 99)), 3),
                                  "mrays_s": round(rays_meas / wall / 1e6, 1)}
         log(f"serving: rho {rho}: {results[f'rho_{rho}']}")
     peak = srv.pool_peak()
     srv.close()
+    top = f"rho_{max(rhos)}"
     out = {"metric": "serving p50/p99 latency (ms) and Mrays/s under Poisson arrivals",
-           "value": results["rho_0.8"]["p99_ms"], "unit": "ms (p99 at 80% of saturation)", "higher_is_better": False,
+           "value": results[top]["p99_ms"], "unit": f"ms (p99 at {round(100 * max(rhos))}% of saturation)",
+           "higher_is_better": False,
            "n_gpus": 1, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "8 resident scenes (1e5-2e6 tris), requests 1e3-1e6 rays log-uniform "
-                                  "(20% primary exact closest, 40% shadow, 40% AO), 8 GiB pool, 8 slots, "
-                                  "2 predictor replicas per scene and kind, epoch 2^19",
+                                  "(20% primary exact closest, 40% shadow, 40% AO), 8 GiB pool, "
+                                  f"{args.serve_slots} slots, "
+                                  f"{args.serve_replicas} predictor replicas per scene and kind, epoch 2^19",
                       "triangles": int(sum(s["tris"] for s in specs))},
            "saturation_mrays_s": round(sat_rate / 1e6, 1), "mean_request_rays": round(mean_size),
            "pool_peak_bytes": int(peak), "pool_bytes": pool_bytes, "results": results}
-    print(json.dumps(out), flush=True)
+    del srv, scenes, bvhs, pools
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batched(args, np, torch, hrpp, sg):
