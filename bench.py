@@ -18,7 +18,8 @@ tree.  Rays and the BVH are resident in HBM before timing; shadow rays are
 built once, in setup, from the GPU's exact primary hits.
 
 Prints one JSON line.  Options: --steps, --warmup, --no-cpu-baseline,
---no-ao (skip the incoherent AO measurement), --no-progressive (skip the
+--no-ao (skip the incoherent AO measurement), --no-rowmajor (skip the step
+in row-major pixel order), --no-progressive (skip the
 frames with tables kept across them), --no-serving (skip the serving run
 that gives the line its p99 latency), --gpus (only 1 is supported).
 """
@@ -58,6 +59,7 @@ def parse():
     ap.add_argument("--no-ao", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement that gives the line its p99 latency")
+    ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major ray order measurement")
     ap.add_argument("--no-progressive", action="store_true",
                     help="skip the progressive-frames measurement (tables kept across frames)")
     ap.add_argument("--no-profile", action="store_true")
@@ -357,6 +359,7 @@ def main():
         args.no_ao = True
         args.no_progressive = True
         args.no_serving = True
+        args.no_rowmajor = True
         args.reference_epoch = 0
         args.steps = max(1, args.steps)
     log("timing")
@@ -499,46 +502,102 @@ def main():
         # A renderer that refines one view keeps its tables: four frames of 2 x 2
         # stratified sub-pixel samples, each frame's shadow rays from its own exact
         # hits with new light samples, tables never reset inside the timed region
-        # (each frame sees the tables the previous frames left)
+        # (each frame sees the tables the previous frames left).  With tables that
+        # already cover the view, one epoch per frame (E = 2^21) is the tuned choice;
+        # the step's own predictors (E = 2^19) are measured beside it.
         log("progressive frames")
-        frames = []
-        for k, rays_k in enumerate(sg.progressive_primaries(w["width"], w["height"])):
-            pk = torch.from_numpy(rays_k).cuda()
-            hk = hrpp.trace_closest(bvh, None, pk, mode="exact").cpu().numpy()
-            shk = sg.shadow_rays_from_hits(tris, rays_k, hk[:, 0], hk[:, 3].view(np.uint32), seed=w["seed"] + 1 + k,
-                                           light_center=w["light_center"], light_size=w["light_size"])
-            assert shk.shape[0] == n_sh and rays_k.shape[0] == n_prim
-            frames.append((pk, torch.from_numpy(shk).cuda()))
-        rays_prog = sum(int(a.shape[0] + b.shape[0]) for a, b in frames)
+        prog_info = {"frames": len(sg.PROGRESSIVE_OFFSETS),
+                     "note": "tables kept across 4 frames of 2x2 stratified sub-pixel samples; no reset in the "
+                             "timed region; q as the step's predictors, inline lanes 1"}
+        cam_p = sg.camera_for(w["width"], w["height"])
+        for order in ("bayer", "rowmajor"):
+            frames = []
+            for k, off in enumerate(sg.PROGRESSIVE_OFFSETS):
+                rays_k, _ = cam_p.rays(order, off)
+                pk = torch.from_numpy(rays_k).cuda()
+                hk = hrpp.trace_closest(bvh, None, pk, mode="exact").cpu().numpy()
+                shk = sg.shadow_rays_from_hits(tris, rays_k, hk[:, 0], hk[:, 3].view(np.uint32),
+                                               seed=w["seed"] + 1 + k, light_center=w["light_center"],
+                                               light_size=w["light_size"])
+                assert shk.shape[0] == n_sh and rays_k.shape[0] == n_prim
+                frames.append((pk, torch.from_numpy(shk).cuda()))
+            rays_prog = sum(int(a_.shape[0] + b_.shape[0]) for a_, b_ in frames)
 
-        def prog(pa, pb, sa=None, sb=None):
+            def prog(pa, pb, sa=None, sb=None):
+                def run():
+                    for pk, sk in frames:
+                        on_two_streams(lambda: hrpp.trace_closest(bvh, pa, pk, mode="paper", out=hits_out, stats=sb),
+                                       lambda: hrpp.trace_anyhit(bvh, pb, sk, out=occ_out, stats=sa))
+                return run
+
+            ms_prog_p = timed(torch, prog(None, None), args.steps, 1)[0]
+            qa, qb = hrpp.new_stats(), hrpp.new_stats()
+            prog(None, None, qa, qb)()
+            torch.cuda.synchronize()
+            qa, qb = hrpp.stats_dict(qa), hrpp.stats_dict(qb)
+            for label, ep in (("frame_epoch", 1 << 21), ("step_epoch", pq[2])):
+                ca = dict(cfg_all, epoch_rays=ep, inline_lanes=1)
+                cb = dict(cfg_any, epoch_rays=ep, inline_lanes=1)
+                pa_, pb_ = hrpp.Predictor(bvh, **ca), hrpp.Predictor(bvh, **cb)
+                ms_prog_h = timed(torch, prog(pa_, pb_), args.steps, 1)[0]
+                ga, gb = hrpp.new_stats(), hrpp.new_stats()
+                prog(pa_, pb_, ga, gb)()
+                torch.cuda.synchronize()
+                ga, gb = hrpp.stats_dict(ga), hrpp.stats_dict(gb)
+                prog_info[f"{order}_{label}"] = {
+                    "epoch_rays": ep, "rays": rays_prog,
+                    "hrpp_mrays_s": round(mrays(rays_prog, ms_prog_h), 2),
+                    "plain_mrays_s": round(mrays(rays_prog, ms_prog_p), 2),
+                    "speedup_vs_plain": round(ms_prog_p / ms_prog_h, 4),
+                    "pct_nodes_skipped": round(100.0 * (1 - (ga["nodes_visited"] + gb["nodes_visited"])
+                                                        / (qa["nodes_visited"] + qb["nodes_visited"])), 3),
+                    "pct_nodes_skipped_primary": round(pct_saved("nodes_visited", gb, qb), 3),
+                    "pct_nodes_skipped_shadow": round(pct_saved("nodes_visited", ga, qa), 3),
+                    "prediction_hit_rate_primary": round(gb["pred_hits"] / (len(frames) * n_prim), 4)}
+                del pa_, pb_
+            del frames
+
+    row_info = None
+    if not args.no_rowmajor:
+        # the secondary ray order: the same pixels row by row, so that an epoch
+        # covers a band of the image instead of a sparse sample of all of it
+        log("row-major order")
+        cam_rm, _ = sg.camera_for(w["width"], w["height"]).rays("rowmajor")
+        prm = torch.from_numpy(cam_rm).cuda()
+        hrm = hrpp.trace_closest(bvh, None, prm, mode="exact").cpu().numpy()
+        srm = torch.from_numpy(sg.shadow_rays_from_hits(tris, cam_rm, hrm[:, 0], hrm[:, 3].view(np.uint32),
+                                                        seed=w["seed"], light_center=w["light_center"],
+                                                        light_size=w["light_size"])).cuda()
+
+        def rm_step(pa, pb, sa=None, sb=None):
             def run():
-                for pk, sk in frames:
-                    on_two_streams(lambda: hrpp.trace_closest(bvh, pa, pk, mode="paper", out=hits_out, stats=sb),
-                                   lambda: hrpp.trace_anyhit(bvh, pb, sk, out=occ_out, stats=sa))
+                def fa():
+                    if pa is not None:
+                        pa.reset()
+                    hrpp.trace_closest(bvh, pa, prm, mode="paper", out=hits_out, stats=sb)
+
+                def fb():
+                    if pb is not None:
+                        pb.reset()
+                    hrpp.trace_anyhit(bvh, pb, srm, out=occ_out, stats=sa)
+                on_two_streams(fa, fb)
             return run
 
-        pred_all.reset()
-        pred_any.reset()
-        ms_prog_h = timed(torch, prog(pred_all, pred_any), args.steps, 1)[0]
-        ms_prog_p = timed(torch, prog(None, None), args.steps, 1)[0]
+        ms_rm_h = timed(torch, rm_step(pred_all, pred_any), args.steps, 1)[0]
+        ms_rm_p = timed(torch, rm_step(None, None), args.steps, 1)[0]
         ga, gb, qa, qb = (hrpp.new_stats() for _ in range(4))
-        prog(pred_all, pred_any, ga, gb)()
-        prog(None, None, qa, qb)()
+        rm_step(pred_all, pred_any, ga, gb)()
+        rm_step(None, None, qa, qb)()
         torch.cuda.synchronize()
         ga, gb, qa, qb = (hrpp.stats_dict(x) for x in (ga, gb, qa, qb))
-        prog_info = {"frames": len(frames), "rays": rays_prog,
-                     "hrpp_mrays_s": round(mrays(rays_prog, ms_prog_h), 2),
-                     "plain_mrays_s": round(mrays(rays_prog, ms_prog_p), 2),
-                     "speedup_vs_plain": round(ms_prog_p / ms_prog_h, 4),
-                     "pct_nodes_skipped": round(100.0 * (1 - (ga["nodes_visited"] + gb["nodes_visited"])
-                                                         / (qa["nodes_visited"] + qb["nodes_visited"])), 3),
-                     "pct_nodes_skipped_primary": round(pct_saved("nodes_visited", gb, qb), 3),
-                     "pct_nodes_skipped_shadow": round(pct_saved("nodes_visited", ga, qa), 3),
-                     "prediction_hit_rate_primary": round(gb["pred_hits"] / (len(frames) * n_prim), 4),
-                     "prediction_hit_rate_shadow": round(ga["pred_hits"] / (len(frames) * n_sh), 4),
-                     "note": "tables kept across 4 frames of 2x2 stratified sub-pixel samples; no reset in the "
-                             "timed region"}
+        row_info = {"hrpp_mrays_s": round(mrays(rays_per_step, ms_rm_h), 2),
+                    "plain_mrays_s": round(mrays(rays_per_step, ms_rm_p), 2),
+                    "speedup_vs_plain": round(ms_rm_p / ms_rm_h, 4),
+                    "pct_nodes_skipped": round(100.0 * (1 - (ga["nodes_visited"] + gb["nodes_visited"])
+                                                        / (qa["nodes_visited"] + qb["nodes_visited"])), 3),
+                    "pct_nodes_skipped_primary": round(pct_saved("nodes_visited", gb, qb), 3),
+                    "prediction_hit_rate_primary": round(gb["pred_hits"] / n_prim, 4)}
+        del prm, srm
 
     ao_info = None
     if not args.no_ao:
@@ -627,7 +686,7 @@ def main():
         "pct_nodes_skipped": round(100.0 * (1 - nodes_h / nodes_p), 3),
         "pct_box_tests_skipped": round(100.0 * (1 - box_h / box_p), 3),
         "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "reference_epoch": ref_info,
-        "progressive": prog_info,
+        "progressive": prog_info, "row_major_order": row_info,
         "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
         "p99_latency_ms": serve["value"] if serve else None,
         "serving": ({"p99_ms_at_80pct_load": serve["value"], "saturation_mrays_s": serve["saturation_mrays_s"],
