@@ -552,6 +552,47 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
     check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any)
 
 
+def test_full_size_progressive_frames(hrpp, full_terrain):
+    # the benchmark's warm-table measurement: successive frames of jittered
+    # row-major primaries (and their shadow rays) traced with the tables kept,
+    # one epoch per frame; every frame against the oracle, which carries its
+    # own tables across the frames in the same way
+    import torch
+    w = sg.AT_SCALE
+    tris, _ = full_terrain
+    bvh = hrpp.BVH(tris)
+    ob = oracle.build_sah(tris)
+    vtx = oracle.bvh_vertices(tris, ob)
+    pq, sq = w["primary_q"], w["shadow_q"]
+    E = 1 << 21
+    pa = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1],
+                        epoch_rays=E, inline_lanes=1)
+    pb = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1],
+                        epoch_rays=E, inline_lanes=1)
+    ta = oracle.Table(w["log2_entries"], w["ways"], pq[0], pq[1])
+    tb = oracle.Table(w["log2_entries"], w["ways"], sq[0], sq[1])
+    cam = sg.camera_for(w["width"], w["height"])
+    for k, off in enumerate(sg.PROGRESSIVE_OFFSETS[:2]):
+        _say(f"progressive frame {k}, offset {off}")
+        prim, _ = cam.rays("rowmajor", off)
+        got, gs = gpu_run(hrpp, bvh, prim, "closest", "paper", pa)
+        want, ws = oracle.trace(ob, tris, prim, query="closest", mode="paper", table=ta, epoch=E, vtx=vtx)
+        assert_same_result("closest", got, want)
+        assert {k2: gs[k2] for k2 in ws} == ws
+        assert_same_table(pa, ta)
+        if k > 0:
+            assert ws["pred_hits"] > 0.9 * prim.shape[0]      # the previous frame's entries predict
+        he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact", vtx=vtx)
+        shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"] + 1 + k,
+                                          light_center=w["light_center"], light_size=w["light_size"])
+        got, gs = gpu_run(hrpp, bvh, shadow, "any", "paper", pb)
+        want, ws = oracle.trace(ob, tris, shadow, query="any", table=tb, epoch=E, vtx=vtx)
+        assert_same_result("any", got, want)
+        assert {k2: gs[k2] for k2 in ws} == ws
+        assert_same_table(pb, tb)
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("cfg", [
     (sg.INCOHERENT["log2_entries"], sg.INCOHERENT["ways"], sg.INCOHERENT["origin_bits"], sg.INCOHERENT["dir_bits"],
      sg.INCOHERENT["epoch"], 0, 0, sg.INCOHERENT["inline_lanes"]),     # the benchmark's AO predictor
