@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement that gives the line its p99 latency")
     ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major ray order measurement")
+    ap.add_argument("--prog-orders", default="bayer,rowmajor", help="pixel orders of the progressive frames")
+    ap.add_argument("--prog-epochs", default="frame,step",
+                    help="epochs of the progressive frames: frame (one per frame) and/or step (the step's)")
     ap.add_argument("--no-progressive", action="store_true",
                     help="skip the progressive-frames measurement (tables kept across frames)")
     ap.add_argument("--no-profile", action="store_true")
@@ -74,7 +77,7 @@ def parse():
     ap.add_argument("--reference-epoch", type=int, default=1 << 17,
                     help="also time the HRPP step at this epoch size (0 = skip)")
     ap.add_argument("--workload", default="at_scale",
-                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup", "policy"],
+                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup", "policy", "progressive"],
                     help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
                          "graph-captured batch")
     ap.add_argument("--sweep-epoch", type=int, default=1 << 17,
@@ -264,6 +267,9 @@ def main():
         return
     if args.workload == "policy":
         run_policy(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "progressive":
+        run_progressive(args, np, torch, hrpp, sg)
         return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
@@ -499,63 +505,9 @@ def main():
 
     prog_info = None
     if not args.no_progressive:
-        # A renderer that refines one view keeps its tables: four frames of 2 x 2
-        # stratified sub-pixel samples, each frame's shadow rays from its own exact
-        # hits with new light samples, tables never reset inside the timed region
-        # (each frame sees the tables the previous frames left).  With tables that
-        # already cover the view, one epoch per frame (E = 2^21) is the tuned choice;
-        # the step's own predictors (E = 2^19) are measured beside it.
         log("progressive frames")
-        prog_info = {"frames": len(sg.PROGRESSIVE_OFFSETS),
-                     "note": "tables kept across 4 frames of 2x2 stratified sub-pixel samples; no reset in the "
-                             "timed region; q as the step's predictors, inline lanes 1"}
-        cam_p = sg.camera_for(w["width"], w["height"])
-        for order in ("bayer", "rowmajor"):
-            frames = []
-            for k, off in enumerate(sg.PROGRESSIVE_OFFSETS):
-                rays_k, _ = cam_p.rays(order, off)
-                pk = torch.from_numpy(rays_k).cuda()
-                hk = hrpp.trace_closest(bvh, None, pk, mode="exact").cpu().numpy()
-                shk = sg.shadow_rays_from_hits(tris, rays_k, hk[:, 0], hk[:, 3].view(np.uint32),
-                                               seed=w["seed"] + 1 + k, light_center=w["light_center"],
-                                               light_size=w["light_size"])
-                assert shk.shape[0] == n_sh and rays_k.shape[0] == n_prim
-                frames.append((pk, torch.from_numpy(shk).cuda()))
-            rays_prog = sum(int(a_.shape[0] + b_.shape[0]) for a_, b_ in frames)
-
-            def prog(pa, pb, sa=None, sb=None):
-                def run():
-                    for pk, sk in frames:
-                        on_two_streams(lambda: hrpp.trace_closest(bvh, pa, pk, mode="paper", out=hits_out, stats=sb),
-                                       lambda: hrpp.trace_anyhit(bvh, pb, sk, out=occ_out, stats=sa))
-                return run
-
-            ms_prog_p = timed(torch, prog(None, None), args.steps, 1)[0]
-            qa, qb = hrpp.new_stats(), hrpp.new_stats()
-            prog(None, None, qa, qb)()
-            torch.cuda.synchronize()
-            qa, qb = hrpp.stats_dict(qa), hrpp.stats_dict(qb)
-            for label, ep in (("frame_epoch", 1 << 21), ("step_epoch", pq[2])):
-                ca = dict(cfg_all, epoch_rays=ep, inline_lanes=1)
-                cb = dict(cfg_any, epoch_rays=ep, inline_lanes=1)
-                pa_, pb_ = hrpp.Predictor(bvh, **ca), hrpp.Predictor(bvh, **cb)
-                ms_prog_h = timed(torch, prog(pa_, pb_), args.steps, 1)[0]
-                ga, gb = hrpp.new_stats(), hrpp.new_stats()
-                prog(pa_, pb_, ga, gb)()
-                torch.cuda.synchronize()
-                ga, gb = hrpp.stats_dict(ga), hrpp.stats_dict(gb)
-                prog_info[f"{order}_{label}"] = {
-                    "epoch_rays": ep, "rays": rays_prog,
-                    "hrpp_mrays_s": round(mrays(rays_prog, ms_prog_h), 2),
-                    "plain_mrays_s": round(mrays(rays_prog, ms_prog_p), 2),
-                    "speedup_vs_plain": round(ms_prog_p / ms_prog_h, 4),
-                    "pct_nodes_skipped": round(100.0 * (1 - (ga["nodes_visited"] + gb["nodes_visited"])
-                                                        / (qa["nodes_visited"] + qb["nodes_visited"])), 3),
-                    "pct_nodes_skipped_primary": round(pct_saved("nodes_visited", gb, qb), 3),
-                    "pct_nodes_skipped_shadow": round(pct_saved("nodes_visited", ga, qa), 3),
-                    "prediction_hit_rate_primary": round(gb["pred_hits"] / (len(frames) * n_prim), 4)}
-                del pa_, pb_
-            del frames
+        prog_info = measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, hits_out, occ_out,
+                                        on_two_streams, n_prim, n_sh)
 
     row_info = None
     if not args.no_rowmajor:
@@ -693,6 +645,143 @@ def main():
                      "results": serve["results"], "workload": serve["config"]["workload"]} if serve else None),
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, hits_out, occ_out, on_two_streams,
+                        n_prim, n_sh, orders=("bayer", "rowmajor"), epochs=None, profile=None):
+    """A renderer that refines one view keeps its tables: four frames of 2 x 2
+    stratified sub-pixel samples, each frame's shadow rays from its own exact
+    hits with new light samples, tables never reset inside the timed region
+    (each frame sees the tables the previous frames left).  With tables that
+    already cover the view, one epoch per frame (E = 2^21) is the tuned choice;
+    the step's own epochs are measured beside it.  `profile(label, fn)` may
+    time the kernels of one configuration."""
+    w = sg.AT_SCALE
+    if epochs is None:
+        epochs = ("frame", "step")
+    epochs = tuple((f"{e}_epoch", 1 << 21 if e == "frame" else cfg_all["epoch_rays"]) for e in epochs)
+
+    def mrays(n, ms):
+        return n / (ms * 1e-3) / 1e6
+
+    def pct_saved(key, h, p):
+        return 100.0 * (1.0 - h[key] / p[key]) if p[key] else 0.0
+
+    info = {"frames": len(sg.PROGRESSIVE_OFFSETS),
+            "note": "tables kept across 4 frames of 2x2 stratified sub-pixel samples; no reset in the timed "
+                    "region; q as the step's predictors, inline lanes 1"}
+    cam_p = sg.camera_for(w["width"], w["height"])
+    for order in orders:
+        frames = []
+        for k, off in enumerate(sg.PROGRESSIVE_OFFSETS):
+            rays_k, _ = cam_p.rays(order, off)
+            pk = torch.from_numpy(rays_k).cuda()
+            hk = hrpp.trace_closest(bvh, None, pk, mode="exact").cpu().numpy()
+            shk = sg.shadow_rays_from_hits(tris, rays_k, hk[:, 0], hk[:, 3].view(np.uint32),
+                                           seed=w["seed"] + 1 + k, light_center=w["light_center"],
+                                           light_size=w["light_size"])
+            assert shk.shape[0] == n_sh and rays_k.shape[0] == n_prim
+            frames.append((pk, torch.from_numpy(shk).cuda()))
+        rays_prog = sum(int(a_.shape[0] + b_.shape[0]) for a_, b_ in frames)
+
+        def prog(pa, pb, sa=None, sb=None):
+            def run():
+                for pk, sk in frames:
+                    on_two_streams(lambda: hrpp.trace_closest(bvh, pa, pk, mode="paper", out=hits_out, stats=sb),
+                                   lambda: hrpp.trace_anyhit(bvh, pb, sk, out=occ_out, stats=sa))
+            return run
+
+        def prog_one_stream(pa, pb):
+            # one query after the other, so that a kernel's event window is its own
+            def run():
+                for pk, sk in frames:
+                    hrpp.trace_closest(bvh, pa, pk, mode="paper", out=hits_out)
+                    hrpp.trace_anyhit(bvh, pb, sk, out=occ_out)
+            return run
+
+        ms_prog_p = timed(torch, prog(None, None), args.steps, 1)[0]
+        qa, qb = hrpp.new_stats(), hrpp.new_stats()
+        prog(None, None, qa, qb)()
+        torch.cuda.synchronize()
+        qa, qb = hrpp.stats_dict(qa), hrpp.stats_dict(qb)
+        for label, ep in epochs:
+            ca = dict(cfg_all, epoch_rays=ep, inline_lanes=1)
+            cb = dict(cfg_any, epoch_rays=ep, inline_lanes=1)
+            pa_, pb_ = hrpp.Predictor(bvh, **ca), hrpp.Predictor(bvh, **cb)
+            ms_prog_h = timed(torch, prog(pa_, pb_), args.steps, 1)[0]
+            ga, gb = hrpp.new_stats(), hrpp.new_stats()
+            prog(pa_, pb_, ga, gb)()
+            torch.cuda.synchronize()
+            ga, gb = hrpp.stats_dict(ga), hrpp.stats_dict(gb)
+            entry = {
+                "epoch_rays": ep, "rays": rays_prog,
+                "hrpp_mrays_s": round(mrays(rays_prog, ms_prog_h), 2),
+                "plain_mrays_s": round(mrays(rays_prog, ms_prog_p), 2),
+                "speedup_vs_plain": round(ms_prog_p / ms_prog_h, 4),
+                "pct_nodes_skipped": round(100.0 * (1 - (ga["nodes_visited"] + gb["nodes_visited"])
+                                                    / (qa["nodes_visited"] + qb["nodes_visited"])), 3),
+                "pct_nodes_skipped_primary": round(pct_saved("nodes_visited", gb, qb), 3),
+                "pct_nodes_skipped_shadow": round(pct_saved("nodes_visited", ga, qa), 3),
+                "prediction_hit_rate_primary": round(gb["pred_hits"] / (len(frames) * n_prim), 4)}
+            if profile is not None:
+                entry["kernels"] = profile(prog_one_stream(pa_, pb_), ga, gb, ca["ways"], len(frames))
+            info[f"{order}_{label}"] = entry
+            del pa_, pb_
+        del frames
+    return info
+
+
+def run_progressive(args, np, torch, hrpp, sg):
+    """Frames of one view traced with the tables kept (see measure_progressive),
+    with per-kernel HIP-event timing and algorithmic bytes of each configuration
+    (a pass with the two queries on one stream); one JSON line."""
+    w = sg.AT_SCALE
+    tris, prim = sg.terrain_workload()
+    bvh = hrpp.BVH(tris)
+    n = prim.shape[0]
+    pq, sq = w["primary_q"], w["shadow_q"]
+    cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2],
+                   inline_lanes=pq[3])
+    cfg_any = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1], epoch_rays=sq[2],
+                   inline_lanes=sq[3])
+    hits_out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    occ_out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def on_two_streams(fa, fb):
+        cur = torch.cuda.current_stream()
+        s_a.wait_stream(cur)
+        s_b.wait_stream(cur)
+        with torch.cuda.stream(s_a):
+            fa()
+        with torch.cuda.stream(s_b):
+            fb()
+        cur.wait_stream(s_a)
+        cur.wait_stream(s_b)
+
+    def prof(fn, ga, gb, ways, frames):
+        entry_b = 64 if ways > 4 else 32
+        fn()
+        torch.cuda.synchronize()
+        hrpp.profile_start()
+        fn()
+        res = hrpp.profile_stop()
+        out = {}
+        for k, (launches, total_ms) in res.items():
+            nb = kernel_bytes(k, ga, gb, entry_b, frames * n, frames * n)
+            avg_ms = total_ms / launches
+            out[k] = {"launches": launches, "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(nb / launches),
+                      "gbs": round(nb / launches / (avg_ms * 1e-3) / 1e9, 1),
+                      "frac_of_hbm_peak": round(nb / launches / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        return out
+
+    info = measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, hits_out, occ_out,
+                               on_two_streams, n, n, orders=tuple(args.prog_orders.split(",")),
+                               epochs=tuple(args.prog_epochs.split(",")), profile=prof)
+    print(json.dumps({"metric": "Mrays/s HRPP vs plain over progressive frames with the tables kept",
+                      "config": {"workload": "terrain 1M tris, 4 frames of 1920x1080 jittered primaries (closest, "
+                                             "PAPER) + shadow rays (any hit), tables 2^20 x 8 kept across frames"},
+                      "results": info}), flush=True)
 
 
 def run_autotune(args, np, torch, hrpp, sg):
