@@ -11,9 +11,12 @@ that the parity tests check against the oracle.
 
 Search: coordinate descent from a start point, one knob at a time over its
 candidate list, for `rounds` passes; each point is timed with HIP events
-(median of `reps` runs, each run = predictor reset + trace).  Optionally a
-minimum fraction of skipped nodes can be imposed, so that the tuner does not
-trade all prediction away for speed.
+(median of `reps` runs, each run = predictor reset + trace).  With `warm_rays`
+(the rays of an earlier frame of the same view) each run first traces those,
+untimed, after the reset, so that the timed trace sees the tables a renderer
+would carry from frame to frame.  Optionally a minimum fraction of skipped
+nodes can be imposed, so that the tuner does not trade all prediction away
+for speed.
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ import torch
 from . import hrpp
 
 DEFAULT_SPACE = {
-    "epoch_rays": [1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20],
+    "epoch_rays": [1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22],
     "log2_entries": [16, 18, 20, 22],
     "ways": [4, 8],
     "origin_bits": [3, 4, 5, 6, 7],
@@ -42,22 +45,39 @@ class TuneResult:
     trials: list = field(default_factory=list)
 
 
-def _time_config(bvh, rays, query, mode, cfg, reps, plain_nodes):
+def _time_config(bvh, rays, query, mode, cfg, reps, plain_nodes, warm_rays=None):
     pred = hrpp.Predictor(bvh, **cfg)
     out = (torch.empty(rays.shape[0], dtype=torch.uint8, device=rays.device) if query == "any"
            else torch.empty((rays.shape[0], 4), dtype=torch.float32, device=rays.device))
+    wout = None
+    if warm_rays is not None:
+        wout = (torch.empty(warm_rays.shape[0], dtype=torch.uint8, device=rays.device) if query == "any"
+                else torch.empty((warm_rays.shape[0], 4), dtype=torch.float32, device=rays.device))
+
+    def trace(r, o, stats=None):
+        if query == "any":
+            hrpp.trace_anyhit(bvh, pred, r, out=o, stats=stats)
+        else:
+            hrpp.trace_closest(bvh, pred, r, mode=mode, out=o, stats=stats)
+
+    def prepare():
+        # untimed: the tables of the earlier frame
+        if warm_rays is not None:
+            pred.reset()
+            trace(warm_rays, wout)
 
     def run(stats=None):
-        pred.reset()
-        if query == "any":
-            hrpp.trace_anyhit(bvh, pred, rays, out=out, stats=stats)
-        else:
-            hrpp.trace_closest(bvh, pred, rays, mode=mode, out=out, stats=stats)
+        # timed: reset + trace, or (warm) the trace alone
+        if warm_rays is None:
+            pred.reset()
+        trace(rays, out, stats)
 
+    prepare()
     run()
     torch.cuda.synchronize()
     times = []
     for _ in range(reps):
+        prepare()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         run()
@@ -65,6 +85,7 @@ def _time_config(bvh, rays, query, mode, cfg, reps, plain_nodes):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     st = hrpp.new_stats()
+    prepare()
     run(st)
     torch.cuda.synchronize()
     s = hrpp.stats_dict(st)
@@ -75,7 +96,8 @@ def _time_config(bvh, rays, query, mode, cfg, reps, plain_nodes):
 
 def tune(bvh, rays, query: str = "any", mode: str = "paper", start: dict | None = None,
          space: dict | None = None, rounds: int = 2, reps: int = 3, min_skip_pct: float | None = None,
-         knobs=("epoch_rays", "log2_entries", "ways", "origin_bits", "dir_bits"), log=None) -> TuneResult:
+         knobs=("epoch_rays", "log2_entries", "ways", "origin_bits", "dir_bits"), log=None,
+         warm_rays=None) -> TuneResult:
     """Coordinate-descent search of the predictor configuration minimising trace time."""
     space = dict(DEFAULT_SPACE, **(space or {}))
     cfg = dict(log2_entries=20, ways=8, origin_bits=5, dir_bits=6, epoch_rays=1 << 19)
@@ -95,7 +117,7 @@ def tune(bvh, rays, query: str = "any", mode: str = "paper", start: dict | None 
     def evaluate(c):
         key = tuple(sorted(c.items()))
         if key not in seen:
-            ms, s = _time_config(bvh, rays, query, mode, c, reps, plain_nodes)
+            ms, s = _time_config(bvh, rays, query, mode, c, reps, plain_nodes, warm_rays)
             ok = min_skip_pct is None or s["pct_nodes_skipped"] >= min_skip_pct
             seen[key] = (ms, s, ok)
             trials.append(dict(config=dict(c), ms=ms, pct_nodes_skipped=s["pct_nodes_skipped"], feasible=ok))
