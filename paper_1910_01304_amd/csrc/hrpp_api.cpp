@@ -299,7 +299,8 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
     // may have been written without a mark
     launch_reset_table(p->d_table, p->entry_bytes, 1u << p->desc.log2_entries, p->d_dirty,
                        p->table_unmarked || p->scratch_dirty, s);
-    if (p->scratch_dirty) {
+    const bool scratch = p->scratch_dirty;
+    if (scratch) {
         // every epoch leaves the fresh-id lists, record slots and sub-queue
         // counts cleared; they are cleared here only at creation and after a
         // failed launch
@@ -307,11 +308,15 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
         launch_fill32(p->d_ctrl, 64, 0u, s);
         launch_fill32(p->d_topw, E * p->desc.ways, kNone, s);
         launch_fill32(p->d_rec_idx, E, kNone, s);
-        p->scratch_dirty = false;
     }
     const hrpp_status st = check(hipGetLastError());
-    if (st == HRPP_OK) p->table_unmarked = false;
-    p->empty = true;
+    if (st == HRPP_OK) {
+        // only a reset whose launches were accepted establishes a clean state;
+        // otherwise the next reset clears everything again
+        p->table_unmarked = false;
+        p->scratch_dirty = false;
+        p->empty = true;
+    }
     return st;
 }
 
