@@ -89,7 +89,8 @@ def parse():
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
     ap.add_argument("--tune-queries", default="",
                     help="comma list of primary,shadow,ao,primary_warm,shadow_warm (default all)")
-    ap.add_argument("--tune-knobs", default="epoch_rays,log2_entries,ways,origin_bits,dir_bits,inline_lanes",
+    ap.add_argument("--tune-knobs",
+                    default="epoch_rays,first_epoch_rays,log2_entries,ways,origin_bits,dir_bits,inline_lanes",
                     help="autotune: comma-separated knobs to search (the others stay at the workload's values)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=500)
@@ -232,7 +233,7 @@ def main():
         import scenegen as sg
         w = sg.AT_SCALE
         cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
-                     inline_lanes=q[3]) for q in (w["primary_q"], w["shadow_q"])]
+                     inline_lanes=q[3], first_epoch_rays=q[4]) for q in (w["primary_q"], w["shadow_q"])]
         summarize_traffic(*args.summarize_traffic, configs=cfgs)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -282,12 +283,12 @@ def main():
     log(f"BVH: {bvh.num_nodes} nodes, depth {bvh.max_depth}, built in {build_s:.2f} s")
     pq, sq = w["primary_q"], w["shadow_q"]
     if args.epoch:
-        pq, sq = (pq[0], pq[1], args.epoch, pq[3]), (sq[0], sq[1], args.epoch, sq[3])
+        pq, sq = (pq[0], pq[1], args.epoch, pq[3], 0), (sq[0], sq[1], args.epoch, sq[3], 0)
     epoch = pq[2]
     cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2],
-                   inline_lanes=pq[3])
+                   inline_lanes=pq[3], first_epoch_rays=pq[4])
     cfg_any = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1], epoch_rays=sq[2],
-                   inline_lanes=sq[3])
+                   inline_lanes=sq[3], first_epoch_rays=sq[4])
     pcfg = cfg_all
     pred_all = hrpp.Predictor(bvh, **cfg_all)
     pred_any = hrpp.Predictor(bvh, **cfg_any)
@@ -475,7 +476,8 @@ def main():
     ref_info = None
     if args.reference_epoch:
         # the untuned reference: both predictors at q_o 5, q_d 6 and the reference epoch
-        rcfg = dict(pcfg, origin_bits=5, dir_bits=6, epoch_rays=args.reference_epoch, inline_lanes=0)
+        rcfg = dict(pcfg, origin_bits=5, dir_bits=6, epoch_rays=args.reference_epoch, inline_lanes=0,
+                    first_epoch_rays=0)
         ra_, rb_ = hrpp.Predictor(bvh, **rcfg), hrpp.Predictor(bvh, **rcfg)
 
         def ref_step():
@@ -623,9 +625,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_hrpp, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) + shadow any-hit, "
-                               f"HRPP tables 2^20 x 8; hit-all q_o {pq[0]} q_d {pq[1]} epoch {pq[2]} "
-                               f"inline lanes {pq[3]}; hit-any q_o {sq[0]} q_d {sq[1]} epoch {sq[2]} "
-                               f"inline lanes {sq[3]} (autotuned)",
+                               f"HRPP tables 2^20 x 8; hit-all q_o {pq[0]} q_d {pq[1]} first epoch {pq[4]} "
+                               f"then epochs of {pq[2]}, inline lanes {pq[3]}; hit-any q_o {sq[0]} q_d {sq[1]} "
+                               f"first epoch {sq[4]} then epochs of {sq[2]}, inline lanes {sq[3]} (autotuned)",
                    "hit_all_predictor": cfg_all, "hit_any_predictor": cfg_any,
                    "triangles": int(tris.shape[0]), "rays_per_step": int(rays_per_step),
                    "bvh_nodes": int(bvh.num_nodes), "bvh_depth": int(bvh.max_depth)},
@@ -660,7 +662,10 @@ def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, 
     w = sg.AT_SCALE
     if epochs is None:
         epochs = ("frame", "step")
-    epochs = tuple((f"{e}_epoch", 1 << 21 if e == "frame" else cfg_all["epoch_rays"]) for e in epochs)
+    # "frame": one epoch per frame; "step": the at-scale step's schedule (first epoch, then epochs)
+    epochs = tuple((f"{e}_epoch" if e == "frame" else "step_schedule",
+                    (1 << 21, 0) if e == "frame" else (cfg_all["epoch_rays"], cfg_all["first_epoch_rays"]))
+                   for e in epochs)
 
     def mrays(n, ms):
         return n / (ms * 1e-3) / 1e6
@@ -705,9 +710,10 @@ def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, 
         prog(None, None, qa, qb)()
         torch.cuda.synchronize()
         qa, qb = hrpp.stats_dict(qa), hrpp.stats_dict(qb)
-        for label, ep in epochs:
-            ca = dict(cfg_all, epoch_rays=ep, inline_lanes=1)
-            cb = dict(cfg_any, epoch_rays=ep, inline_lanes=1)
+        for label, (ep, fe) in epochs:
+            ca = dict(cfg_all, epoch_rays=ep, inline_lanes=1, first_epoch_rays=fe)
+            cb = dict(cfg_any, epoch_rays=ep, inline_lanes=1,
+                      first_epoch_rays=cfg_any["first_epoch_rays"] if label == "step_schedule" else 0)
             pa_, pb_ = hrpp.Predictor(bvh, **ca), hrpp.Predictor(bvh, **cb)
             ms_prog_h = timed(torch, prog(pa_, pb_), args.steps, 1)[0]
             ga, gb = hrpp.new_stats(), hrpp.new_stats()
@@ -715,7 +721,8 @@ def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, 
             torch.cuda.synchronize()
             ga, gb = hrpp.stats_dict(ga), hrpp.stats_dict(gb)
             entry = {
-                "epoch_rays": ep, "rays": rays_prog,
+                "epoch_rays": ep, "first_epoch_rays": [ca["first_epoch_rays"], cb["first_epoch_rays"]],
+                "rays": rays_prog,
                 "hrpp_mrays_s": round(mrays(rays_prog, ms_prog_h), 2),
                 "plain_mrays_s": round(mrays(rays_prog, ms_prog_p), 2),
                 "speedup_vs_plain": round(ms_prog_p / ms_prog_h, 4),
@@ -742,9 +749,9 @@ def run_progressive(args, np, torch, hrpp, sg):
     n = prim.shape[0]
     pq, sq = w["primary_q"], w["shadow_q"]
     cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2],
-                   inline_lanes=pq[3])
+                   inline_lanes=pq[3], first_epoch_rays=pq[4])
     cfg_any = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1], epoch_rays=sq[2],
-                   inline_lanes=sq[3])
+                   inline_lanes=sq[3], first_epoch_rays=sq[4])
     hits_out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
     occ_out = torch.empty(n, dtype=torch.uint8, device="cuda")
     s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
@@ -818,7 +825,7 @@ def run_autotune(args, np, torch, hrpp, sg):
         warm.append((pk, torch.from_numpy(sk).cuda()))
     res = {}
     knobs = tuple(k for k in args.tune_knobs.split(",") if k)
-    ao_q = (wi["origin_bits"], wi["dir_bits"], wi["epoch"], wi["inline_lanes"])
+    ao_q = (wi["origin_bits"], wi["dir_bits"], wi["epoch"], wi["inline_lanes"], 0)
     for name, rays, query, q, warm_rays in (("primary", prim_d, "closest", w["primary_q"], None),
                                             ("shadow", shadow_d, "any", w["shadow_q"], None),
                                             ("ao", ao_d, "any", ao_q, None),
@@ -827,7 +834,7 @@ def run_autotune(args, np, torch, hrpp, sg):
         if args.tune_queries and name not in args.tune_queries.split(","):
             continue
         start = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1],
-                     epoch_rays=q[2], inline_lanes=q[3])
+                     epoch_rays=q[2], inline_lanes=q[3], first_epoch_rays=q[4])
         r = autotune.tune(bvh, rays, query=query, mode="paper", start=start, rounds=2, reps=3, knobs=knobs, log=log,
                           warm_rays=warm_rays)
         res[name] = {"best": r.best, "best_ms": round(r.best_ms, 4),
@@ -966,7 +973,8 @@ def run_goup(args, np, torch, hrpp, sg):
         pts = []
         for g in range(0, 5):
             pred = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0],
-                                  dir_bits=q[1], epoch_rays=q[2], inline_lanes=q[3], go_up_level=g)
+                                  dir_bits=q[1], epoch_rays=q[2], inline_lanes=q[3], go_up_level=g,
+                                  first_epoch_rays=q[4])
 
             def run(st=None):
                 pred.reset()
@@ -1022,7 +1030,7 @@ def run_policy(args, np, torch, hrpp, sg):
     res = {}
     for name, rays, query, q in (("primary", prim_d, "closest", pq),
                                  ("ao", ao_d, "any", (wi["origin_bits"], wi["dir_bits"], wi["epoch"],
-                                                      wi["inline_lanes"]))):
+                                                      wi["inline_lanes"], 0))):
         n = rays.shape[0]
         out = (torch.empty((n, 4), dtype=torch.float32, device="cuda") if query == "closest"
                else torch.empty(n, dtype=torch.uint8, device="cuda"))
@@ -1042,7 +1050,7 @@ def run_policy(args, np, torch, hrpp, sg):
         for T in (6, 8, 10, 12, 14, 16, 20):
             for pol in (0, 1, 2, 3):
                 pred = hrpp.Predictor(bvh, log2_entries=T, ways=8, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
-                                      inline_lanes=q[3], replace_policy=pol)
+                                      inline_lanes=q[3], replace_policy=pol, first_epoch_rays=q[4])
 
                 def run(st=None):
                     pred.reset()

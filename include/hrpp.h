@@ -95,10 +95,15 @@ typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
  *                bit 0 = FIFO within an entry: the oldest slots make room for
  *                up to `ways` new ids; bit 1 = the resident tag keeps its
  *                entry: records of another key are conflicts and only empty
- *                entries are claimed.  0..3. */
+ *                entries are claimed.  0..3.
+ *  first_epoch_rays  length of each call's first epoch (0 = epoch_rays,
+ *                otherwise 1..epoch_rays); the other epochs keep epoch_rays.
+ *                A short first epoch fills the table early: when the rays
+ *                are ordered so that it samples the whole view, the rest of
+ *                the call sees a table that covers it. */
 typedef struct {
     uint32_t log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level, inline_lanes,
-             replace_policy;
+             replace_policy, first_epoch_rays;
 } hrpp_predictor_desc;
 
 /* Work counters, accumulated (added to) by every trace call that is given
@@ -250,7 +255,7 @@ void hrpp_predictor_destroy(hrpp_predictor *pred);
 /* Any-hit (shadow / hit-any) query for n rays d_rays[0..n).  d_occluded[i]
  * = 1 if some triangle is hit inside (tmin, tmax), else 0.  pred NULL =
  * plain traversal; otherwise rays are processed in epochs of epoch_rays in
- * index order: hash, lookup, test the predicted leaves (stop at the first
+ * index order (the first one first_epoch_rays long): hash, lookup, test the predicted leaves (stop at the first
  * hit), traverse the rest, then update the table.  The flag does not depend
  * on the predictor.  d_stats (may be NULL) is accumulated.  n == 0 is a
  * no-op.  Errors: EINVAL (null arrays with n > 0, n >= 2^31, predictor

@@ -163,8 +163,11 @@ def stats_dict(arr: np.ndarray) -> dict:
 
 def trace(bvh: CanonBVH, tris: np.ndarray, rays: np.ndarray, query: str = "any", mode: str = "paper",
           table: Table | None = None, epoch: int = 1 << 17, nthreads: int = 0, vtx: np.ndarray | None = None,
-          outcome: np.ndarray | None = None):
+          outcome: np.ndarray | None = None, first_epoch: int = 0):
     """Run the oracle.  Returns ``(result, stats)``.
+
+    Epochs of ``epoch`` rays in ray order, the first of them ``first_epoch``
+    rays long (0: ``epoch``; at most ``epoch``).
 
     ``result`` is a uint8 occlusion array (any-hit) or a ``[n, 4]`` float32
     array (t, u, v, prim bits) for closest hit.  ``table`` is updated in place.
@@ -190,7 +193,7 @@ def trace(bvh: CanonBVH, tris: np.ndarray, rays: np.ndarray, query: str = "any",
                         C.c_int(1 if mode == "exact" else 0), _p(tg), _p(sl), C.c_uint32(l2), C.c_uint32(W),
                         C.c_uint32(qo), C.c_uint32(qd), C.c_uint32(epoch), _p(occ), _p(hits), _p(stats),
                         _p(outcome), C.c_int(nthreads), C.c_uint32(hm), C.c_uint32(gu),
-                        C.c_uint32(pol))
+                        C.c_uint32(pol), C.c_uint32(first_epoch))
     if rc != 0:
         raise ValueError("oracle trace rejected its arguments")
     return (hits if closest else occ), stats_dict(stats)

@@ -840,7 +840,8 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
 /* Trace n rays.  query: 0 any-hit, 1 closest.  cmode: 0 PAPER, 1 EXACT
    (closest only).  tags/slots NULL = plain traversal, otherwise the table
    (log2n entries of W slots) is read and updated in place, epochs of
-   `epoch` rays in ray order.  occ (n bytes) or hits (4 floats per ray: t,
+   `epoch` rays in ray order, the first of them `first_epoch` rays long
+   (0: `epoch`; at most `epoch`).  occ (n bytes) or hits (4 floats per ray: t,
    u, v, prim bits) receive the results; stats (STATS_SLOTS uint64) are
    accumulated; outcome (n bytes, optional) receives 0 invalid, 1 traversed
    without a positive prediction, 2 prediction hit, 3 false positive.
@@ -849,9 +850,10 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
 int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t n, int query, int cmode,
               uint64_t *tags, uint32_t *slots, uint32_t log2n, uint32_t W, uint32_t qo, uint32_t qd,
               uint32_t epoch, uint8_t *occ, float *hits, uint64_t *stats, uint8_t *outcome, int nthreads,
-              uint32_t hash_mode, uint32_t go_up, uint32_t policy)
+              uint32_t hash_mode, uint32_t go_up, uint32_t policy, uint32_t first_epoch)
 {
     if (!bvh || bvh->num_nodes == 0) return -1;
+    if (tags && first_epoch > epoch) return -1;
     if (tags && (W < 1 || log2n < 1 || log2n > 31 || qo < 1 || qo > 10 || qd < 1 || qd > 10 || epoch < 1)) return -1;
     if (tags && (hash_mode > 1 || (hash_mode == 1 && (qo > 7 || qd != qo)))) return -1;
     if (tags && (go_up > 64 || policy > 3)) return -1;
@@ -890,9 +892,11 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
     }
     if (nthreads > 0) omp_set_num_threads(nthreads);
     uint32_t E = ptb ? epoch : (n ? n : 1);
+    uint32_t F = (ptb && first_epoch) ? first_epoch : E;   /* the first epoch's length */
     record *recs = (record *)malloc(sizeof(record) * (size_t)(E < n ? E : (n ? n : 1)));
-    for (uint32_t base = 0; base < n; base += E) {
-        uint32_t cnt = (n - base < E) ? n - base : E;
+    for (uint32_t base = 0; base < n;) {
+        uint32_t len = base == 0 ? F : E;
+        uint32_t cnt = (n - base < len) ? n - base : len;
         uint64_t acc[STATS_SLOTS];
         memset(acc, 0, sizeof acc);
         #pragma omp parallel
@@ -910,6 +914,7 @@ int orc_trace(const orc_bvh *bvh, const float *vtx, const float *rays, uint32_t 
         }
         if (ptb) update_table(ptb, recs, base, cnt, acc);
         for (int s = 0; s < STATS_SLOTS; s++) stats[s] += acc[s];
+        base += cnt;
     }
     free(recs);
     free(lnode);

@@ -1,6 +1,7 @@
 """Autotuner for the predictor's knobs, by measured throughput on the GPU.
 
-Knobs: epoch size (the unit of batch-synchronous work, a "chunk"), table size
+Knobs: epoch size (the unit of batch-synchronous work, a "chunk"), the length
+of a call's first epoch (a short one fills the table early), table size
 (log2 entries), ways, origin / direction quantisation bits, and the number of
 failing lanes at which a prediction wave traverses at once instead of
 queueing (a pure scheduling knob: results do not depend on it).  The traversal
@@ -34,6 +35,7 @@ DEFAULT_SPACE = {
     "origin_bits": [3, 4, 5, 6, 7],
     "dir_bits": [3, 4, 5, 6, 7],
     "inline_lanes": [16, 32, 48, 56, 64, 65],
+    "first_epoch_rays": [0, 1 << 16, 1 << 17, 1 << 18, 1 << 19],
 }
 
 
@@ -131,6 +133,8 @@ def tune(bvh, rays, query: str = "any", mode: str = "paper", start: dict | None 
         for knob in knobs:
             for v in space[knob]:
                 c = dict(cfg, **{knob: v})
+                if c.get("first_epoch_rays", 0) > c["epoch_rays"]:
+                    continue                          # not a valid predictor
                 ms, s, ok = evaluate(c)
                 if ok and (not best_ok or ms < best_ms):
                     cfg, best_ms, best_s, best_ok, changed = c, ms, s, True, True

@@ -38,7 +38,7 @@ bool desc_ok(const hrpp_predictor_desc *d) {
     return d && d->log2_entries >= 1 && d->log2_entries <= 26 && d->ways >= 1 && d->ways <= 8 &&
            d->origin_bits >= 1 && d->origin_bits <= 10 && d->dir_bits >= 1 && d->dir_bits <= 10 &&
            d->epoch_rays >= 1 && d->epoch_rays <= (1u << 22) && d->go_up_level <= 64 && d->inline_lanes <= 65 &&
-           d->replace_policy <= 3 &&
+           d->replace_policy <= 3 && d->first_epoch_rays <= d->epoch_rays &&
            (d->hash_mode == 0 || (d->hash_mode == 1 && d->origin_bits <= 7 && d->dir_bits == d->origin_bits));
 }
 
@@ -464,7 +464,9 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
     const hrpp_status st = check_trace_args(bvh, pred, d_rays, n, any, any ? (const void *)d_occ : d_hits);
     if (st != HRPP_OK || n == 0) return st;
     const TraceArgs a = make_args(bvh, pred, d_rays, d_occ, d_hits, d_stats);
-    launch_trace(a, n, any, exact, pred != nullptr, pred ? pred->desc.epoch_rays : n, pred && pred->empty,
+    const uint32_t epoch = pred ? pred->desc.epoch_rays : n;
+    const uint32_t first = pred && pred->desc.first_epoch_rays ? pred->desc.first_epoch_rays : epoch;
+    launch_trace(a, n, any, exact, pred != nullptr, epoch, first, pred && pred->empty,
                  static_cast<hipStream_t>(stream));
     const hrpp_status ls = check(hipGetLastError());
     if (pred) {
@@ -560,6 +562,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
                          any ? nullptr : static_cast<hrpp_hit *>(J.d_out), J.d_stats);
         bj.n = J.n;
         bj.epoch = J.pred ? J.pred->desc.epoch_rays : std::max(1u, J.n);
+        bj.first = J.pred && J.pred->desc.first_epoch_rays ? J.pred->desc.first_epoch_rays : bj.epoch;
         b->jobs.push_back(bj);
         if (J.pred) b->preds.push_back(J.pred);
         if (J.pred) kind_of[j] = any ? kBatchAnyHrpp : (J.mode == HRPP_CLOSEST_EXACT ? kBatchExactHrpp : kBatchPaperHrpp);
@@ -583,7 +586,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
             g.max_epoch = std::max(g.max_epoch, std::min(bj.epoch, bj.n));
             g.max_cap = std::max(g.max_cap, bj.a.stack_cap);
             g.max_n = std::max(g.max_n, bj.n);
-            g.rounds = std::max(g.rounds, (bj.n + bj.epoch - 1) / bj.epoch);
+            g.rounds = std::max(g.rounds, bj.n <= bj.first ? 1u : 1u + (bj.n - bj.first + bj.epoch - 1) / bj.epoch);
             if (bj.a.stats) g.stats = true;
         }
         if (g.count == 0) continue;

@@ -70,10 +70,11 @@ struct TraceArgs {
     uint32_t *topw;
 };
 
-// One job of a batch (see hrpp_batch_create): its arguments, ray count and epoch size.
+// One job of a batch (see hrpp_batch_create): its arguments, ray count, epoch
+// size and the length of its first epoch (<= epoch).
 struct BatchJob {
     TraceArgs a;
-    uint32_t n, epoch, pad0, pad1;
+    uint32_t n, epoch, first, pad1;
 };
 
 enum BatchKind : int { kBatchAnyHrpp, kBatchPaperHrpp, kBatchExactHrpp, kBatchAnyPlain, kBatchClosestPlain };
@@ -103,8 +104,9 @@ int profile_stop(double *ms, uint64_t *launches);   // synchronises the recorded
 
 // empty_table: the predictor was reset and not traced since (its first epoch
 // then traverses in place).
-void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, bool empty_table,
-                  hipStream_t s);
+// Epochs of `epoch` rays, the first one `first_epoch` rays long (<= epoch).
+void launch_trace(const TraceArgs &a, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch,
+                  uint32_t first_epoch, bool empty_table, hipStream_t s);
 void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
 // Empties every group of kResetGroup entries whose mark is set (all groups
 // when `full`) and clears the marks.

@@ -1023,10 +1023,11 @@ __global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t bas
 // share nothing, so every job computes exactly what its own call computes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool batch_epoch(const BatchJob &J, uint32_t round, uint32_t &base, uint32_t &count) {
-    const uint64_t b = (uint64_t)round * J.epoch;
+    // round 0 is the first epoch (J.first rays), round r >= 1 the r-th of J.epoch
+    const uint64_t b = round == 0 ? 0 : (uint64_t)J.first + (uint64_t)(round - 1) * J.epoch;
     if (b >= J.n) return false;
     base = (uint32_t)b;
-    count = min(J.epoch, J.n - base);
+    count = min(round == 0 ? J.first : J.epoch, J.n - base);
     return true;
 }
 
@@ -1260,16 +1261,16 @@ static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL((k_traverse_plain<ANY, STATS>), dim3(blocks), dim3(128), lds, s, a, n);
 }
 
-void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch, bool empty_table,
-                  hipStream_t s) {
+void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool hrpp, uint32_t epoch,
+                  uint32_t first_epoch, bool empty_table, hipStream_t s) {
     const bool st = args.stats != nullptr;
     if (!hrpp) {
         if (any) { if (st) launch_plain<true, true>(args, n, s); else launch_plain<true, false>(args, n, s); }
         else     { if (st) launch_plain<false, true>(args, n, s); else launch_plain<false, false>(args, n, s); }
         return;
     }
-    for (uint32_t base = 0; base < n; base += epoch) {
-        const uint32_t cnt = std::min(epoch, n - base);
+    for (uint32_t base = 0; base < n;) {
+        const uint32_t cnt = std::min(base == 0 ? first_epoch : epoch, n - base);
         // an empty table predicts nothing: the first epoch after a reset
         // traverses every ray, with the dedicated kernel
         const bool e0 = (base == 0 && empty_table);
@@ -1283,6 +1284,7 @@ void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool 
             if (st) launch_epoch<false, false, true>(args, base, cnt, e0, s);
             else    launch_epoch<false, false, false>(args, base, cnt, e0, s);
         }
+        base += cnt;
     }
 }
 

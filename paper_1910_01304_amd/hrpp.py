@@ -53,7 +53,8 @@ class _BvhDesc(C.Structure):
 class _PredDesc(C.Structure):
     _fields_ = [("log2_entries", C.c_uint32), ("ways", C.c_uint32), ("origin_bits", C.c_uint32),
                 ("dir_bits", C.c_uint32), ("epoch_rays", C.c_uint32), ("hash_mode", C.c_uint32),
-                ("go_up_level", C.c_uint32), ("inline_lanes", C.c_uint32), ("replace_policy", C.c_uint32)]
+                ("go_up_level", C.c_uint32), ("inline_lanes", C.c_uint32), ("replace_policy", C.c_uint32),
+                ("first_epoch_rays", C.c_uint32)]
 
 
 class _KernelTime(C.Structure):
@@ -226,10 +227,10 @@ class Predictor:
 
     def __init__(self, bvh: BVH, log2_entries: int = 12, ways: int = 4, origin_bits: int = 5, dir_bits: int = 6,
                  epoch_rays: int = 1 << 17, hash_mode: int = 0, go_up_level: int = 0, inline_lanes: int = 0,
-                 replace_policy: int = 0, device: str = "cuda"):
+                 replace_policy: int = 0, first_epoch_rays: int = 0, device: str = "cuda"):
         lib = load_library()
         self.desc = _PredDesc(log2_entries, ways, origin_bits, dir_bits, epoch_rays, hash_mode, go_up_level,
-                              inline_lanes, replace_policy)
+                              inline_lanes, replace_policy, first_epoch_rays)
         need = lib.hrpp_predictor_required_bytes(C.byref(self.desc))
         if need == 0:
             raise HrppError("hrpp_predictor_required_bytes: invalid descriptor")

@@ -371,12 +371,12 @@ def scene_diagonal(tris: np.ndarray) -> float:
 TINY = dict(seed=1, n_tris=256, n_rays=4096, log2_entries=12, ways=4, origin_bits=5, dir_bits=6, epoch=256)
 AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin_bits=5, dir_bits=6,
                 epoch=1 << 19, light_center=(0.5, 1.0, 0.5), light_size=0.1,
-                # (origin bits, direction bits, epoch rays, inline lanes) of the hit-all
-                # and hit-any predictors, chosen by the autotuner (table fixed at
-                # 2^20 x 8) and a sweep of the two-stream step over epochs and the
-                # inline split; the hit-all predictor keeps epochs of 2^19, where
-                # about 70% of the nodes are skipped (46% at 2^20)
-                primary_q=(5, 7, 1 << 19, 1), shadow_q=(6, 3, 1 << 19, 1))
+                # (origin bits, direction bits, epoch rays, inline lanes, first epoch
+                # rays) of the hit-all and hit-any predictors, chosen by the autotuner
+                # (table fixed at 2^20 x 8) and a sweep of the two-stream step: a first
+                # epoch of one Bayer pass (2^17 rays, the whole view at 1/16 density)
+                # or two, then the rest of the frame in one epoch
+                primary_q=(5, 7, 1 << 21, 1, 1 << 17), shadow_q=(6, 3, 1 << 21, 1, 1 << 18))
 INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=20, ways=8, origin_bits=5,
                   dir_bits=5, epoch=1 << 20, inline_lanes=16, tmax_frac=0.05)
 

@@ -97,6 +97,10 @@ def test_host_argument_validation():
     # replacement policies 0..3
     assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 0, 3))) > 0
     assert lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 0, 4))) == 0
+    # first epoch: 0 (= epoch_rays) .. epoch_rays
+    for first, ok in ((0, True), (1, True), (256, True), (257, False)):
+        need = lib.hrpp_predictor_required_bytes(C.byref(hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0, 0, 0, first)))
+        assert (need > 0) == ok, first
     assert lib.hrpp_status_string(4) == b"BVH deeper than max_depth"
 
 

@@ -81,15 +81,16 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
         gu = pred_cfg[6] if len(pred_cfg) > 6 else 0
         il = pred_cfg[7] if len(pred_cfg) > 7 else 0
         rp = pred_cfg[8] if len(pred_cfg) > 8 else 0
+        fe = pred_cfg[9] if len(pred_cfg) > 9 else 0
         pred = hrpp.Predictor(bvh, log2_entries=T, ways=W, origin_bits=qo, dir_bits=qd, epoch_rays=E,
-                              hash_mode=hm, go_up_level=gu, inline_lanes=il, replace_policy=rp)
+                              hash_mode=hm, go_up_level=gu, inline_lanes=il, replace_policy=rp, first_epoch_rays=fe)
         tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu, policy=rp)
     first = None
     if pred is not None and rays.shape[0] > 0:
         # the first epoch of a new predictor sees an empty table: the GPU runs it in
         # its own kernel, whose schedule counters equal the oracle's counts for
         # those rays alone
-        e0 = min(pred_cfg[4], rays.shape[0])
+        e0 = min(fe or pred_cfg[4], rays.shape[0])
         _, w0 = oracle.trace(ob, tris, rays[:e0], query=query, mode=mode, table=oracle.Table(T, W, qo, qd,
                              hash_mode=hm, go_up=gu, policy=rp), epoch=pred_cfg[4], vtx=vtx)
         first = {"empty_rays": w0["rays"], "empty_lookups": w0["lookups"],
@@ -99,7 +100,8 @@ def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None,
     for c in range(calls):
         got, gs = gpu_run(hrpp, bvh, rays, query, mode, pred, gst)
         want, ws = oracle.trace(ob, tris, rays, query=query, mode=mode, table=tb,
-                                epoch=pred_cfg[4] if pred_cfg else 1 << 30, vtx=vtx)
+                                epoch=pred_cfg[4] if pred_cfg else 1 << 30, vtx=vtx,
+                                first_epoch=fe if pred_cfg else 0)
         assert_same_result(query, got, want)
         if c == 0:
             acc = dict(ws)
@@ -142,6 +144,19 @@ def test_tiny_hrpp_successive_calls_accumulate(hrpp):
     tris, rays = sg.tiny_workload()
     _, st = check_case(hrpp, "tiny hrpp x3", tris, rays, pred_cfg=(12, 4, 5, 6, 256), calls=3)
     assert st["pred_hits"] > 0
+
+
+@pytest.mark.parametrize("first", [1, 100, 256, 999])
+def test_tiny_first_epoch(hrpp, first):
+    # a shorter first epoch in every call, epochs of 1000 after it (ragged tail)
+    tris, rays = sg.tiny_workload()
+    _, st = check_case(hrpp, f"tiny first epoch {first}", tris, rays, pred_cfg=(12, 4, 5, 6, 1000, 0, 0, 0, 0, first),
+                       calls=2)
+    closest = rays.copy()
+    closest[:, 7] = np.inf
+    for mode in ("paper", "exact"):
+        check_case(hrpp, f"tiny closest {mode} first epoch {first}", tris, closest, query="closest", mode=mode,
+                   pred_cfg=(12, 4, 5, 6, 1000, 0, 0, 1, 0, first))
 
 
 @pytest.mark.parametrize("mode", ["paper", "exact"])
@@ -309,8 +324,25 @@ def test_full_size_policy(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     _, st = check_case(hrpp, "full primary paper, FIFO + resident, 2^12 x 4", tris, prim, query="closest",
-                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3))
+                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3, pq[4]))
     assert st["evictions"] > 0
+
+
+@pytest.mark.parametrize("inline", [1, 65])
+def test_terrain_short_first_epoch(hrpp, small_terrain, inline):
+    # one Bayer pass (3,600 of 57,600 primaries) as the first epoch, the rest in
+    # one epoch that sees the table the pass left; shadow rays with go-up 1
+    tris, prim = small_terrain
+    _, st = check_case(hrpp, f"terrain primary paper, first epoch 3600, inline {inline}", tris, prim,
+                       query="closest", mode="paper", pred_cfg=(14, 8, 5, 7, 1 << 16, 0, 0, inline, 0, 3600))
+    assert st["pred_hits"] > 30000
+    check_case(hrpp, f"terrain primary exact, first epoch 1000, inline {inline}", tris, prim[:30000],
+               query="closest", mode="exact", pred_cfg=(13, 4, 4, 5, 8192, 0, 0, inline, 0, 1000))
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=2)
+    check_case(hrpp, f"terrain shadow go-up 1, first epoch 7200, inline {inline}", tris, shadow,
+               pred_cfg=(14, 8, 6, 3, 1 << 15, 0, 1, inline, 0, 7200))
 
 
 @pytest.mark.parametrize("inline", [1, 32, 64, 65])
@@ -389,7 +421,7 @@ def test_full_size_go_up(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     check_case(hrpp, "full primary paper go-up 1", tris, prim, query="closest", mode="paper",
-               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3]))
+               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3], 0, pq[4]))
 
 
 def test_import_validates_slots(hrpp, small_terrain):
@@ -524,7 +556,8 @@ def test_reset_clears_written_entries(hrpp, small_terrain):
 # ---------------------------------------------------------------------------
 # Full size: the 1M-triangle scene at 1920x1080, in the benchmark's launch
 # configuration (hit-all predictor 2^20 x 8 for primaries, hit-any predictor
-# for shadow rays, epochs of 2^17 rays)
+# for shadow rays, a short first epoch then the rest of the frame) and at the
+# untuned epochs of 2^17 rays
 # ---------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
@@ -538,9 +571,9 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
     # and the untuned reference (q_o 5, q_d 6, epochs of 2^17)
     w = sg.AT_SCALE
     tris, prim = full_terrain
-    pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17, 0), (5, 6, 1 << 17, 0))
-    cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3])
-    cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3])
+    pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17, 0, 0), (5, 6, 1 << 17, 0, 0))
+    cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3], 0, pq[4])
+    cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3], 0, sq[4])
     _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all)
     assert st["rays"] == 1920 * 1080
     ob = oracle.build_sah(tris)

@@ -702,6 +702,61 @@ def test_update_rule_smallest_ray_id_owns_the_entry():
         assert [x for x in tb.slots[1].tolist() if x != NONE32] == want
 
 
+def test_first_epoch_length_hand_case():
+    # 30 rays of one key (8) towards the three squares.  With epochs of 30 the
+    # table is empty for all of them; with a first epoch of 3 rays (one per
+    # square) the other 27 find all three leaves and are predicted, each by the
+    # leaf of its own square (the other two boxes miss it).
+    tris, b, sq_leaf = _three_squares()
+    squares = np.array([2, 0, 1] * 10)
+    rays = _rays_to_squares([-0.5, 1.0, 0.1], squares, 50)
+    tb = oracle.Table(4, 4, 1, 1)
+    _, st = oracle.trace(b, tris, rays, query="closest", mode="paper", table=tb, epoch=30)
+    assert (st["positives"], st["pred_hits"], st["records"]) == (0, 0, 30)
+    tb = oracle.Table(4, 4, 1, 1)
+    hp, st = oracle.trace(b, tris, rays, query="closest", mode="paper", table=tb, epoch=30, first_epoch=3)
+    assert (st["positives"], st["pred_hits"], st["records"], st["traversals"]) == (27, 27, 3, 3)
+    e = int(np.nonzero(tb.tags != EMPTY_TAG)[0][0])
+    assert sorted(x for x in tb.slots[e].tolist() if x != NONE32) == sorted(sq_leaf)
+    exact, _ = oracle.trace(b, tris, rays, query="closest", mode="exact")
+    assert np.array_equal(hp.view(np.uint32), exact.view(np.uint32))
+    # a first epoch as long as the others is no first epoch at all
+    t1, t2 = oracle.Table(4, 4, 1, 1), oracle.Table(4, 4, 1, 1)
+    r1, s1 = oracle.trace(b, tris, rays, query="closest", mode="paper", table=t1, epoch=7, first_epoch=7)
+    r2, s2 = oracle.trace(b, tris, rays, query="closest", mode="paper", table=t2, epoch=7)
+    assert np.array_equal(r1.view(np.uint32), r2.view(np.uint32)) and s1 == s2
+    assert np.array_equal(t1.tags, t2.tags) and np.array_equal(t1.slots, t2.slots)
+    # longer than the other epochs: rejected
+    with pytest.raises(ValueError):
+        oracle.trace(b, tris, rays, query="closest", mode="paper", table=oracle.Table(4, 4, 1, 1), epoch=7,
+                     first_epoch=8)
+
+
+@pytest.mark.parametrize("first,epoch", [(1, 256), (100, 256), (256, 1000), (1000, 1000), (37, 4096)])
+def test_first_epoch_equals_a_split_call(first, epoch):
+    # epochs are boundaries in ray order, each seeing the table the earlier
+    # ones left, with ray ids relative to the call: a call whose first epoch is
+    # F rays long computes what a call of its first F rays (one epoch) followed
+    # by a call of the rest (epochs of E) computes
+    tris, rays = sg.tiny_workload()
+    b = oracle.build_sah(tris)
+    for query, mode in (("any", "paper"), ("closest", "paper"), ("closest", "exact")):
+        r = rays.copy()
+        if query == "closest":
+            r[:, 7] = np.inf
+        t1, t2 = oracle.Table(8, 4, 5, 6), oracle.Table(8, 4, 5, 6)
+        a1, s1 = oracle.trace(b, tris, r, query=query, mode=mode, table=t1, epoch=epoch, first_epoch=first)
+        a2, s2a = oracle.trace(b, tris, r[:first], query=query, mode=mode, table=t2, epoch=first)
+        a3, s2b = oracle.trace(b, tris, r[first:], query=query, mode=mode, table=t2, epoch=epoch)
+        both = np.concatenate([a2, a3])
+        if query == "any":
+            assert np.array_equal(a1, both)
+        else:
+            assert np.array_equal(a1.view(np.uint32), both.view(np.uint32))
+        assert s1 == {k: s2a[k] + s2b[k] for k in s1}
+        assert np.array_equal(t1.tags, t2.tags) and np.array_equal(t1.slots, t2.slots)
+
+
 # ---------------------------------------------------------------------------
 # The paper's IEEE-754 bit hash (hash_mode 1)
 # ---------------------------------------------------------------------------
