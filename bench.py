@@ -999,7 +999,7 @@ def run_goup(args, np, torch, hrpp, sg):
                             dropped=d["dropped"]))
             log(f"go-up {name} g {g}: {pts[-1]}")
             del pred
-        res[name] = dict(rays=n, query=query, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
+        res[name] = dict(rays=n, query=query, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2], first_epoch_rays=q[4],
                          plain_mrays_s=round(n / (ms_plain * 1e-3) / 1e6, 1), points=pts)
     hrpp.get_error(bvh)
     print(json.dumps({
@@ -1072,7 +1072,7 @@ def run_policy(args, np, torch, hrpp, sg):
                                 evictions=d["evictions"]))
                 log(f"policy {name} T {T} p {pol}: {pts[-1]}")
                 del pred
-        res[name] = dict(rays=n, query=query, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
+        res[name] = dict(rays=n, query=query, origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2], first_epoch_rays=q[4],
                          plain_mrays_s=round(n / (ms_plain * 1e-3) / 1e6, 1), points=pts)
     hrpp.get_error(bvh)
     print(json.dumps({
