@@ -566,7 +566,8 @@ def main():
         ao_d = torch.from_numpy(ao).cuda()
         ao_out = torch.empty(ao.shape[0], dtype=torch.uint8, device="cuda")
         pred_ao = hrpp.Predictor(bvh, log2_entries=wi["log2_entries"], ways=wi["ways"], origin_bits=wi["origin_bits"],
-                                 dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"], inline_lanes=wi["inline_lanes"])
+                                 dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"], inline_lanes=wi["inline_lanes"],
+                                 first_epoch_rays=wi["first_epoch"])
 
         def ao_hrpp():
             pred_ao.reset()
@@ -825,7 +826,7 @@ def run_autotune(args, np, torch, hrpp, sg):
         warm.append((pk, torch.from_numpy(sk).cuda()))
     res = {}
     knobs = tuple(k for k in args.tune_knobs.split(",") if k)
-    ao_q = (wi["origin_bits"], wi["dir_bits"], wi["epoch"], wi["inline_lanes"], 0)
+    ao_q = (wi["origin_bits"], wi["dir_bits"], wi["epoch"], wi["inline_lanes"], wi["first_epoch"])
     for name, rays, query, q, warm_rays in (("primary", prim_d, "closest", w["primary_q"], None),
                                             ("shadow", shadow_d, "any", w["shadow_q"], None),
                                             ("ao", ao_d, "any", ao_q, None),
@@ -1030,7 +1031,7 @@ def run_policy(args, np, torch, hrpp, sg):
     res = {}
     for name, rays, query, q in (("primary", prim_d, "closest", pq),
                                  ("ao", ao_d, "any", (wi["origin_bits"], wi["dir_bits"], wi["epoch"],
-                                                      wi["inline_lanes"], 0))):
+                                                      wi["inline_lanes"], wi["first_epoch"]))):
         n = rays.shape[0]
         out = (torch.empty((n, 4), dtype=torch.float32, device="cuda") if query == "closest"
                else torch.empty(n, dtype=torch.uint8, device="cuda"))

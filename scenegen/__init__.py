@@ -377,8 +377,10 @@ AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin
                 # epoch of one Bayer pass (2^17 rays, the whole view at 1/16 density)
                 # or two, then the rest of the frame in one epoch
                 primary_q=(5, 7, 1 << 21, 1, 1 << 17), shadow_q=(6, 3, 1 << 21, 1, 1 << 18))
-INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=20, ways=8, origin_bits=5,
-                  dir_bits=5, epoch=1 << 20, inline_lanes=16, tmax_frac=0.05)
+# the AO predictor: q_o 6, q_d 5, a first epoch of 2^16 rays then epochs of 2^22,
+# waves with >= 16 failing lanes traverse in place (the autotuner's choice)
+INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=20, ways=8, origin_bits=6,
+                  dir_bits=5, epoch=1 << 22, inline_lanes=16, first_epoch=1 << 16, tmax_frac=0.05)
 
 
 def tiny_workload():

@@ -628,7 +628,8 @@ def test_full_size_progressive_frames(hrpp, full_terrain):
 
 @pytest.mark.parametrize("cfg", [
     (sg.INCOHERENT["log2_entries"], sg.INCOHERENT["ways"], sg.INCOHERENT["origin_bits"], sg.INCOHERENT["dir_bits"],
-     sg.INCOHERENT["epoch"], 0, 0, sg.INCOHERENT["inline_lanes"]),     # the benchmark's AO predictor
+     sg.INCOHERENT["epoch"], 0, 0, sg.INCOHERENT["inline_lanes"], 0,
+     sg.INCOHERENT["first_epoch"]),                                   # the benchmark's AO predictor
     (16, 8, 3, 3, 1 << 17, 1),     # sweep corners, the IEEE-754 bit hash
     (22, 8, 7, 7, 1 << 17, 1),
 ])
