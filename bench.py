@@ -9,10 +9,11 @@ One step = the whole query path over one frame of the at-scale workload
   3. one shadow ray per primary hit towards a 0.1 x 0.1 area light, any hit,
      hit-any predictor,
 with the predictor quantisation, epoch sizes and fallback split chosen by the
-autotuner and a sweep of the two-stream step (hit-all: q_o 5, q_d 7; hit-any:
-q_o 6, q_d 3; both 2^19-ray epochs with every failing ray traversed in place;
-the first epoch after a reset always traverses in place; the line also
-reports the untuned q_o 5 / q_d 6 step at epochs of 2^17).  The same rays are
+autotuner and a sweep of the two-stream step (hit-all: q_o 5, q_d 7, a first
+epoch of 2^17 rays -- one of the 16 interleaved pixel passes -- then the rest
+of the frame as one epoch; hit-any: q_o 6, q_d 3, a first epoch of 2^18; every
+failing ray traversed in place; the line also reports the untuned q_o 5 /
+q_d 6 step at epochs of 2^17).  The same rays are
 also traced without a predictor ("plain"), on the binary and on the 4-wide
 tree.  Rays and the BVH are resident in HBM before timing; shadow rays are
 built once, in setup, from the GPU's exact primary hits.
