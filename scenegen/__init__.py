@@ -373,11 +373,10 @@ AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin
                 epoch=1 << 19, light_center=(0.5, 1.0, 0.5), light_size=0.1,
                 # (origin bits, direction bits, epoch rays, inline lanes, first epoch
                 # rays) of the hit-all and hit-any predictors, chosen by the autotuner
-                # (table fixed at 2^20 x 8) and sweeps of the two-stream step: a first
+                # (table fixed at 2^20 x 8) and a sweep of the two-stream step: a first
                 # epoch of one Bayer pass (2^17 rays, the whole view at 1/16 density)
-                # or two, then the rest of the frame in one epoch; the hit-all
-                # predictor queues the failing rays of waves with fewer than 32 of them
-                primary_q=(5, 7, 1 << 21, 32, 1 << 17), shadow_q=(6, 3, 1 << 21, 1, 1 << 18))
+                # or two, then the rest of the frame in one epoch
+                primary_q=(5, 7, 1 << 21, 1, 1 << 17), shadow_q=(6, 3, 1 << 21, 1, 1 << 18))
 # the AO predictor: q_o 6, q_d 5, a first epoch of 2^16 rays then epochs of 2^22,
 # waves with >= 16 failing lanes traverse in place (the autotuner's choice)
 INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=20, ways=8, origin_bits=6,
