@@ -666,8 +666,9 @@ def test_maximum_epoch_and_large_table(hrpp, full_terrain):
 def test_random_configurations(hrpp):
     # random predictor configurations on small random scenes, every one against
     # the oracle: hash mode, go-up level, replacement policy, fallback split,
-    # epoch (ragged), table shape, query and closest-hit mode
+    # epoch (ragged) and first epoch, table shape, query and closest-hit mode
     g = np.random.default_rng(2024)
+    gf = np.random.default_rng(2025)          # first epochs (drawn apart, so the other draws stay as they were)
     for case in range(40):
         seed = int(g.integers(1, 1 << 30))
         n_tris = int(g.integers(1, 3000))
@@ -684,6 +685,7 @@ def test_random_configurations(hrpp):
         qo, qd = (q, q) if hm else (int(g.integers(1, 9)), int(g.integers(1, 9)))
         cfg = (int(g.integers(1, 15)), int(g.integers(1, 9)), qo, qd, int(g.integers(1, 3000)), hm,
                int(g.choice([0, 0, 1, 2, 5])), int(g.choice([0, 1, 16, 48, 64, 65])), int(g.integers(0, 4)))
+        cfg = cfg + ((0 if gf.random() < 0.4 else int(gf.integers(1, cfg[4] + 1))),)
         check_case(hrpp, f"random {case}", tris, rays, query=query, mode=mode, pred_cfg=cfg,
                    calls=int(g.integers(1, 3)), leaf_max=int(g.choice([1, 2, 4, 8])))
 
