@@ -1,6 +1,7 @@
 // HIP kernels of the HRPP library for CDNA4 (gfx950, wave64).
 //
-// Per epoch of E rays (rays of epoch k see the table after epoch k-1):
+// Per epoch (a call's first epoch F rays, the others E; rays of epoch k see the
+// table after epoch k-1):
 //   k_predict    one lane per ray: validate, hash, probe the table, test the
 //                predicted leaves (or walk the predicted subtrees, go-up
 //                level >= 1); successes write their result; a wave with
