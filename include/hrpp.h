@@ -255,8 +255,9 @@ void hrpp_predictor_destroy(hrpp_predictor *pred);
 /* Any-hit (shadow / hit-any) query for n rays d_rays[0..n).  d_occluded[i]
  * = 1 if some triangle is hit inside (tmin, tmax), else 0.  pred NULL =
  * plain traversal; otherwise rays are processed in epochs of epoch_rays in
- * index order (the first one first_epoch_rays long): hash, lookup, test the predicted leaves (stop at the first
- * hit), traverse the rest, then update the table.  The flag does not depend
+ * index order (the first one first_epoch_rays long): hash, lookup, test the
+ * predicted leaves (stop at the first hit), traverse the rest, then update
+ * the table.  The flag does not depend
  * on the predictor.  d_stats (may be NULL) is accumulated.  n == 0 is a
  * no-op.  Errors: EINVAL (null arrays with n > 0, n >= 2^31, predictor
  * built for another BVH). */
@@ -306,8 +307,9 @@ hrpp_status hrpp_trace_wide_closest(const hrpp_bvh *bvh, const hrpp_ray *d_rays,
 
 /* ------------------------------------------------------------------------
  * Batches: many independent jobs (each its own BVH, predictor or none, rays
- * and outputs) executed together.  Round r runs epoch r of every job in one
- * launch per kernel, so scenes of uneven size fill the GPU together; the
+ * and outputs) executed together.  Round r runs epoch r of every job (round
+ * 0: each job's first epoch) in one launch per kernel, so scenes of uneven
+ * size fill the GPU together; the
  * whole sequence can be captured once into a hipGraph and replayed.  Each
  * job computes exactly what its own hrpp_trace_* call would (results,
  * counters and table), because jobs share nothing and each job's epochs
