@@ -1174,7 +1174,7 @@ struct ProfScope {
 const char *kernel_kind_name(int k) {
     static const char *names[kNumKernelKinds] = {"k_predict", "k_traverse_queue", "k_traverse_plain",
                                                  "k_update_classify", "k_update_apply", "k_update_finish",
-                                                 "k_fill32", "k_traverse_wide", "k_epoch_empty"};
+                                                 "k_fill32", "k_traverse_wide", "k_epoch_empty", "k_reset_table"};
     return (k >= 0 && k < kNumKernelKinds) ? names[k] : "unknown";
 }
 
@@ -1325,7 +1325,7 @@ void launch_reset_table(void *table, uint32_t entry_bytes, uint32_t n_entries, u
     const uint32_t n_groups = (n_entries + kResetGroup - 1u) / kResetGroup;
     const uint32_t waves = (n_groups + 63u) / 64u;
     const uint32_t blocks = (waves + 3u) / 4u;
-    ProfScope prof(kKindFill, s);
+    ProfScope prof(kKindResetTable, s);
     hipLaunchKernelGGL(k_reset_table, dim3(blocks), dim3(256), 0, s, (uint4 *)table, entry_bytes / 16u, n_entries,
                        dirty, full ? 1u : 0u);
 }
