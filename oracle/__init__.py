@@ -6,7 +6,7 @@ fixed order, OpenMP across the rays of one epoch) and adds the fp64 and
 validation helpers the pins use.  It shares no code with the GPU library.
 """
 from .core import (  # noqa: F401
-    STAT_NAMES, CanonBVH, Table, build_sah, build_median, bvh_vertices, trace, brute_force,
+    STAT_NAMES, CanonBVH, Table, build_sah, build_median, build_lbvh, lbvh_codes, bvh_vertices, trace, brute_force,
     hash_rays, mt, slab, lib_path, build_library,
 )
 from .validate import validate_bvh  # noqa: F401

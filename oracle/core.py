@@ -124,6 +124,19 @@ def build_median(tris: np.ndarray, leaf_max: int = 4, max_depth: int = 100) -> C
     return _run_build(_L().orc_build_median, tris, leaf_max, max_depth)
 
 
+def build_lbvh(tris: np.ndarray, leaf_max: int = 4, max_depth: int = 64) -> CanonBVH:
+    """Linear BVH: Morton order of the triangle centres, radix-tree splits."""
+    return _run_build(_L().orc_build_lbvh, tris, leaf_max, max_depth)
+
+
+def lbvh_codes(tris: np.ndarray) -> np.ndarray:
+    """The 63-bit Morton code of every triangle (original order)."""
+    tris = np.ascontiguousarray(tris, np.float32).reshape(-1, 9)
+    out = np.zeros(tris.shape[0], np.uint64)
+    _L().orc_lbvh_codes(_p(tris), C.c_uint32(tris.shape[0]), _p(out))
+    return out
+
+
 def bvh_vertices(tris: np.ndarray, bvh: CanonBVH) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(tris, np.float32).reshape(-1, 9)[bvh.perm])
 

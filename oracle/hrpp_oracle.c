@@ -321,6 +321,139 @@ int orc_build_median(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t 
     return ctx.error ? -2 : 0;
 }
 
+/* A third builder, the linear BVH of the device build (Lauterbach et al.,
+   "Fast BVH Construction on GPUs", 2009; the binary radix tree of Karras,
+   "Maximizing Parallelism in the Construction of BVHs, Octrees, and k-d
+   Trees", HPG 2012), written top-down from its definition:
+   * centre of triangle t on axis a: c = (lo + hi) * 0.5 with lo / hi the
+     vertices' min / max (the same centre as the SAH builder);
+   * cmin / cmax = min / max centre over all triangles; per axis
+     scale = 2^21 / (cmax - cmin), or 0 when that extent is 0 or the
+     quotient is not finite; cell q = min(floor((c - cmin) * scale), 2^21 - 1);
+   * Morton code: bit k of the x / y / z cell goes to bit 3k+2 / 3k+1 / 3k;
+   * triangles sorted by (code, primitive id);
+   * the node over sorted positions [b, e) is a leaf when e - b <= leaf_max;
+     otherwise it splits where the key (code, position) first changes at the
+     highest bit in which its first and last keys differ: the code's bit when
+     the codes differ, else the position's bit;
+   * boxes are the exact bounds of the node's triangles; DFS pre-order. */
+typedef struct {
+    uint64_t *code;      /* by sorted position */
+    uint32_t *perm;      /* sorted position -> primitive id */
+    const float *tris;
+    orc_bvh *out;
+    uint32_t leaf_max, max_depth;
+    int error;
+} lbvh_ctx;
+
+static const uint64_t *g_lb_codes;
+static int lb_cmp(const void *pa, const void *pb)
+{
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    if (g_lb_codes[a] != g_lb_codes[b]) return g_lb_codes[a] < g_lb_codes[b] ? -1 : 1;
+    return a < b ? -1 : (a > b);
+}
+
+static int top_bit64(uint64_t x) { int h = 63; while (!((x >> h) & 1u)) h--; return h; }
+
+static uint32_t lbvh_node(lbvh_ctx *ctx, uint32_t b, uint32_t e, uint32_t depth)
+{
+    orc_bvh *o = ctx->out;
+    uint32_t node = o->num_nodes++;
+    float mn[3] = { INFINITY, INFINITY, INFINITY }, mx[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (uint32_t i = b; i < e; i++) {
+        const float *v = ctx->tris + 9 * (size_t)ctx->perm[i];
+        for (int k = 0; k < 3; k++)
+            for (int a = 0; a < 3; a++) {
+                if (v[3 * k + a] < mn[a]) mn[a] = v[3 * k + a];
+                if (v[3 * k + a] > mx[a]) mx[a] = v[3 * k + a];
+            }
+    }
+    for (int a = 0; a < 3; a++) { o->box[6 * node + a] = mn[a]; o->box[6 * node + 3 + a] = mx[a]; }
+    o->depth[node] = depth;
+    if (e - b <= ctx->leaf_max) {
+        if (depth > ctx->max_depth) ctx->error = 1;
+        o->right[node] = NONE32; o->first[node] = b; o->count[node] = e - b;
+        return node;
+    }
+    uint32_t split = e;
+    uint64_t cb = ctx->code[b], ce = ctx->code[e - 1];
+    if (cb != ce) {
+        int h = top_bit64(cb ^ ce);
+        for (uint32_t i = b + 1; i < e; i++)
+            if ((ctx->code[i] >> h) != (cb >> h)) { split = i; break; }
+    } else {
+        int h = top_bit64((uint64_t)(b ^ (e - 1)));
+        for (uint32_t i = b + 1; i < e; i++)
+            if ((i >> h) != (b >> h)) { split = i; break; }
+    }
+    o->first[node] = 0; o->count[node] = 0;
+    lbvh_node(ctx, b, split, depth + 1);
+    o->right[node] = lbvh_node(ctx, split, e, depth + 1);
+    return node;
+}
+
+/* Morton code of every triangle (original order), as defined above. */
+void orc_lbvh_codes(const float *tris, uint32_t n, uint64_t *code)
+{
+    float *c = (float *)malloc(sizeof(float) * 3 * (size_t)n);
+    float cmin[3] = { INFINITY, INFINITY, INFINITY }, cmax[3] = { -INFINITY, -INFINITY, -INFINITY };
+    for (uint32_t t = 0; t < n; t++) {
+        const float *v = tris + 9 * (size_t)t;
+        for (int a = 0; a < 3; a++) {
+            float lo = v[a], hi = v[a];
+            if (v[3 + a] < lo) lo = v[3 + a];
+            if (v[6 + a] < lo) lo = v[6 + a];
+            if (v[3 + a] > hi) hi = v[3 + a];
+            if (v[6 + a] > hi) hi = v[6 + a];
+            float ce = (lo + hi) * 0.5f;
+            c[3 * (size_t)t + a] = ce;
+            if (ce < cmin[a]) cmin[a] = ce;
+            if (ce > cmax[a]) cmax[a] = ce;
+        }
+    }
+    float scale[3];
+    for (int a = 0; a < 3; a++) {
+        float ext = cmax[a] - cmin[a];
+        float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
+        scale[a] = isfinite(s) ? s : 0.0f;
+    }
+    for (uint32_t t = 0; t < n; t++) {
+        uint32_t q[3];
+        for (int a = 0; a < 3; a++) {
+            float f = floorf((c[3 * (size_t)t + a] - cmin[a]) * scale[a]);
+            q[a] = f >= 2097151.0f ? 2097151u : (uint32_t)f;
+        }
+        uint64_t m = 0;
+        for (int k = 0; k < 21; k++) {
+            m |= (uint64_t)((q[0] >> k) & 1u) << (3 * k + 2);
+            m |= (uint64_t)((q[1] >> k) & 1u) << (3 * k + 1);
+            m |= (uint64_t)((q[2] >> k) & 1u) << (3 * k);
+        }
+        code[t] = m;
+    }
+    free(c);
+}
+
+int orc_build_lbvh(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t max_depth, orc_bvh *out)
+{
+    if (n == 0 || leaf_max < 1 || leaf_max > 8 || n >= (1u << 28) || max_depth > 120) return -1;
+    for (size_t i = 0; i < 9 * (size_t)n; i++) if (!isfinite(tris[i])) return -1;
+    uint64_t *code = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    uint64_t *sorted = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    orc_lbvh_codes(tris, n, code);
+    for (uint32_t t = 0; t < n; t++) out->perm[t] = t;
+    g_lb_codes = code;
+    qsort(out->perm, n, sizeof(uint32_t), lb_cmp);
+    for (uint32_t i = 0; i < n; i++) sorted[i] = code[out->perm[i]];
+    lbvh_ctx ctx = { sorted, out->perm, tris, out, leaf_max, max_depth, 0 };
+    out->num_nodes = 0;
+    out->num_tris = n;
+    lbvh_node(&ctx, 0, n, 0);
+    free(code); free(sorted);
+    return ctx.error ? -2 : 0;
+}
+
 /* ======================================================================== */
 /* Ray primitives                                                           */
 /* ======================================================================== */

@@ -276,6 +276,77 @@ def test_sah_beats_median_on_cost():
     assert s_sah["box_tests"] < s_med["box_tests"]
 
 
+def _point_tris(pts):
+    """Degenerate triangles with all three vertices at each point."""
+    pts = np.asarray(pts, np.float32).reshape(-1, 3)
+    return np.ascontiguousarray(np.tile(pts, (1, 3)))
+
+
+def test_lbvh_codes_hand_cases():
+    # centres span [0, 2^21] on every axis, so a cell is the integer part of the
+    # centre; cell (1, 2, 4) interleaves to bits 2 (x bit 0), 4 (y bit 1) and
+    # 6 (z bit 2); the far corner clamps to 2^21 - 1 on every axis
+    S = 2.0 ** 21
+    tris = _point_tris([[0, 0, 0], [S, S, S], [1, 2, 4], [2 ** 20, 0, 0], [0, 2 ** 20 + 0.5, 0], [0, 0, 3]])
+    c = oracle.lbvh_codes(tris).astype(object)
+    assert c.tolist() == [0, 2 ** 63 - 1, 4 + 16 + 64, 2 ** 62, 2 ** 61, 1 + 8]
+    # a flat axis has a single cell: every z bit stays 0
+    flat = _point_tris([[0, 0, 5], [S, S, 5], [1, 1, 5]])
+    assert oracle.lbvh_codes(flat).tolist() == [0, 0b110 * (2 ** 63 - 1) // 7, 0b110]
+
+
+def test_lbvh_equal_codes_split_by_position():
+    # five copies of one triangle share a code, so the splits follow the
+    # sorted positions' bits: [0,5) -> [0,4) + [4]; [0,4) -> [0,2) + [2,4)
+    tris = np.repeat(sg.triangle_soup(5, 1), 5, axis=0)
+    b = oracle.build_lbvh(tris, leaf_max=1)
+    assert b.right.tolist() == [8, 5, 4, NONE32, NONE32, 7, NONE32, NONE32, NONE32]
+    assert b.first[b.right == NONE32].tolist() == [0, 1, 2, 3, 4]
+    assert b.depth.tolist() == [0, 1, 2, 3, 3, 2, 3, 3, 1]
+    assert b.perm.tolist() == [0, 1, 2, 3, 4]          # equal codes keep primitive order
+    with pytest.raises(ValueError):
+        oracle.build_lbvh(np.repeat(tris, 10, axis=0), leaf_max=1, max_depth=3)
+
+
+def _lbvh_keys(tris, b):
+    code = oracle.lbvh_codes(tris)
+    return [(int(code[p]) << 28) | k for k, p in enumerate(b.perm.tolist())], code
+
+
+@pytest.mark.parametrize("n,leaf_max", [(1, 4), (4, 4), (5, 4), (97, 1), (700, 2), (3000, 4)])
+def test_lbvh_is_the_radix_tree_of_the_sorted_codes(n, leaf_max):
+    # independent of the builder: the tree is valid, its triangles are in
+    # (code, id) order, a node is a leaf exactly when it holds <= leaf_max
+    # triangles, and each split leaves both children a longer common prefix of
+    # the key (code, position) than their parent; for sorted distinct keys
+    # only the radix-tree split does that
+    tris = sg.triangle_soup(40 + n, n)
+    if n >= 700:
+        tris[: n // 3] = tris[n // 3: 2 * (n // 3)]        # many equal codes
+    b = oracle.build_lbvh(tris, leaf_max=leaf_max)
+    oracle.validate_bvh(b, tris, leaf_max, 64)
+    keys, code = _lbvh_keys(tris, b)
+    order = sorted(range(n), key=lambda t: (int(code[t]), t))
+    assert b.perm.tolist() == order
+
+    def prefix(lo, hi):        # common leading bits of keys[lo .. hi-1], 91-bit keys
+        return 91 - (keys[lo] ^ keys[hi - 1]).bit_length()
+
+    rng = {}
+    for i in range(b.num_nodes - 1, -1, -1):
+        if b.right[i] == NONE32:
+            rng[i] = (int(b.first[i]), int(b.first[i] + b.count[i]))
+            assert rng[i][1] - rng[i][0] <= leaf_max
+        else:
+            L, R = rng[i + 1], rng[int(b.right[i])]
+            assert L[1] == R[0]
+            rng[i] = (L[0], R[1])
+            assert rng[i][1] - rng[i][0] > leaf_max
+            p = prefix(*rng[i])
+            for lo, hi in (L, R):
+                assert hi - lo == 1 or prefix(lo, hi) > p
+
+
 # ---------------------------------------------------------------------------
 # Traversal versus brute force (plain definitions of any-hit and closest hit)
 # ---------------------------------------------------------------------------
@@ -352,6 +423,11 @@ def test_results_do_not_depend_on_tree_shape():
     ha, _ = oracle.trace(a, tris, rays, query="closest", mode="exact")
     hm, _ = oracle.trace(m, tris, rays, query="closest", mode="exact")
     _allowed_mismatch(tris, rays, np.any(ha.view(np.uint32) != hm.view(np.uint32), axis=1))
+    lb = oracle.build_lbvh(tris)
+    ol, _ = oracle.trace(lb, tris, rays)
+    _allowed_mismatch(tris, rays, oa != ol)
+    hl, _ = oracle.trace(lb, tris, rays, query="closest", mode="exact")
+    _allowed_mismatch(tris, rays, np.any(ha.view(np.uint32) != hl.view(np.uint32), axis=1))
 
 
 def test_invalid_rays_are_counted_misses():
