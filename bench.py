@@ -78,7 +78,8 @@ def parse():
     ap.add_argument("--reference-epoch", type=int, default=1 << 17,
                     help="also time the HRPP step at this epoch size (0 = skip)")
     ap.add_argument("--workload", default="at_scale",
-                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup", "policy", "progressive"],
+                    choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup", "policy", "progressive",
+                             "build"],
                     help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
                          "graph-captured batch")
     ap.add_argument("--sweep-epoch", type=int, default=1 << 17,
@@ -273,6 +274,9 @@ def main():
         return
     if args.workload == "progressive":
         run_progressive(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "build":
+        run_build(args, np, torch, hrpp, sg)
         return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
@@ -1010,6 +1014,117 @@ def run_goup(args, np, torch, hrpp, sg):
         "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) and shadow any-hit, "
                                f"tables 2^{w['log2_entries']} x {w['ways']}"},
         "results": res}), flush=True)
+
+
+def run_build(args, np, torch, hrpp, sg):
+    """Device build versus host build of the at-scale scene (2^20 triangles),
+    and what the tree costs the queries: the host binned-SAH tree (built on
+    the CPU, then uploaded) against the linear BVH built on the GPU from
+    resident vertices, each timed (median of 5; the device build's HIP-event
+    time and wall time, the call included), then the at-scale step (primary
+    closest PAPER + shadow any-hit on two streams, tables reset every step)
+    traced over each tree, HRPP and plain."""
+    w = sg.AT_SCALE
+    log("generating the at-scale workload")
+    tris, prim = sg.terrain_workload()
+    n_tris = tris.shape[0]
+    host_s = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        sah = hrpp.BVH(tris, device=None)
+        host_s.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    sah.upload()
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t0) * 1e3
+    verts_d = torch.from_numpy(np.ascontiguousarray(tris.reshape(-1, 9))).cuda()
+    dev_ms, dev_wall = [], []
+    for rep in range(6):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        lb = hrpp.BVH.build_on_device(verts_d)
+        e1.record()
+        torch.cuda.synchronize()
+        if rep:                              # the first build pays for the allocations
+            dev_wall.append((time.perf_counter() - t0) * 1e3)
+            dev_ms.append(e0.elapsed_time(e1))
+        if rep < 5:
+            lb.close()
+    log(f"host SAH {statistics.median(host_s):.2f} s + upload {upload_ms:.1f} ms; device LBVH "
+        f"{statistics.median(dev_ms):.3f} ms (wall {statistics.median(dev_wall):.3f} ms)")
+    prim_d = torch.from_numpy(prim).cuda()
+    he = hrpp.trace_closest(sah, None, prim_d, mode="exact").cpu().numpy()
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
+                                      light_center=w["light_center"], light_size=w["light_size"])
+    shadow_d = torch.from_numpy(shadow).cuda()
+    n_prim, n_sh = prim.shape[0], shadow.shape[0]
+    hits_out = torch.empty((n_prim, 4), dtype=torch.float32, device="cuda")
+    occ_out = torch.empty(n_sh, dtype=torch.uint8, device="cuda")
+    pq, sq = w["primary_q"], w["shadow_q"]
+    s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def on_two_streams(fa, fb):
+        cur = torch.cuda.current_stream()
+        s_a.wait_stream(cur)
+        s_b.wait_stream(cur)
+        with torch.cuda.stream(s_a):
+            fa()
+        with torch.cuda.stream(s_b):
+            fb()
+        cur.wait_stream(s_a)
+        cur.wait_stream(s_b)
+
+    trees = {}
+    for name, bvh in (("host_sah", sah), ("device_lbvh", lb)):
+        pa = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1],
+                            epoch_rays=pq[2], inline_lanes=pq[3], first_epoch_rays=pq[4])
+        pb = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1],
+                            epoch_rays=sq[2], inline_lanes=sq[3], first_epoch_rays=sq[4])
+
+        def prim_run(pred, st=None):
+            if pred is not None:
+                pred.reset()
+            hrpp.trace_closest(bvh, pred, prim_d, mode="paper", out=hits_out, stats=st)
+
+        def sh_run(pred, st=None):
+            if pred is not None:
+                pred.reset()
+            hrpp.trace_anyhit(bvh, pred, shadow_d, out=occ_out, stats=st)
+
+        ms_h = timed(torch, lambda: on_two_streams(lambda: prim_run(pa), lambda: sh_run(pb)), args.steps,
+                     args.warmup)[0]
+        ms_p = timed(torch, lambda: on_two_streams(lambda: prim_run(None), lambda: sh_run(None)), args.steps,
+                     args.warmup)[0]
+        st = {k: hrpp.new_stats() for k in ("ph", "pp", "sh", "sp")}
+        prim_run(pa, st["ph"])
+        prim_run(None, st["pp"])
+        sh_run(pb, st["sh"])
+        sh_run(None, st["sp"])
+        torch.cuda.synchronize()
+        d = {k: hrpp.stats_dict(v) for k, v in st.items()}
+        hrpp.get_error(bvh)
+        trees[name] = dict(
+            nodes=bvh.num_nodes, depth=bvh.max_depth,
+            step_hrpp_mrays_s=round((n_prim + n_sh) / (ms_h * 1e-3) / 1e6, 1),
+            step_plain_mrays_s=round((n_prim + n_sh) / (ms_p * 1e-3) / 1e6, 1),
+            primary_nodes_per_ray_plain=round(d["pp"]["nodes_visited"] / n_prim, 2),
+            shadow_nodes_per_ray_plain=round(d["sp"]["nodes_visited"] / n_sh, 2),
+            primary_pct_nodes_skipped=round(100 * (1 - d["ph"]["nodes_visited"] / d["pp"]["nodes_visited"]), 2),
+            shadow_pct_nodes_skipped=round(100 * (1 - d["sh"]["nodes_visited"] / d["sp"]["nodes_visited"]), 2))
+        log(f"{name}: {trees[name]}")
+        del pa, pb
+    print(json.dumps({
+        "metric": "BVH build time and the step over each tree", "unit": "ms", "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"terrain {n_tris} tris; step = 1920x1080 primary closest (PAPER) + shadow any-hit, "
+                               f"tables 2^{w['log2_entries']} x {w['ways']}", "steps": args.steps},
+        "host_sah_build_s": round(statistics.median(host_s), 3), "host_upload_ms": round(upload_ms, 2),
+        "device_lbvh_build_ms": round(statistics.median(dev_ms), 3),
+        "device_lbvh_build_min_ms": round(min(dev_ms), 3),
+        "device_lbvh_build_wall_ms": round(statistics.median(dev_wall), 3),
+        "build_speedup": round(statistics.median(host_s) * 1e3 / statistics.median(dev_wall), 1),
+        "trees": trees}), flush=True)
 
 
 def run_policy(args, np, torch, hrpp, sg):

@@ -199,12 +199,41 @@ size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh);
  * another buffer moves the BVH there (predictors stay bound to it). */
 hrpp_status hrpp_bvh_upload(hrpp_bvh *bvh, void *d_buf, size_t bytes, void *stream);
 
+/* Device build (a GPU builder for callers that take new scenes while they
+ * run, such as the serving loop; the paper takes the BVH as given,
+ * "Overview").  Builds a linear BVH entirely on the GPU: the binary radix
+ * tree over 63-bit Morton codes of the triangle centres (Karras, HPG 2012),
+ * triangles ordered by (code, primitive id), every subtree over at most
+ * leaf_max triangles kept as one leaf, exact boxes, DFS pre-order -- a
+ * different tree from the host builder's SAH tree, with the same query
+ * results.
+ *
+ * Scratch bytes the build needs for num_tris triangles (0 when num_tris is 0
+ * or >= 2^28, or when no HIP device answers the sort's size query). */
+size_t hrpp_bvh_device_build_scratch_bytes(uint32_t num_tris);
+
+/* d_verts: device array of 9 floats per triangle (original order =
+ * primitive id), 4-byte aligned, read only.  d_scratch (>= the bytes above)
+ * and d_buf (>= hrpp_bvh_required_bytes) are caller-owned, 256-byte aligned;
+ * the scratch is free again when the call returns, d_buf holds the BVH.
+ * desc->sah_bins is ignored.  Enqueues the build on `stream` and
+ * synchronises it.  Errors: EINVAL (null pointers, misalignment, num_tris
+ * == 0 or >= 2^28, bad desc, a non-finite vertex), ENOMEM (a buffer too
+ * small), EDEPTH (a leaf deeper than desc->max_depth), EDEVICE.  The handle
+ * can be traced, used by predictors, batches and the server, and exported
+ * (hrpp_bvh_export then copies the tree back); it has no 4-wide tree
+ * (hrpp_trace_wide_* return EINVAL) and cannot be uploaded again. */
+hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                  void *d_scratch, size_t scratch_bytes, void *d_buf, size_t bytes, void *stream,
+                                  hrpp_bvh **out);
+
 /* Node count, triangle count and maximum leaf depth of a built BVH. */
 hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *num_tris,
                           uint32_t *max_depth);
 
 /* Copy the canonical form of the tree into caller-owned host arrays
- * (sized from hrpp_bvh_info).  Synchronous, host only. */
+ * (sized from hrpp_bvh_info).  Synchronous: host only for a host-built
+ * tree; a device-built tree is copied back from device memory. */
 hrpp_status hrpp_bvh_export(const hrpp_bvh *bvh, hrpp_bvh_canon *h_out);
 
 /* Release the handle (the caller's device buffer is not touched). */

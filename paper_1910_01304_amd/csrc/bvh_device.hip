@@ -1,0 +1,507 @@
+// Device BVH build of the HRPP library: a linear BVH over Morton codes.
+//
+// The paper takes the BVH as given ("Overview", "Limit Study").  The host
+// builder (bvh_build.cpp) makes a binned-SAH tree; this file builds, entirely
+// on the GPU, the binary radix tree over the triangles' Morton codes
+// (Lauterbach et al. 2009; Karras, HPG 2012), for callers that must build
+// scenes quickly (the serving loop takes new scenes while it runs).  The tree:
+//   * centre of a triangle on axis a: (lo + hi) * 0.5 with lo / hi the min /
+//     max of its vertices (the SAH builder's centre);
+//   * per axis, over all centres: scale = 2^21 / (cmax - cmin), 0 when that
+//     extent is 0 or the quotient is not finite; cell = min(floor((c - cmin)
+//     * scale), 2^21 - 1); code bit 3k+2 / 3k+1 / 3k = bit k of the x / y / z
+//     cell (63 bits);
+//   * triangles sorted by (code, primitive id) -- a stable radix sort;
+//   * the radix tree over the keys (code, sorted position): each node splits
+//     its range at the highest bit in which its first and last keys differ;
+//   * a node over at most leaf_max triangles is a leaf (its subtree is
+//     dropped); boxes are exact bounds; nodes numbered in DFS pre-order.
+// The output is the same GPU layout hrpp_bvh_upload writes for a host tree:
+// interior nodes (64 B), triangles (48 B), leaf boxes (32 B), canonical node
+// records (48 B); there is no 4-wide tree.
+//
+// No kernel hands data to another workgroup of the same launch: every
+// dependency is a kernel boundary.  In launch order:
+//   k_lbvh_bounds / k_lbvh_bounds_final  centre bounds (per-block partials)
+//   k_lbvh_codes, radix sort             Morton codes in (code, id) order
+//   k_lbvh_karras                        each internal node's range and split
+//   k_lbvh_mark, exclusive scan          output leaves starting before each
+//                                        sorted position
+//   k_lbvh_number                        depth and DFS pre-order index
+//   k_lbvh_leaf_boxes, k_lbvh_level      leaf boxes, then interior boxes one
+//                                        depth at a time, deepest first
+//   k_lbvh_emit                          the GPU layout
+// The pre-order index of a node is closed-form: the subtrees left of it along
+// its root path tile the sorted positions before its range, and a subtree of
+// k leaves has 2k - 1 nodes, so index = 2 * (output leaves before its first
+// position) + (ancestors it descends from on the left).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "hrpp_internal.h"
+#include "hrpp_kernels.h"
+
+namespace hrpp {
+
+namespace {
+
+constexpr uint32_t kCellMax = (1u << 21) - 1u;
+constexpr uint32_t kWalkLimit = 128;   // deeper than any radix tree over 63-bit codes + 28-bit positions
+
+// Header of the build scratch (also read back by the host).
+struct LbvhHeader {
+    uint32_t bad;          // bit 0: a non-finite vertex; bit 1: inconsistent numbering; bit 2: too deep
+    uint32_t cmin[3];      // order-preserving images of the centre bounds
+    uint32_t cmax[3];
+    uint32_t max_depth;    // deepest leaf
+    uint32_t num_nodes;    // nodes of the output tree
+    float root_box[6];
+    uint32_t pad[49];
+};
+static_assert(sizeof(LbvhHeader) == 256, "one 256-byte header");
+
+// Total order of binary32 values as unsigned integers (for atomic min / max).
+__device__ inline uint32_t ord_of(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float float_of(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// Vertex min / max of one triangle on each axis (strict comparisons, first
+// vertex wins ties) and its centre.
+__device__ inline void tri_bounds(const float *__restrict__ v, float lo[3], float hi[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        float l = v[a], h = v[a];
+        if (v[3 + a] < l) l = v[3 + a];
+        if (v[6 + a] < l) l = v[6 + a];
+        if (v[3 + a] > h) h = v[3 + a];
+        if (v[6 + a] > h) h = v[6 + a];
+        lo[a] = l;
+        hi[a] = h;
+    }
+}
+
+// Spread the low 21 bits of x so that bit k lands on bit 3k.
+__device__ inline uint64_t spread3(uint64_t x) {
+    x &= 0x1FFFFFull;
+    x = (x | (x << 32)) & 0x1F00000000FFFFull;
+    x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+constexpr uint32_t kBoundBlocks = 512;   // blocks of the bounds pass (partials reduced by one block)
+constexpr uint32_t kRightChild = 0x80000000u;   // parent word: the node is its parent's right child
+
+__device__ inline uint32_t wave_min(uint32_t x) {
+    for (int off = 32; off >= 1; off >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, off, 64));
+    return x;
+}
+__device__ inline uint32_t wave_max(uint32_t x) {
+    for (int off = 32; off >= 1; off >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, off, 64));
+    return x;
+}
+
+// Block reduction of 7 words (min of 0..2, max of 3..5, or of 6) over 256
+// threads; thread 0 ends with the block's values.
+__device__ inline void block_reduce7(uint32_t v[7], uint32_t (*lds)[7]) {
+    for (int k = 0; k < 7; k++) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
+    const uint32_t w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63u) == 0)
+        for (int k = 0; k < 7; k++) lds[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (uint32_t q = 1; q < (blockDim.x >> 6); q++)
+            for (int k = 0; k < 7; k++) v[k] = k < 3 ? min(v[k], lds[q][k]) : max(v[k], lds[q][k]);
+}
+
+// Centre bounds and the non-finite check: each block reduces a strided share
+// of the triangles into partial[block] (cmin xyz, cmax xyz, bad).
+__global__ __launch_bounds__(256) void k_lbvh_bounds(const float *__restrict__ verts, uint32_t n,
+                                                     uint32_t *__restrict__ partial) {
+    __shared__ uint32_t lds[4][7];
+    uint32_t v[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const float *p = verts + 9 * (size_t)t;
+        bool finite = true;
+        for (int k = 0; k < 9; k++) finite = finite && isfinite(p[k]);
+        if (!finite) v[6] = 1u;
+        float lo[3], hi[3];
+        tri_bounds(p, lo, hi);
+        for (int a = 0; a < 3; a++) {
+            const uint32_t c = ord_of((lo[a] + hi[a]) * 0.5f);
+            v[a] = min(v[a], c);
+            v[3 + a] = max(v[3 + a], c);
+        }
+    }
+    block_reduce7(v, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 7; k++) partial[7 * blockIdx.x + k] = v[k];
+}
+
+// One block: the partials into the header; the header's other fields start.
+__global__ __launch_bounds__(256) void k_lbvh_bounds_final(const uint32_t *__restrict__ partial, uint32_t nblocks,
+                                                           LbvhHeader *h, uint32_t *parent) {
+    __shared__ uint32_t lds[4][7];
+    uint32_t v[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
+    for (uint32_t b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int k = 0; k < 7; k++) v[k] = k < 3 ? min(v[k], partial[7 * b + k]) : max(v[k], partial[7 * b + k]);
+    block_reduce7(v, lds);
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; a++) { h->cmin[a] = v[a]; h->cmax[a] = v[3 + a]; }
+        h->bad = v[6];
+        h->max_depth = 0;
+        h->num_nodes = 0;
+        parent[0] = kNone;   // node 0 is the root (internal node 0, or the only leaf)
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lbvh_codes(const float *__restrict__ verts, uint32_t n,
+                                                    const LbvhHeader *__restrict__ h, uint64_t *__restrict__ code,
+                                                    uint32_t *__restrict__ id) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float lo[3], hi[3];
+    tri_bounds(verts + 9 * (size_t)t, lo, hi);
+    uint64_t q[3];
+    for (int a = 0; a < 3; a++) {
+        const float cmin = float_of(h->cmin[a]), cmax = float_of(h->cmax[a]);
+        const float ext = cmax - cmin;
+        float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
+        if (!isfinite(s)) s = 0.0f;
+        const float f = floorf(((lo[a] + hi[a]) * 0.5f - cmin) * s);
+        q[a] = f >= (float)kCellMax ? kCellMax : (uint32_t)f;
+    }
+    code[t] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    id[t] = t;
+}
+
+// Length of the common prefix of the keys (code, position) at sorted
+// positions i and j; -1 outside [0, n).
+__device__ inline int prefix_len(const uint64_t *__restrict__ code, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    const uint64_t a = code[i], b = code[j];
+    if (a != b) return __clzll((long long)(a ^ b));
+    return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
+// Node ids: internal node i in [0, n-1), leaf k at n - 1 + k.  Internal node
+// i covers sorted positions [lo[i], hi[i]] and splits after position gamma.
+__global__ __launch_bounds__(256) void k_lbvh_karras(const uint64_t *__restrict__ code, uint32_t n,
+                                                     uint32_t *__restrict__ parent, uint32_t *__restrict__ left,
+                                                     uint32_t *__restrict__ right, uint32_t *__restrict__ lo,
+                                                     uint32_t *__restrict__ hi) {
+    const uint32_t iu = blockIdx.x * blockDim.x + threadIdx.x;
+    if (iu + 1 >= n) return;
+    const int64_t i = iu, nn = n;
+    const int d = prefix_len(code, nn, i, i + 1) > prefix_len(code, nn, i, i - 1) ? 1 : -1;
+    const int dmin = prefix_len(code, nn, i, i - d);
+    int64_t lmax = 2;
+    while (prefix_len(code, nn, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (prefix_len(code, nn, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = prefix_len(code, nn, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (prefix_len(code, nn, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    const uint32_t first = (uint32_t)(i < j ? i : j), last = (uint32_t)(i < j ? j : i);
+    const uint32_t g = (uint32_t)gamma;
+    const uint32_t lc = (first == g) ? (n - 1u + g) : g;
+    const uint32_t rc = (last == g + 1u) ? (n - 1u + g + 1u) : g + 1u;
+    left[iu] = lc;
+    right[iu] = rc;
+    lo[iu] = first;
+    hi[iu] = last;
+    parent[lc] = iu;
+    parent[rc] = iu | kRightChild;
+}
+
+struct Tree {
+    uint32_t n, leaf_max;
+    const uint32_t *parent, *left, *right, *lo, *hi;
+    __device__ uint32_t up(uint32_t v) const { return parent[v] & ~kRightChild; }
+    __device__ uint32_t first(uint32_t v) const { return v + 1u < n ? lo[v] : v - (n - 1u); }
+    __device__ uint32_t size(uint32_t v) const { return v + 1u < n ? hi[v] - lo[v] + 1u : 1u; }
+    __device__ bool out_interior(uint32_t v) const { return v + 1u < n && size(v) > leaf_max; }
+    __device__ bool out_leaf(uint32_t v) const { return size(v) <= leaf_max && (v == 0 || size(up(v)) > leaf_max); }
+};
+
+// mark[k] = 1 when sorted position k is the first of an output leaf (the
+// leaf holding k is found by climbing while the parent is small enough to be
+// a leaf itself: at most log2(leaf_max) + 1 steps); mark[n] = 0.
+__global__ __launch_bounds__(256) void k_lbvh_mark(Tree tr, uint32_t *__restrict__ mark) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > tr.n) return;
+    if (k == tr.n) { mark[k] = 0u; return; }
+    uint32_t v = tr.n - 1u + k;
+    for (uint32_t step = 0; v != 0 && step < 8 && tr.size(tr.up(v)) <= tr.leaf_max; step++) v = tr.up(v);
+    mark[k] = tr.first(v) == k ? 1u : 0u;
+}
+
+// Depth and pre-order index of every output node (dep = kNone for dropped
+// nodes; bit 31 of dep set for leaves).  lb[k] = output leaves starting
+// before position k.
+__global__ __launch_bounds__(256) void k_lbvh_number(Tree tr, const uint32_t *__restrict__ lb,
+                                                     uint32_t *__restrict__ pre, uint32_t *__restrict__ dep,
+                                                     LbvhHeader *h) {
+    __shared__ uint32_t lds[4][7];
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t deepest[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
+    if (v < 2u * tr.n - 1u) {
+        const bool leaf = tr.out_leaf(v);
+        if (leaf || tr.out_interior(v)) {
+            uint32_t depth = 0, lefts = 0, cur = v;
+            while (cur != 0 && depth < kWalkLimit) {
+                const uint32_t w = tr.parent[cur];
+                lefts += (w & kRightChild) ? 0u : 1u;
+                depth += 1u;
+                cur = w & ~kRightChild;
+            }
+            if (cur != 0) atomicOr(&h->bad, 4u);
+            pre[v] = 2u * lb[tr.first(v)] + lefts;
+            dep[v] = depth | (leaf ? 0x80000000u : 0u);
+            if (leaf) deepest[6] = depth;
+        } else {
+            dep[v] = kNone;
+        }
+    }
+    if (v == 0) h->num_nodes = 2u * lb[tr.n] - 1u;
+    block_reduce7(deepest, lds);
+    if (threadIdx.x == 0 && deepest[6]) atomicMax(&h->max_depth, deepest[6]);
+}
+
+// Boxes keep the first minimum / maximum in triangle order, as a sequential
+// scan would (a union keeps the left child's value on ties).
+__global__ __launch_bounds__(256) void k_lbvh_leaf_boxes(Tree tr, const float *__restrict__ verts,
+                                                         const uint32_t *__restrict__ perm,
+                                                         const uint32_t *__restrict__ dep, float *__restrict__ box) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= 2u * tr.n - 1u) return;
+    const uint32_t d = dep[v];
+    if (d == kNone || !(d & 0x80000000u)) return;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const uint32_t f = tr.first(v), c = tr.size(v);
+    for (uint32_t k = f; k < f + c; k++) {
+        const float *p = verts + 9 * (size_t)perm[k];
+        for (int q = 0; q < 3; q++)
+            for (int a = 0; a < 3; a++) {
+                const float x = p[3 * q + a];
+                if (x < mn[a]) mn[a] = x;
+                if (x > mx[a]) mx[a] = x;
+            }
+    }
+    for (int a = 0; a < 3; a++) { box[6 * (size_t)v + a] = mn[a]; box[6 * (size_t)v + 3 + a] = mx[a]; }
+}
+
+// Interior nodes at one depth: the union of their children's boxes (written
+// by an earlier launch).
+__global__ __launch_bounds__(256) void k_lbvh_level(Tree tr, const uint32_t *__restrict__ dep, uint32_t level,
+                                                    float *__restrict__ box) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v + 1u >= tr.n || dep[v] != level) return;
+    const float *bl = box + 6 * (size_t)tr.left[v], *br = box + 6 * (size_t)tr.right[v];
+    float out[6];
+    for (int a = 0; a < 3; a++) {
+        out[a] = br[a] < bl[a] ? br[a] : bl[a];
+        out[3 + a] = br[3 + a] > bl[3 + a] ? br[3 + a] : bl[3 + a];
+    }
+    for (int a = 0; a < 6; a++) box[6 * (size_t)v + a] = out[a];
+}
+
+struct EmitOut {
+    float *nodes;       // 16 words per interior node
+    float *tris;        // 12 words per triangle
+    float *leafbox;     // 8 words per triangle position
+    uint32_t *cnode;    // 12 words per node
+    uint32_t node_cap;  // 2n - 1
+    uint32_t interior_cap;
+};
+
+// Reference of an output node: a leaf id, or the interior node's index among
+// interior nodes in pre-order (its pre-order index minus the leaves before it).
+__device__ inline uint32_t ref_of(const Tree &tr, const uint32_t *pre, const uint32_t *lb, uint32_t v) {
+    if (tr.out_leaf(v)) return kLeafFlag | (tr.first(v) << 3) | (tr.size(v) - 1u);
+    return pre[v] - lb[tr.first(v)];
+}
+
+__global__ __launch_bounds__(256) void k_lbvh_emit(Tree tr, const float *__restrict__ verts,
+                                                   const uint32_t *__restrict__ perm, const float *__restrict__ box,
+                                                   const uint32_t *__restrict__ pre, const uint32_t *__restrict__ lb,
+                                                   const uint32_t *__restrict__ dep, EmitOut o, LbvhHeader *h) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= 2u * tr.n - 1u) return;
+    const uint32_t dw = dep[v];
+    if (dw == kNone) return;
+    const bool leaf = (dw & 0x80000000u) != 0;
+    const uint32_t depth = dw & 0x7FFFFFFFu;
+    const uint32_t i = pre[v];
+    const uint32_t f = tr.first(v), c = tr.size(v);
+    if (i >= o.node_cap || f + c > tr.n) { atomicOr(&h->bad, 2u); return; }
+    const float *b = box + 6 * (size_t)v;
+    uint32_t *cn = o.cnode + 12 * (size_t)i;
+    for (int a = 0; a < 6; a++) cn[a] = __float_as_uint(b[a]);
+    cn[6] = ref_of(tr, pre, lb, v);
+    cn[7] = depth;
+    cn[8] = v == 0 ? kNone : pre[tr.up(v)];
+    cn[9] = f;
+    cn[10] = f + c;
+    cn[11] = 0u;
+    if (v == 0)
+        for (int a = 0; a < 6; a++) h->root_box[a] = b[a];
+    if (!leaf) {
+        const uint32_t iid = pre[v] - lb[f];
+        if (iid >= o.interior_cap) { atomicOr(&h->bad, 2u); return; }
+        const uint32_t l = tr.left[v], r = tr.right[v];
+        float *nd = o.nodes + 16 * (size_t)iid;
+        for (int a = 0; a < 6; a++) { nd[a] = box[6 * (size_t)l + a]; nd[6 + a] = box[6 * (size_t)r + a]; }
+        nd[12] = __uint_as_float(ref_of(tr, pre, lb, l));
+        nd[13] = __uint_as_float(ref_of(tr, pre, lb, r));
+        nd[14] = 0.0f;
+        nd[15] = 0.0f;
+        return;
+    }
+    float *lbx = o.leafbox + 8 * (size_t)f;
+    for (int a = 0; a < 6; a++) lbx[a] = b[a];
+    lbx[6] = __uint_as_float(depth);
+    lbx[7] = __uint_as_float(i);
+    for (uint32_t k = f; k < f + c; k++) {
+        const uint32_t prim = perm[k];
+        const float *p = verts + 9 * (size_t)prim;
+        float *t = o.tris + 12 * (size_t)k;
+        t[0] = p[0]; t[1] = p[1]; t[2] = p[2];
+        t[3] = __uint_as_float(prim);
+        t[4] = p[3] - p[0]; t[5] = p[4] - p[1]; t[6] = p[5] - p[2];
+        t[7] = __uint_as_float(depth);
+        t[8] = p[6] - p[0]; t[9] = p[7] - p[1]; t[10] = p[8] - p[2];
+        t[11] = 0.0f;
+    }
+}
+
+struct ScratchLayout {
+    size_t hdr, partial, code_in, code_out, id_in, perm, sort_tmp, sort_tmp_bytes, scan_tmp, scan_tmp_bytes, parent,
+        left, right, lo, hi, mark, lb, pre, dep, box, total;
+};
+
+ScratchLayout scratch_layout(uint32_t n) {
+    ScratchLayout L{};
+    size_t sort_tmp = 0, scan_tmp = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                           (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 63,
+                                           (hipStream_t)0) != hipSuccess ||
+        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                         (int)n + 1, (hipStream_t)0) != hipSuccess)
+        return L;   // total = 0
+    const size_t N = n, M = 2 * (size_t)n - 1, I = n > 1 ? (size_t)n - 1 : 1;
+    size_t off = 0;
+    L.hdr = off; off += 256;
+    L.partial = off; off += align256((size_t)kBoundBlocks * 7 * 4);
+    L.code_in = off; off += align256(N * 8);
+    L.code_out = off; off += align256(N * 8);
+    L.id_in = off; off += align256(N * 4);
+    L.perm = off; off += align256(N * 4);
+    L.sort_tmp = off; L.sort_tmp_bytes = sort_tmp; off += align256(sort_tmp);
+    L.scan_tmp = off; L.scan_tmp_bytes = scan_tmp; off += align256(scan_tmp);
+    L.parent = off; off += align256(M * 4);
+    L.left = off; off += align256(I * 4);
+    L.right = off; off += align256(I * 4);
+    L.lo = off; off += align256(I * 4);
+    L.hi = off; off += align256(I * 4);
+    L.mark = off; off += align256((N + 1) * 4);
+    L.lb = off; off += align256((N + 1) * 4);
+    L.pre = off; off += align256(M * 4);
+    L.dep = off; off += align256(M * 4);
+    L.box = off; off += align256(M * 24);
+    L.total = off;
+    return L;
+}
+
+inline dim3 grid_for(size_t n, uint32_t block) { return dim3((uint32_t)((n + block - 1) / block)); }
+
+}  // namespace
+
+size_t lbvh_scratch_bytes(uint32_t n) { return n ? scratch_layout(n).total : 0; }
+
+hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, void *d_scratch,
+                      const LbvhOut &out, hipStream_t s, LbvhResult *res) {
+    const ScratchLayout L = scratch_layout(n);
+    if (L.total == 0) return hipErrorInvalidValue;
+    char *base = static_cast<char *>(d_scratch);
+    auto *h = reinterpret_cast<LbvhHeader *>(base + L.hdr);
+    auto *partial = reinterpret_cast<uint32_t *>(base + L.partial);
+    auto *code_in = reinterpret_cast<uint64_t *>(base + L.code_in);
+    auto *code_out = reinterpret_cast<uint64_t *>(base + L.code_out);
+    auto *id_in = reinterpret_cast<uint32_t *>(base + L.id_in);
+    auto *perm = reinterpret_cast<uint32_t *>(base + L.perm);
+    auto *parent = reinterpret_cast<uint32_t *>(base + L.parent);
+    auto *left = reinterpret_cast<uint32_t *>(base + L.left);
+    auto *right = reinterpret_cast<uint32_t *>(base + L.right);
+    auto *lo = reinterpret_cast<uint32_t *>(base + L.lo);
+    auto *hi = reinterpret_cast<uint32_t *>(base + L.hi);
+    auto *mark = reinterpret_cast<uint32_t *>(base + L.mark);
+    auto *lb = reinterpret_cast<uint32_t *>(base + L.lb);
+    auto *pre = reinterpret_cast<uint32_t *>(base + L.pre);
+    auto *dep = reinterpret_cast<uint32_t *>(base + L.dep);
+    auto *box = reinterpret_cast<float *>(base + L.box);
+    const uint32_t n_internal = n - 1u;
+    const size_t m = 2 * (size_t)n - 1;
+    const uint32_t bound_blocks = (uint32_t)std::min<size_t>(kBoundBlocks, (n + 255) / 256);
+
+    hipError_t e = hipMemsetAsync(out.leafbox, 0, (size_t)n * kLeafBoxBytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lbvh_bounds, dim3(bound_blocks), dim3(256), 0, s, d_verts, n, partial);
+    hipLaunchKernelGGL(k_lbvh_bounds_final, dim3(1), dim3(256), 0, s, partial, bound_blocks, h, parent);
+    hipLaunchKernelGGL(k_lbvh_codes, grid_for(n, 256), dim3(256), 0, s, d_verts, n, h, code_in, id_in);
+    size_t tmp = L.sort_tmp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(base + L.sort_tmp, tmp, code_in, code_out, id_in, perm, (int)n, 0, 63, s);
+    if (e != hipSuccess) return e;
+    if (n_internal)
+        hipLaunchKernelGGL(k_lbvh_karras, grid_for(n_internal, 256), dim3(256), 0, s, code_out, n, parent, left,
+                           right, lo, hi);
+    Tree tr{n, leaf_max, parent, left, right, lo, hi};
+    hipLaunchKernelGGL(k_lbvh_mark, grid_for((size_t)n + 1, 256), dim3(256), 0, s, tr, mark);
+    tmp = L.scan_tmp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(base + L.scan_tmp, tmp, mark, lb, (int)n + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lbvh_number, grid_for(m, 256), dim3(256), 0, s, tr, lb, pre, dep, h);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the depth decides how many interior levels follow
+    LbvhHeader hh;
+    e = hipMemcpyAsync(&hh, h, sizeof hh, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    res->bad = hh.bad;
+    res->max_depth = hh.max_depth;
+    res->num_nodes = hh.num_nodes;
+    if (hh.bad || hh.max_depth > max_depth || hh.num_nodes == 0 || hh.num_nodes > m) return hipSuccess;
+    hipLaunchKernelGGL(k_lbvh_leaf_boxes, grid_for(m, 256), dim3(256), 0, s, tr, d_verts, perm, dep, box);
+    for (uint32_t level = hh.max_depth; level-- > 0;)
+        hipLaunchKernelGGL(k_lbvh_level, grid_for(n_internal ? n_internal : 1, 256), dim3(256), 0, s, tr, dep,
+                           level, box);
+    EmitOut o{static_cast<float *>(out.nodes), static_cast<float *>(out.tris), static_cast<float *>(out.leafbox),
+              static_cast<uint32_t *>(out.cnode), (uint32_t)m, n_internal ? n_internal : 1u};
+    hipLaunchKernelGGL(k_lbvh_emit, grid_for(m, 256), dim3(256), 0, s, tr, d_verts, perm, box, pre, lb, dep, o, h);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(&hh, h, sizeof hh, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    res->bad = hh.bad;
+    for (int a = 0; a < 6; a++) res->root_box[a] = hh.root_box[a];
+    return hipSuccess;
+}
+
+}  // namespace hrpp

@@ -124,8 +124,26 @@ hrpp_status hrpp_bvh_build_host(const float *h_verts, uint32_t num_tris, const h
     return HRPP_OK;
 }
 
+// Region offsets of a device-built BVH inside its buffer: sized for the
+// largest tree over n triangles, since the node counts are known only after
+// the build.
+struct DeviceBvhLayout {
+    size_t nodes, tris, leafbox, cnode, total;
+};
+
+static DeviceBvhLayout device_bvh_layout(uint32_t n) {
+    DeviceBvhLayout L{};
+    L.nodes = kHeaderBytes;
+    L.tris = L.nodes + align256((size_t)(n - 1) * kNodeBytes);
+    L.leafbox = L.tris + align256((size_t)n * kTriBytes);
+    L.cnode = L.leafbox + align256((size_t)n * kLeafBoxBytes);
+    L.total = L.cnode + align256((2 * (size_t)n - 1) * kCNodeBytes);
+    return L;
+}
+
 size_t hrpp_bvh_device_bytes(const hrpp_bvh *bvh) {
     if (!bvh) return 0;
+    if (bvh->device_built) return device_bvh_layout(bvh->num_tris).total;
     return kHeaderBytes + align256((size_t)bvh->num_interior * kNodeBytes) +
            align256((size_t)bvh->num_tris * kTriBytes) + align256((size_t)bvh->num_tris * kLeafBoxBytes) +
            align256((size_t)bvh->num_nodes * kCNodeBytes) + align256(bvh->wide.words.size() * 4);
@@ -242,6 +260,57 @@ hrpp_status hrpp_build_bvh(const float *h_verts, uint32_t num_tris, const hrpp_b
     return HRPP_OK;
 }
 
+size_t hrpp_bvh_device_build_scratch_bytes(uint32_t num_tris) {
+    if (num_tris == 0 || num_tris >= (1u << 28)) return 0;
+    return lbvh_scratch_bytes(num_tris);
+}
+
+hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                  void *d_scratch, size_t scratch_bytes, void *d_buf, size_t bytes, void *stream,
+                                  hrpp_bvh **out) {
+    if (!out) return HRPP_EINVAL;
+    *out = nullptr;
+    if (!d_verts || !desc || !d_scratch || !d_buf || num_tris == 0 || num_tris >= (1u << 28)) return HRPP_EINVAL;
+    if (desc->leaf_max < 1 || desc->leaf_max > 8 || desc->max_depth < 1 || desc->max_depth > (uint32_t)kMaxDepth)
+        return HRPP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_buf) % 256 || reinterpret_cast<uintptr_t>(d_scratch) % 256 ||
+        reinterpret_cast<uintptr_t>(d_verts) % 4)
+        return HRPP_EINVAL;
+    const size_t need = lbvh_scratch_bytes(num_tris);
+    if (need == 0) return HRPP_EDEVICE;
+    const DeviceBvhLayout L = device_bvh_layout(num_tris);
+    if (scratch_bytes < need || bytes < hrpp_bvh_required_bytes(num_tris, desc)) return HRPP_ENOMEM;
+    char *base = static_cast<char *>(d_buf);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemsetAsync(base, 0, kHeaderBytes, s) != hipSuccess) return HRPP_EDEVICE;
+    LbvhOut o{base + L.nodes, base + L.tris, base + L.leafbox, base + L.cnode};
+    LbvhResult r{};
+    if (lbvh_build(d_verts, num_tris, desc->leaf_max, desc->max_depth, d_scratch, o, s, &r) != hipSuccess)
+        return HRPP_EDEVICE;
+    if (r.bad & 1u) return HRPP_EINVAL;
+    const uint32_t m = r.num_nodes;
+    if ((r.bad & 6u) || m == 0 || m % 2 == 0 || m > 2 * num_tris - 1) return HRPP_EDEVICE;
+    if (r.max_depth > desc->max_depth) return HRPP_EDEPTH;
+    hrpp_bvh *b = new (std::nothrow) hrpp_bvh();
+    if (!b) return HRPP_ENOMEM;
+    b->uid = g_uid.fetch_add(1);
+    b->device_built = true;
+    b->num_tris = num_tris;
+    b->num_nodes = m;
+    b->num_interior = (m - 1) / 2;
+    b->max_depth = r.max_depth;
+    b->leaf_max = desc->leaf_max;
+    for (int a = 0; a < 6; a++) b->root_box[a] = r.root_box[a];
+    b->root_ref = m == 1 ? (kLeafFlag | (num_tris - 1u)) : 0u;
+    b->d_nodes = o.nodes;
+    b->d_tris = o.tris;
+    b->d_leafbox = o.leafbox;
+    b->d_cnode = o.cnode;
+    b->d_wide = nullptr;
+    *out = b;
+    return HRPP_OK;
+}
+
 hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *num_tris, uint32_t *max_depth) {
     if (!bvh) return HRPP_EINVAL;
     if (num_nodes) *num_nodes = bvh->num_nodes;
@@ -269,6 +338,31 @@ hrpp_status hrpp_bvh_wide_export(const hrpp_bvh *bvh, uint32_t *h_words, size_t 
 hrpp_status hrpp_bvh_export(const hrpp_bvh *bvh, hrpp_bvh_canon *o) {
     if (!bvh || !o || !o->box || !o->right || !o->first_tri || !o->count || !o->depth || !o->tri_perm)
         return HRPP_EINVAL;
+    if (bvh->device_built) {
+        // read the canonical node records and triangle records back
+        const uint32_t m = bvh->num_nodes, n = bvh->num_tris;
+        std::vector<uint32_t> hc((size_t)m * 12), ht((size_t)n * 12);
+        if (hipMemcpy(hc.data(), bvh->d_cnode, hc.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(ht.data(), bvh->d_tris, ht.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return HRPP_EDEVICE;
+        for (uint32_t i = 0; i < m; i++) {
+            const uint32_t *p = &hc[(size_t)i * 12];
+            std::memcpy(&o->box[6 * (size_t)i], p, 6 * sizeof(float));
+            const uint32_t ref = p[6];
+            const bool leaf = (ref & kLeafFlag) != 0;
+            o->right[i] = kNone;
+            o->first_tri[i] = leaf ? (ref & ~kLeafFlag) >> 3 : 0u;
+            o->count[i] = leaf ? (ref & 7u) + 1u : 0u;
+            o->depth[i] = p[7];
+        }
+        for (uint32_t j = 1; j < m; j++) {   // a child that is not the next node is its parent's right child
+            const uint32_t par = hc[(size_t)j * 12 + 8];
+            if (par >= m) return HRPP_EDEVICE;
+            if (j != par + 1) o->right[par] = j;
+        }
+        for (uint32_t k = 0; k < n; k++) o->tri_perm[k] = ht[(size_t)k * 12 + 3];
+        return HRPP_OK;
+    }
     const CanonTree &t = bvh->canon;
     std::memcpy(o->box, t.box.data(), t.box.size() * 4);
     std::memcpy(o->right, t.right.data(), t.right.size() * 4);

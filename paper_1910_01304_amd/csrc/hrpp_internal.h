@@ -70,6 +70,7 @@ struct hrpp_bvh {
     const void *d_leafbox;      // num_tris * 32 B (valid at leaf start positions)
     const void *d_cnode;        // num_nodes * 48 B, canonical (depth-first pre-order) node records
     const void *d_wide;         // 4-wide nodes, 128 B each (plain-traversal baseline)
+    bool device_built = false;  // built by hrpp_build_bvh_device: no host tree, no 4-wide tree
     hrpp::CanonTree canon;
     hrpp::WideTree wide;
     std::vector<float> verts;   // host copy of the input, used by the upload

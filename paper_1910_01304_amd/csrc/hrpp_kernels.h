@@ -113,6 +113,25 @@ void launch_fill32(uint32_t *p, size_t n, uint32_t value, hipStream_t s);
 void launch_reset_table(void *table, uint32_t entry_bytes, uint32_t n_entries, uint8_t *dirty, bool full,
                         hipStream_t s);
 
+// Device build of a linear BVH (bvh_device.hip).  The output regions are
+// sized for the largest tree over n triangles: n - 1 interior nodes, n
+// triangles and leaf-box slots, 2n - 1 canonical node records.
+struct LbvhOut {
+    void *nodes, *tris, *leafbox, *cnode;
+};
+struct LbvhResult {
+    uint32_t bad;          // bit 0: non-finite vertex; bits 1-2: internal inconsistency
+    uint32_t max_depth, num_nodes;
+    float root_box[6];
+};
+// Scratch bytes for n triangles (0 when the sort's size query fails).
+size_t lbvh_scratch_bytes(uint32_t n);
+// Enqueues the build on `s` and synchronises it twice: once to read the
+// tree's depth (a tree deeper than max_depth, or a non-finite vertex, ends
+// the build there) and once at the end.
+hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, void *d_scratch,
+                      const LbvhOut &out, hipStream_t s, LbvhResult *res);
+
 // Plain traversal of the 4-wide tree (a.wide, a.wide_root; a.stack_cap = the
 // tree's stack need); closest hit is the exact one.
 void launch_wide(const TraceArgs &a, uint32_t n, bool any, hipStream_t s);

@@ -39,6 +39,7 @@ EXPORTED = [
     "hrpp_batch_launch", "hrpp_batch_destroy", "hrpp_serve_create", "hrpp_serve_submit", "hrpp_serve_poll",
     "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy", "hrpp_bvh_wide_info",
     "hrpp_bvh_wide_export", "hrpp_trace_wide_anyhit", "hrpp_trace_wide_closest",
+    "hrpp_bvh_device_build_scratch_bytes", "hrpp_build_bvh_device",
 ]
 
 
@@ -100,6 +101,9 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_bvh_device_bytes.restype = sz
     lib.hrpp_bvh_device_bytes.argtypes = [vp]
     lib.hrpp_bvh_upload.argtypes = [vp, vp, sz, vp]
+    lib.hrpp_bvh_device_build_scratch_bytes.restype = sz
+    lib.hrpp_bvh_device_build_scratch_bytes.argtypes = [u32]
+    lib.hrpp_build_bvh_device.argtypes = [vp, u32, vp, vp, sz, vp, sz, vp, C.POINTER(vp)]
     lib.hrpp_bvh_info.argtypes = [vp, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
     lib.hrpp_bvh_export.argtypes = [vp, vp]
     lib.hrpp_bvh_destroy.argtypes = [vp]
@@ -179,6 +183,34 @@ class BVH:
         self.buffer = None
         if device is not None:
             self.upload(device)
+
+    @classmethod
+    def build_on_device(cls, verts: torch.Tensor, leaf_max: int = 4, max_depth: int = 64) -> "BVH":
+        """Linear BVH built on the GPU from a device tensor of [n, 9] (or [n, 3, 3]) float32 vertices."""
+        lib = load_library()
+        if not (isinstance(verts, torch.Tensor) and verts.is_cuda and verts.dtype == torch.float32):
+            raise HrppError("build_on_device takes a float32 device tensor")
+        v = verts.reshape(-1, 9).contiguous()
+        self = cls.__new__(cls)
+        self.num_tris = int(v.shape[0])
+        self.desc = _BvhDesc(leaf_max, 32, max_depth)
+        need = lib.hrpp_bvh_device_build_scratch_bytes(self.num_tris)
+        if need == 0:
+            raise HrppError("hrpp_bvh_device_build_scratch_bytes: no scratch size (bad count or no device)")
+        self.device_bytes = lib.hrpp_bvh_required_bytes(self.num_tris, C.byref(self.desc))
+        self._raw, self.buffer = _aligned(self.device_bytes, v.device)
+        scratch_raw, scratch = _aligned(need, v.device)
+        h = C.c_void_p()
+        self.handle = None
+        _check(lib.hrpp_build_bvh_device(v.data_ptr(), self.num_tris, C.byref(self.desc), scratch.data_ptr(), need,
+                                         self.buffer.data_ptr(), self.device_bytes, _stream(), C.byref(h)),
+               "hrpp_build_bvh_device")
+        del scratch_raw, scratch
+        self.handle = h
+        nn, nt, md = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib.hrpp_bvh_info(h, C.byref(nn), C.byref(nt), C.byref(md)), "hrpp_bvh_info")
+        self.num_nodes, self.max_depth = nn.value, md.value
+        return self
 
     def wide_info(self) -> dict:
         """The 4-wide tree of the plain-traversal baseline: nodes, root reference, stack need, depth."""

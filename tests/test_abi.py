@@ -76,6 +76,20 @@ def test_host_argument_validation():
     assert lib.hrpp_bvh_build_host(v.ctypes.data, 16, C.byref(desc), C.byref(h)) == 0
     assert lib.hrpp_trace_anyhit(h, None, C.c_void_p(16), 4, C.c_void_p(16), None, None) == 1
     lib.hrpp_bvh_destroy(h)
+    # the device build rejects null pointers, empty input, a bad descriptor and
+    # misaligned buffers before any device call
+    p16 = C.c_void_p(256)
+    assert lib.hrpp_bvh_device_build_scratch_bytes(0) == 0
+    assert lib.hrpp_bvh_device_build_scratch_bytes(1 << 28) == 0
+    assert lib.hrpp_build_bvh_device(None, 16, C.byref(desc), p16, 1 << 20, p16, 1 << 20, None, C.byref(h)) == 1
+    assert lib.hrpp_build_bvh_device(p16, 0, C.byref(desc), p16, 1 << 20, p16, 1 << 20, None, C.byref(h)) == 1
+    assert lib.hrpp_build_bvh_device(p16, 16, C.byref(bad), p16, 1 << 20, p16, 1 << 20, None, C.byref(h)) == 1
+    assert lib.hrpp_build_bvh_device(p16, 16, C.byref(shallow), None, 1 << 20, p16, 1 << 20, None, C.byref(h)) == 1
+    assert lib.hrpp_build_bvh_device(p16, 16, C.byref(desc), C.c_void_p(260), 1 << 20, p16, 1 << 20, None,
+                                     C.byref(h)) == 1
+    assert lib.hrpp_build_bvh_device(p16, 16, C.byref(hrpp.hrpp._BvhDesc(4, 32, 65)), p16, 1 << 20, p16, 1 << 20,
+                                     None, C.byref(h)) == 1
+    assert lib.hrpp_build_bvh_device(p16, 16, C.byref(desc), p16, 1 << 20, p16, 1 << 20, None, None) == 1
     # predictor descriptor limits
     pd = hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0)
     assert lib.hrpp_predictor_required_bytes(C.byref(pd)) > (1 << 12) * 32

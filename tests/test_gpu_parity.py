@@ -68,11 +68,34 @@ def assert_same_table(pred, tb: oracle.Table):
     assert np.array_equal(slots, tb.slots), f"{int(np.count_nonzero(np.any(slots != tb.slots, 1)))} entries differ"
 
 
-def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None, calls=1, leaf_max=4):
-    """Run `calls` successive traces of `rays` on both sides and compare all."""
-    _say(f"{name}: {tris.shape[0]} tris, {rays.shape[0]} rays, {query}/{mode}, pred={pred_cfg}, calls={calls}")
-    bvh = hrpp.BVH(tris, leaf_max=leaf_max)
-    ob = oracle.build_sah(tris, leaf_max=leaf_max)
+def device_bvh(hrpp, tris, leaf_max=4, max_depth=64):
+    """The library's device-built linear BVH, checked against the oracle's."""
+    import torch
+    bvh = hrpp.BVH.build_on_device(torch.from_numpy(np.ascontiguousarray(tris, np.float32)).cuda(),
+                                   leaf_max=leaf_max, max_depth=max_depth)
+    ob = oracle.build_lbvh(tris, leaf_max=leaf_max, max_depth=max_depth)
+    got = bvh.export()
+    assert bvh.num_nodes == ob.num_nodes
+    assert np.array_equal(got["box"].view(np.uint32), ob.box.view(np.uint32)), "boxes differ"
+    for k in ("right", "first", "count", "depth", "perm"):
+        assert np.array_equal(got[k], getattr(ob, k)), f"{k} differs"
+    assert bvh.max_depth == ob.max_depth()
+    return bvh, ob
+
+
+def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None, calls=1, leaf_max=4,
+               builder="sah"):
+    """Run `calls` successive traces of `rays` on both sides and compare all.
+
+    builder "sah": the host SAH tree on both sides; "device": the library's
+    device-built linear BVH against the oracle's linear BVH."""
+    _say(f"{name}: {tris.shape[0]} tris, {rays.shape[0]} rays, {query}/{mode}, pred={pred_cfg}, calls={calls}, "
+         f"builder={builder}")
+    if builder == "device":
+        bvh, ob = device_bvh(hrpp, tris, leaf_max)
+    else:
+        bvh = hrpp.BVH(tris, leaf_max=leaf_max)
+        ob = oracle.build_sah(tris, leaf_max=leaf_max)
     vtx = oracle.bvh_vertices(tris, ob)
     pred = tb = None
     if pred_cfg is not None:
