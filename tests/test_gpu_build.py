@@ -219,3 +219,45 @@ def test_serving_device_built_scenes(hrpp):
                                mode="exact")
         assert r["out"].numpy().tobytes() == want.tobytes()
     srv.close()
+
+
+def test_batch_over_device_built_scenes(hrpp):
+    # a graph-captured batch over device-built scenes computes what each job's
+    # own call computes, on every replay; one job also against the oracle
+    import torch
+    from tests.test_gpu_batch import _jobs_spec, _method_stats, _new_pred, _single
+    _say("batch over device-built scenes")
+    jobs = []
+    for seed, ntri, nray, query, mode, pc in [j for k, j in enumerate(_jobs_spec()) if k in (0, 2, 3, 4, 9, 13)]:
+        tris = sg.mixed_scene(seed, ntri)
+        sh, ao = sg.secondary_rays_on_surface(tris, nray, seed + 100)
+        rays = np.concatenate([sh, ao])
+        if query == "closest":
+            rays[:, 7] = np.inf
+        jobs.append(dict(tris=tris, rays_np=rays, bvh=hrpp.BVH.build_on_device(_dev(tris)), query=query, mode=mode,
+                         pc=pc, rays=torch.from_numpy(rays).cuda()))
+    ref = [_single(hrpp, torch, j, _new_pred(hrpp, j)) for j in jobs]
+    j = jobs[0]
+    T, W, qo, qd, E = j["pc"][:5]
+    want, ws = oracle.trace(oracle.build_lbvh(j["tris"]), j["tris"], j["rays_np"], query=j["query"], mode=j["mode"],
+                            table=oracle.Table(T, W, qo, qd), epoch=E)
+    assert want.tobytes() == ref[0][0] and ws == ref[0][1]
+    preds = [_new_pred(hrpp, j) for j in jobs]
+    stats = [hrpp.new_stats() for _ in jobs]
+    b = hrpp.Batch([dict(bvh=j["bvh"], pred=p, rays=j["rays"], query=j["query"], mode=j["mode"], stats=s)
+                    for j, p, s in zip(jobs, preds, stats)])
+    for rep in range(3):
+        for p in preds:
+            if p is not None:
+                p.reset()
+        for s in stats:
+            s.zero_()
+        torch.cuda.synchronize()
+        b.launch(use_graph=True)
+        torch.cuda.synchronize()
+        for k in range(len(jobs)):
+            assert b.outputs[k].cpu().numpy().tobytes() == ref[k][0], f"job {k} results differ (replay {rep})"
+            assert _method_stats(hrpp, stats[k]) == ref[k][1], f"job {k} counters differ (replay {rep})"
+            assert (preds[k].export_raw().tobytes() if preds[k] else b"") == ref[k][2], f"job {k} table (replay {rep})"
+        _ = _single(hrpp, torch, jobs[0], None)
+    b.close()
