@@ -414,6 +414,16 @@ typedef struct hrpp_server hrpp_server;
 hrpp_status hrpp_serve_create(const hrpp_serve_scene *scenes, uint32_t nscenes, uint32_t slots, void *d_pool,
                               size_t pool_bytes, hrpp_server **out);
 
+/* Add a scene to a running server (a scene that arrives while it serves,
+ * e.g. one just built with hrpp_build_bvh_device).  The BVH and predictors
+ * must be ready: their build and creation have completed (the device build
+ * synchronises; predictor creation is ordered on its own stream, so
+ * synchronise it), and they outlive the server.  Its predictors must not
+ * serve another scene.  *index receives the new scene's index for
+ * hrpp_serve_submit; the scenes already served keep theirs.  EINVAL for a
+ * bad description or a server being destroyed. */
+hrpp_status hrpp_serve_add_scene(hrpp_server *server, const hrpp_serve_scene *scene, uint32_t *index);
+
 /* Queue a request: n rays in host memory (pinned memory lets the copies run
  * asynchronously), results to h_out (uint8_t[n] for query 0 = any-hit,
  * hrpp_hit[n] for query 1 = EXACT closest-hit).  Both buffers must stay

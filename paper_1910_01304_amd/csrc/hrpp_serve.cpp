@@ -220,6 +220,33 @@ struct hrpp_server {
     }
 };
 
+namespace {
+
+// Validates one scene description: a device-resident BVH, at least one
+// predictor per query kind, each bound to this BVH and not yet used (in
+// `seen`, which it extends).
+hrpp_status make_scene(const hrpp_serve_scene &s, std::vector<const hrpp_predictor *> &seen,
+                       hrpp_server::Scene &sc) {
+    if (!s.bvh || !s.bvh->d_nodes || s.n_any == 0 || s.n_closest == 0 || !s.any_preds || !s.closest_preds)
+        return HRPP_EINVAL;
+    sc.bvh = s.bvh;
+    for (int kind = 0; kind < 2; kind++) {
+        const uint32_t cnt = kind == 0 ? s.n_any : s.n_closest;
+        hrpp_predictor *const *ps = kind == 0 ? s.any_preds : s.closest_preds;
+        for (uint32_t k = 0; k < cnt; k++) {
+            hrpp_predictor *p = ps[k];
+            if (!p || p->bvh_uid != s.bvh->uid || std::find(seen.begin(), seen.end(), p) != seen.end())
+                return HRPP_EINVAL;   // a predictor serves exactly one scene and one replica slot
+            seen.push_back(p);
+            sc.preds[kind].push_back(p);
+            sc.busy[kind].push_back(false);
+        }
+    }
+    return HRPP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 hrpp_status hrpp_serve_create(const hrpp_serve_scene *scenes, uint32_t nscenes, uint32_t slots, void *d_pool,
@@ -230,28 +257,12 @@ hrpp_status hrpp_serve_create(const hrpp_serve_scene *scenes, uint32_t nscenes, 
     *out = nullptr;
     hrpp_server *sv = new (std::nothrow) hrpp_server(pool_bytes);
     if (!sv) return HRPP_ENOMEM;
-    std::vector<hrpp_predictor *> seen;
+    std::vector<const hrpp_predictor *> seen;
     for (uint32_t i = 0; i < nscenes; i++) {
-        const hrpp_serve_scene &s = scenes[i];
-        if (!s.bvh || !s.bvh->d_nodes || s.n_any == 0 || s.n_closest == 0 || !s.any_preds || !s.closest_preds) {
+        hrpp_server::Scene sc;
+        if (make_scene(scenes[i], seen, sc) != HRPP_OK) {
             delete sv;
             return HRPP_EINVAL;
-        }
-        hrpp_server::Scene sc;
-        sc.bvh = s.bvh;
-        for (int kind = 0; kind < 2; kind++) {
-            const uint32_t cnt = kind == 0 ? s.n_any : s.n_closest;
-            hrpp_predictor *const *ps = kind == 0 ? s.any_preds : s.closest_preds;
-            for (uint32_t k = 0; k < cnt; k++) {
-                hrpp_predictor *p = ps[k];
-                if (!p || p->bvh_uid != s.bvh->uid || std::find(seen.begin(), seen.end(), p) != seen.end()) {
-                    delete sv;
-                    return HRPP_EINVAL;   // a predictor serves exactly one scene and one replica slot
-                }
-                seen.push_back(p);
-                sc.preds[kind].push_back(p);
-                sc.busy[kind].push_back(false);
-            }
         }
         sv->scenes.push_back(sc);
     }
@@ -272,11 +283,23 @@ hrpp_status hrpp_serve_create(const hrpp_serve_scene *scenes, uint32_t nscenes, 
     return HRPP_OK;
 }
 
+hrpp_status hrpp_serve_add_scene(hrpp_server *sv, const hrpp_serve_scene *scene, uint32_t *index) {
+    if (!sv || !scene || !index) return HRPP_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return HRPP_EINVAL;
+    std::vector<const hrpp_predictor *> seen;
+    for (const auto &sc : sv->scenes)
+        for (int kind = 0; kind < 2; kind++) seen.insert(seen.end(), sc.preds[kind].begin(), sc.preds[kind].end());
+    hrpp_server::Scene sc;
+    if (make_scene(*scene, seen, sc) != HRPP_OK) return HRPP_EINVAL;
+    sv->scenes.push_back(sc);
+    *index = (uint32_t)(sv->scenes.size() - 1);
+    return HRPP_OK;
+}
+
 hrpp_status hrpp_serve_submit(hrpp_server *sv, uint32_t scene, uint32_t query, const hrpp_ray *h_rays, uint32_t n,
                               void *h_out, uint64_t *request_id) {
-    if (!sv || !request_id || scene >= sv->scenes.size() || query > 1 || n == 0 || n >= (1u << 31) || !h_rays ||
-        !h_out)
-        return HRPP_EINVAL;
+    if (!sv || !request_id || query > 1 || n == 0 || n >= (1u << 31) || !h_rays || !h_out) return HRPP_EINVAL;
     Request *r = new (std::nothrow) Request();
     if (!r) return HRPP_ENOMEM;
     r->scene = scene;
@@ -292,7 +315,7 @@ hrpp_status hrpp_serve_submit(hrpp_server *sv, uint32_t scene, uint32_t query, c
     }
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop) { delete r; return HRPP_EINVAL; }
+    if (sv->stop || scene >= sv->scenes.size()) { delete r; return HRPP_EINVAL; }
     r->id = sv->next_id++;
     sv->all[r->id] = r;
     sv->queue.push_back(r);

@@ -39,7 +39,7 @@ EXPORTED = [
     "hrpp_batch_launch", "hrpp_batch_destroy", "hrpp_serve_create", "hrpp_serve_submit", "hrpp_serve_poll",
     "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy", "hrpp_bvh_wide_info",
     "hrpp_bvh_wide_export", "hrpp_trace_wide_anyhit", "hrpp_trace_wide_closest",
-    "hrpp_bvh_device_build_scratch_bytes", "hrpp_build_bvh_device",
+    "hrpp_bvh_device_build_scratch_bytes", "hrpp_build_bvh_device", "hrpp_serve_add_scene",
 ]
 
 
@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_batch_destroy.restype = None
     lib.hrpp_serve_create.argtypes = [vp, u32, u32, vp, sz, C.POINTER(vp)]
     lib.hrpp_serve_submit.argtypes = [vp, u32, u32, vp, u32, vp, C.POINTER(C.c_uint64)]
+    lib.hrpp_serve_add_scene.argtypes = [vp, vp, C.POINTER(u32)]
     lib.hrpp_serve_poll.argtypes = [vp, C.c_uint64, vp]
     lib.hrpp_serve_wait_all.argtypes = [vp]
     lib.hrpp_serve_pool_peak.argtypes = [vp, C.POINTER(sz)]
@@ -476,6 +477,18 @@ class Server:
                "hrpp_serve_create")
         self.handle = h
         self._reqs = {}
+
+    def add_scene(self, bvh: BVH, any_preds, closest_preds) -> int:
+        """Add a scene while the server runs; returns its index for submit."""
+        a = (C.c_void_p * len(any_preds))(*[p.handle.value for p in any_preds])
+        c = (C.c_void_p * len(closest_preds))(*[p.handle.value for p in closest_preds])
+        self._keep += [a, c, bvh, list(any_preds), list(closest_preds)]
+        sc = _ServeScene(bvh.handle, C.cast(a, C.c_void_p), len(any_preds), C.cast(c, C.c_void_p),
+                         len(closest_preds))
+        torch.cuda.current_stream().synchronize()     # the predictors' creation (reset) has run
+        idx = C.c_uint32()
+        _check(load_library().hrpp_serve_add_scene(self.handle, C.byref(sc), C.byref(idx)), "hrpp_serve_add_scene")
+        return idx.value
 
     def submit(self, scene: int, query: str, rays: torch.Tensor, out: torch.Tensor) -> int:
         if rays.is_cuda or out.is_cuda or not rays.is_contiguous() or not out.is_contiguous():

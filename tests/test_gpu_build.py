@@ -188,33 +188,47 @@ def test_device_tree_full_size(hrpp, full_terrain):
 
 
 def test_serving_device_built_scenes(hrpp):
-    # scenes built on the device serve requests like host-built ones: any-hit
-    # flags and exact closest hits equal the oracle's
+    # scenes built on the device serve requests like host-built ones, also a
+    # scene added while the server runs: any-hit flags and exact closest hits
+    # equal the oracle's
     import torch
     _say("serving device-built scenes")
     scenes = []
-    for k in range(2):
-        tris = sg.mixed_scene(930 + k, [30000, 8000][k])
-        bvh = hrpp.BVH.build_on_device(_dev(tris))
-        anyp = [hrpp.Predictor(bvh, 14, 8, 5, 6, 4096)]
-        clp = [hrpp.Predictor(bvh, 14, 8, 5, 6, 4096)]
+    for k in range(3):
+        tris = sg.mixed_scene(930 + k, [30000, 8000, 20000][k])
+        bvh = hrpp.BVH.build_on_device(_dev(tris)) if k != 2 else None
         sh, ao = sg.secondary_rays_on_surface(tris, 20000, 960 + k)
         prim = sh.copy()
         prim[:, 7] = np.inf
-        scenes.append(dict(tris=tris, bvh=bvh, anyp=anyp, clp=clp, sec=np.concatenate([sh, ao]), prim=prim))
-    srv = hrpp.Server([(s["bvh"], s["anyp"], s["clp"]) for s in scenes], slots=2, pool_bytes=8 << 20)
-    reqs = []
-    for i in range(8):
-        k, query = i % 2, ("any" if i % 3 else "closest")
+        scenes.append(dict(tris=tris, bvh=bvh, sec=np.concatenate([sh, ao]), prim=prim))
+    for sc in scenes[:2]:
+        sc["anyp"], sc["clp"] = [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)], [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)]
+    srv = hrpp.Server([(s["bvh"], s["anyp"], s["clp"]) for s in scenes[:2]], slots=2, pool_bytes=8 << 20)
+
+    def request(k, i):
+        query = "any" if i % 3 else "closest"
         pool = scenes[k]["prim"] if query == "closest" else scenes[k]["sec"]
         rays = torch.from_numpy(np.ascontiguousarray(pool[i * 1000:(i + 1) * 1000 + 4000])).pin_memory()
         n = rays.shape[0]
         out = (torch.empty(n, dtype=torch.uint8) if query == "any" else
                torch.empty((n, 4), dtype=torch.float32)).pin_memory()
-        reqs.append(dict(scene=k, query=query, rays=rays, out=out, id=srv.submit(k, query, rays, out)))
+        return dict(scene=k, query=query, rays=rays, out=out, id=srv.submit(k, query, rays, out))
+
+    reqs = [request(i % 2, i) for i in range(8)]
+    # a third scene arrives while those run: built on the device, then added
+    sc = scenes[2]
+    sc["bvh"] = hrpp.BVH.build_on_device(_dev(sc["tris"]))
+    sc["anyp"], sc["clp"] = [hrpp.Predictor(sc["bvh"], 12, 4, 5, 6, 2048)], [hrpp.Predictor(sc["bvh"], 12, 4, 5, 6, 2048)]
+    with pytest.raises(hrpp.HrppError):          # a predictor that serves scene 0 (and indexes its tree)
+        srv.add_scene(sc["bvh"], scenes[0]["anyp"], sc["clp"])
+    with pytest.raises(hrpp.HrppError):          # no scene 2 yet
+        srv.submit(2, "any", reqs[0]["rays"], reqs[0]["out"])
+    assert srv.add_scene(sc["bvh"], sc["anyp"], sc["clp"]) == 2
+    reqs += [request(2, i) for i in range(6)] + [request(0, 9)]
     srv.wait_all()
     for r in reqs:
         sc = scenes[r["scene"]]
+        assert srv.poll(r["id"])["state"] == 2
         want, _ = oracle.trace(oracle.build_sah(sc["tris"]), sc["tris"], r["rays"].numpy(), query=r["query"],
                                mode="exact")
         assert r["out"].numpy().tobytes() == want.tobytes()
