@@ -610,14 +610,25 @@ def main():
             tb = oracle.Table(cfg_any["log2_entries"], cfg_any["ways"], cfg_any["origin_bits"], cfg_any["dir_bits"])
             c0 = time.perf_counter()
             oracle.trace(ob, tris, prim, query="closest", mode="paper", table=ta, epoch=cfg_all["epoch_rays"],
-                         vtx=vtx, nthreads=threads)
+                         vtx=vtx, nthreads=threads, first_epoch=cfg_all["first_epoch_rays"])
             oracle.trace(ob, tris, shadow, query="any", table=tb, epoch=cfg_any["epoch_rays"], vtx=vtx,
-                         nthreads=threads)
+                         nthreads=threads, first_epoch=cfg_any["first_epoch_rays"])
             times.append(time.perf_counter() - c0)
         med = statistics.median(times)
         cpu = {"value": round(rays_per_step / med / 1e6, 3), "unit": "Mrays/s", "cores": threads, "kind": "oracle",
                "sample": f"the full step ({rays_per_step} rays, HRPP, same tables and epochs), median of "
                          f"{len(times)} runs ({sum(times):.1f} s in all), {med:.3f} s each"}
+        # the same step on one thread, once
+        ta = oracle.Table(cfg_all["log2_entries"], cfg_all["ways"], cfg_all["origin_bits"], cfg_all["dir_bits"])
+        tb = oracle.Table(cfg_any["log2_entries"], cfg_any["ways"], cfg_any["origin_bits"], cfg_any["dir_bits"])
+        c0 = time.perf_counter()
+        oracle.trace(ob, tris, prim, query="closest", mode="paper", table=ta, epoch=cfg_all["epoch_rays"], vtx=vtx,
+                     nthreads=1, first_epoch=cfg_all["first_epoch_rays"])
+        oracle.trace(ob, tris, shadow, query="any", table=tb, epoch=cfg_any["epoch_rays"], vtx=vtx, nthreads=1,
+                     first_epoch=cfg_any["first_epoch_rays"])
+        t1 = time.perf_counter() - c0
+        cpu["single_thread"] = {"value": round(rays_per_step / t1 / 1e6, 3), "cores": 1,
+                                "sample": f"one full step, {t1:.2f} s"}
 
     serve = None
     if not args.no_serving:
