@@ -202,7 +202,8 @@ hrpp_status hrpp_bvh_upload(hrpp_bvh *bvh, void *d_buf, size_t bytes, void *stre
 /* Device build (a GPU builder for callers that take new scenes while they
  * run, such as the serving loop; the paper takes the BVH as given,
  * "Overview").  Builds a linear BVH entirely on the GPU: the binary radix
- * tree over 63-bit Morton codes of the triangle centres (Karras, HPG 2012),
+ * tree over 63-bit Morton codes of the triangle centres on a grid of cubic
+ * cells (Karras, HPG 2012),
  * triangles ordered by (code, primitive id), every subtree over at most
  * leaf_max triangles kept as one leaf, exact boxes, DFS pre-order -- a
  * different tree from the host builder's SAH tree, with the same query

@@ -327,9 +327,10 @@ int orc_build_median(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t 
    Trees", HPG 2012), written top-down from its definition:
    * centre of triangle t on axis a: c = (lo + hi) * 0.5 with lo / hi the
      vertices' min / max (the same centre as the SAH builder);
-   * cmin / cmax = min / max centre over all triangles; per axis
-     scale = 2^21 / (cmax - cmin), or 0 when that extent is 0 or the
-     quotient is not finite; cell q = min(floor((c - cmin) * scale), 2^21 - 1);
+   * cmin / cmax = min / max centre over all triangles; cubic cells: one
+     scale = 2^21 / (the largest of the three extents cmax - cmin), or 0 when
+     that extent is 0 or the quotient is not finite;
+     cell q = min(floor((c - cmin) * scale), 2^21 - 1) on each axis;
    * Morton code: bit k of the x / y / z cell goes to bit 3k+2 / 3k+1 / 3k;
    * triangles sorted by (code, primitive id);
    * the node over sorted positions [b, e) is a leaf when e - b <= leaf_max;
@@ -412,16 +413,18 @@ void orc_lbvh_codes(const float *tris, uint32_t n, uint64_t *code)
             if (ce > cmax[a]) cmax[a] = ce;
         }
     }
-    float scale[3];
+    /* cubic cells: one scale, from the largest extent */
+    float emax = 0.0f;
     for (int a = 0; a < 3; a++) {
         float ext = cmax[a] - cmin[a];
-        float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
-        scale[a] = isfinite(s) ? s : 0.0f;
+        if (ext > emax) emax = ext;
     }
+    float scale = emax > 0.0f ? 2097152.0f / emax : 0.0f;
+    if (!isfinite(scale)) scale = 0.0f;
     for (uint32_t t = 0; t < n; t++) {
         uint32_t q[3];
         for (int a = 0; a < 3; a++) {
-            float f = floorf((c[3 * (size_t)t + a] - cmin[a]) * scale[a]);
+            float f = floorf((c[3 * (size_t)t + a] - cmin[a]) * scale);
             q[a] = f >= 2097151.0f ? 2097151u : (uint32_t)f;
         }
         uint64_t m = 0;

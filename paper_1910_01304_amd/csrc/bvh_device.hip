@@ -7,10 +7,10 @@
 // scenes quickly (the serving loop takes new scenes while it runs).  The tree:
 //   * centre of a triangle on axis a: (lo + hi) * 0.5 with lo / hi the min /
 //     max of its vertices (the SAH builder's centre);
-//   * per axis, over all centres: scale = 2^21 / (cmax - cmin), 0 when that
-//     extent is 0 or the quotient is not finite; cell = min(floor((c - cmin)
-//     * scale), 2^21 - 1); code bit 3k+2 / 3k+1 / 3k = bit k of the x / y / z
-//     cell (63 bits);
+//   * cubic cells over the centres' bounds: one scale = 2^21 / (the largest
+//     extent cmax - cmin), 0 when that extent is 0 or the quotient is not
+//     finite; cell = min(floor((c - cmin) * scale), 2^21 - 1) per axis; code
+//     bit 3k+2 / 3k+1 / 3k = bit k of the x / y / z cell (63 bits);
 //   * triangles sorted by (code, primitive id) -- a stable radix sort;
 //   * the radix tree over the keys (code, sorted position): each node splits
 //     its range at the highest bit in which its first and last keys differ;
@@ -171,13 +171,17 @@ __global__ __launch_bounds__(256) void k_lbvh_codes(const float *__restrict__ ve
     if (t >= n) return;
     float lo[3], hi[3];
     tri_bounds(verts + 9 * (size_t)t, lo, hi);
+    // cubic cells: one scale, from the largest extent
+    float emax = 0.0f;
+    for (int a = 0; a < 3; a++) {
+        const float ext = float_of(h->cmax[a]) - float_of(h->cmin[a]);
+        if (ext > emax) emax = ext;
+    }
+    float s = emax > 0.0f ? 2097152.0f / emax : 0.0f;
+    if (!isfinite(s)) s = 0.0f;
     uint64_t q[3];
     for (int a = 0; a < 3; a++) {
-        const float cmin = float_of(h->cmin[a]), cmax = float_of(h->cmax[a]);
-        const float ext = cmax - cmin;
-        float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
-        if (!isfinite(s)) s = 0.0f;
-        const float f = floorf(((lo[a] + hi[a]) * 0.5f - cmin) * s);
+        const float f = floorf(((lo[a] + hi[a]) * 0.5f - float_of(h->cmin[a])) * s);
         q[a] = f >= (float)kCellMax ? kCellMax : (uint32_t)f;
     }
     code[t] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);

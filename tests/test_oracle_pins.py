@@ -293,6 +293,12 @@ def test_lbvh_codes_hand_cases():
     # a flat axis has a single cell: every z bit stays 0
     flat = _point_tris([[0, 0, 5], [S, S, 5], [1, 1, 5]])
     assert oracle.lbvh_codes(flat).tolist() == [0, 0b110 * (2 ** 63 - 1) // 7, 0b110]
+    # cells are cubes sized by the largest extent: with y spanning a quarter of
+    # x, y's top cell is 2^19 (bit 19 -> code bit 58) and 2^18 lands on bit 55,
+    # where per-axis cells would put them on bits 61 and 58
+    flat_y = _point_tris([[0, 0, 0], [S, S / 4, 0], [S / 2, S / 8, 0]])
+    x_all = sum(1 << (3 * k + 2) for k in range(21))
+    assert oracle.lbvh_codes(flat_y).astype(object).tolist() == [0, x_all + 2 ** 58, 2 ** 62 + 2 ** 55]
 
 
 def test_lbvh_equal_codes_split_by_position():
