@@ -49,6 +49,16 @@ def test_device_build_equals_oracle(hrpp, n, leaf_max):
     oracle.validate_bvh(ob, tris, leaf_max, 64)
 
 
+def test_device_build_large(hrpp):
+    # 2^22 triangles (a heightfield), and 2^20 copies of one triangle, where
+    # every split falls back to the positions' bits
+    _say("device build 2^22 heightfield")
+    device_bvh(hrpp, sg.heightfield_scene(91, 1 << 22), 4)
+    _say("device build 2^20 equal triangles")
+    bvh, ob = device_bvh(hrpp, np.repeat(sg.triangle_soup(92, 1), 1 << 20, axis=0), 2)
+    assert bvh.max_depth == 19                  # a balanced tree: 2^19 leaves of two
+
+
 def test_device_build_degenerate_scenes(hrpp):
     _say("device build degenerate scenes")
     same = np.repeat(sg.triangle_soup(5, 1), 50, axis=0)    # one code: splits by position
