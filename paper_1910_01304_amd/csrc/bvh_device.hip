@@ -63,7 +63,8 @@ struct LbvhHeader {
 };
 static_assert(sizeof(LbvhHeader) == 256, "one 256-byte header");
 
-// Total order of binary32 values as unsigned integers (for atomic min / max).
+// Total order of binary32 values as unsigned integers (for integer min / max
+// reductions; NaN images lie outside the finite ones and are rejected).
 __device__ inline uint32_t ord_of(float f) {
     const uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
@@ -73,7 +74,7 @@ __device__ inline float float_of(uint32_t k) {
 }
 
 // Vertex min / max of one triangle on each axis (strict comparisons, first
-// vertex wins ties) and its centre.
+// vertex wins ties); the centre is (lo + hi) * 0.5.
 __device__ inline void tri_bounds(const float *__restrict__ v, float lo[3], float hi[3]) {
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -110,7 +111,7 @@ __device__ inline uint32_t wave_max(uint32_t x) {
     return x;
 }
 
-// Block reduction of 7 words (min of 0..2, max of 3..5, or of 6) over 256
+// Block reduction of 7 words (min of words 0..2, max of words 3..6) over 256
 // threads; thread 0 ends with the block's values.
 __device__ inline void block_reduce7(uint32_t v[7], uint32_t (*lds)[7]) {
     for (int k = 0; k < 7; k++) v[k] = k < 3 ? wave_min(v[k]) : wave_max(v[k]);
@@ -245,7 +246,8 @@ struct Tree {
 
 // mark[k] = 1 when sorted position k is the first of an output leaf (the
 // leaf holding k is found by climbing while the parent is small enough to be
-// a leaf itself: at most log2(leaf_max) + 1 steps); mark[n] = 0.
+// a leaf itself: at most leaf_max - 1 <= 7 steps, since a subtree of at most
+// leaf_max leaves is at most that tall); mark[n] = 0.
 __global__ __launch_bounds__(256) void k_lbvh_mark(Tree tr, uint32_t *__restrict__ mark) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k > tr.n) return;
