@@ -236,6 +236,7 @@ def main():
         w = sg.AT_SCALE
         cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
                      inline_lanes=q[3], first_epoch_rays=q[4]) for q in (w["primary_q"], w["shadow_q"])]
+        cfgs.append(dict(leaf_max=w["leaf_max"]))
         summarize_traffic(*args.summarize_traffic, configs=cfgs)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -283,7 +284,7 @@ def main():
     tris, prim = sg.terrain_workload()
     n_prim = prim.shape[0]
     t0 = time.perf_counter()
-    bvh = hrpp.BVH(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     build_s = time.perf_counter() - t0
     log(f"BVH: {bvh.num_nodes} nodes, depth {bvh.max_depth}, built in {build_s:.2f} s")
     pq, sq = w["primary_q"], w["shadow_q"]
@@ -468,7 +469,7 @@ def main():
         dom = max((k for k in kernels if k.startswith("hrpp:")), key=lambda k: kernels[k]["ms_per_step"])
         d = kernels[dom]
         kname = dom.split(":", 1)[1]
-        traffic = load_traffic(kname, [cfg_all, cfg_any])
+        traffic = load_traffic(kname, [cfg_all, cfg_any, dict(leaf_max=w["leaf_max"])])
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(d["gbs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
                     "traffic": int(traffic) if traffic is not None else None,
@@ -600,7 +601,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         log("oracle on the host cores")
-        ob = oracle.build_sah(tris)
+        ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
         vtx = oracle.bvh_vertices(tris, ob)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         times = []
@@ -647,7 +648,7 @@ def main():
                                f"first epoch {sq[4]} then epochs of {sq[2]}, inline lanes {sq[3]} (autotuned)",
                    "hit_all_predictor": cfg_all, "hit_any_predictor": cfg_any,
                    "triangles": int(tris.shape[0]), "rays_per_step": int(rays_per_step),
-                   "bvh_nodes": int(bvh.num_nodes), "bvh_depth": int(bvh.max_depth)},
+                   "bvh_nodes": int(bvh.num_nodes), "bvh_depth": int(bvh.max_depth), "bvh_leaf_max": w["leaf_max"]},
         "plain_mrays_s": round(mrays(rays_per_step, ms_plain), 2),
         "plain_ms_per_step": round(ms_plain, 4),
         "speedup_vs_plain": round(ms_plain / ms_hrpp, 4),
@@ -762,7 +763,7 @@ def run_progressive(args, np, torch, hrpp, sg):
     (a pass with the two queries on one stream); one JSON line."""
     w = sg.AT_SCALE
     tris, prim = sg.terrain_workload()
-    bvh = hrpp.BVH(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     n = prim.shape[0]
     pq, sq = w["primary_q"], w["shadow_q"]
     cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2],
@@ -817,7 +818,7 @@ def run_autotune(args, np, torch, hrpp, sg):
 
     tris, prim = sg.terrain_workload()
     w = sg.AT_SCALE
-    bvh = hrpp.BVH(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     prim_d = torch.from_numpy(prim).cuda()
     he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
@@ -877,7 +878,7 @@ def run_sweep(args, np, torch, hrpp, sg):
     wi = sg.INCOHERENT
     log("generating the incoherent AO workload")
     tris, _ = sg.terrain_scene(sg.AT_SCALE["seed"])
-    bvh = hrpp.BVH(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     cam_rays, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
     cam_d = torch.from_numpy(cam_rays).cuda()
     hh = hrpp.trace_closest(bvh, None, cam_d, mode="exact").cpu().numpy()
@@ -929,7 +930,7 @@ def run_sweep(args, np, torch, hrpp, sg):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        ob = oracle.build_sah(tris)
+        ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
         vtx = oracle.bvh_vertices(tris, ob)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         sample_pts = [(m, T, q) for m in modes for (T, q) in ((16, 3), (16, 7), (22, 3), (22, 7), (20, 5))]
@@ -963,7 +964,7 @@ def run_goup(args, np, torch, hrpp, sg):
     w = sg.AT_SCALE
     log("generating the at-scale workload")
     tris, prim = sg.terrain_workload()
-    bvh = hrpp.BVH(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     prim_d = torch.from_numpy(prim).cuda()
     he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
@@ -1042,7 +1043,7 @@ def run_build(args, np, torch, hrpp, sg):
     host_s = []
     for _ in range(3):
         t0 = time.perf_counter()
-        sah = hrpp.BVH(tris, device=None)
+        sah = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], device=None)
         host_s.append(time.perf_counter() - t0)
     t0 = time.perf_counter()
     sah.upload()
@@ -1055,7 +1056,7 @@ def run_build(args, np, torch, hrpp, sg):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record()
-        lb = hrpp.BVH.build_on_device(verts_d)
+        lb = hrpp.BVH.build_on_device(verts_d, leaf_max=sg.AT_SCALE["leaf_max"])
         e1.record()
         torch.cuda.synchronize()
         if rep:                              # the first build pays for the allocations
@@ -1163,9 +1164,9 @@ def measure_scene_arrival(np, torch, hrpp, sg, bvh0, shadow0):
             srv.submit(0, "any", bg_rays, o)
         t0 = time.perf_counter()
         if builder == "device":
-            bvh2 = hrpp.BVH.build_on_device(verts2.cuda())
+            bvh2 = hrpp.BVH.build_on_device(verts2.cuda(), leaf_max=sg.AT_SCALE["leaf_max"])
         else:
-            bvh2 = hrpp.BVH(tris2)
+            bvh2 = hrpp.BVH(tris2, leaf_max=sg.AT_SCALE["leaf_max"])
         t_built = time.perf_counter()
         pa = hrpp.Predictor(bvh2, 16, 8, 6, 3, 1 << 17)
         pc = hrpp.Predictor(bvh2, 16, 8, 5, 7, 1 << 17)
@@ -1199,7 +1200,7 @@ def run_policy(args, np, torch, hrpp, sg):
     w, wi = sg.AT_SCALE, sg.INCOHERENT
     log("generating the at-scale and AO workloads")
     tris, prim = sg.terrain_workload()
-    bvh = hrpp.BVH(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     prim_d = torch.from_numpy(prim).cuda()
     cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
     hh = hrpp.trace_closest(bvh, None, torch.from_numpy(cam).cuda(), mode="exact").cpu().numpy()

@@ -182,19 +182,21 @@ def full_terrain():
 
 def test_device_tree_full_size(hrpp, full_terrain):
     # the at-scale scene (2^20 triangles) and its 2,073,600 primaries and
-    # shadow rays, with the benchmark's predictor configurations
+    # shadow rays, with the benchmark's leaf size and predictor configurations
     w = sg.AT_SCALE
     tris, prim = full_terrain
     pq, sq = w["primary_q"], w["shadow_q"]
     cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3], 0, pq[4])
     cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3], 0, sq[4])
     _, st = check_case(hrpp, "full primary paper (device tree)", tris, prim, query="closest", mode="paper",
-                       pred_cfg=cfg_all, builder="device")
+                       pred_cfg=cfg_all, builder="device", leaf_max=w["leaf_max"])
     assert st["rays"] == 1920 * 1080
     he, _ = oracle.trace(oracle.build_sah(tris), tris, prim, query="closest", mode="exact")
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
-    check_case(hrpp, "full shadow hrpp (device tree)", tris, shadow, pred_cfg=cfg_any, builder="device")
+    check_case(hrpp, "full shadow hrpp (device tree)", tris, shadow, pred_cfg=cfg_any, builder="device",
+               leaf_max=w["leaf_max"])
+    check_case(hrpp, "full shadow plain (device tree, leaves of 4)", tris, shadow, builder="device")
 
 
 def test_serving_device_built_scenes(hrpp):

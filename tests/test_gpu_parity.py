@@ -304,12 +304,12 @@ def test_wide_terrain(hrpp, small_terrain):
 def test_wide_full_size(hrpp, full_terrain):
     w = sg.AT_SCALE
     tris, prim = full_terrain
-    wide_case(hrpp, "full primary", tris, prim, "closest")
-    ob = oracle.build_sah(tris)
+    wide_case(hrpp, "full primary", tris, prim, "closest", leaf_max=sg.AT_SCALE["leaf_max"])
+    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
-    wide_case(hrpp, "full shadow", tris, shadow)
+    wide_case(hrpp, "full shadow", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"])
 
 
 # ---------------------------------------------------------------------------
@@ -347,7 +347,7 @@ def test_full_size_policy(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     _, st = check_case(hrpp, "full primary paper, FIFO + resident, 2^12 x 4", tris, prim, query="closest",
-                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3, pq[4]))
+                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3, pq[4]), leaf_max=sg.AT_SCALE["leaf_max"])
     assert st["evictions"] > 0
 
 
@@ -444,7 +444,7 @@ def test_full_size_go_up(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     check_case(hrpp, "full primary paper go-up 1", tris, prim, query="closest", mode="paper",
-               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3], 0, pq[4]))
+               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3], 0, pq[4]), leaf_max=sg.AT_SCALE["leaf_max"])
 
 
 def test_import_validates_slots(hrpp, small_terrain):
@@ -597,15 +597,15 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
     pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17, 0, 0), (5, 6, 1 << 17, 0, 0))
     cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3], 0, pq[4])
     cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3], 0, sq[4])
-    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all)
+    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all, leaf_max=sg.AT_SCALE["leaf_max"])
     assert st["rays"] == 1920 * 1080
-    ob = oracle.build_sah(tris)
+    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
-    check_case(hrpp, "full primary exact (plain)", tris, prim, query="closest", mode="exact")
+    check_case(hrpp, "full primary exact (plain)", tris, prim, query="closest", mode="exact", leaf_max=sg.AT_SCALE["leaf_max"])
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
-    check_case(hrpp, "full shadow plain", tris, shadow)
-    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any)
+    check_case(hrpp, "full shadow plain", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"])
+    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any, leaf_max=sg.AT_SCALE["leaf_max"])
 
 
 def test_full_size_progressive_frames(hrpp, full_terrain):
@@ -616,8 +616,8 @@ def test_full_size_progressive_frames(hrpp, full_terrain):
     import torch
     w = sg.AT_SCALE
     tris, _ = full_terrain
-    bvh = hrpp.BVH(tris)
-    ob = oracle.build_sah(tris)
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     vtx = oracle.bvh_vertices(tris, ob)
     pq, sq = w["primary_q"], w["shadow_q"]
     E = 1 << 21
@@ -661,12 +661,12 @@ def test_full_size_ao(hrpp, full_terrain, cfg):
     wi = sg.INCOHERENT
     tris, _ = full_terrain
     cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
-    ob = oracle.build_sah(tris)
+    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     hh, _ = oracle.trace(ob, tris, cam, query="closest", mode="exact")
     ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
                               samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
     assert ao.shape[0] == 7372800
-    _, st = check_case(hrpp, f"full AO {cfg}", tris, ao, pred_cfg=cfg)
+    _, st = check_case(hrpp, f"full AO {cfg}", tris, ao, pred_cfg=cfg, leaf_max=sg.AT_SCALE["leaf_max"])
     assert st["rays"] == 7372800
 
 
@@ -676,13 +676,13 @@ def test_maximum_epoch_and_large_table(hrpp, full_terrain):
     wi = sg.INCOHERENT
     tris, _ = full_terrain
     cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
-    ob = oracle.build_sah(tris)
+    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     hh, _ = oracle.trace(ob, tris, cam, query="closest", mode="exact")
     ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
                               samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
     for inline in (65, 1):
         _, st = check_case(hrpp, f"AO, epoch 2^22, table 2^24 x 4, inline {inline}", tris, ao,
-                           pred_cfg=(24, 4, 5, 6, 1 << 22, 0, 0, inline))
+                           pred_cfg=(24, 4, 5, 6, 1 << 22, 0, 0, inline), leaf_max=sg.AT_SCALE["leaf_max"])
         assert st["rays"] == 7372800 and st["pred_hits"] > 0
 
 
