@@ -89,6 +89,8 @@ def parse():
                     help="inline_lanes of the batched and serving predictors (-1: the workload's default)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
+    ap.add_argument("--scene-leaf-max", type=int, default=2,
+                    help="leaf size of the batched and serving scenes' BVHs (the at-scale scene uses its own)")
     ap.add_argument("--tune-queries", default="",
                     help="comma list of primary,shadow,ao,primary_warm,shadow_warm (default all)")
     ap.add_argument("--tune-knobs",
@@ -1294,7 +1296,7 @@ def measure_serving(args, np, torch, hrpp, sg, rhos, n_requests, n_warmup):
 
     with ThreadPoolExecutor(8) as ex:
         made = list(ex.map(make, specs))
-        bvhs = list(ex.map(lambda m: hrpp.BVH(m[0], device=None), made))
+        bvhs = list(ex.map(lambda m: hrpp.BVH(m[0], leaf_max=args.scene_leaf_max, device=None), made))
     for b in bvhs:
         b.upload()
     pools = []
@@ -1394,7 +1396,7 @@ def measure_serving(args, np, torch, hrpp, sg, rhos, n_requests, n_warmup):
                                   "(20% primary exact closest, 40% shadow, 40% AO), 8 GiB pool, "
                                   f"{args.serve_slots} slots, "
                                   f"{args.serve_replicas} predictor replicas per scene and kind, epoch 2^19",
-                      "triangles": int(sum(s["tris"] for s in specs))},
+                      "triangles": int(sum(s["tris"] for s in specs)), "bvh_leaf_max": args.scene_leaf_max},
            "saturation_mrays_s": round(sat_rate / 1e6, 1), "mean_request_rays": round(mean_size),
            "pool_peak_bytes": int(peak), "pool_bytes": pool_bytes, "results": results}
     del srv, scenes, bvhs, pools
@@ -1421,7 +1423,7 @@ def run_batched(args, np, torch, hrpp, sg):
     with ThreadPoolExecutor(8) as ex:
         tris = list(ex.map(lambda sp: sg.mixed_scene(sp["seed"], sp["tris"]), specs))
         t0 = time.perf_counter()
-        bvhs = list(ex.map(lambda t: hrpp.BVH(t, device=None), tris))
+        bvhs = list(ex.map(lambda t: hrpp.BVH(t, leaf_max=args.scene_leaf_max, device=None), tris))
         build_s = time.perf_counter() - t0
         rays = list(ex.map(lambda it: np.concatenate(sg.secondary_rays_on_surface(it[1], it[0]["rays"],
                                                                                    it[0]["seed"] + 1)),
@@ -1474,7 +1476,7 @@ def run_batched(args, np, torch, hrpp, sg):
         dev = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dev = [hrpp.BVH.build_on_device(v) for v in verts_d]
+        dev = [hrpp.BVH.build_on_device(v, leaf_max=args.scene_leaf_max) for v in verts_d]
         torch.cuda.synchronize()
         dev_ms = (time.perf_counter() - t0) * 1e3
     log(f"batched: device build of {len(dev)} scenes {dev_ms:.1f} ms (host {build_s:.2f} s)")
@@ -1498,7 +1500,8 @@ def run_batched(args, np, torch, hrpp, sg):
         "config": {"workload": f"{len(specs)} scenes (soup/heightfield 50/50, 1e4-2e6 tris log-uniform), "
                                "rays 2^16-2^22 log-uniform per scene (60% shadow, 40% AO), any-hit, "
                                f"tables 2^16-2^20 x 8, q 5/6, epoch {E}",
-                   "scenes": len(specs), "triangles": int(sum(sp["tris"] for sp in specs)), "rays": total},
+                   "scenes": len(specs), "triangles": int(sum(sp["tris"] for sp in specs)), "rays": total,
+                   "bvh_leaf_max": args.scene_leaf_max},
         "sequential_calls_mrays_s": round(total / (ms_seq * 1e-3) / 1e6, 2),
         "plain_batched_mrays_s": round(total / (ms_plain * 1e-3) / 1e6, 2),
         "batch_speedup_vs_sequential": round(ms_seq / ms_batch, 3),
