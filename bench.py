@@ -1130,6 +1130,30 @@ def run_build(args, np, torch, hrpp, sg):
         log(f"{name}: {trees[name]}")
         del pa, pb
     arrival = measure_scene_arrival(np, torch, hrpp, sg, sah, shadow)
+    # device build time against scene size (heightfields; median of 3 after one
+    # untimed build; HIP events around the call)
+    scaling = []
+    for lg in (16, 18, 20, 22, 24):
+        v = torch.from_numpy(np.ascontiguousarray(sg.heightfield_scene(91, 1 << lg).reshape(-1, 9))).cuda()
+        ts = []
+        for rep in range(4):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b = hrpp.BVH.build_on_device(v, leaf_max=w["leaf_max"])
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:
+                ts.append(e0.elapsed_time(e1))
+            nodes, depth = b.num_nodes, b.max_depth
+            b.close()
+            del b
+        ms = statistics.median(ts)
+        scaling.append(dict(triangles=1 << lg, build_ms=round(ms, 3), mtris_s=round((1 << lg) / (ms * 1e-3) / 1e6, 1),
+                            nodes=nodes, depth=depth))
+        log(f"device build scaling: {scaling[-1]}")
+        del v
+        torch.cuda.empty_cache()
     print(json.dumps({
         "metric": "BVH build time and the step over each tree", "unit": "ms", "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"terrain {n_tris} tris; step = 1920x1080 primary closest (PAPER) + shadow any-hit, "
@@ -1139,7 +1163,7 @@ def run_build(args, np, torch, hrpp, sg):
         "device_lbvh_build_min_ms": round(min(dev_ms), 3),
         "device_lbvh_build_wall_ms": round(statistics.median(dev_wall), 3),
         "build_speedup": round(statistics.median(host_s) * 1e3 / statistics.median(dev_wall), 1),
-        "trees": trees, "scene_arrival": arrival}), flush=True)
+        "trees": trees, "scene_arrival": arrival, "device_build_scaling": scaling}), flush=True)
 
 
 def measure_scene_arrival(np, torch, hrpp, sg, bvh0, shadow0):
