@@ -95,7 +95,8 @@ def parse():
                     help="comma list of primary,shadow,ao,primary_warm,shadow_warm (default all)")
     ap.add_argument("--tune-knobs",
                     default="epoch_rays,first_epoch_rays,log2_entries,ways,origin_bits,dir_bits,inline_lanes",
-                    help="autotune: comma-separated knobs to search (the others stay at the workload's values)")
+                    help="autotune: comma-separated knobs to search (the others stay at the workload's values); "
+                         "leaf_max rebuilds the scene's tree per leaf size")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-slots", type=int, default=8, help="stream slots of the server")
@@ -821,6 +822,14 @@ def run_autotune(args, np, torch, hrpp, sg):
     tris, prim = sg.terrain_workload()
     w = sg.AT_SCALE
     bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    trees = {sg.AT_SCALE["leaf_max"]: bvh}
+
+    def tree_for(leaf):
+        # the at-scale scene's SAH tree at another leaf size (knob "leaf_max")
+        if leaf not in trees:
+            trees[leaf] = hrpp.BVH(tris, leaf_max=leaf)
+        return trees[leaf]
+
     prim_d = torch.from_numpy(prim).cuda()
     he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
@@ -855,7 +864,10 @@ def run_autotune(args, np, torch, hrpp, sg):
             continue
         start = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1],
                      epoch_rays=q[2], inline_lanes=q[3], first_epoch_rays=q[4])
-        r = autotune.tune(bvh, rays, query=query, mode="paper", start=start, rounds=2, reps=3, knobs=knobs, log=log,
+        if "leaf_max" in knobs:
+            start["leaf_max"] = sg.AT_SCALE["leaf_max"]
+        r = autotune.tune(tree_for if "leaf_max" in knobs else bvh, rays, query=query, mode="paper", start=start,
+                          rounds=2, reps=3, knobs=knobs, log=log,
                           warm_rays=warm_rays)
         res[name] = {"best": r.best, "best_ms": round(r.best_ms, 4),
                      "best_mrays_s": round(rays.shape[0] / (r.best_ms * 1e-3) / 1e6, 1),

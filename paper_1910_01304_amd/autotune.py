@@ -2,9 +2,11 @@
 
 Knobs: epoch size (the unit of batch-synchronous work, a "chunk"), the length
 of a call's first epoch (a short one fills the table early), table size
-(log2 entries), ways, origin / direction quantisation bits, and the number of
+(log2 entries), ways, origin / direction quantisation bits, the number of
 failing lanes at which a prediction wave traverses at once instead of
-queueing (a pure scheduling knob: results do not depend on it).  The traversal
+queueing (a pure scheduling knob: results do not depend on it), and the BVH's
+leaf size (given a function that builds the tree for a leaf size; each size is
+built once and its plain traversal is the reference for the skip constraint).  The traversal
 stack depth is not a knob: the per-lane stack holds the deepest tree the
 library accepts (64 levels), which is what makes overflow impossible.  Every configuration the tuner
 can pick is an ordinary predictor configuration, traced by the same kernels
@@ -36,6 +38,7 @@ DEFAULT_SPACE = {
     "dir_bits": [3, 4, 5, 6, 7],
     "inline_lanes": [16, 32, 48, 56, 64, 65],
     "first_epoch_rays": [0, 1 << 16, 1 << 17, 1 << 18, 1 << 19],
+    "leaf_max": [1, 2, 3, 4],
 }
 
 
@@ -100,26 +103,46 @@ def tune(bvh, rays, query: str = "any", mode: str = "paper", start: dict | None 
          space: dict | None = None, rounds: int = 2, reps: int = 3, min_skip_pct: float | None = None,
          knobs=("epoch_rays", "log2_entries", "ways", "origin_bits", "dir_bits"), log=None,
          warm_rays=None) -> TuneResult:
-    """Coordinate-descent search of the predictor configuration minimising trace time."""
+    """Coordinate-descent search of the predictor configuration minimising trace time.
+
+    `bvh` is a BVH, or a function from a leaf size to a BVH over the same
+    triangles; the latter is required to tune "leaf_max", and the returned
+    configuration then carries the chosen "leaf_max" next to the predictor's
+    knobs."""
     space = dict(DEFAULT_SPACE, **(space or {}))
+    tree_fn = bvh if callable(bvh) else None
+    if "leaf_max" in knobs and tree_fn is None:
+        raise ValueError("tuning leaf_max needs a function from a leaf size to a BVH")
     cfg = dict(log2_entries=20, ways=8, origin_bits=5, dir_bits=6, epoch_rays=1 << 19)
+    if tree_fn is not None:
+        cfg["leaf_max"] = 4
     if start:
         cfg.update(start)
-    # plain node count, for the skip constraint and the report
-    st = hrpp.new_stats()
-    if query == "any":
-        hrpp.trace_anyhit(bvh, None, rays, stats=st)
-    else:
-        hrpp.trace_closest(bvh, None, rays, mode=mode, stats=st)
-    torch.cuda.synchronize()
-    plain_nodes = hrpp.stats_dict(st)["nodes_visited"]
+    trees, plain = {}, {}
+
+    def tree_of(c):
+        # the tree and its plain node count (for the skip constraint and the report)
+        leaf = c.get("leaf_max") if tree_fn is not None else None
+        if leaf not in trees:
+            t = tree_fn(leaf) if tree_fn is not None else bvh
+            st = hrpp.new_stats()
+            if query == "any":
+                hrpp.trace_anyhit(t, None, rays, stats=st)
+            else:
+                hrpp.trace_closest(t, None, rays, mode=mode, stats=st)
+            torch.cuda.synchronize()
+            trees[leaf], plain[leaf] = t, hrpp.stats_dict(st)["nodes_visited"]
+        return trees[leaf], plain[leaf]
+
     seen = {}
     trials = []
 
     def evaluate(c):
         key = tuple(sorted(c.items()))
         if key not in seen:
-            ms, s = _time_config(bvh, rays, query, mode, c, reps, plain_nodes, warm_rays)
+            t, plain_nodes = tree_of(c)
+            pc = {k: v for k, v in c.items() if k != "leaf_max"}
+            ms, s = _time_config(t, rays, query, mode, pc, reps, plain_nodes, warm_rays)
             ok = min_skip_pct is None or s["pct_nodes_skipped"] >= min_skip_pct
             seen[key] = (ms, s, ok)
             trials.append(dict(config=dict(c), ms=ms, pct_nodes_skipped=s["pct_nodes_skipped"], feasible=ok))

@@ -56,3 +56,32 @@ def test_autotune_warm_tables():
     st = autotune._time_config(bvh, second, "any", "paper", one_epoch, 1, 1, warm_rays=first)[1]
     st0 = autotune._time_config(bvh, second, "any", "paper", one_epoch, 1, 1)[1]
     assert st["positives"] > 0 and st0["positives"] == 0
+
+
+def test_autotune_leaf_size():
+    # with a tree builder the tuner also picks the leaf size; each size is built
+    # once and judged against its own plain traversal
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_01304_amd as hrpp
+    from paper_1910_01304_amd import autotune
+    print("[gpu-case] autotune tiny, leaf size", flush=True)
+    tris, rays = sg.tiny_workload()
+    r = torch.from_numpy(rays).cuda()
+    built = []
+
+    def tree(leaf):
+        built.append(leaf)
+        return hrpp.BVH(tris, leaf_max=leaf)
+
+    space = {"leaf_max": [1, 2, 4], "epoch_rays": [256, 1024]}
+    start = dict(log2_entries=12, ways=4, origin_bits=5, dir_bits=6, epoch_rays=256, leaf_max=4)
+    res = autotune.tune(tree, r, query="any", start=start, space=space, rounds=2, reps=2,
+                        knobs=("leaf_max", "epoch_rays"))
+    assert res.best["leaf_max"] in space["leaf_max"] and res.best["epoch_rays"] in space["epoch_rays"]
+    assert sorted(built) == [1, 2, 4]                      # one tree per leaf size
+    assert {t["config"]["leaf_max"] for t in res.trials} == {1, 2, 4}
+    assert res.best_ms == min(t["ms"] for t in res.trials if t["feasible"])
+    with pytest.raises(ValueError):
+        autotune.tune(hrpp.BVH(tris), r, knobs=("leaf_max",))
