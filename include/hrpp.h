@@ -425,6 +425,14 @@ hrpp_status hrpp_serve_create(const hrpp_serve_scene *scenes, uint32_t nscenes, 
  * bad description or a server being destroyed. */
 hrpp_status hrpp_serve_add_scene(hrpp_server *server, const hrpp_serve_scene *scene, uint32_t *index);
 
+/* Remove a scene from a running server (to free its BVH and tables, e.g. to
+ * stay within an HBM budget).  New requests for it are refused (EINVAL);
+ * the call blocks until its queued and running requests are done, after
+ * which its BVH and predictors may be freed or added again with another
+ * scene.  The other scenes keep their indices; the index is not reused.
+ * EINVAL for an unknown or already removed scene. */
+hrpp_status hrpp_serve_remove_scene(hrpp_server *server, uint32_t index);
+
 /* Queue a request: n rays in host memory (pinned memory lets the copies run
  * asynchronously), results to h_out (uint8_t[n] for query 0 = any-hit,
  * hrpp_hit[n] for query 1 = EXACT closest-hit).  Both buffers must stay

@@ -101,7 +101,17 @@ struct hrpp_server {
         const hrpp_bvh *bvh;
         std::vector<hrpp_predictor *> preds[2];   // [0] hit-any, [1] hit-all
         std::vector<bool> busy[2];
+        bool removed = false;                     // no new requests; slot kept so indices stay stable
     };
+
+    // Requests of `scene` still queued or running (caller holds mu).
+    bool scene_busy(uint32_t scene) const {
+        for (const Request *r : queue)
+            if (r->scene == scene) return true;
+        for (const Request *r : running)
+            if (r->scene == scene) return true;
+        return false;
+    }
     std::vector<Scene> scenes;
     std::vector<hipStream_t> streams;
     std::vector<bool> slot_busy;
@@ -289,11 +299,21 @@ hrpp_status hrpp_serve_add_scene(hrpp_server *sv, const hrpp_serve_scene *scene,
     if (sv->stop) return HRPP_EINVAL;
     std::vector<const hrpp_predictor *> seen;
     for (const auto &sc : sv->scenes)
-        for (int kind = 0; kind < 2; kind++) seen.insert(seen.end(), sc.preds[kind].begin(), sc.preds[kind].end());
+        if (!sc.removed)
+            for (int kind = 0; kind < 2; kind++) seen.insert(seen.end(), sc.preds[kind].begin(), sc.preds[kind].end());
     hrpp_server::Scene sc;
     if (make_scene(*scene, seen, sc) != HRPP_OK) return HRPP_EINVAL;
     sv->scenes.push_back(sc);
     *index = (uint32_t)(sv->scenes.size() - 1);
+    return HRPP_OK;
+}
+
+hrpp_status hrpp_serve_remove_scene(hrpp_server *sv, uint32_t index) {
+    if (!sv) return HRPP_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (index >= sv->scenes.size() || sv->scenes[index].removed) return HRPP_EINVAL;
+    sv->scenes[index].removed = true;
+    sv->cv.wait(lk, [sv, index] { return !sv->scene_busy(index); });
     return HRPP_OK;
 }
 
@@ -315,7 +335,7 @@ hrpp_status hrpp_serve_submit(hrpp_server *sv, uint32_t scene, uint32_t query, c
     }
     r->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop || scene >= sv->scenes.size()) { delete r; return HRPP_EINVAL; }
+    if (sv->stop || scene >= sv->scenes.size() || sv->scenes[scene].removed) { delete r; return HRPP_EINVAL; }
     r->id = sv->next_id++;
     sv->all[r->id] = r;
     sv->queue.push_back(r);

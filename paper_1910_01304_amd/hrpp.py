@@ -40,6 +40,7 @@ EXPORTED = [
     "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy", "hrpp_bvh_wide_info",
     "hrpp_bvh_wide_export", "hrpp_trace_wide_anyhit", "hrpp_trace_wide_closest",
     "hrpp_bvh_device_build_scratch_bytes", "hrpp_build_bvh_device", "hrpp_serve_add_scene",
+    "hrpp_serve_remove_scene",
 ]
 
 
@@ -135,6 +136,7 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_serve_create.argtypes = [vp, u32, u32, vp, sz, C.POINTER(vp)]
     lib.hrpp_serve_submit.argtypes = [vp, u32, u32, vp, u32, vp, C.POINTER(C.c_uint64)]
     lib.hrpp_serve_add_scene.argtypes = [vp, vp, C.POINTER(u32)]
+    lib.hrpp_serve_remove_scene.argtypes = [vp, u32]
     lib.hrpp_serve_poll.argtypes = [vp, C.c_uint64, vp]
     lib.hrpp_serve_wait_all.argtypes = [vp]
     lib.hrpp_serve_pool_peak.argtypes = [vp, C.POINTER(sz)]
@@ -489,6 +491,10 @@ class Server:
         idx = C.c_uint32()
         _check(load_library().hrpp_serve_add_scene(self.handle, C.byref(sc), C.byref(idx)), "hrpp_serve_add_scene")
         return idx.value
+
+    def remove_scene(self, index: int):
+        """Refuse new requests for a scene and wait for its queued and running ones."""
+        _check(load_library().hrpp_serve_remove_scene(self.handle, index), "hrpp_serve_remove_scene")
 
     def submit(self, scene: int, query: str, rays: torch.Tensor, out: torch.Tensor) -> int:
         if rays.is_cuda or out.is_cuda or not rays.is_contiguous() or not out.is_contiguous():

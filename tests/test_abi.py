@@ -92,6 +92,7 @@ def test_host_argument_validation():
     assert lib.hrpp_build_bvh_device(p16, 16, C.byref(desc), p16, 1 << 20, p16, 1 << 20, None, None) == 1
     idx = C.c_uint32()
     assert lib.hrpp_serve_add_scene(None, None, C.byref(idx)) == 1
+    assert lib.hrpp_serve_remove_scene(None, 0) == 1
     # predictor descriptor limits
     pd = hrpp.hrpp._PredDesc(12, 4, 5, 6, 256, 0, 0)
     assert lib.hrpp_predictor_required_bytes(C.byref(pd)) > (1 << 12) * 32

@@ -217,14 +217,16 @@ def test_serving_device_built_scenes(hrpp):
         sc["anyp"], sc["clp"] = [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)], [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)]
     srv = hrpp.Server([(s["bvh"], s["anyp"], s["clp"]) for s in scenes[:2]], slots=2, pool_bytes=8 << 20)
 
-    def request(k, i):
+    def request(k, i, index=None):
+        # rays of scenes[k], submitted to server scene `index` (default k)
         query = "any" if i % 3 else "closest"
         pool = scenes[k]["prim"] if query == "closest" else scenes[k]["sec"]
         rays = torch.from_numpy(np.ascontiguousarray(pool[i * 1000:(i + 1) * 1000 + 4000])).pin_memory()
         n = rays.shape[0]
         out = (torch.empty(n, dtype=torch.uint8) if query == "any" else
                torch.empty((n, 4), dtype=torch.float32)).pin_memory()
-        return dict(scene=k, query=query, rays=rays, out=out, id=srv.submit(k, query, rays, out))
+        return dict(scene=k, query=query, rays=rays, out=out,
+                    id=srv.submit(k if index is None else index, query, rays, out))
 
     reqs = [request(i % 2, i) for i in range(8)]
     # a third scene arrives while those run: built on the device, then added
@@ -237,6 +239,18 @@ def test_serving_device_built_scenes(hrpp):
         srv.submit(2, "any", reqs[0]["rays"], reqs[0]["out"])
     assert srv.add_scene(sc["bvh"], sc["anyp"], sc["clp"]) == 2
     reqs += [request(2, i) for i in range(6)] + [request(0, 9)]
+    # scene 1 leaves while its requests may still run: the call waits for them
+    srv.remove_scene(1)
+    for r in reqs:
+        if r["scene"] == 1:
+            assert srv.poll(r["id"])["state"] == 2
+    with pytest.raises(hrpp.HrppError):          # no new requests for a removed scene
+        srv.submit(1, "any", reqs[0]["rays"], reqs[0]["out"])
+    with pytest.raises(hrpp.HrppError):          # removed already
+        srv.remove_scene(1)
+    # its predictors may serve again, with another scene on the same tree
+    assert srv.add_scene(scenes[1]["bvh"], scenes[1]["anyp"], scenes[1]["clp"]) == 3
+    reqs += [request(1, 2, index=3), request(1, 4, index=3)]
     srv.wait_all()
     for r in reqs:
         sc = scenes[r["scene"]]
