@@ -512,6 +512,51 @@ def test_edge_cases(hrpp):
                leaf_max=8)
 
 
+def _adversarial_rays(tris, n, seed):
+    """Valid rays built to stress the binary32 assumptions both sides share:
+    direction components of +-0, subnormal, tiny and huge magnitude (1/d of
+    +-inf, huge or subnormal), origins on BVH box planes and on triangle
+    planes (slab terms of 0 * inf), tmin of -0 and tmax of +inf."""
+    g = np.random.default_rng(seed)
+    v = tris.reshape(-1, 3)
+    lo, hi = v.min(0), v.max(0)
+    specials = np.float32([0.0, -0.0, 1e-45, -1e-45, 1e-39, -1e-39, 1.2e-38, -1.2e-38, 1e-30, -1e30, 3e38])
+    tgt = tris[g.integers(0, tris.shape[0], n)].mean(1)
+    o = (lo + (hi - lo) * g.uniform(-0.2, 1.2, (n, 3))).astype(np.float32)
+    k = g.integers(0, 3, n)
+    on_box = g.random(n) < 0.3
+    o[on_box, k[on_box]] = np.where(g.random(int(on_box.sum())) < 0.5, lo[k[on_box]], hi[k[on_box]])
+    on_tri = g.random(n) < 0.15                       # origin on a vertex's plane
+    o[on_tri, k[on_tri]] = v[g.integers(0, v.shape[0], int(on_tri.sum())), k[on_tri]]
+    d = (tgt - o).astype(np.float32)
+    for axis in range(3):                             # replace components by special values
+        m = g.random(n) < 0.3
+        d[m, axis] = specials[g.integers(0, specials.size, int(m.sum()))]
+    zero = ~np.any(d != 0, axis=1)                    # keep every ray valid
+    d[zero, 1] = -1.0
+    tmin = np.where(g.random(n) < 0.5, np.float32(-0.0), np.float32(0.0))
+    tmax = np.where(g.random(n) < 0.5, np.float32(np.inf), np.float32(1e30))
+    r = sg.pack_rays(o, d, 0.0, 0.0)
+    r[:, 3], r[:, 7] = tmin, tmax
+    return r
+
+
+def test_adversarial_binary32_rays(hrpp):
+    # the GPU's reciprocal, min/max with NaN operands and subnormal handling
+    # match the oracle's host arithmetic on rays built to hit those cases
+    tris, _ = sg.tiny_workload()
+    rays = _adversarial_rays(tris, 4096, 77)
+    occ, st = check_case(hrpp, "adversarial binary32, plain any", tris, rays)
+    assert st["invalid"] == 0 and 0 < st["hits"] < rays.shape[0]
+    check_case(hrpp, "adversarial binary32, hrpp any", tris, rays, pred_cfg=(10, 4, 4, 4, 512), calls=2)
+    check_case(hrpp, "adversarial binary32, closest exact", tris, rays, query="closest", mode="exact")
+    check_case(hrpp, "adversarial binary32, closest paper", tris, rays, query="closest", mode="paper",
+               pred_cfg=(10, 8, 4, 4, 1024, 0, 1))
+    terr, _ = sg.terrain_workload(total=30000, width=64, height=36)
+    check_case(hrpp, "adversarial binary32, terrain closest exact", terr, _adversarial_rays(terr, 4096, 78),
+               query="closest", mode="exact")
+
+
 def test_determinism_and_reset(hrpp, small_terrain):
     import torch
     tris, prim = small_terrain
