@@ -214,7 +214,8 @@ def test_serving_device_built_scenes(hrpp):
         prim[:, 7] = np.inf
         scenes.append(dict(tris=tris, bvh=bvh, sec=np.concatenate([sh, ao]), prim=prim))
     for sc in scenes[:2]:
-        sc["anyp"], sc["clp"] = [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)], [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)]
+        sc["anyp"] = [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)]
+        sc["clp"] = [hrpp.Predictor(sc["bvh"], 14, 8, 5, 6, 4096)]
     srv = hrpp.Server([(s["bvh"], s["anyp"], s["clp"]) for s in scenes[:2]], slots=2, pool_bytes=8 << 20)
 
     def request(k, i, index=None):
@@ -232,7 +233,8 @@ def test_serving_device_built_scenes(hrpp):
     # a third scene arrives while those run: built on the device, then added
     sc = scenes[2]
     sc["bvh"] = hrpp.BVH.build_on_device(_dev(sc["tris"]))
-    sc["anyp"], sc["clp"] = [hrpp.Predictor(sc["bvh"], 12, 4, 5, 6, 2048)], [hrpp.Predictor(sc["bvh"], 12, 4, 5, 6, 2048)]
+    sc["anyp"] = [hrpp.Predictor(sc["bvh"], 12, 4, 5, 6, 2048)]
+    sc["clp"] = [hrpp.Predictor(sc["bvh"], 12, 4, 5, 6, 2048)]
     with pytest.raises(hrpp.HrppError):          # a predictor that serves scene 0 (and indexes its tree)
         srv.add_scene(sc["bvh"], scenes[0]["anyp"], sc["clp"])
     with pytest.raises(hrpp.HrppError):          # no scene 2 yet

@@ -347,7 +347,8 @@ def test_full_size_policy(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     _, st = check_case(hrpp, "full primary paper, FIFO + resident, 2^12 x 4", tris, prim, query="closest",
-                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3, pq[4]), leaf_max=sg.AT_SCALE["leaf_max"])
+                       mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3, pq[4]),
+                           leaf_max=sg.AT_SCALE["leaf_max"])
     assert st["evictions"] > 0
 
 
@@ -444,7 +445,8 @@ def test_full_size_go_up(hrpp, full_terrain):
     tris, prim = full_terrain
     pq = w["primary_q"]
     check_case(hrpp, "full primary paper go-up 1", tris, prim, query="closest", mode="paper",
-               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3], 0, pq[4]), leaf_max=sg.AT_SCALE["leaf_max"])
+               pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3], 0, pq[4]),
+                   leaf_max=sg.AT_SCALE["leaf_max"])
 
 
 def test_import_validates_slots(hrpp, small_terrain):
@@ -642,11 +644,13 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
     pq, sq = (w["primary_q"], w["shadow_q"]) if tuned else ((5, 6, 1 << 17, 0, 0), (5, 6, 1 << 17, 0, 0))
     cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3], 0, pq[4])
     cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3], 0, sq[4])
-    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all, leaf_max=sg.AT_SCALE["leaf_max"])
+    _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all,
+                       leaf_max=sg.AT_SCALE["leaf_max"])
     assert st["rays"] == 1920 * 1080
     ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
-    check_case(hrpp, "full primary exact (plain)", tris, prim, query="closest", mode="exact", leaf_max=sg.AT_SCALE["leaf_max"])
+    check_case(hrpp, "full primary exact (plain)", tris, prim, query="closest", mode="exact",
+               leaf_max=sg.AT_SCALE["leaf_max"])
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
     check_case(hrpp, "full shadow plain", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"])
