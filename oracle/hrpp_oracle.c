@@ -886,11 +886,13 @@ write:
 /*     only its own key's records count.  If the stored tag differs from    */
 /*     the owner key, the tag is replaced and all slots emptied;            */
 /*  2. records with another key are discarded (conflicts);                 */
-/*  3. the owner key's ids not yet present are taken in increasing order.  */
+/*  3. the owner key's ids not yet present are taken in the order of the  */
+/*     smallest ray id that recorded each of them (the smallest ray id wins */
+/*     any conflict, so an earlier ray's leaf goes before a later ray's).   */
 /*     Without eviction (the paper: no replacement policy, section          */
 /*     "Precision and Recall") they fill the empty slots front to back and */
-/*     the rest are dropped.  With FIFO eviction (bit 0) the W smallest     */
-/*     enter at the back and the oldest slots at the front make room.       */
+/*     the rest are dropped.  With FIFO eviction (bit 0) the first W of     */
+/*     them enter at the back and the oldest slots at the front make room.  */
 /*     Every record whose id is absent from the final entry counts a drop.  */
 /* The future-work sections ask for a replacement policy; bits 0 and 1 are  */
 /* two simple, deterministic ones.                                          */
@@ -901,11 +903,6 @@ static int rec_ref_cmp(const void *pa, const void *pb)
     const rec_ref *a = (const rec_ref *)pa, *b = (const rec_ref *)pb;
     if (a->idx != b->idx) return a->idx < b->idx ? -1 : 1;
     return a->rid < b->rid ? -1 : (a->rid > b->rid);
-}
-static int u32_cmp(const void *pa, const void *pb)
-{
-    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
-    return a < b ? -1 : (a > b);
 }
 
 static void update_table(table *tb, const record *recs, uint32_t base, uint32_t count, uint64_t *st)
@@ -933,7 +930,9 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
         }
         uint32_t used = 0;
         while (used < W && slots[used] != NONE32) used++;
-        /* distinct owner-key leaves not already present */
+        /* distinct owner-key leaves not already present, each at the place
+           of the first (smallest ray id) record that names it: the records
+           of this entry are visited in increasing ray id */
         uint32_t nf = 0;
         for (uint32_t j = g; j < e; j++) {
             const record *r = &recs[refs[j].rid - base];
@@ -943,9 +942,8 @@ static void update_table(table *tb, const record *recs, uint32_t base, uint32_t 
             for (uint32_t f = 0; f < nf; f++) if (fresh[f] == r->leaf) present = 1;
             if (!present) fresh[nf++] = r->leaf;
         }
-        qsort(fresh, nf, sizeof(uint32_t), u32_cmp);
         if (tb->policy & 1u) {
-            /* FIFO: the oldest (front) slots make room for up to W new ids */
+            /* FIFO: the oldest (front) slots make room for the first W new ids */
             uint32_t take = nf < W ? nf : W;
             uint32_t evict = used + take > W ? used + take - W : 0;
             for (uint32_t s = 0; s + evict < used; s++) slots[s] = slots[s + evict];

@@ -753,7 +753,8 @@ def test_update_rule_capacity_hand_case():
         _, st = oracle.trace(b, tris, rays, query="closest", mode="exact", table=tb, epoch=30)
         entry = np.nonzero(tb.tags != EMPTY_TAG)[0]
         assert len(entry) == 1 and int(tb.tags[entry[0]]) == 8
-        kept = sorted(sq_leaf)[:W]                      # smallest leaf ids first, front to back
+        # leaves in the order of the first ray that reached each: squares 2, 0, 1
+        kept = [sq_leaf[2], sq_leaf[0], sq_leaf[1]][:W]
         assert tb.slots[entry[0]].tolist() == kept
         assert (st["records"], st["tag_claims"], st["leaf_inserts"], st["conflicts"]) == (30, 1, W, 0)
         assert st["dropped"] == sum(1 for q in squares if sq_leaf[q] not in kept)
@@ -762,8 +763,40 @@ def test_update_rule_capacity_hand_case():
     oracle.trace(b, tris, rays[squares == 0], query="closest", mode="exact", table=tb, epoch=1000)
     _, st = oracle.trace(b, tris, rays[squares != 0], query="closest", mode="exact", table=tb, epoch=1000)
     e = int(np.nonzero(tb.tags != EMPTY_TAG)[0][0])
-    assert tb.slots[e].tolist() == [sq_leaf[0], min(sq_leaf[1], sq_leaf[2])]
+    # the second call's first ray reaches square 2: its leaf takes the free slot
+    assert tb.slots[e].tolist() == [sq_leaf[0], sq_leaf[2]]
     assert st["tag_claims"] == 0 and st["leaf_inserts"] == 1 and st["positives"] == 20
+
+
+def _first_distinct(seq):
+    return list(dict.fromkeys(seq))
+
+
+@pytest.mark.parametrize("order", [(0, 1, 2), (2, 1, 0), (1, 2, 0), (2, 0, 2, 1), (1, 1, 0, 1, 2), (0, 2, 0, 1, 2)])
+def test_update_rule_earliest_ray_wins_a_full_entry(order):
+    # More distinct leaves than slots compete for one entry (one key, one
+    # epoch).  The smallest ray id wins any conflict: leaves enter in the order
+    # of the first ray that reached each, and the later ones are dropped.  A
+    # rule that fills by leaf id (the squares' leaf ids increase with the
+    # square) keeps 0, 1 whatever the order, and fails the orders that start
+    # with square 2 or reach square 2 before square 1.
+    tris, b, sq_leaf = _three_squares()
+    assert sq_leaf == sorted(sq_leaf)
+    squares = np.array(list(order) * 4)
+    rays = _rays_to_squares([-0.5, 1.0, 0.1], squares, 70 + len(order))
+    for W in (1, 2, 3):
+        tb = oracle.Table(4, W, 1, 1)
+        _, st = oracle.trace(b, tris, rays, query="closest", mode="exact", table=tb, epoch=len(squares))
+        e = int(np.nonzero(tb.tags != EMPTY_TAG)[0][0])
+        kept = [sq_leaf[q] for q in _first_distinct(order)][:W]
+        assert [x for x in tb.slots[e].tolist() if x != NONE32] == kept, (order, W)
+        assert st["leaf_inserts"] == len(kept)
+        assert st["dropped"] == sum(1 for q in squares if sq_leaf[q] not in kept)
+    # FIFO: the first W of them, in that order, as well
+    tb = oracle.Table(4, 2, 1, 1, policy=1)
+    oracle.trace(b, tris, rays, query="closest", mode="exact", table=tb, epoch=len(squares))
+    e = int(np.nonzero(tb.tags != EMPTY_TAG)[0][0])
+    assert tb.slots[e].tolist() == [sq_leaf[q] for q in _first_distinct(order)][:2]
 
 
 def test_update_rule_smallest_ray_id_owns_the_entry():
@@ -780,7 +813,7 @@ def test_update_rule_smallest_ray_id_owns_the_entry():
         assert int(tb.tags[1]) == owner and int(tb.tags[0]) == 0xFFFFFFFFFFFFFFFF
         n_owner = 5 if owner == 24 else 20
         assert st["conflicts"] == 25 - n_owner and st["tag_claims"] == 1
-        want = [sq_leaf[1]] if owner == 24 else sorted([sq_leaf[0], sq_leaf[2]])
+        want = [sq_leaf[1]] if owner == 24 else [sq_leaf[0], sq_leaf[2]]   # first reached first
         assert [x for x in tb.slots[1].tolist() if x != NONE32] == want
 
 
@@ -996,7 +1029,7 @@ def test_go_up_records_name_ancestors_of_exact_hits():
         drops = conflicts = 0
         for i, recs in groups.items():
             kstar = recs[0][1]
-            fresh = sorted({n for _, k, n in recs if k == kstar})
+            fresh = list(dict.fromkeys(n for _, k, n in recs if k == kstar))   # first record first
             want_tags[i] = kstar
             want_slots[i, :min(W, len(fresh))] = fresh[:W]
             drops += sum(1 for _, k, n in recs if k == kstar and n not in fresh[:W])
@@ -1122,8 +1155,9 @@ def test_fifo_eviction_hand_case():
     # epoch 3 square 0 again (each call is one epoch)
     tris, b, sq_leaf = _three_squares()
     r0 = _rays_to_squares([-0.5, 1.0, 0.1], np.array([0] * 6), 60)
-    r12 = _rays_to_squares([-0.5, 1.0, 0.1], np.array([1, 2] * 5), 61)
-    lo, hi = sorted(sq_leaf[1:])
+    # square 2 is reached first: its leaf (the larger id) goes first
+    r12 = _rays_to_squares([-0.5, 1.0, 0.1], np.array([2, 1] * 5), 61)
+    first, second = sq_leaf[2], sq_leaf[1]
     for policy in (0, 1):
         tb = oracle.Table(4, 2, 1, 1, policy=policy)
         oracle.trace(b, tris, r0, query="closest", mode="exact", table=tb, epoch=1000)
@@ -1131,19 +1165,19 @@ def test_fifo_eviction_hand_case():
         assert tb.slots[e].tolist() == [sq_leaf[0], NONE32]
         _, st = oracle.trace(b, tris, r12, query="closest", mode="exact", table=tb, epoch=1000)
         if policy == 0:
-            # no eviction: one free slot takes the smaller new leaf, the other is dropped
-            assert tb.slots[e].tolist() == [sq_leaf[0], lo]
+            # no eviction: one free slot takes the first reached new leaf, the other is dropped
+            assert tb.slots[e].tolist() == [sq_leaf[0], first]
             assert (st["leaf_inserts"], st["evictions"], st["dropped"]) == (1, 0, 5)
         else:
-            # FIFO: the oldest leaf (square 0) leaves, both new leaves enter in id order
-            assert tb.slots[e].tolist() == [lo, hi]
+            # FIFO: the oldest leaf (square 0) leaves, both new leaves enter in ray order
+            assert tb.slots[e].tolist() == [first, second]
             assert (st["leaf_inserts"], st["evictions"], st["dropped"]) == (2, 1, 0)
         _, st = oracle.trace(b, tris, r0, query="closest", mode="exact", table=tb, epoch=1000)
         if policy == 1:
-            assert tb.slots[e].tolist() == [hi, sq_leaf[0]]
+            assert tb.slots[e].tolist() == [second, sq_leaf[0]]
             assert (st["leaf_inserts"], st["evictions"]) == (1, 1)
         else:
-            assert tb.slots[e].tolist() == [sq_leaf[0], lo] and st["leaf_inserts"] == 0
+            assert tb.slots[e].tolist() == [sq_leaf[0], first] and st["leaf_inserts"] == 0
 
 
 def test_resident_tag_keeps_its_entry_hand_case():
