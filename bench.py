@@ -126,7 +126,8 @@ def kernel_source_hash():
 
 def short_kernel_name(name):
     for k in ("k_predict", "k_epoch_empty", "k_traverse_queue", "k_traverse_plain", "k_traverse_wide",
-              "k_update_classify", "k_update_apply", "k_update_finish", "k_fill32", "k_reset_table"):
+              "k_update_classify", "k_update_rank", "k_update_apply", "k_update_finish", "k_fill32",
+              "k_reset_table"):
         if k in name:
             return k
     return None

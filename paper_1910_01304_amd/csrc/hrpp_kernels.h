@@ -28,6 +28,14 @@ constexpr uint32_t kDefaultInlineLanes = 48;   // failing lanes of a wave that t
 // block b appends to sub-queue (b % kSubQueues), so with blocks of 128 rays a
 // sub-queue receives at most ceil(ceil(E/128) / kSubQueues) * 128 rays, which
 // never exceeds ceil(ceil(E/256) / kSubQueues) * 256.
+// Size of the per-epoch (claiming ray, id) set: the power of two >= 2 E, so
+// that it is at most half full.
+inline uint32_t pair_hash_bits_for(uint32_t epoch) {
+    uint32_t b = 1;
+    while ((1ull << b) < 2ull * epoch) b++;
+    return b;
+}
+
 inline uint32_t queue_subcap_for(uint32_t epoch) {
     const uint32_t blocks = (epoch + 255u) / 256u;
     return ((blocks + kSubQueues - 1u) / kSubQueues) * 256u;
@@ -66,8 +74,11 @@ struct TraceArgs {
     uint64_t *rec_key;
     uint32_t *rec_idx;
     uint32_t *rec_leaf;
-    uint32_t *rec_status;
-    uint32_t *topw;
+    uint32_t *rec_status;         // status | free slots << 2 | (hash slot + 1) << 8
+    uint64_t *topw;               // per claiming ray: W fresh (ray id << 32 | id), increasing
+    uint64_t *hkey;               // per-epoch set of (claiming ray - base) << 32 | id ...
+    uint32_t *hmin;               // ... with the smallest ray id that recorded the pair
+    uint32_t hash_bits;           // log2 of the set's size (>= 2 x the epoch)
 };
 
 // One job of a batch (see hrpp_batch_create): its arguments, ray count, epoch
@@ -96,7 +107,8 @@ void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<B
 
 enum KernelKind : int {
     kKindPredict, kKindTraverseQueue, kKindTraversePlain, kKindUpdateClassify, kKindUpdateApply,
-    kKindUpdateFinish, kKindFill, kKindTraverseWide, kKindEpochEmpty, kKindResetTable, kNumKernelKinds
+    kKindUpdateFinish, kKindFill, kKindTraverseWide, kKindEpochEmpty, kKindResetTable, kKindUpdateRank,
+    kNumKernelKinds
 };
 const char *kernel_kind_name(int k);
 void profile_start();

@@ -846,20 +846,33 @@ __global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t ba
 // K3: epoch-end update (section "HRPP Hash Function": a conflicting ray's
 // leaf is inserted into the existing entry unless already present; the paper
 // has no replacement policy, section "Precision and Recall").  Deterministic
-// batch form: the key of the smallest claiming ray id owns an entry touched
-// this epoch (with the resident policy only the resident key's records, or
-// any record for an empty entry, claim); the owner's new ids go into the free
-// slots in increasing id order and the rest are dropped, or, with FIFO
-// eviction, the W smallest enter at the back and the oldest slots make room.
-//   U1 (records): classify each record against the claim winner; collect the
-//       owner's fresh ids in a sorted, duplicate-free list (atomicMin
-//       insertion cascade, bounded by the room the entry has) kept per
-//       claiming ray.
-//   U2 (winning records): rewrite the entry, release the claim; an entry
-//       that was empty marks its group for the reset.
-//   U3 (records): count drops, clear the record slot, reset the queue count.
+// batch form in which the smallest ray id wins every conflict: the key of the
+// smallest claiming ray id owns an entry touched this epoch (with the
+// resident policy only the resident key's records, or any record for an
+// empty entry, claim); the owner's new ids enter the free slots in the order
+// of the smallest ray id that recorded each, and the rest are dropped, or,
+// with FIFO eviction, the first W of them enter at the back and the oldest
+// slots make room.
+//   U1 classify (records): classify each record against the claim winner; a
+//       fresh (owner, id) pair enters the epoch's pair set, which keeps the
+//       smallest ray id that recorded it (64-bit compare-and-swap on the pair,
+//       32-bit atomicMin on its ray id).
+//   U2 rank (records): the record holding its pair's smallest ray id inserts
+//       (ray id << 32 | id) into the owner's list of the entry's free-slot
+//       count smallest such values (64-bit atomicMin cascade); one record per
+//       id, so the list holds distinct ids in ray order.
+//   U3 apply (winning records): rewrite the entry, release the claim, clear
+//       the list and the pair set; an entry that was empty marks its group
+//       for the reset.
+//   U4 finish (records, with counters only): count drops, clear the record
+//       slot, reset the queue count.
 // ---------------------------------------------------------------------------
 enum : uint32_t { kRecConflict = 1, kRecPresent = 2, kRecFresh = 3 };
+constexpr uint64_t kNone64 = 0xFFFFFFFFFFFFFFFFull;
+
+__device__ __forceinline__ uint32_t pair_slot(uint64_t pair, uint32_t bits) {
+    return (uint32_t)((pair * 0x9E3779B97F4A7C15ull) >> (64u - bits));
+}
 
 template <bool STATS>
 __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
@@ -867,8 +880,8 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
     c.zero();
     const uint32_t i = bx * blockDim.x + threadIdx.x;
     const uint32_t W = a.ways;
-    // a fresh record's insertion: the owner's list and the id to insert
-    uint32_t ins_owner = kNone, ins_leaf = kNone, free_slots = 0;
+    // a fresh record's pair: the claiming ray and the id to insert
+    uint32_t ins_owner = kNone, ins_leaf = kNone, free_slots = 0, status = 0;
     if (i < count && a.rec_idx[i] != kNone) {
         const uint32_t idx = a.rec_idx[i];
         const uint32_t *e = entry_ptr(a, idx);
@@ -877,7 +890,6 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
         // of the epoch had another key than the resident tag
         const uint64_t kstar = owner == kNone ? ~a.rec_key[i] : a.rec_key[owner - base];
         const uint32_t leaf = a.rec_leaf[i];
-        uint32_t status;
         if (a.rec_key[i] != kstar) {
             status = kRecConflict;
             c.v[kConflicts]++;
@@ -906,35 +918,64 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
                 ins_leaf = leaf;
             }
         }
-        a.rec_status[i] = status;
     }
-    // Coherent rays give runs of identical (owner, id) insertions; inserting
-    // an id twice into a sorted duplicate-free list changes nothing, so a
-    // record whose neighbour lane carries the same pair leaves it to that lane.
+    // Record slots are ray ids: a record whose left neighbour lane carries the
+    // same (owner, id) pair has a larger ray id than that neighbour, so it is
+    // not its pair's first record and takes no further part.
     const uint32_t lane = __lane_id();
     const uint32_t prev_owner = __shfl_up(ins_owner, 1), prev_leaf = __shfl_up(ins_leaf, 1);
     const bool dup = lane > 0 && prev_owner == ins_owner && prev_leaf == ins_leaf;
-    if (ins_owner != kNone && !dup) {
-        // sorted insertion of the id into the owner's list of the free_slots
-        // smallest fresh ids; list values only ever decrease, so a plain read
-        // that is already <= x lets us skip the atomic at that position
-        uint32_t *list = a.topw + (size_t)(ins_owner - base) * W;
-        uint32_t x = ins_leaf;
-        for (uint32_t s = 0; s < free_slots && x != kNone; s++) {
-            const uint32_t seen = __hip_atomic_load(&list[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (seen == x) break;            // already listed
-            if (seen < x) continue;          // x cannot go here
-            const uint32_t old = atomicMin(&list[s], x);
-            if (old == x) break;
-            if (old > x) x = old;            // x took this place; carry the old value on
+    uint32_t hslot1 = 0;
+    if (ins_owner != kNone && !dup && free_slots > 0) {
+        // enter the pair into the set (linear probing; the set is at most half
+        // full, so a free or matching slot is always found) and lower its ray id
+        const uint64_t pair = ((uint64_t)(ins_owner - base) << 32) | ins_leaf;
+        const uint32_t mask = (1u << a.hash_bits) - 1u;
+        uint32_t h = pair_slot(pair, a.hash_bits);
+        for (;;) {
+            uint64_t k = __hip_atomic_load(&a.hkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k == kNone64) k = atomicCAS((unsigned long long *)&a.hkey[h], kNone64, (unsigned long long)pair);
+            if (k == kNone64 || k == pair) break;
+            h = (h + 1u) & mask;
         }
+        const uint32_t seen = __hip_atomic_load(&a.hmin[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen > base + i) atomicMin(&a.hmin[h], base + i);
+        hslot1 = h + 1u;
     }
+    if (i < count && status != 0) a.rec_status[i] = status | (free_slots << 2) | (hslot1 << 8);
     flush_counters<STATS>(c, a.stats);
 }
 
 template <bool STATS>
 __global__ __launch_bounds__(256) void k_update_classify(TraceArgs a, uint32_t base, uint32_t count) {
     body_update_classify<STATS>(a, base, count, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void body_update_rank(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
+    const uint32_t i = bx * blockDim.x + threadIdx.x;
+    if (i >= count || a.rec_idx[i] == kNone) return;
+    const uint32_t st = a.rec_status[i];
+    if ((st & 3u) != kRecFresh || (st >> 8) == 0) return;
+    const uint32_t h = (st >> 8) - 1u;
+    const uint32_t rid = base + i;
+    if (a.hmin[h] != rid) return;                      // a smaller ray id recorded the same pair
+    const uint32_t free_slots = (st >> 2) & 15u;
+    const uint32_t owner = entry_ptr(a, a.rec_idx[i])[2 + a.ways];
+    // sorted insertion into the owner's list of the free_slots smallest
+    // (ray id, id) values; list values only ever decrease, so a plain read that
+    // is already below x lets us skip the atomic at that position
+    uint64_t *list = a.topw + (size_t)(owner - base) * a.ways;
+    uint64_t x = ((uint64_t)rid << 32) | a.rec_leaf[i];
+    for (uint32_t s = 0; s < free_slots && x != kNone64; s++) {
+        const uint64_t seen = __hip_atomic_load(&list[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen < x) continue;                      // x cannot go here
+        const uint64_t old = atomicMin((unsigned long long *)&list[s], (unsigned long long)x);
+        if (old > x) x = old;                        // x took this place; carry the old value on
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update_rank(TraceArgs a, uint32_t base, uint32_t count) {
+    body_update_rank(a, base, count, blockIdx.x, gridDim.x);
 }
 
 template <bool STATS>
@@ -959,25 +1000,32 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
             } else {
                 while (used < W && e[2 + used] != kNone) used++;
             }
-            uint32_t *list = a.topw + (size_t)i * W;
+            uint64_t *list = a.topw + (size_t)i * W;
             if (a.policy & 1u) {
                 // FIFO: the oldest (front) slots make room for the new ids
                 uint32_t nf = 0;
-                while (nf < W && list[nf] != kNone) nf++;
+                while (nf < W && list[nf] != kNone64) nf++;
                 const uint32_t evict = used + nf > W ? used + nf - W : 0;
                 for (uint32_t s = 0; s + evict < used; s++) e[2 + s] = e[2 + s + evict];
                 used -= evict;
                 c.v[kEvictions] += evict;
             }
             for (uint32_t s = 0; s < W; s++) {
-                const uint32_t l = list[s];
-                if (l != kNone && used < W) {
-                    e[2 + used++] = l;
+                const uint64_t l = list[s];
+                if (l != kNone64 && used < W) {
+                    e[2 + used++] = (uint32_t)l;           // ids in increasing ray id
                     c.v[kLeafInserts]++;
                 }
-                list[s] = kNone;
+                list[s] = kNone64;
             }
             e[2 + W] = kNone;                          // release the claim
+        }
+        // the pair set is read no more in this epoch: empty this record's slot
+        // (every record of the pair writes the same values)
+        const uint32_t st = a.rec_status[i];
+        if ((st >> 8) != 0) {
+            a.hkey[(st >> 8) - 1u] = kNone64;
+            a.hmin[(st >> 8) - 1u] = kNone;
         }
         if (!STATS) a.rec_idx[i] = kNone;            // no drop count to take: retire the record now
     }
@@ -999,7 +1047,7 @@ __device__ __forceinline__ void body_update_finish(const TraceArgs &a, uint32_t 
     if (i < count && a.rec_idx[i] != kNone) {
         // a record of the owner key counts a drop if its id is not in the
         // final entry (with FIFO eviction this includes ids present before)
-        if (a.rec_status[i] != kRecConflict) {
+        if ((a.rec_status[i] & 3u) != kRecConflict) {
             const uint32_t *e = entry_ptr(a, a.rec_idx[i]);
             const uint32_t leaf = a.rec_leaf[i];
             bool present = false;
@@ -1057,6 +1105,14 @@ __global__ __launch_bounds__(256) void kb_update_classify(const BatchJob *__rest
     uint32_t base, count;
     if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
     body_update_classify<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void kb_update_rank(const BatchJob *__restrict__ jobs,
+                                                      const uint32_t *__restrict__ ids, uint32_t round) {
+    const BatchJob &J = jobs[ids[blockIdx.y]];
+    uint32_t base, count;
+    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
+    body_update_rank(J.a, base, count, blockIdx.x, gridDim.x);
 }
 
 template <bool STATS>
@@ -1174,7 +1230,8 @@ struct ProfScope {
 const char *kernel_kind_name(int k) {
     static const char *names[kNumKernelKinds] = {"k_predict", "k_traverse_queue", "k_traverse_plain",
                                                  "k_update_classify", "k_update_apply", "k_update_finish",
-                                                 "k_fill32", "k_traverse_wide", "k_epoch_empty", "k_reset_table"};
+                                                 "k_fill32", "k_traverse_wide", "k_epoch_empty", "k_reset_table",
+                                                 "k_update_rank"};
     return (k >= 0 && k < kNumKernelKinds) ? names[k] : "unknown";
 }
 
@@ -1242,6 +1299,10 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool
     {
         ProfScope p(kKindUpdateClassify, s);
         hipLaunchKernelGGL((k_update_classify<STATS>), dim3(g256), dim3(256), 0, s, a, base, count);
+    }
+    {
+        ProfScope p(kKindUpdateRank, s);
+        hipLaunchKernelGGL(k_update_rank, dim3(g256), dim3(256), 0, s, a, base, count);
     }
     {
         ProfScope p(kKindUpdateApply, s);
@@ -1349,6 +1410,7 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
         hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, false>), g256, dim3(256), 0, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_traverse_queue<ANY, EXACT, STATS>), g128, dim3(128), lds, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_update_classify<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+    hipLaunchKernelGGL(kb_update_rank, g256, dim3(256), 0, s, jobs, gid, r);
     hipLaunchKernelGGL((kb_update_apply<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
     if (STATS) hipLaunchKernelGGL((kb_update_finish<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
 }
