@@ -457,7 +457,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
         return false;
     }
     if (positive) c.v[kFalsePos]++;
-    return true;   // "re-added to the ray pool" (section "Precision and Recall")
+    return true;   // back to the pool of rays to traverse (section "Precision and Recall")
 }
 
 // Full traversal of ray `rid`.  HRPP: a fallback ray (already validated and
