@@ -228,6 +228,23 @@ hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const
                                   void *d_scratch, size_t scratch_bytes, void *d_buf, size_t bytes, void *stream,
                                   hrpp_bvh **out);
 
+/* The device build for callers that cannot allocate device memory (code
+ * under hipGraph capture, serving loops that take new scenes, harnesses that
+ * forbid hipMalloc): as hrpp_build_bvh_device, but the build scratch is a
+ * static device array of 64 MiB inside the library (one per GPU, held until
+ * the process ends) instead of a caller buffer.  The call allocates nothing:
+ * no hipMalloc, no hipFree, no allocating library routine.  The caller still
+ * passes the vertices and d_buf (>= hrpp_bvh_required_bytes, 256-byte
+ * aligned), which holds the BVH.  The scratch is free again when the call
+ * returns, so handles built by earlier calls stay valid; but every call on
+ * one GPU uses that GPU's one array, so calls that overlap on one GPU (from
+ * several host threads) race and must be serialised by the caller.  Errors
+ * as hrpp_build_bvh_device, plus ENOMEM when the build needs more than the
+ * static 64 MiB (hrpp_bvh_device_build_scratch_bytes(num_tris) > 64 MiB:
+ * about 470,000 triangles and more; then nothing is enqueued). */
+hrpp_status hrpp_build_bvh_device_static(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                         void *d_buf, size_t bytes, void *stream, hrpp_bvh **out);
+
 /* Node count, triangle count and maximum leaf depth of a built BVH. */
 hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *num_tris,
                           uint32_t *max_depth);

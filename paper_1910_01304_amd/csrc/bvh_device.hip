@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "hrpp_internal.h"
 #include "hrpp_kernels.h"
@@ -439,6 +440,37 @@ inline dim3 grid_for(size_t n, uint32_t block) { return dim3((uint32_t)((n + blo
 }  // namespace
 
 size_t lbvh_scratch_bytes(uint32_t n) { return n ? scratch_layout(n).total : 0; }
+
+// Build scratch of the entry point that allocates nothing: a file-scope
+// device array, one copy per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kStaticBuildScratchBytes];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxStaticDevices] = {};
+}  // namespace
+
+hipError_t lbvh_static_scratch(void **ptr) {
+    *ptr = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256) return hipErrorInvalidSymbol;
+        g_static_ptr[dev] = p;
+    }
+    *ptr = g_static_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, void *d_scratch,
                       const LbvhOut &out, hipStream_t s, LbvhResult *res) {

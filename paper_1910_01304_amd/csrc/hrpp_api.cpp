@@ -268,9 +268,10 @@ size_t hrpp_bvh_device_build_scratch_bytes(uint32_t num_tris) {
     return lbvh_scratch_bytes(num_tris);
 }
 
-hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
-                                  void *d_scratch, size_t scratch_bytes, void *d_buf, size_t bytes, void *stream,
-                                  hrpp_bvh **out) {
+// The device build on a given scratch region (both entry points below).
+static hrpp_status device_build(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                void *d_scratch, size_t scratch_bytes, void *d_buf, size_t bytes, void *stream,
+                                hrpp_bvh **out) {
     if (!out) return HRPP_EINVAL;
     *out = nullptr;
     if (!d_verts || !desc || !d_scratch || !d_buf || num_tris == 0 || num_tris >= (1u << 28)) return HRPP_EINVAL;
@@ -312,6 +313,25 @@ hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const
     b->d_wide = nullptr;
     *out = b;
     return HRPP_OK;
+}
+
+hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                  void *d_scratch, size_t scratch_bytes, void *d_buf, size_t bytes, void *stream,
+                                  hrpp_bvh **out) {
+    return device_build(d_verts, num_tris, desc, d_scratch, scratch_bytes, d_buf, bytes, stream, out);
+}
+
+hrpp_status hrpp_build_bvh_device_static(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
+                                         void *d_buf, size_t bytes, void *stream, hrpp_bvh **out) {
+    if (!out) return HRPP_EINVAL;
+    *out = nullptr;
+    if (num_tris == 0 || num_tris >= (1u << 28)) return HRPP_EINVAL;
+    const size_t need = lbvh_scratch_bytes(num_tris);
+    if (need == 0) return HRPP_EDEVICE;
+    if (need > kStaticBuildScratchBytes) return HRPP_ENOMEM;   // more triangles than the static scratch holds
+    void *d_scratch = nullptr;
+    if (lbvh_static_scratch(&d_scratch) != hipSuccess || !d_scratch) return HRPP_EDEVICE;
+    return device_build(d_verts, num_tris, desc, d_scratch, kStaticBuildScratchBytes, d_buf, bytes, stream, out);
 }
 
 hrpp_status hrpp_bvh_info(const hrpp_bvh *bvh, uint32_t *num_nodes, uint32_t *num_tris, uint32_t *max_depth) {

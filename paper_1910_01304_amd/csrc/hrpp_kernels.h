@@ -138,6 +138,10 @@ struct LbvhResult {
 };
 // Scratch bytes for n triangles (0 when the sort's size query fails).
 size_t lbvh_scratch_bytes(uint32_t n);
+// The device build's static scratch (one per GPU, kStaticBuildScratchBytes):
+// its device address on the current device, looked up on first use.
+constexpr size_t kStaticBuildScratchBytes = size_t(64) << 20;
+hipError_t lbvh_static_scratch(void **ptr);
 // Enqueues the build on `s` and synchronises it twice: once to read the
 // tree's depth (a tree deeper than max_depth, or a non-finite vertex, ends
 // the build there) and once at the end.

@@ -40,7 +40,7 @@ EXPORTED = [
     "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy", "hrpp_bvh_wide_info",
     "hrpp_bvh_wide_export", "hrpp_trace_wide_anyhit", "hrpp_trace_wide_closest",
     "hrpp_bvh_device_build_scratch_bytes", "hrpp_build_bvh_device", "hrpp_serve_add_scene",
-    "hrpp_serve_remove_scene",
+    "hrpp_serve_remove_scene", "hrpp_build_bvh_device_static",
 ]
 
 
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_bvh_device_build_scratch_bytes.restype = sz
     lib.hrpp_bvh_device_build_scratch_bytes.argtypes = [u32]
     lib.hrpp_build_bvh_device.argtypes = [vp, u32, vp, vp, sz, vp, sz, vp, C.POINTER(vp)]
+    lib.hrpp_build_bvh_device_static.argtypes = [vp, u32, vp, vp, sz, vp, C.POINTER(vp)]
     lib.hrpp_bvh_info.argtypes = [vp, C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
     lib.hrpp_bvh_export.argtypes = [vp, vp]
     lib.hrpp_bvh_destroy.argtypes = [vp]
@@ -188,8 +189,12 @@ class BVH:
             self.upload(device)
 
     @classmethod
-    def build_on_device(cls, verts: torch.Tensor, leaf_max: int = 4, max_depth: int = 64) -> "BVH":
-        """Linear BVH built on the GPU from a device tensor of [n, 9] (or [n, 3, 3]) float32 vertices."""
+    def build_on_device(cls, verts: torch.Tensor, leaf_max: int = 4, max_depth: int = 64,
+                        static_scratch: bool = False) -> "BVH":
+        """Linear BVH built on the GPU from a device tensor of [n, 9] (or [n, 3, 3]) float32 vertices.
+
+        static_scratch: build in the library's static scratch (hrpp_build_bvh_device_static) instead of a
+        scratch buffer allocated here."""
         lib = load_library()
         if not (isinstance(verts, torch.Tensor) and verts.is_cuda and verts.dtype == torch.float32):
             raise HrppError("build_on_device takes a float32 device tensor")
@@ -197,6 +202,20 @@ class BVH:
         self = cls.__new__(cls)
         self.num_tris = int(v.shape[0])
         self.desc = _BvhDesc(leaf_max, 32, max_depth)
+        if static_scratch:
+            # the library's static scratch: the build allocates no scratch
+            self.device_bytes = lib.hrpp_bvh_required_bytes(self.num_tris, C.byref(self.desc))
+            self._raw, self.buffer = _aligned(self.device_bytes, v.device)
+            h = C.c_void_p()
+            self.handle = None
+            _check(lib.hrpp_build_bvh_device_static(v.data_ptr(), self.num_tris, C.byref(self.desc),
+                                                    self.buffer.data_ptr(), self.device_bytes, _stream(),
+                                                    C.byref(h)), "hrpp_build_bvh_device_static")
+            self.handle = h
+            nn, nt, md = C.c_uint32(), C.c_uint32(), C.c_uint32()
+            _check(lib.hrpp_bvh_info(h, C.byref(nn), C.byref(nt), C.byref(md)), "hrpp_bvh_info")
+            self.num_nodes, self.max_depth = nn.value, md.value
+            return self
         need = lib.hrpp_bvh_device_build_scratch_bytes(self.num_tris)
         if need == 0:
             raise HrppError("hrpp_bvh_device_build_scratch_bytes: no scratch size (bad count or no device)")

@@ -1,0 +1,132 @@
+"""The device build that allocates nothing (hrpp_build_bvh_device_static).
+
+Its tree must equal, node for node and byte for byte, the tree the existing
+entry point hrpp_build_bvh_device builds from a caller scratch buffer, on
+two calls in a row, the second with fewer triangles than the first (the
+static scratch then still holds the first call's contents).  Traces over the
+two trees must give the same results and counters, a tree built before
+another call must stay usable after it, and a scene too large for the static
+scratch must be refused with ENOMEM.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+STATIC_BYTES = 64 << 20
+
+
+@pytest.fixture(scope="module")
+def hrpp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1910_01304_amd as h
+    h.load_library()
+    return h
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _dev(tris):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(tris, np.float32)).cuda()
+
+
+def _same_tree(a, b):
+    ea, eb = a.export(), b.export()
+    assert a.num_nodes == b.num_nodes and a.max_depth == b.max_depth
+    for k in ea:
+        assert np.array_equal(ea[k].view(np.uint32), eb[k].view(np.uint32)), k
+
+
+def _rays(tris, seed, n):
+    # shadow-like rays from points on the scene's triangles towards a small light above it
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = tris[rng.integers(0, len(tris), n)]
+    w = rng.random((n, 2), dtype=np.float32)
+    w = np.where(w.sum(1, keepdims=True) > 1, 1 - w, w)
+    p = t[:, 0] + w[:, :1] * (t[:, 1] - t[:, 0]) + w[:, 1:] * (t[:, 2] - t[:, 0])
+    lo, hi = tris.reshape(-1, 3).min(0), tris.reshape(-1, 3).max(0)
+    target = np.stack([lo[0] + (hi[0] - lo[0]) * rng.random(n), np.full(n, hi[1] + 0.5),
+                       lo[2] + (hi[2] - lo[2]) * rng.random(n)], 1).astype(np.float32)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, 0:3] = p + np.float32(1e-4) * np.array([0, 1, 0], np.float32)
+    rays[:, 3] = 0.0
+    rays[:, 4:7] = target - rays[:, 0:3]
+    rays[:, 7] = 1.0
+    return rays
+
+
+def _trace_both(hrpp, a, b, rays):
+    import torch
+    r = torch.from_numpy(rays).cuda()
+    sa, sb = hrpp.new_stats(), hrpp.new_stats()
+    oa = hrpp.trace_anyhit(a, None, r, stats=sa).cpu().numpy()
+    ob = hrpp.trace_anyhit(b, None, r, stats=sb).cpu().numpy()
+    r2 = r.clone()
+    r2[:, 7] = float("inf")
+    ha = hrpp.trace_closest(a, None, r2, mode="exact", stats=sa).cpu().numpy()
+    hb = hrpp.trace_closest(b, None, r2, mode="exact", stats=sb).cpu().numpy()
+    hrpp.get_error(a)
+    assert np.array_equal(oa, ob)
+    assert np.array_equal(ha.view(np.uint32), hb.view(np.uint32))
+    assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
+    return oa, ha
+
+
+def test_static_build_equals_scratch_build_twice(hrpp):
+    lib = hrpp.load_library()
+    big = sg.heightfield_scene(31, 300_000)          # first call: a large scene
+    small = sg.triangle_soup(32, 5_003)               # second call: fewer triangles, ragged count
+    for n in (len(big), len(small)):
+        need = lib.hrpp_bvh_device_build_scratch_bytes(n)
+        assert 0 < need <= STATIC_BYTES, (n, need)
+    _say(f"static device build 1: heightfield n={len(big)}")
+    a1 = hrpp.BVH.build_on_device(_dev(big), leaf_max=4, static_scratch=True)
+    b1 = hrpp.BVH.build_on_device(_dev(big), leaf_max=4)
+    _same_tree(a1, b1)
+    rays1 = _rays(big, 41, 20_000)
+    first = _trace_both(hrpp, a1, b1, rays1)
+    _say(f"static device build 2: soup n={len(small)}")
+    a2 = hrpp.BVH.build_on_device(_dev(small), leaf_max=2, static_scratch=True)
+    b2 = hrpp.BVH.build_on_device(_dev(small), leaf_max=2)
+    _same_tree(a2, b2)
+    _trace_both(hrpp, a2, b2, _rays(small, 42, 7_001))
+    # the first tree does not depend on the scratch after its call returned
+    _say("static device build: first tree after the second call")
+    again = _trace_both(hrpp, a1, b1, rays1)
+    assert np.array_equal(first[0], again[0])
+    assert np.array_equal(first[1].view(np.uint32), again[1].view(np.uint32))
+
+
+def test_static_build_refuses_oversize_and_bad_arguments(hrpp):
+    import torch
+    lib = hrpp.load_library()
+    # the smallest power of two whose scratch exceeds the static array
+    n = 1 << 16
+    while n < (1 << 24) and 0 < lib.hrpp_bvh_device_build_scratch_bytes(n) <= STATIC_BYTES:
+        n *= 2
+    assert lib.hrpp_bvh_device_build_scratch_bytes(n) > STATIC_BYTES, n
+    _say(f"static device build refuses n={n}")
+    import importlib
+    desc = importlib.import_module("paper_1910_01304_amd.hrpp")._BvhDesc(4, 32, 64)
+    need = lib.hrpp_bvh_required_bytes(n, C.byref(desc))
+    raw = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    buf = (raw.data_ptr() + 255) // 256 * 256
+    verts = torch.zeros((n, 9), dtype=torch.float32, device="cuda")
+    h = C.c_void_p()
+    st = lib.hrpp_build_bvh_device_static(verts.data_ptr(), n, C.byref(desc), buf, need, None, C.byref(h))
+    assert st == 2 and not h.value                   # HRPP_ENOMEM, no handle
+    st = lib.hrpp_build_bvh_device_static(None, 10, C.byref(desc), buf, need, None, C.byref(h))
+    assert st == 1 and not h.value                   # HRPP_EINVAL
+    st = lib.hrpp_build_bvh_device_static(verts.data_ptr(), 0, C.byref(desc), buf, need, None, C.byref(h))
+    assert st == 1 and not h.value
