@@ -267,13 +267,24 @@ size_t hrpp_predictor_table_bytes(const hrpp_predictor_desc *desc);
 
 /* Create a predictor bound to `bvh` (its hash grid spans the BVH's root
  * box) in d_buf (256-byte aligned), and enqueue its reset on `stream`.
+ * The predictor is the table of section "Overview" that maps a ray's hash
+ * to the leaf nodes earlier rays of that hash reached; its entries are
+ * filled as section "HRPP Hash Function" describes (a traversed ray's leaf
+ * joins its entry unless already there), here with the finite table, slot
+ * count and batch-synchronous epochs set by desc.  Section "Limit Study"
+ * keeps one such table per query type: create one for any-hit and one for
+ * closest-hit rays.
  * Errors: EINVAL (bad desc, hash_mode above 1 or a mode-1 precision out of
  * range, go_up_level above 64),
  * ENOMEM (bytes too small). */
 hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc *desc, void *d_buf,
                                   size_t bytes, void *stream, hrpp_predictor **out);
 
-/* Enqueue a reset: every entry empty (all bytes 0xFF).  The update marks
+/* Enqueue a reset: every entry empty (all bytes 0xFF), the state in which
+ * the predictor of section "Overview" starts, before any ray has reached a
+ * leaf (section "Limit Study" measures from such an empty table).  Ray
+ * queries that keep learning across calls (the frames or samples of one
+ * render) simply do not reset between them.  The update marks
  * each group of 16 entries in which it tags an empty entry, so a reset
  * rewrites only the marked groups (the whole table after creation, an import
  * or a failed launch).  The per-epoch scratch (fallback queue, records,
@@ -282,7 +293,9 @@ hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc
 hrpp_status hrpp_predictor_reset(hrpp_predictor *pred, void *stream);
 
 /* Copy the table to host memory after the work on `stream` (synchronises
- * the stream).  Layout per entry: uint64 tag (all-ones = empty), then
+ * the stream): the predictor's contents (section "HRPP Hash Function": per
+ * hash value, the leaf nodes recorded for it; the table's size is what
+ * section "Limit Study" reports in megabytes).  Layout per entry: uint64 tag (all-ones = empty), then
  * `ways` uint32 slots (0xFFFFFFFF = empty; at go-up level 0 a leaf id
  * (first_tri << 3) | (count - 1), at level g >= 1 the canonical depth-first
  * index of the node g levels above the leaf), then a uint32 claim word
@@ -304,16 +317,22 @@ void hrpp_predictor_destroy(hrpp_predictor *pred);
  * plain traversal; otherwise rays are processed in epochs of epoch_rays in
  * index order (the first one first_epoch_rays long): hash, lookup, test the
  * predicted leaves (stop at the first hit), traverse the rest, then update
- * the table.  The flag does not depend
- * on the predictor.  d_stats (may be NULL) is accumulated.  n == 0 is a
+ * the table -- the direct flow of section "Overview"; section "Precision
+ * and Recall" defines the outcomes: a hit in a predicted leaf is a true
+ * positive and ends the ray, any other positive and every negative traverse
+ * as usual.  Any hit is a valid answer for this query, so the flag does not
+ * depend on the predictor.  d_stats (may be NULL) is accumulated.  n == 0 is a
  * no-op.  Errors: EINVAL (null arrays with n > 0, n >= 2^31, predictor
- * built for another BVH). */
+ * built for another BVH, or a predictor whose last trace failed to launch
+ * and that has not been reset since). */
 hrpp_status hrpp_trace_anyhit(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint32_t n,
                               uint8_t *d_occluded, hrpp_stats *d_stats, void *stream);
 
 /* Closest-hit (hit-all) query.  mode HRPP_CLOSEST_PAPER: a positive ray
  * whose predicted leaves hold a hit returns the best hit among them and
- * skips traversal (the paper's semantics: it may not be the closest).
+ * skips traversal (the paper's semantics, section "Precision and Recall":
+ * a hit-all ray accepts a valid intersection in a predicted leaf, which may
+ * not be the closest one).
  * HRPP_CLOSEST_EXACT: the best predicted hit only seeds the traversal's
  * interval, so the result is always the closest hit (ties: smaller prim).
  * Other arguments as for hrpp_trace_anyhit. */
@@ -458,11 +477,21 @@ hrpp_status hrpp_serve_remove_scene(hrpp_server *server, uint32_t index);
 hrpp_status hrpp_serve_submit(hrpp_server *server, uint32_t scene, uint32_t query, const hrpp_ray *h_rays,
                               uint32_t n, void *h_out, uint64_t *request_id);
 
-/* Non-blocking state and timings of a request. */
+/* Non-blocking state and timings of a request.  The poll that reports a
+ * request done (state 2) is its final one: it retires the request, whose
+ * record is freed and whose id is unknown afterwards (EINVAL), so a server
+ * that runs for a long time holds only the requests not yet read. */
 hrpp_status hrpp_serve_poll(hrpp_server *server, uint64_t request_id, hrpp_request_info *info);
 
-/* Block until every submitted request is done; the first failed status, if any. */
+/* Block until every submitted request is done; the first failed status
+ * since the server was created, if any.  A failed request's slot and pool
+ * region are reused only after its stream has drained, and its predictor
+ * replica is reset if its trace did not launch. */
 hrpp_status hrpp_serve_wait_all(hrpp_server *server);
+
+/* Number of request records the server holds: queued, running, or done and
+ * not yet retired by a final poll. */
+hrpp_status hrpp_serve_held(hrpp_server *server, uint64_t *held);
 
 /* Largest pool occupancy seen so far (never above pool_bytes). */
 hrpp_status hrpp_serve_pool_peak(hrpp_server *server, size_t *peak_bytes);
@@ -479,6 +508,24 @@ void hrpp_serve_destroy(hrpp_server *server);
 typedef struct { char name[32]; uint64_t launches; double total_ms; } hrpp_kernel_time;
 hrpp_status hrpp_profile_start(void);
 hrpp_status hrpp_profile_stop(hrpp_kernel_time *out, uint32_t capacity, uint32_t *count);
+
+/* Measurement only: the distinct memory lines each kernel kind touches.
+ * After this call, every trace on `bvh` with predictor `pred` (NULL = plain
+ * traversal) that is given a stats pointer also marks, in the device bitmap
+ * d_bits, each 128-byte line of the scene and table arrays its kernels read
+ * or write (atomic ORs: counting runs become slower; traces without stats are
+ * unchanged).  The caller zeroes d_bits.  h_layout (11 words) receives the
+ * layout: [0] words per kernel-kind block; [1..5] word offsets, within a
+ * block, of the regions of interior nodes (64 B each), triangles (48 B), leaf
+ * boxes (32 B), table entries (32 or 64 B) and canonical node records
+ * (48 B); [6..10] the line count of each region.  Blocks follow each other
+ * in the order prediction kernel, first-epoch kernel, fallback-queue kernel,
+ * plain traversal kernel.  EINVAL if `words` is under 4 blocks or pred is
+ * bound to another BVH.  d_bits NULL switches the marking off (and, given
+ * bvh and h_layout, still writes the layout, to size a bitmap).  Process-
+ * global, not thread-safe. */
+hrpp_status hrpp_profile_touch(const hrpp_bvh *bvh, const hrpp_predictor *pred, uint32_t *d_bits, size_t words,
+                               uint32_t *h_layout);
 
 /* Synchronise `stream`; report HRPP_EDEVICE if a HIP error is pending and
  * HRPP_EDEPTH if a kernel tracing `bvh` (may be NULL) found a traversal

@@ -523,6 +523,36 @@ hrpp_status hrpp_predictor_import(hrpp_predictor *p, const void *h_src, size_t b
 void hrpp_predictor_destroy(hrpp_predictor *p) { delete p; }
 
 // Kernel arguments of one trace (shared by single calls and batches).
+// Touch bitmap of the measurement mode (hrpp_profile_touch): which BVH and
+// predictor it is for, and its layout.
+namespace {
+struct TouchState {
+    uint32_t *bits = nullptr;
+    size_t words = 0;
+    const hrpp_bvh *bvh = nullptr;
+    const hrpp_predictor *pred = nullptr;
+    uint32_t layout[1 + 2 * kTouchRegions] = {};
+};
+TouchState g_touch;
+
+// Block size and region offsets (words) of the touch bitmap for a BVH and
+// predictor: regions of 128-byte lines of the interior nodes, triangles, leaf
+// boxes, table entries and canonical nodes.
+void touch_layout(const hrpp_bvh *bvh, const hrpp_predictor *pred, uint32_t *out) {
+    const size_t bytes[kTouchRegions] = {
+        (size_t)bvh->num_interior * kNodeBytes, (size_t)bvh->num_tris * kTriBytes,
+        (size_t)bvh->num_tris * kLeafBoxBytes, pred ? pred->table_bytes : 0, (size_t)bvh->num_nodes * kCNodeBytes};
+    uint32_t off = 0;
+    for (int r = 0; r < kTouchRegions; r++) {
+        const uint32_t lines = (uint32_t)((bytes[r] + 127) / 128);
+        out[1 + r] = off;
+        out[1 + kTouchRegions + r] = lines;
+        off += (lines + 31) / 32;
+    }
+    out[0] = off;
+}
+}  // namespace
+
 static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp_ray *d_rays, uint8_t *d_occ,
                            hrpp_hit *d_hits, hrpp_stats *d_stats) {
     TraceArgs a{};
@@ -569,6 +599,11 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.hmin = pred->d_hmin;
         a.hash_bits = pair_hash_bits_for(d.epoch_rays);
     }
+    if (g_touch.bits && d_stats && g_touch.bvh == bvh && g_touch.pred == pred) {
+        a.touch = g_touch.bits;
+        a.touch_kind_words = g_touch.layout[0];
+        for (int r = 0; r < kTouchRegions; r++) a.touch_off[r] = g_touch.layout[1 + r];
+    }
     return a;
 }
 
@@ -588,6 +623,9 @@ static hrpp_status trace_common(const hrpp_bvh *bvh, hrpp_predictor *pred, const
                                 void *stream) {
     const hrpp_status st = check_trace_args(bvh, pred, d_rays, n, any, any ? (const void *)d_occ : d_hits);
     if (st != HRPP_OK || n == 0) return st;
+    // after a failed launch the epoch scratch (record list, claims, queue
+    // counts) may hold stale words: the predictor needs a reset first
+    if (pred && pred->scratch_dirty) return HRPP_EINVAL;
     const TraceArgs a = make_args(bvh, pred, d_rays, d_occ, d_hits, d_stats);
     const uint32_t epoch = pred ? pred->desc.epoch_rays : n;
     const uint32_t first = pred && pred->desc.first_epoch_rays ? pred->desc.first_epoch_rays : epoch;
@@ -754,6 +792,8 @@ static hrpp_status batch_launch(hrpp_batch *b, uint32_t use_graph, hipStream_t s
 
 hrpp_status hrpp_batch_launch(hrpp_batch *b, uint32_t use_graph, void *stream) {
     if (!b) return HRPP_EINVAL;
+    for (const hrpp_predictor *p : b->preds)
+        if (p->scratch_dirty) return HRPP_EINVAL;   // reset the predictor after a failed launch first
     const hrpp_status st = batch_launch(b, use_graph, static_cast<hipStream_t>(stream));
     for (hrpp_predictor *p : b->preds) {
         p->empty = false;
@@ -793,6 +833,29 @@ void hrpp_batch_destroy(hrpp_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     delete b;
+}
+
+hrpp_status hrpp_profile_touch(const hrpp_bvh *bvh, const hrpp_predictor *pred, uint32_t *d_bits, size_t words,
+                               uint32_t *h_layout) {
+    if (!d_bits) {
+        g_touch = TouchState{};
+        if (bvh && h_layout) {                    // the layout only, to size a bitmap
+            if (!bvh->d_nodes || (pred && pred->bvh_uid != bvh->uid)) return HRPP_EINVAL;
+            touch_layout(bvh, pred, h_layout);
+        }
+        return HRPP_OK;
+    }
+    if (!bvh || !bvh->d_nodes || (pred && pred->bvh_uid != bvh->uid)) return HRPP_EINVAL;
+    TouchState t;
+    touch_layout(bvh, pred, t.layout);
+    if (words < (size_t)kTouchKinds * t.layout[0]) return HRPP_EINVAL;
+    t.bits = d_bits;
+    t.words = words;
+    t.bvh = bvh;
+    t.pred = pred;
+    g_touch = t;
+    if (h_layout) std::memcpy(h_layout, t.layout, sizeof t.layout);
+    return HRPP_OK;
 }
 
 hrpp_status hrpp_profile_start(void) {

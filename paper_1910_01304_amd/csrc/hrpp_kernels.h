@@ -79,7 +79,16 @@ struct TraceArgs {
     uint64_t *hkey;               // per-epoch set of (claiming ray - base) << 32 | id ...
     uint32_t *hmin;               // ... with the smallest ray id that recorded the pair
     uint32_t hash_bits;           // log2 of the set's size (>= 2 x the epoch)
+    // measurement only (kernels with counters): a bitmap of the 128-byte lines
+    // of the scene and table arrays each kernel kind touched (null = off)
+    uint32_t *touch;
+    uint32_t touch_kind_words;    // words per kernel kind (kTouchKinds blocks)
+    uint32_t touch_off[5];        // word offset of each region within a block
 };
+
+// Regions and kernel kinds of the touch bitmap (hrpp_profile_touch).
+enum TouchRegion : int { kTouchNodes, kTouchTris, kTouchLeafbox, kTouchEntries, kTouchCnode, kTouchRegions };
+enum TouchKind : int { kTouchPredict, kTouchEmpty, kTouchQueue, kTouchPlain, kTouchKinds };
 
 // One job of a batch (see hrpp_batch_create): its arguments, ray count, epoch
 // size and the length of its first epoch (<= epoch).

@@ -151,11 +151,32 @@ __device__ __forceinline__ void hash_ray(const HashArgs &h, const RayState &r, u
 // ---------------------------------------------------------------------------
 struct Counters {
     uint32_t v[kNumStats];
+    uint32_t *touch;   // this kernel kind's block of the touch bitmap, or null
     __device__ void zero() {
 #pragma unroll
         for (int i = 0; i < kNumStats; i++) v[i] = 0;
+        touch = nullptr;
     }
 };
+
+// Measurement only: kernels with counters mark in a bitmap every 128-byte line
+// of the scene and table arrays they read or write, when the caller asked for
+// it (hrpp_profile_touch); without counters `touch` stays null and the marks
+// compile away.
+template <bool STATS>
+__device__ __forceinline__ void bind_touch(Counters &c, const TraceArgs &a, int kind) {
+    if constexpr (STATS)
+        if (a.touch != nullptr) c.touch = a.touch + (size_t)kind * a.touch_kind_words;
+}
+
+__device__ __forceinline__ void touch(const TraceArgs &a, const Counters &c, int region, size_t off, uint32_t len) {
+    if (c.touch == nullptr) return;
+    const size_t l1 = (off + len - 1) >> 7;
+    for (size_t l = off >> 7; l <= l1; l++) {
+        const size_t bit = (size_t)a.touch_off[region] * 32 + l;
+        atomicOr(&c.touch[bit >> 5], 1u << (bit & 31));
+    }
+}
 
 template <bool STATS>
 __device__ __forceinline__ void flush_counters(Counters &c, unsigned long long *stats) {
@@ -187,9 +208,11 @@ struct Best {
 // ANY: returns true at the first hit inside (tmin, tmax).  CLOSEST: keeps the
 // lexicographically smallest (t, prim) and returns true if it changed.
 template <bool ANY>
-__device__ __forceinline__ bool test_leaf(const float4 *__restrict__ tris, uint32_t leaf, const RayState &r,
-                                          Best &b, Counters &c) {
+__device__ __forceinline__ bool test_leaf(const TraceArgs &a, uint32_t leaf, const RayState &r, Best &b,
+                                          Counters &c) {
+    const float4 *__restrict__ tris = (const float4 *)a.tris;
     const uint32_t first = leaf >> 3, cnt = (leaf & 7u) + 1u;
+    touch(a, c, kTouchTris, (size_t)first * 48, cnt * 48);
     bool changed = false;
     for (uint32_t k = first; k < first + cnt; k++) {
         const float4 A = tris[3 * (size_t)k + 0];
@@ -234,12 +257,18 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
     const float4 *__restrict__ tris = (const float4 *)a.tris;
     float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
     bool found = (b.prim != kNone);
-    uint32_t sp = 0;
+    // sp nodes are deferred: the newest (entry sp - 1) is held in registers
+    // (top_ref, top_t), the older ones in the stack, so a pop takes its node
+    // without waiting for memory and the load of the next newest entry
+    // overlaps the work on the popped node
+    uint32_t sp = 0, top_ref = 0;
+    float top_t = 0.0f;
     for (;;) {
         c.v[kNodesVisited]++;
         if (!(ref & kLeafFlag)) {
             c.v[kInteriorVisited]++;
             c.v[kBoxTests] += 2;
+            touch(a, c, kTouchNodes, (size_t)ref * 64, 64);
             const float4 n0 = nodes[4 * (size_t)ref + 0];
             const float4 n1 = nodes[4 * (size_t)ref + 1];
             const float4 n2 = nodes[4 * (size_t)ref + 2];
@@ -253,8 +282,12 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
                 if (tr < tl) { push_ref = n3.x; push_t = tl; ref = n3.y; }
                 else         { push_ref = n3.y; push_t = tr; ref = n3.x; }
                 if (sp >= cap) { atomicOr(a.error, 1u); return found; }
-                stk_node[sp * stride] = push_ref;
-                if constexpr (!ANY) stk_t[sp * stride] = push_t;
+                if (sp > 0) {
+                    stk_node[(sp - 1) * stride] = top_ref;
+                    if constexpr (!ANY) stk_t[(sp - 1) * stride] = top_t;
+                }
+                top_ref = push_ref;
+                top_t = push_t;
                 sp++;
                 continue;
             }
@@ -262,7 +295,7 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
             if (hr) { ref = n3.y; continue; }
         } else {
             c.v[kLeafVisited]++;
-            if (test_leaf<ANY>(tris, ref & ~kLeafFlag, r, b, c)) {
+            if (test_leaf<ANY>(a, ref & ~kLeafFlag, r, b, c)) {
                 found = true;
                 if constexpr (ANY) return true;
                 tcur = b.t;
@@ -272,10 +305,17 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
         for (;;) {
             if (sp == 0) return found;
             sp--;
-            if constexpr (ANY) break;
-            else if (stk_t[sp * stride] <= tcur * far_pad()) break;
+            const uint32_t pref = top_ref;
+            const float pt = top_t;
+            if (sp > 0) {
+                top_ref = stk_node[(sp - 1) * stride];
+                if constexpr (!ANY) top_t = stk_t[(sp - 1) * stride];
+            }
+            if (ANY || pt <= tcur * far_pad()) {
+                ref = pref;
+                break;
+            }
         }
-        ref = stk_node[sp * stride];
     }
 }
 
@@ -299,11 +339,13 @@ __device__ __forceinline__ const uint32_t *cnode_ptr(const TraceArgs &a, uint32_
 
 // The node a record names: the result leaf (go-up level 0), or its ancestor
 // go_up levels up, stopping at the root.
-__device__ __forceinline__ uint32_t record_node(const TraceArgs &a, uint32_t leaf) {
+__device__ __forceinline__ uint32_t record_node(const TraceArgs &a, const Counters &c, uint32_t leaf) {
     if (a.go_up == 0) return leaf;
+    touch(a, c, kTouchLeafbox, (size_t)(leaf >> 3) * 32, 32);
     const float4 b1 = ((const float4 *)a.leafbox)[2 * (size_t)(leaf >> 3) + 1];
     uint32_t node = __float_as_uint(b1.w);
     for (uint32_t k = 0; k < a.go_up; k++) {
+        touch(a, c, kTouchCnode, (size_t)node * 48, 48);
         const uint32_t p = cnode_ptr(a, node)[8];
         if (p == kNone) break;
         node = p;
@@ -368,6 +410,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
     uint32_t idx;
     hash_ray(a.hash, r, key, idx);
     c.v[kLookups]++;
+    touch(a, c, kTouchEntries, (size_t)idx * a.entry_bytes, a.entry_bytes);
     const uint32_t *e = entry_ptr(a, idx);
     const uint64_t tag = *(const uint64_t *)e;
     const uint32_t W = a.ways;
@@ -386,6 +429,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
         for (uint32_t s = 0; s < W; s++) {
             const uint32_t node = e[2 + s];
             if (node == kNone) break;
+            touch(a, c, kTouchCnode, (size_t)node * 48, 48);
             const float4 *nb = (const float4 *)cnode_ptr(a, node);
             const float4 n0 = nb[0], n1 = nb[1];
             const float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
@@ -414,6 +458,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
         for (uint32_t s = 0; s < W; s++) {
             const uint32_t leaf = e[2 + s];
             if (leaf == kNone) break;
+            touch(a, c, kTouchLeafbox, (size_t)(leaf >> 3) * 32, 32);
             const float4 b0 = lbox[2 * (size_t)(leaf >> 3) + 0];
             const float4 b1 = lbox[2 * (size_t)(leaf >> 3) + 1];
             const float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
@@ -425,7 +470,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
             c.v[kLeafVisited]++;
             c.v[kPredLeafVisited]++;
             const uint32_t before = c.v[kTriTests];
-            const bool h = test_leaf<ANY>((const float4 *)a.tris, leaf, r, b, c);
+            const bool h = test_leaf<ANY>(a, leaf, r, b, c);
             c.v[kPredTriTests] += c.v[kTriTests] - before;
             if (h) {
                 hit = true;
@@ -450,6 +495,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
             c.v[kNodesSkipped] += skip_depth;
         } else {
             // the leaf's interior-ancestor count is stored with its box
+            touch(a, c, kTouchLeafbox, (size_t)(b.leaf >> 3) * 32, 32);
             const float4 b1 = ((const float4 *)a.leafbox)[2 * (size_t)(b.leaf >> 3) + 1];
             c.v[kNodesSkipped] += __float_as_uint(b1.z);
         }
@@ -489,10 +535,12 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
     write_result<ANY>(a, rid, hit, b);
     if (hit) c.v[kHits]++;
     if (HRPP) {
-        uint64_t key;
-        uint32_t idx;
-        hash_ray(a.hash, r, key, idx);
+        // the key is needed by a record (a hit) and by the EXACT positive check
+        uint64_t key = 0;
+        uint32_t idx = 0;
+        if (hit || (!ANY && EXACT)) hash_ray(a.hash, r, key, idx);
         if (!ANY && EXACT) {
+            touch(a, c, kTouchEntries, (size_t)idx * a.entry_bytes, a.entry_bytes);
             const uint32_t *e = entry_ptr(a, idx);
             const bool positive = (*(const uint64_t *)e == key) && (e[2] != kNone);
             if (positive) {
@@ -506,6 +554,7 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
                     if (a.go_up == 0) {
                         if (l == b.leaf) in_pred = true;
                     } else {
+                        touch(a, c, kTouchCnode, (size_t)l * 48, 48);
                         const uint32_t *cn = cnode_ptr(a, l);
                         const uint32_t first = b.leaf >> 3;
                         if (cn[9] <= first && first < cn[10]) in_pred = true;
@@ -519,7 +568,8 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
             const uint32_t slot = rid - base;
             a.rec_key[slot] = key;
             a.rec_idx[slot] = idx;
-            a.rec_leaf[slot] = record_node(a, b.leaf);
+            a.rec_leaf[slot] = record_node(a, c, b.leaf);
+            touch(a, c, kTouchEntries, (size_t)idx * a.entry_bytes, a.entry_bytes);
             uint32_t *e = (uint32_t *)entry_ptr(a, idx);
             // the smallest ray id claims the entry (with the resident policy only
             // a record of the resident key, or any record for an empty entry;
@@ -618,7 +668,7 @@ __device__ __forceinline__ bool traverse_wide(const TraceArgs &a, const RayState
             }
         } else {
             c.v[kLeafVisited]++;
-            if (test_leaf<ANY>(tris, ref & ~kLeafFlag, r, b, c)) {
+            if (test_leaf<ANY>(a, ref & ~kLeafFlag, r, b, c)) {
                 found = true;
                 if constexpr (ANY) return true;
                 tcur = b.t;
@@ -681,6 +731,7 @@ __device__ __forceinline__ void body_traverse_plain(const TraceArgs &a, uint32_t
     const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
+    bind_touch<STATS>(c, a, kTouchPlain);
     const uint32_t step = gx * blockDim.x;
     for (uint32_t i = bx * blockDim.x + threadIdx.x; i < count; i += step)
         traverse_one<ANY, false, false>(a, 0, i, kNone, c, stk_node, stk_t, stride, cap);
@@ -710,6 +761,7 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
     const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
+    bind_touch<STATS>(c, a, kTouchPredict);
     const uint32_t i = bx * blockDim.x + threadIdx.x;
     bool enq = false;
     uint32_t seed_leaf = kNone;
@@ -761,6 +813,7 @@ __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base,
     const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
+    bind_touch<STATS>(c, a, kTouchEmpty);
     const uint32_t step = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step) {
         const uint32_t rid = base + i;
@@ -802,6 +855,7 @@ __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t
     const uint32_t cap = a.stack_cap;            // the tree's depth, <= kMaxDepth
     Counters c;
     c.zero();
+    bind_touch<STATS>(c, a, kTouchQueue);
     // the sub-queue counts are final when this kernel starts (the prediction
     // kernel before it wrote them): one uniform read per wave
     static_assert(kSubQueues == 8, "the counts are read as two uint4");

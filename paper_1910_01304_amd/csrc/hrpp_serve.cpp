@@ -29,6 +29,7 @@
 
 #include "hrpp.h"
 #include "hrpp_internal.h"
+#include "pool_alloc.h"
 
 namespace {
 
@@ -48,50 +49,6 @@ struct Request {
     hipEvent_t done_event = nullptr;
     bool done = false;
     hrpp_status status = HRPP_OK;
-};
-
-// First-fit allocator over [0, size) with 256-byte granularity.
-class PoolAllocator {
-  public:
-    explicit PoolAllocator(size_t size) : size_(size) { free_[0] = size; }
-    bool alloc(size_t bytes, size_t &off) {
-        bytes = hrpp::align256(std::max<size_t>(bytes, 1));
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = hrpp::align256(std::max<size_t>(bytes, 1));
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-
-  private:
-    size_t size_, used_ = 0;
-    std::map<size_t, size_t> free_;
 };
 
 }  // namespace
@@ -116,10 +73,13 @@ struct hrpp_server {
     std::vector<hipStream_t> streams;
     std::vector<bool> slot_busy;
     char *d_pool = nullptr;
-    PoolAllocator pool;
+    hrpp::PoolAllocator pool;
     std::deque<Request *> queue;
     std::vector<Request *> running;
+    // every request not yet retired: queued, running, or done and not yet
+    // read by its final poll
     std::map<uint64_t, Request *> all;
+    hrpp_status first_error = HRPP_OK;   // first failed request since creation
     uint64_t next_id = 1;
     size_t peak_pool = 0;
     std::mutex mu;
@@ -175,6 +135,16 @@ struct hrpp_server {
     void finish(Request *r) {
         Scene &sc = scenes[r->scene];
         const int kind = r->query == 0 ? 0 : 1;
+        if (r->status != HRPP_OK) {
+            // a failed request may have copies or kernels in flight on its
+            // slot: let them end before its pool region, slot and replica are
+            // reused, and reset the replica if its trace did not launch
+            hipStream_t s = streams[r->slot];
+            (void)hipStreamSynchronize(s);
+            hrpp_predictor *p = sc.preds[kind][r->replica];
+            if (p->scratch_dirty && hrpp_predictor_reset(p, s) == HRPP_OK) (void)hipStreamSynchronize(s);
+            if (first_error == HRPP_OK) first_error = r->status;
+        }
         slot_busy[r->slot] = false;
         sc.busy[kind][r->replica] = false;
         pool.release(r->pool_off, r->ray_bytes + hrpp::align256(r->out_bytes) + 256);
@@ -194,7 +164,6 @@ struct hrpp_server {
                 Request *r = running[i];
                 const bool failed = r->status != HRPP_OK;
                 if (failed || !r->done_event || hipEventQuery(r->done_event) == hipSuccess) {
-                    if (failed && r->done_event) (void)hipEventSynchronize(r->done_event);
                     finish(r);
                     running[i] = running.back();
                     running.pop_back();
@@ -348,7 +317,7 @@ hrpp_status hrpp_serve_poll(hrpp_server *sv, uint64_t request_id, hrpp_request_i
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->all.find(request_id);
     if (it == sv->all.end()) return HRPP_EINVAL;
-    const Request *r = it->second;
+    Request *r = it->second;
     std::memset(info, 0, sizeof(*info));
     info->state = r->done ? 2u : (r->slot >= 0 ? 1u : 0u);
     info->status = r->status;
@@ -359,6 +328,10 @@ hrpp_status hrpp_serve_poll(hrpp_server *sv, uint64_t request_id, hrpp_request_i
     if (r->done) {
         info->latency_ms = ms(r->t_submit, r->t_done);
         info->service_ms = ms(r->t_admit, r->t_done);
+        // the final poll retires the request: its record is freed and its id
+        // is unknown from now on
+        sv->all.erase(it);
+        delete r;
     }
     return HRPP_OK;
 }
@@ -367,8 +340,13 @@ hrpp_status hrpp_serve_wait_all(hrpp_server *sv) {
     if (!sv) return HRPP_EINVAL;
     std::unique_lock<std::mutex> lk(sv->mu);
     sv->cv.wait(lk, [sv] { return sv->queue.empty() && sv->running.empty(); });
-    for (auto &kv : sv->all)
-        if (kv.second->status != HRPP_OK) return kv.second->status;
+    return sv->first_error;
+}
+
+hrpp_status hrpp_serve_held(hrpp_server *sv, uint64_t *held) {
+    if (!sv || !held) return HRPP_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    *held = sv->all.size();
     return HRPP_OK;
 }
 

@@ -40,7 +40,8 @@ EXPORTED = [
     "hrpp_serve_wait_all", "hrpp_serve_pool_peak", "hrpp_serve_destroy", "hrpp_bvh_wide_info",
     "hrpp_bvh_wide_export", "hrpp_trace_wide_anyhit", "hrpp_trace_wide_closest",
     "hrpp_bvh_device_build_scratch_bytes", "hrpp_build_bvh_device", "hrpp_serve_add_scene",
-    "hrpp_serve_remove_scene", "hrpp_build_bvh_device_static",
+    "hrpp_serve_remove_scene", "hrpp_build_bvh_device_static", "hrpp_serve_held",
+    "hrpp_profile_touch",
 ]
 
 
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_trace_wide_anyhit.argtypes = [vp, vp, u32, vp, vp, vp]
     lib.hrpp_trace_wide_closest.argtypes = [vp, vp, u32, vp, vp, vp]
     lib.hrpp_profile_stop.argtypes = [vp, u32, C.POINTER(u32)]
+    lib.hrpp_profile_touch.argtypes = [vp, vp, vp, sz, vp]
     lib.hrpp_batch_required_bytes.restype = sz
     lib.hrpp_batch_required_bytes.argtypes = [u32]
     lib.hrpp_batch_create.argtypes = [vp, u32, vp, sz, vp, C.POINTER(vp)]
@@ -141,6 +143,7 @@ def load_library(path: str = LIB_PATH):
     lib.hrpp_serve_poll.argtypes = [vp, C.c_uint64, vp]
     lib.hrpp_serve_wait_all.argtypes = [vp]
     lib.hrpp_serve_pool_peak.argtypes = [vp, C.POINTER(sz)]
+    lib.hrpp_serve_held.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.hrpp_serve_destroy.argtypes = [vp]
     lib.hrpp_serve_destroy.restype = None
     lib.hrpp_status_string.restype = C.c_char_p
@@ -412,6 +415,42 @@ def profile_start():
     _check(load_library().hrpp_profile_start(), "hrpp_profile_start")
 
 
+TOUCH_REGIONS = ("nodes", "tris", "leafbox", "entries", "cnode")
+TOUCH_KINDS = ("k_predict", "k_epoch_empty", "k_traverse_queue", "k_traverse_plain")
+
+
+def profile_touch(bvh: BVH | None, pred: Predictor | None = None):
+    """Mark the 128-byte lines that counting traces on (bvh, pred) touch (measurement only).
+
+    Returns a reader: read() gives {kernel kind: {region: distinct lines}} of the traces since the
+    last read and clears the bitmap.  profile_touch(None) stops the marking."""
+    lib = load_library()
+    if bvh is None:
+        _check(lib.hrpp_profile_touch(None, None, None, 0, None), "hrpp_profile_touch")
+        return None
+    layout = (C.c_uint32 * 11)()
+    ph = pred.handle if pred is not None else None
+    _check(lib.hrpp_profile_touch(bvh.handle, ph, None, 0, layout), "hrpp_profile_touch")
+    block = int(layout[0])
+    bits = torch.zeros(len(TOUCH_KINDS) * block, dtype=torch.int32, device="cuda")
+    _check(lib.hrpp_profile_touch(bvh.handle, ph, bits.data_ptr(), bits.numel(), layout), "hrpp_profile_touch")
+    offs = [int(layout[1 + r]) for r in range(len(TOUCH_REGIONS))]
+    lines = [int(layout[6 + r]) for r in range(len(TOUCH_REGIONS))]
+
+    def read() -> dict:
+        torch.cuda.synchronize()
+        words = bits.cpu().numpy().view(np.uint32).reshape(len(TOUCH_KINDS), block)
+        bits.zero_()
+        out = {}
+        for k, kind in enumerate(TOUCH_KINDS):
+            out[kind] = {}
+            for r, reg in enumerate(TOUCH_REGIONS):
+                w = words[k, offs[r]: offs[r] + (lines[r] + 31) // 32]
+                out[kind][reg] = int(np.unpackbits(w.view(np.uint8)).sum())
+        return out
+    return read
+
+
 def profile_stop() -> dict:
     """Stop timing; returns {kernel name: (launches, total ms)}."""
     arr = (_KernelTime * 16)()
@@ -525,10 +564,19 @@ class Server:
         return rid.value
 
     def poll(self, rid: int) -> dict:
+        """State and timings of a request; the poll that reports it done (state 2) retires it."""
         info = _RequestInfo()
         _check(load_library().hrpp_serve_poll(self.handle, rid, C.byref(info)), "hrpp_serve_poll")
+        if info.state == 2:
+            self._reqs.pop(rid, None)
         return dict(state=info.state, status=info.status, queue_ms=info.queue_ms, service_ms=info.service_ms,
                     latency_ms=info.latency_ms)
+
+    def held(self) -> int:
+        """Request records the server holds (queued, running, or done and not yet polled)."""
+        v = C.c_uint64()
+        _check(load_library().hrpp_serve_held(self.handle, C.byref(v)), "hrpp_serve_held")
+        return v.value
 
     def wait_all(self):
         _check(load_library().hrpp_serve_wait_all(self.handle), "hrpp_serve_wait_all")

@@ -243,9 +243,11 @@ def test_serving_device_built_scenes(hrpp):
     reqs += [request(2, i) for i in range(6)] + [request(0, 9)]
     # scene 1 leaves while its requests may still run: the call waits for them
     srv.remove_scene(1)
+    retired = set()
     for r in reqs:
         if r["scene"] == 1:
-            assert srv.poll(r["id"])["state"] == 2
+            assert srv.poll(r["id"])["state"] == 2   # this final poll retires the request
+            retired.add(r["id"])
     with pytest.raises(hrpp.HrppError):          # no new requests for a removed scene
         srv.submit(1, "any", reqs[0]["rays"], reqs[0]["out"])
     with pytest.raises(hrpp.HrppError):          # removed already
@@ -256,7 +258,8 @@ def test_serving_device_built_scenes(hrpp):
     srv.wait_all()
     for r in reqs:
         sc = scenes[r["scene"]]
-        assert srv.poll(r["id"])["state"] == 2
+        if r["id"] not in retired:
+            assert srv.poll(r["id"])["state"] == 2
         want, _ = oracle.trace(oracle.build_sah(sc["tris"]), sc["tris"], r["rays"].numpy(), query=r["query"],
                                mode="exact")
         assert r["out"].numpy().tobytes() == want.tobytes()
