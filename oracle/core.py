@@ -42,6 +42,10 @@ _lib = None
 def _L():
     global _lib
     if _lib is None:
+        alt = os.environ.get("HRPP_ORACLE_LIB")   # another build of the same source (a sanitizer build)
+        if alt:
+            _lib = C.CDLL(alt)
+            return _lib
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build_library(force=True)
         _lib = C.CDLL(_LIB)
