@@ -89,6 +89,8 @@ def parse():
                     help="inline_lanes of the batched and serving predictors (-1: the workload's default)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
+    ap.add_argument("--batch-rounds", type=int, default=8,
+                    help="batched workload: size each job's epoch for about this many rounds (0 = --batch-epoch)")
     ap.add_argument("--scene-leaf-max", type=int, default=2,
                     help="leaf size of the batched and serving scenes' BVHs (the at-scale scene uses its own)")
     ap.add_argument("--tune-queries", default="",
@@ -199,6 +201,64 @@ def timed(torch, fn, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) * 1e3 / steps
     return e0.elapsed_time(e1) / steps, wall
+
+
+# Algorithmic VALU lane-operations per unit of work, one per IEEE operation,
+# compare or select of the formulas the kernels evaluate (division counted as
+# one): a box slab test (6 sub, 6 mul, 6 min/max, 3 + 3 for the entry and exit
+# distances, 1 padding mul, 1 compare), a Moller-Trumbore test with its
+# interval and best-hit checks, the grid + octahedral hash, and a ray's
+# validation and reciprocal direction.
+OPS_BOX, OPS_TRI, OPS_HASH, OPS_RAY = 26, 55, 54, 15
+# fp32 VALU issue rate without packed math (packed FP32 is disabled in this
+# build): 256 CUs x 64 lanes per clock x 2.4 GHz; the 157.3 TFLOP/s vector
+# peak counts an FMA as 2 flops and a packed op as 2 lanes (x4).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def kernel_ops(kind, st_any, st_all):
+    """Algorithmic VALU lane-ops of one kernel kind over one step (both calls)."""
+    tot = 0
+    for st in (st_any, st_all):
+        q_trav, q_int, q_tri, q_rec = (st["queue_traversals"], st["queue_interior_visited"], st["queue_tri_tests"],
+                                       st["queue_records"])
+        e_rays, e_trav, e_int, e_tri, e_rec = (st["empty_rays"], st["empty_lookups"], st["empty_interior_visited"],
+                                               st["empty_tri_tests"], st["empty_records"])
+        if kind == "k_traverse_plain":
+            tot += (OPS_RAY * st["rays"] + OPS_BOX * (st["traversals"] + 2 * st["interior_visited"])
+                    + OPS_TRI * st["tri_tests"])
+        elif kind == "k_epoch_empty":
+            # a traversed ray is hashed again only for its record
+            tot += OPS_RAY * e_rays + OPS_BOX * (e_trav + 2 * e_int) + OPS_TRI * e_tri + OPS_HASH * e_rec
+        elif kind == "k_predict":
+            trav = st["traversals"] - q_trav - e_trav
+            tot += (OPS_RAY * (st["rays"] - e_rays)
+                    + OPS_HASH * (st["lookups"] - st["empty_lookups"] + st["records"] - q_rec - e_rec)
+                    + OPS_BOX * (trav + 2 * (st["interior_visited"] - q_int - e_int) + st["pred_box_tests"])
+                    + OPS_TRI * (st["tri_tests"] - q_tri - e_tri))
+        elif kind == "k_traverse_queue":
+            tot += OPS_RAY * q_trav + OPS_BOX * (q_trav + 2 * q_int) + OPS_TRI * q_tri + OPS_HASH * q_rec
+    return tot
+
+
+def kernel_stream_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
+    """The part of kernel_bytes that is streamed once (rays, results, queue and record
+    writes): compulsory as it stands, unlike the gathers of nodes, triangles, leaf boxes and
+    table entries, whose compulsory part is the distinct lines a launch touches."""
+    tot = 0
+    for st, n, out_b in ((st_any, n_any, 1), (st_all, n_all, 16)):
+        q_trav, q_rec = st["queue_traversals"], st["queue_records"]
+        e_rays, e_trav, e_rec = st["empty_rays"], st["empty_lookups"], st["empty_records"]
+        if kind == "k_traverse_plain":
+            tot += n * (RAY_B + out_b)
+        elif kind == "k_epoch_empty":
+            tot += e_rays * (RAY_B + out_b) + e_rec * 16
+        elif kind == "k_predict":
+            tot += ((n - e_rays) * RAY_B + st["pred_hits"] * out_b + q_trav * 8
+                    + (st["traversals"] - q_trav - e_trav) * out_b + (st["records"] - q_rec - e_rec) * 16)
+        elif kind == "k_traverse_queue":
+            tot += q_trav * (8 + RAY_B + out_b) + q_rec * 16
+    return tot
 
 
 def kernel_bytes(kind, st_any, st_all, entry_b, n_any, n_all):
@@ -320,6 +380,12 @@ def main():
         pred_any.reset()
         hrpp.trace_anyhit(bvh, pred_any, shadow_d, out=occ_out)
 
+    def primary_hrpp_exact():
+        # the same predictor and schedule, EXACT semantics (the prediction only
+        # seeds the interval): always the closest hit
+        pred_all.reset()
+        hrpp.trace_closest(bvh, pred_all, prim_d, mode="exact", out=hits_out)
+
     # the hit-all and hit-any queries are independent (separate predictors,
     # resident inputs): issue them on two streams so their epoch chains overlap
     s_a, s_b = torch.cuda.Stream(), torch.cuda.Stream()
@@ -388,7 +454,8 @@ def main():
         ms_plain, wall_plain = timed(torch, step_plain, args.steps, args.warmup)
     ms_wide = float("nan") if args.profile_only else timed(torch, step_wide, args.steps, args.warmup)[0]
     parts = {}
-    for name, fn in (("primary_hrpp", primary_hrpp), ("primary_plain", primary_plain),
+    for name, fn in (("primary_hrpp", primary_hrpp), ("primary_hrpp_exact", primary_hrpp_exact),
+                     ("primary_plain", primary_plain),
                      ("primary_wide", primary_wide), ("shadow_hrpp", shadow_hrpp), ("shadow_plain", shadow_plain),
                      ("shadow_wide", shadow_wide)):
         parts[name] = float("nan") if args.no_parts else timed(torch, fn, args.steps, 1)[0]
@@ -410,6 +477,20 @@ def main():
         hrpp.trace_anyhit(bvh, pred_any, shadow_d, out=occ_out, stats=st)
 
     h_sa, h_sb = counted(h_any, h_all)
+    # what PAPER semantics costs in accuracy: its primary hits (this untimed
+    # counted run) against the exact closest hits of the setup's plain trace
+    paper_h = hits_out.cpu().numpy()
+    differs = ((paper_h.view(np.uint32)[:, 3] != he.view(np.uint32)[:, 3])
+               | (paper_h.view(np.uint32)[:, 0] != he.view(np.uint32)[:, 0]))
+    t_rel = ((paper_h[differs, 0].astype(np.float64) - he[differs, 0].astype(np.float64))
+             / np.maximum(he[differs, 0].astype(np.float64), 1e-30))
+    paper_accuracy = {
+        "primaries_differing_from_exact": int(differs.sum()),
+        "fraction_differing_from_exact": round(float(differs.mean()), 6),
+        "mean_relative_t_excess_of_differing": round(float(t_rel.mean()), 6) if differs.any() else 0.0,
+        "max_relative_t_excess_of_differing": round(float(t_rel.max()), 6) if differs.any() else 0.0,
+        "never_nearer_than_exact": bool((t_rel >= 0).all()),
+    }
     p_sa, p_sb = counted(lambda st: hrpp.trace_anyhit(bvh, None, shadow_d, out=occ_out, stats=st),
                          lambda st: hrpp.trace_closest(bvh, None, prim_d, mode="paper", out=hits_out, stats=st))
     hrpp.get_error(bvh)
@@ -426,7 +507,11 @@ def main():
         pct_nodes_skipped=pct_saved("nodes_visited", h_sb, p_sb),
         pct_box_tests_skipped=pct_saved("box_tests", h_sb, p_sb),
         prediction_hit_rate=h_sb["pred_hits"] / n_prim, false_positive_rate=h_sb["false_pos"] / n_prim,
-        wide_plain_mrays_s=mrays(n_prim, parts["primary_wide"]))
+        wide_plain_mrays_s=mrays(n_prim, parts["primary_wide"]),
+        exact_hrpp_mrays_s=mrays(n_prim, parts["primary_hrpp_exact"]),
+        exact_speedup_vs_plain=(parts["primary_plain"] / parts["primary_hrpp_exact"]
+                                if not args.no_parts else None),
+        paper_accuracy=paper_accuracy)
     shadow_info = dict(
         rays=n_sh, query="any hit", hrpp_mrays_s=mrays(n_sh, parts["shadow_hrpp"]),
         plain_mrays_s=mrays(n_sh, parts["shadow_plain"]),
@@ -470,18 +555,53 @@ def main():
                 kernels[f"{label}:{k}"] = dict(launches_per_step=launches // reps, avg_us=avg_ms * 1e3,
                                                ms_per_step=total_ms / reps, bytes_per_launch=per_launch_b,
                                                gbs=per_launch_b / (avg_ms * 1e-3) / 1e9)
+        # compulsory traffic: the distinct 128-byte lines of nodes, triangles, leaf boxes, table
+        # entries and node records each kernel kind touched in one counted step, plus its
+        # streamed bytes (rays, results, queue and record writes)
+        lines = {}
+        for label, calls in (("hrpp", ((pred_all, h_all), (pred_any, h_any))),
+                             ("plain", ((None, lambda st: hrpp.trace_closest(bvh, None, prim_d, mode="paper",
+                                                                              out=hits_out, stats=st)),
+                                        (None, lambda st: hrpp.trace_anyhit(bvh, None, shadow_d, out=occ_out,
+                                                                             stats=st))))):
+            for pred, fn in calls:
+                read = hrpp.profile_touch(bvh, pred)
+                fn(hrpp.new_stats())
+                for kind, regs in read().items():
+                    lines[f"{label}:{kind}"] = lines.get(f"{label}:{kind}", 0) + sum(regs.values())
+            hrpp.profile_touch(None)
+        for key, d in kernels.items():
+            label, kind = key.split(":", 1)
+            sts = (h_sa, h_sb) if label == "hrpp" else (p_sa, p_sb)
+            per_launch = d["launches_per_step"] or 1
+            comp = (kernel_stream_bytes(kind, sts[0], sts[1], entry_b, n_sh, n_prim)
+                    + 128 * lines.get(key, 0)) / per_launch
+            ops = kernel_ops(kind, sts[0], sts[1]) / per_launch
+            d["compulsory_bytes_per_launch"] = comp
+            d["compulsory_gbs"] = comp / (d["avg_us"] * 1e-6) / 1e9
+            d["valu_ops_per_launch"] = ops
+            d["valu_tops"] = ops / (d["avg_us"] * 1e-6) / 1e12
         dom = max((k for k in kernels if k.startswith("hrpp:")), key=lambda k: kernels[k]["ms_per_step"])
         d = kernels[dom]
         kname = dom.split(":", 1)[1]
         traffic = load_traffic(kname, [cfg_all, cfg_any, dict(leaf_max=w["leaf_max"])])
-        roofline = {"bound": "hbm", "kernel": kname, "achieved": round(d["gbs"], 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["gbs"] / HBM_PEAK_GBS, 4),
+        hbm_frac = d["compulsory_gbs"] / HBM_PEAK_GBS
+        alu_frac = d["valu_tops"] / VALU_PEAK_TOPS
+        hbm = {"achieved": round(d["compulsory_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(hbm_frac, 4), "compulsory_bytes_per_launch": int(d["compulsory_bytes_per_launch"])}
+        alu = {"achieved": round(d["valu_tops"], 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+               "frac": round(alu_frac, 4), "ops_per_launch": int(d["valu_ops_per_launch"])}
+        # the nearer of the two ceilings bounds the kernel
+        main = ("alu", alu) if alu_frac >= hbm_frac else ("hbm", hbm)
+        roofline = {"bound": main[0], "kernel": kname, "achieved": main[1]["achieved"], "peak": main[1]["peak"],
+                    "unit": main[1]["unit"], "frac": main[1]["frac"],
                     "traffic": int(traffic) if traffic is not None else None,
-                    # the measured HBM bytes of a launch over its duration, against the same peak
+                    # the measured HBM bytes of a launch over its duration, against the HBM peak
                     "traffic_frac": (round(traffic / (d["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                      if traffic is not None else None),
-                    "avg_launch_us": round(d["avg_us"], 2),
-                    "algorithmic_bytes_per_launch": int(d["bytes_per_launch"])}
+                    "avg_launch_us": round(d["avg_us"], 2), "hbm": hbm, "alu": alu,
+                    # every node, triangle and entry read counted each time (mostly served by L2 and MALL)
+                    "logical_bytes_per_launch": int(d["bytes_per_launch"])}
 
     ref_info = None
     if args.reference_epoch:
@@ -599,7 +719,7 @@ def main():
                        prediction_hit_rate=a_h["pred_hits"] / ao.shape[0],
                        false_positive_rate=a_h["false_pos"] / ao.shape[0],
                        occluded_fraction=a_h["hits"] / ao.shape[0],
-                       wide_plain_mrays_s=mrays(ao.shape[0], ms_ao_w))
+                       wide_plain_mrays_s=mrays(ao.shape[0], ms_ao_w), hrpp_ms=ms_ao_h, plain_ms=ms_ao_p)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -646,7 +766,9 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_hrpp, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER) + shadow any-hit, "
+        "config": {"workload": "terrain 1M tris, 1920x1080 primary closest (PAPER semantics: lossy, "
+                               f"{100 * paper_accuracy['fraction_differing_from_exact']:.2f}% of primaries return "
+                               "a farther hit than the closest) + shadow any-hit, "
                                f"HRPP tables 2^20 x 8; hit-all q_o {pq[0]} q_d {pq[1]} first epoch {pq[4]} "
                                f"then epochs of {pq[2]}, inline lanes {pq[3]}; hit-any q_o {sq[0]} q_d {sq[1]} "
                                f"first epoch {sq[4]} then epochs of {sq[2]}, inline lanes {sq[3]} (autotuned)",
@@ -656,6 +778,11 @@ def main():
         "plain_mrays_s": round(mrays(rays_per_step, ms_plain), 2),
         "plain_ms_per_step": round(ms_plain, 4),
         "speedup_vs_plain": round(ms_plain / ms_hrpp, 4),
+        # the queries the metric names, each against plain traversal of the same rays
+        "shadow_speedup_vs_plain": (round(parts["shadow_plain"] / parts["shadow_hrpp"], 4)
+                                    if not args.no_parts else None),
+        "ao_speedup_vs_plain": (round(ao_info["plain_ms"] / ao_info["hrpp_ms"], 4) if ao_info else None),
+        "primary_exact_speedup_vs_plain": prim_info["exact_speedup_vs_plain"],
         "wide_plain_mrays_s": round(mrays(rays_per_step, ms_wide), 2),
         "speedup_vs_wide_plain": round(ms_wide / ms_hrpp, 4),
         "wall_ms_per_step": {"hrpp": round(wall_hrpp, 4), "plain": round(wall_plain, 4)},
@@ -1211,10 +1338,11 @@ def measure_scene_arrival(np, torch, hrpp, sg, bvh0, shadow0):
         pc = hrpp.Predictor(bvh2, 16, 8, 5, 7, 1 << 17)
         idx = srv.add_scene(bvh2, [pa], [pc])
         rid = srv.submit(idx, "any", rays2, out2)
-        while srv.poll(rid)["state"] != 2:
-            time.sleep(50e-6)
-        t1 = time.perf_counter()
         info = srv.poll(rid)
+        while info["state"] != 2:                # the poll that sees it done retires it
+            time.sleep(50e-6)
+            info = srv.poll(rid)
+        t1 = time.perf_counter()
         srv.wait_all()
         keep.append((bvh2, pa, pc))              # the server holds the scene until it is destroyed
         res.setdefault(builder, []).append(dict(build_ms=(t_built - t0) * 1e3, first_result_ms=(t1 - t0) * 1e3,
@@ -1472,11 +1600,43 @@ def run_batched(args, np, torch, hrpp, sg):
     del rays
     E = args.batch_epoch
     il = args.inline_lanes if args.inline_lanes >= 0 else BATCH_INLINE
-    preds = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6, epoch_rays=E,
-                            inline_lanes=il)
-             for b, sp in zip(bvhs, specs)]
+    # per scene: table size (2^16..2^20) and quantisation (q_o, q_d in 3..7) chosen by the
+    # autotuner on the scene's own rays; per job: an epoch sized so that every job takes
+    # about the same number of rounds (so the rounds stay full to the end instead of
+    # ending with the largest scenes alone), clamped to [2^14, 2^22]
+    from paper_1910_01304_amd import autotune
+    rounds_target = args.batch_rounds
+
+    def job_epoch(n):
+        e = 1 << 14
+        while e < (1 << 22) and e * rounds_target < n:
+            e <<= 1
+        return e
+
+    tuned = []
+    t_tune = time.perf_counter()
+    for k, (b, r) in enumerate(zip(bvhs, rays_d)):
+        ek = job_epoch(r.shape[0]) if rounds_target else E
+        res = autotune.tune(b, r, query="any", start=dict(log2_entries=18, ways=8, origin_bits=5, dir_bits=5,
+                                                           epoch_rays=ek, inline_lanes=il),
+                            space={"log2_entries": [16, 17, 18, 19, 20], "origin_bits": [3, 4, 5, 6, 7],
+                                   "dir_bits": [3, 4, 5, 6, 7]},
+                            knobs=("log2_entries", "origin_bits", "dir_bits"), rounds=1, reps=2)
+        tuned.append(dict(res.best, triangles=specs[k]["tris"], rays=int(r.shape[0]),
+                          pct_nodes_skipped=round(res.best_stats["pct_nodes_skipped"], 2)))
+    tune_s = time.perf_counter() - t_tune
+    log(f"batched: autotuned {len(tuned)} scenes in {tune_s:.1f} s")
+    preds = [hrpp.Predictor(b, **{k: v for k, v in c.items() if k in (
+                 "log2_entries", "ways", "origin_bits", "dir_bits", "epoch_rays", "inline_lanes")})
+             for b, c in zip(bvhs, tuned)]
+    # the untuned configuration of the same jobs, for comparison
+    preds_fixed = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6,
+                                  epoch_rays=E, inline_lanes=il)
+                   for b, sp in zip(bvhs, specs)]
     outs = [torch.empty(r.shape[0], dtype=torch.uint8, device="cuda") for r in rays_d]
     batch = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o) for b, p, r, o in zip(bvhs, preds, rays_d, outs)])
+    batch_fixed = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o)
+                              for b, p, r, o in zip(bvhs, preds_fixed, rays_d, outs)])
     plain = hrpp.Batch([dict(bvh=b, pred=None, rays=r, out=o) for b, r, o in zip(bvhs, rays_d, outs)])
 
     def reset_all():
@@ -1487,6 +1647,11 @@ def run_batched(args, np, torch, hrpp, sg):
         reset_all()
         batch.launch(use_graph=True)
 
+    def step_batch_fixed():
+        for p in preds_fixed:
+            p.reset()
+        batch_fixed.launch(use_graph=True)
+
     def step_sequential():
         reset_all()
         for b, p, r, o in zip(bvhs, preds, rays_d, outs):
@@ -1494,6 +1659,7 @@ def run_batched(args, np, torch, hrpp, sg):
 
     steps = max(1, args.steps // 2)
     ms_batch = timed(torch, step_batch, steps, 1)[0]
+    ms_batch_fixed = timed(torch, step_batch_fixed, steps, 1)[0]
     ms_seq = timed(torch, step_sequential, steps, 1)[0]
     ms_plain = timed(torch, lambda: plain.launch(use_graph=True), steps, 1)[0]
     ms_reset = timed(torch, reset_all, steps, 1)[0]
@@ -1517,9 +1683,9 @@ def run_batched(args, np, torch, hrpp, sg):
         torch.cuda.synchronize()
         dev_ms = (time.perf_counter() - t0) * 1e3
     log(f"batched: device build of {len(dev)} scenes {dev_ms:.1f} ms (host {build_s:.2f} s)")
-    dpreds = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6, epoch_rays=E,
-                             inline_lanes=il)
-              for b, sp in zip(dev, specs)]
+    dpreds = [hrpp.Predictor(b, **{k: v for k, v in c.items() if k in (
+                  "log2_entries", "ways", "origin_bits", "dir_bits", "epoch_rays", "inline_lanes")})
+              for b, c in zip(dev, tuned)]
     dbatch = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o) for b, p, r, o in zip(dev, dpreds, rays_d, outs)])
     dplain = hrpp.Batch([dict(bvh=b, pred=None, rays=r, out=o) for b, r, o in zip(dev, rays_d, outs)])
 
@@ -1536,11 +1702,15 @@ def run_batched(args, np, torch, hrpp, sg):
         "ms_per_step": round(ms_batch, 3), "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(specs)} scenes (soup/heightfield 50/50, 1e4-2e6 tris log-uniform), "
                                "rays 2^16-2^22 log-uniform per scene (60% shadow, 40% AO), any-hit, "
-                               f"tables 2^16-2^20 x 8, q 5/6, epoch {E}",
+                               "per-scene table size 2^16-2^20 x 8 and q_o, q_d 3-7 autotuned, epochs sized "
+                               f"for about {rounds_target} rounds per job",
                    "scenes": len(specs), "triangles": int(sum(sp["tris"] for sp in specs)), "rays": total,
-                   "bvh_leaf_max": args.scene_leaf_max},
-        "sequential_calls_mrays_s": round(total / (ms_seq * 1e-3) / 1e6, 2),
+                   "bvh_leaf_max": args.scene_leaf_max, "per_scene": tuned, "autotune_s": round(tune_s, 1)},
         "plain_batched_mrays_s": round(total / (ms_plain * 1e-3) / 1e6, 2),
+        "speedup_vs_plain": round(ms_plain / ms_batch, 4),
+        "untuned_batched_mrays_s": round(total / (ms_batch_fixed * 1e-3) / 1e6, 2),
+        "untuned_config": f"tables 2^16-2^20 (random) x 8, q 5/6, epoch {E} for every job",
+        "sequential_calls_mrays_s": round(total / (ms_seq * 1e-3) / 1e6, 2),
         "batch_speedup_vs_sequential": round(ms_seq / ms_batch, 3),
         "predictor_reset_ms": round(ms_reset, 3),
         "host_bvh_build_s": round(build_s, 2),

@@ -67,6 +67,47 @@ def test_kernel_bytes_split_adds_up():
         assert split == whole
 
 
+def test_kernel_ops_split_adds_up():
+    # the prediction, first-epoch and queue kernels together do the call's
+    # algorithmic VALU work: every ray's setup (a queued ray's again in the queue
+    # kernel), the hash of every non-empty lookup and of every record, every box
+    # test (root tests of the traversals, two per interior visit, the predicted
+    # boxes) and every triangle test
+    g = np.random.default_rng(8)
+    for _ in range(200):
+        sa, sb = random_counters(g), random_counters(g)
+        split = sum(bench.kernel_ops(k, sa, sb) for k in KINDS)
+        whole = 0
+        for st in (sa, sb):
+            whole += (bench.OPS_RAY * (st["rays"] + st["queue_traversals"])
+                      + bench.OPS_HASH * (st["lookups"] - st["empty_lookups"] + st["records"])
+                      + bench.OPS_BOX * (st["traversals"] + 2 * st["interior_visited"] + st["pred_box_tests"])
+                      + bench.OPS_TRI * st["tri_tests"])
+        assert split == whole
+
+
+def test_stream_bytes_are_part_of_the_logical_bytes():
+    # the streamed part (rays, results, queue and record writes) never exceeds the
+    # kernel's logical bytes, and equals them when nothing is gathered
+    g = np.random.default_rng(9)
+    for _ in range(100):
+        sa, sb = random_counters(g), random_counters(g)
+        for k in KINDS + ("k_traverse_plain",):
+            assert 0 <= bench.kernel_stream_bytes(k, sa, sb, 64, sa["rays"], sb["rays"]) <= bench.kernel_bytes(
+                k, sa, sb, 64, sa["rays"], sb["rays"])
+    st = {k: 0 for k in random_counters(np.random.default_rng(1))}
+    st.update(rays=10)
+    assert bench.kernel_stream_bytes("k_traverse_plain", st, st, 64, 10, 10) == bench.kernel_bytes(
+        "k_traverse_plain", st, st, 64, 10, 10)
+
+
+def test_valu_peak_from_unit_counts():
+    # 256 CUs x 64 fp32 lanes per clock x 2.4 GHz, a quarter of the 157.3 TFLOP/s
+    # vector peak (which counts an FMA as two flops and packed FP32 as two lanes)
+    assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-3
+    assert abs(4 * bench.VALU_PEAK_TOPS - 157.3) < 0.1
+
+
 def test_kernel_bytes_plain_and_update():
     st = {k: 0 for k in random_counters(np.random.default_rng(1))}
     st.update(rays=10, interior_visited=7, tri_tests=3, records=5)
