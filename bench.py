@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ao", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny configuration (256 triangles)")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-table shadow and AO measurements")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement that gives the line its p99 latency")
     ap.add_argument("--no-rowmajor", action="store_true", help="skip the row-major ray order measurement")
@@ -103,6 +105,8 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--serve-slots", type=int, default=8, help="stream slots of the server")
     ap.add_argument("--serve-replicas", type=int, default=2, help="predictor replicas per scene and query kind")
+    ap.add_argument("--probe", default="step", choices=("step", "ao"),
+                    help="--traffic-probe workload: the at-scale step's queries, or the incoherent AO rays")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 256 MiB calibration copy, then one HRPP and one plain step (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -429,10 +433,26 @@ def main():
         torch.cuda.synchronize()
         y.copy_(x)
         torch.cuda.synchronize()
-        primary_hrpp()
-        shadow_hrpp()
-        primary_plain()
-        shadow_plain()
+        if args.probe == "ao":
+            # the incoherent AO workload, HRPP then plain, once each
+            wi = sg.INCOHERENT
+            cam_rays, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
+            hh = hrpp.trace_closest(bvh, None, torch.from_numpy(cam_rays).cuda(), mode="exact").cpu().numpy()
+            ao = sg.ao_rays_from_hits(tris, cam_rays, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
+                                      samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
+            ao_d = torch.from_numpy(ao).cuda()
+            ao_out = torch.empty(ao.shape[0], dtype=torch.uint8, device="cuda")
+            pred_ao = hrpp.Predictor(bvh, log2_entries=wi["log2_entries"], ways=wi["ways"],
+                                     origin_bits=wi["origin_bits"], dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"],
+                                     inline_lanes=wi["inline_lanes"], first_epoch_rays=wi["first_epoch"])
+            torch.cuda.synchronize()
+            hrpp.trace_anyhit(bvh, pred_ao, ao_d, out=ao_out)
+            hrpp.trace_anyhit(bvh, None, ao_d, out=ao_out)
+        else:
+            primary_hrpp()
+            shadow_hrpp()
+            primary_plain()
+            shadow_plain()
         torch.cuda.synchronize()
         log("traffic probe done")
         return
@@ -441,6 +461,8 @@ def main():
         args.no_parts = True
         args.no_cpu_baseline = True
         args.no_ao = True
+        args.no_tiny = True
+        args.no_warm = True
         args.no_progressive = True
         args.no_serving = True
         args.no_rowmajor = True
@@ -518,7 +540,18 @@ def main():
         pct_nodes_skipped=pct_saved("nodes_visited", h_sa, p_sa),
         pct_box_tests_skipped=pct_saved("box_tests", h_sa, p_sa),
         prediction_hit_rate=h_sa["pred_hits"] / n_sh, false_positive_rate=h_sa["false_pos"] / n_sh,
-        occluded_fraction=h_sa["hits"] / n_sh, wide_plain_mrays_s=mrays(n_sh, parts["shadow_wide"]))
+        occluded_fraction=h_sa["hits"] / n_sh, wide_plain_mrays_s=mrays(n_sh, parts["shadow_wide"]),
+        update={k: h_sa[k] for k in ("records", "tag_claims", "leaf_inserts", "dropped", "conflicts")})
+    if not args.no_parts and not args.no_warm:
+        # warm tables: the hit-any predictor is kept across frames of new light samples
+        # (one epoch per frame), as a renderer that does not reset it between frames
+        frames = [torch.from_numpy(sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32),
+                                                            seed=w["seed"] + 100 + k, light_center=w["light_center"],
+                                                            light_size=w["light_size"])).cuda()
+                  for k in range(4)]
+        shadow_info["warm"] = measure_warm(args, torch, hrpp, bvh, frames, "any",
+                                           dict(cfg_any, epoch_rays=1 << 21, first_epoch_rays=0))
+        del frames
     nodes_h = h_sa["nodes_visited"] + h_sb["nodes_visited"]
     nodes_p = p_sa["nodes_visited"] + p_sb["nodes_visited"]
     box_h = h_sa["box_tests"] + h_sb["box_tests"]
@@ -719,7 +752,51 @@ def main():
                        prediction_hit_rate=a_h["pred_hits"] / ao.shape[0],
                        false_positive_rate=a_h["false_pos"] / ao.shape[0],
                        occluded_fraction=a_h["hits"] / ao.shape[0],
-                       wide_plain_mrays_s=mrays(ao.shape[0], ms_ao_w), hrpp_ms=ms_ao_h, plain_ms=ms_ao_p)
+                       wide_plain_mrays_s=mrays(ao.shape[0], ms_ao_w), hrpp_ms=ms_ao_h, plain_ms=ms_ao_p,
+                       # what the epoch updates handle: records and their outcomes
+                       update={k: a_h[k] for k in ("records", "tag_claims", "leaf_inserts", "dropped",
+                                                   "conflicts")})
+        if not args.no_warm:
+            # warm tables: new AO directions per frame, the predictor kept (epochs of 2^22)
+            frames = [torch.from_numpy(sg.ao_rays_from_hits(tris, cam_rays, hh[:, 0], hh[:, 3].view(np.uint32),
+                                                            seed=wi["seed"] + 100 + k, samples=wi["samples"],
+                                                            tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))).cuda()
+                      for k in range(3)]
+            ao_info["warm"] = measure_warm(args, torch, hrpp, bvh, frames, "any",
+                                           dict(log2_entries=wi["log2_entries"], ways=wi["ways"],
+                                                origin_bits=wi["origin_bits"], dir_bits=wi["dir_bits"],
+                                                epoch_rays=1 << 22, inline_lanes=wi["inline_lanes"]))
+            del frames
+
+    # the tiny configuration: 256 triangles, 4,096 shadow rays, epochs of 256 rays
+    # (16 epochs, each a launch sequence: launch latency is the whole cost at this size)
+    tiny_info = None
+    if not args.no_tiny:
+        ttris, trays = sg.tiny_workload()
+        tw = sg.TINY
+        tbvh = hrpp.BVH(ttris, leaf_max=4)
+        tpred = hrpp.Predictor(tbvh, tw["log2_entries"], tw["ways"], tw["origin_bits"], tw["dir_bits"], tw["epoch"])
+        tr_d = torch.from_numpy(trays).cuda()
+        tocc = torch.empty(trays.shape[0], dtype=torch.uint8, device="cuda")
+
+        def tiny_hrpp():
+            tpred.reset()
+            hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc)
+
+        ms_t_h = timed(torch, tiny_hrpp, args.steps, 2)[0]
+        ms_t_p = timed(torch, lambda: hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc), args.steps, 2)[0]
+        tsh, tsp = hrpp.new_stats(), hrpp.new_stats()
+        tpred.reset()
+        hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc, stats=tsh)
+        hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc, stats=tsp)
+        th, tp = hrpp.stats_dict(tsh), hrpp.stats_dict(tsp)
+        nt = trays.shape[0]
+        tiny_info = dict(rays=nt, query="any hit", epoch_rays=tw["epoch"], hrpp_mrays_s=round(mrays(nt, ms_t_h), 2),
+                         plain_mrays_s=round(mrays(nt, ms_t_p), 2), hrpp_ms=round(ms_t_h, 4),
+                         plain_ms=round(ms_t_p, 4), pct_nodes_skipped=round(pct_saved("nodes_visited", th, tp), 3),
+                         pct_box_tests_skipped=round(pct_saved("box_tests", th, tp), 3),
+                         prediction_hit_rate=round(th["pred_hits"] / nt, 4),
+                         occluded_fraction=round(th["hits"] / nt, 4))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -754,6 +831,23 @@ def main():
         t1 = time.perf_counter() - c0
         cpu["single_thread"] = {"value": round(rays_per_step / t1 / 1e6, 3), "cores": 1,
                                 "sample": f"one full step, {t1:.2f} s"}
+        if tiny_info is not None:
+            # the tiny configuration on the host: the same rays, epochs and table
+            tob = oracle.build_sah(ttris, leaf_max=4)
+            tvtx = oracle.bvh_vertices(ttris, tob)
+            tt = {}
+            for nth in (1, threads):
+                reps = []
+                while len(reps) < 5 or (sum(reps) < 1.0 and len(reps) < 200):
+                    ttb = oracle.Table(tw["log2_entries"], tw["ways"], tw["origin_bits"], tw["dir_bits"])
+                    c0 = time.perf_counter()
+                    oracle.trace(tob, ttris, trays, query="any", table=ttb, epoch=tw["epoch"], vtx=tvtx,
+                                 nthreads=nth)
+                    reps.append(time.perf_counter() - c0)
+                tt[nth] = statistics.median(reps)
+            cpu["tiny"] = {"value": round(trays.shape[0] / tt[threads] / 1e6, 3), "cores": threads,
+                           "single_thread": round(trays.shape[0] / tt[1] / 1e6, 3), "unit": "Mrays/s",
+                           "sample": "the tiny configuration (4,096 shadow rays, 16 epochs), median of runs"}
 
     serve = None
     if not args.no_serving:
@@ -789,7 +883,7 @@ def main():
         "table_bytes": {"hit_all": int(pred_all.table_bytes), "hit_any": int(pred_any.table_bytes)},
         "pct_nodes_skipped": round(100.0 * (1 - nodes_h / nodes_p), 3),
         "pct_box_tests_skipped": round(100.0 * (1 - box_h / box_p), 3),
-        "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "reference_epoch": ref_info,
+        "primary": prim_info, "shadow": shadow_info, "ao": ao_info, "tiny": tiny_info, "reference_epoch": ref_info,
         "progressive": prog_info, "row_major_order": row_info,
         "kernels": kernels, "roofline": roofline, "cpu_baseline": cpu,
         "p99_latency_ms": serve["value"] if serve else None,
@@ -797,6 +891,39 @@ def main():
                      "results": serve["results"], "workload": serve["config"]["workload"]} if serve else None),
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_warm(args, torch, hrpp, bvh, frames, query, cfg):
+    """HRPP with tables kept across frames against plain traversal of the same frames.
+    The first frame fills the table (untimed); each timed trace takes the next frame of
+    the others in turn, on the table the previous traces left."""
+    pred = hrpp.Predictor(bvh, **cfg)
+    out = torch.empty(frames[0].shape[0], dtype=torch.uint8, device="cuda")
+    pred.reset()
+    hrpp.trace_anyhit(bvh, pred, frames[0], out=out)
+    k = [0]
+
+    def warm():
+        k[0] = k[0] % (len(frames) - 1) + 1
+        hrpp.trace_anyhit(bvh, pred, frames[k[0]], out=out)
+
+    def plain():
+        k[0] = k[0] % (len(frames) - 1) + 1
+        hrpp.trace_anyhit(bvh, None, frames[k[0]], out=out)
+
+    n = frames[0].shape[0]
+    ms_h = timed(torch, warm, args.steps, 1)[0]
+    ms_p = timed(torch, plain, args.steps, 1)[0]
+    sh, sp = hrpp.new_stats(), hrpp.new_stats()
+    hrpp.trace_anyhit(bvh, pred, frames[1], out=out, stats=sh)
+    hrpp.trace_anyhit(bvh, None, frames[1], out=out, stats=sp)
+    h, p = hrpp.stats_dict(sh), hrpp.stats_dict(sp)
+    return dict(frames=len(frames), epoch_rays=cfg["epoch_rays"], hrpp_mrays_s=round(n / ms_h / 1e3, 2),
+                plain_mrays_s=round(n / ms_p / 1e3, 2), speedup_vs_plain=round(ms_p / ms_h, 4),
+                pct_nodes_skipped=round(100.0 * (1 - h["nodes_visited"] / p["nodes_visited"]), 3),
+                prediction_hit_rate=round(h["pred_hits"] / n, 4), false_positive_rate=round(h["false_pos"] / n, 4),
+                records=h["records"], note="table kept across frames of new samples, one epoch per 2^21/2^22 rays, "
+                                           "no reset")
 
 
 def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, hits_out, occ_out, on_two_streams,
@@ -1624,6 +1751,8 @@ def run_batched(args, np, torch, hrpp, sg):
                             knobs=("log2_entries", "origin_bits", "dir_bits"), rounds=1, reps=2)
         tuned.append(dict(res.best, triangles=specs[k]["tris"], rays=int(r.shape[0]),
                           pct_nodes_skipped=round(res.best_stats["pct_nodes_skipped"], 2)))
+        log(f"batched: scene {k} ({specs[k]['tris']} tris, {r.shape[0]} rays): T {res.best['log2_entries']} "
+            f"q_o {res.best['origin_bits']} q_d {res.best['dir_bits']} epoch {res.best['epoch_rays']}")
     tune_s = time.perf_counter() - t_tune
     log(f"batched: autotuned {len(tuned)} scenes in {tune_s:.1f} s")
     preds = [hrpp.Predictor(b, **{k: v for k, v in c.items() if k in (

@@ -762,7 +762,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
     b->d_ids = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)));
     uint32_t *d_off = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)) +
                                                    align256((size_t)njobs * sizeof(uint32_t)));
-    // plain groups: blocks in proportion to each job's rays (about 8 rays per lane)
+    // plain groups: one lane per ray of each job
     std::vector<uint32_t> offs;
     for (BatchGroup &g : b->groups) {
         if (g.kind != kBatchAnyPlain && g.kind != kBatchClosestPlain) continue;
@@ -770,7 +770,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
         uint32_t acc = 0;
         for (uint32_t k = 0; k < g.count; k++) {
             offs.push_back(acc);
-            acc += std::max(1u, (b->jobs[b->ids[g.first_id + k]].n + 1023u) / 1024u);
+            acc += std::max(1u, (b->jobs[b->ids[g.first_id + k]].n + 127u) / 128u);
         }
         offs.push_back(acc);
         g.total_blocks = acc;

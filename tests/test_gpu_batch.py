@@ -102,16 +102,30 @@ def test_batch_equals_single_calls(hrpp):
     for j in jobs:
         pred = _new_pred(hrpp, j)
         ref.append(_single(hrpp, torch, j, pred))
-    # the oracle agrees with the single calls for three of the jobs
-    for k in (0, 2, 13):
-        j = jobs[k]
+    # the oracle agrees with the single calls for every job: results, the
+    # method's counters and (with a predictor) the table's tags and slots
+    for k, j in enumerate(jobs):
+        _say(f"batch: oracle for job {k}")
         ob = oracle.build_sah(j["tris"])
-        T, W, qo, qd, E = j["pc"][:5]
-        fe = j["pc"][9] if len(j["pc"]) > 9 else 0
-        tb = oracle.Table(T, W, qo, qd)
-        want, ws = oracle.trace(ob, j["tris"], j["rays_np"], query=j["query"], mode=j["mode"], table=tb, epoch=E,
-                                first_epoch=fe)
-        assert want.tobytes() == ref[k][0] and ws == ref[k][1]
+        if j["pc"] is None:
+            want, ws = oracle.trace(ob, j["tris"], j["rays_np"], query=j["query"], mode=j["mode"])
+            got_table = None
+        else:
+            T, W, qo, qd, E = j["pc"][:5]
+            hm, gu = (j["pc"][5], j["pc"][6]) if len(j["pc"]) > 5 else (0, 0)
+            rp = j["pc"][8] if len(j["pc"]) > 8 else 0
+            fe = j["pc"][9] if len(j["pc"]) > 9 else 0
+            tb = oracle.Table(T, W, qo, qd, hash_mode=hm, go_up=gu, policy=rp)
+            want, ws = oracle.trace(ob, j["tris"], j["rays_np"], query=j["query"], mode=j["mode"], table=tb,
+                                    epoch=E, first_epoch=fe)
+            got_table = tb
+        assert want.tobytes() == ref[k][0], f"job {k}: results differ from the oracle"
+        assert {n: v for n, v in ref[k][1].items() if n in ws} == ws, f"job {k}: counters differ from the oracle"
+        if got_table is not None:
+            raw = np.frombuffer(ref[k][2], np.uint8).reshape(1 << got_table.log2n, -1)
+            assert np.array_equal(raw[:, :8].copy().view(np.uint64)[:, 0], got_table.tags), f"job {k}: tags"
+            W = got_table.W
+            assert np.array_equal(raw[:, 8:8 + 4 * W].copy().view(np.uint32), got_table.slots), f"job {k}: slots"
     for use_graph in (False, True):
         _say(f"batch: graph={use_graph}")
         preds = [_new_pred(hrpp, j) for j in jobs]
