@@ -45,7 +45,7 @@ bool desc_ok(const hrpp_predictor_desc *d) {
 uint32_t entry_bytes_for(uint32_t ways) { return ways <= 4 ? 32u : 64u; }
 
 struct PredLayout {
-    size_t table, topw, hkey, hmin, rec_key, rec_idx, rec_leaf, rec_status, queue, dirty, ctrl, total;
+    size_t table, topw, topw_rows, pairs, rec_key, rec_idx, rec_leaf, rec_status, queue, dirty, ctrl, total;
 };
 
 PredLayout pred_layout(const hrpp_predictor_desc *d) {
@@ -54,9 +54,11 @@ PredLayout pred_layout(const hrpp_predictor_desc *d) {
     size_t off = 0;
     L.table = off; off += align256(N * entry_bytes_for(d->ways));
     const size_t H = size_t(1) << pair_hash_bits_for((uint32_t)E);
-    L.topw = off; off += align256(E * W * 8);
-    L.hkey = off; off += align256(H * 8);
-    L.hmin = off; off += align256(H * 4);
+    // one fresh-id list per claimed entry of an epoch: indexed by the entry when
+    // the table is no larger than an epoch, else by the claiming ray's offset
+    L.topw_rows = N <= E ? N : E;
+    L.topw = off; off += align256(L.topw_rows * W * 8);
+    L.pairs = off; off += align256(H * sizeof(PairSlot));
     L.rec_key = off; off += align256(E * 8);
     L.rec_idx = off; off += align256(E * 4);
     L.rec_leaf = off; off += align256(E * 4);
@@ -423,10 +425,10 @@ hrpp_status hrpp_predictor_reset(hrpp_predictor *p, void *stream) {
         // failed launch
         const size_t E = p->desc.epoch_rays;
         launch_fill32(p->d_ctrl, 64, 0u, s);
-        launch_fill32(reinterpret_cast<uint32_t *>(p->d_topw), 2 * E * p->desc.ways, kNone, s);
+        const PredLayout L = pred_layout(&p->desc);
+        launch_fill32(reinterpret_cast<uint32_t *>(p->d_topw), 2 * L.topw_rows * p->desc.ways, kNone, s);
         const size_t H = size_t(1) << pair_hash_bits_for((uint32_t)E);
-        launch_fill32(reinterpret_cast<uint32_t *>(p->d_hkey), 2 * H, kNone, s);
-        launch_fill32(p->d_hmin, H, kNone, s);
+        launch_fill32(static_cast<uint32_t *>(p->d_pairs), 4 * H, kNone, s);
         launch_fill32(p->d_rec_idx, E, kNone, s);
     }
     const hrpp_status st = check(hipGetLastError());
@@ -458,8 +460,8 @@ hrpp_status hrpp_predictor_create(const hrpp_bvh *bvh, const hrpp_predictor_desc
     p->table_bytes = (size_t(1) << desc->log2_entries) * p->entry_bytes;
     p->d_table = base + L.table;
     p->d_topw = reinterpret_cast<uint64_t *>(base + L.topw);
-    p->d_hkey = reinterpret_cast<uint64_t *>(base + L.hkey);
-    p->d_hmin = reinterpret_cast<uint32_t *>(base + L.hmin);
+    p->topw_by_entry = L.topw_rows == (size_t(1) << desc->log2_entries);
+    p->d_pairs = base + L.pairs;
     p->d_rec_key = reinterpret_cast<uint64_t *>(base + L.rec_key);
     p->d_rec_idx = reinterpret_cast<uint32_t *>(base + L.rec_idx);
     p->d_rec_leaf = reinterpret_cast<uint32_t *>(base + L.rec_leaf);
@@ -595,8 +597,8 @@ static TraceArgs make_args(const hrpp_bvh *bvh, hrpp_predictor *pred, const hrpp
         a.rec_leaf = pred->d_rec_leaf;
         a.rec_status = pred->d_rec_status;
         a.topw = pred->d_topw;
-        a.hkey = pred->d_hkey;
-        a.hmin = pred->d_hmin;
+        a.topw_by_entry = pred->topw_by_entry ? 1u : 0u;
+        a.pairs = static_cast<PairSlot *>(pred->d_pairs);
         a.hash_bits = pair_hash_bits_for(d.epoch_rays);
     }
     if (g_touch.bits && d_stats && g_touch.bvh == bvh && g_touch.pred == pred) {

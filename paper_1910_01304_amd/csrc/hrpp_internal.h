@@ -88,9 +88,9 @@ struct hrpp_predictor {
     float bmin[3], scale[3];    // hash grid over the BVH root box
     // device regions inside the caller's buffer
     void *d_table;              // 2^T entries
-    uint64_t *d_topw;           // E * W fresh-id lists (per claiming ray), ray id << 32 | id
-    uint64_t *d_hkey;           // 2^hash_bits (claiming ray, id) pairs of the epoch
-    uint32_t *d_hmin;           // 2^hash_bits smallest ray ids of those pairs
+    uint64_t *d_topw;           // min(2^T, E) * W fresh-id lists, ray id << 32 | id
+    bool topw_by_entry;         // lists indexed by table entry (2^T <= E) or by claiming ray
+    void *d_pairs;              // 2^hash_bits 16-byte slots: (claiming ray, id) pair + smallest ray id
     uint64_t *d_rec_key;        // E
     uint32_t *d_rec_idx;        // E (kNone = no record)
     uint32_t *d_rec_leaf;       // E

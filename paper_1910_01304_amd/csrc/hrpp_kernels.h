@@ -41,6 +41,15 @@ inline uint32_t queue_subcap_for(uint32_t epoch) {
     return ((blocks + kSubQueues - 1u) / kSubQueues) * 256u;
 }
 
+// One slot of the per-epoch set of (claiming ray, id) pairs: the pair and the
+// smallest ray id that recorded it, in one 16-byte record, so that a probe, its
+// compare-and-swap and its minimum touch one cache line.
+struct PairSlot {
+    unsigned long long key;
+    uint32_t min;
+    uint32_t pad;
+};
+
 struct TraceArgs {
     // scene
     const void *nodes;            // interior nodes, 64 B each
@@ -75,9 +84,10 @@ struct TraceArgs {
     uint32_t *rec_idx;
     uint32_t *rec_leaf;
     uint32_t *rec_status;         // status | free slots << 2 | (hash slot + 1) << 8
-    uint64_t *topw;               // per claiming ray: W fresh (ray id << 32 | id), increasing
-    uint64_t *hkey;               // per-epoch set of (claiming ray - base) << 32 | id ...
-    uint32_t *hmin;               // ... with the smallest ray id that recorded the pair
+    uint64_t *topw;               // W fresh (ray id << 32 | id), increasing, per claimed entry: indexed by
+    uint32_t topw_by_entry;       // ... the entry (1, when the table has no more entries than an epoch
+                                  // has rays) or by the claiming ray's offset in the epoch (0)
+    PairSlot *pairs;              // per-epoch set of (claiming ray - base) << 32 | id
     uint32_t hash_bits;           // log2 of the set's size (>= 2 x the epoch)
     // measurement only (kernels with counters): a bitmap of the 128-byte lines
     // of the scene and table arrays each kernel kind touched (null = off)

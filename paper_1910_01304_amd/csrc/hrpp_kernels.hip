@@ -236,16 +236,24 @@ __device__ __forceinline__ bool test_leaf(const TraceArgs &a, uint32_t leaf, con
     return changed;
 }
 
+// Traversal kernels run blocks of kTraceBlock lanes; the first entries of each
+// lane's traversal stack live in LDS (walk()).  8 entries: for closest hit 4
+// and 12 measured slower, for any hit 4 was slower and 12 or 16 no faster;
+// 4 KB of LDS per block for any hit, 8 KB with the distances for closest hit.
+constexpr uint32_t kTraceBlock = 128;
+constexpr uint32_t kLdsStackAny = 8;
+constexpr uint32_t kLdsStackClosest = 8;
+
 // ---------------------------------------------------------------------------
 // Stack traversal.  Fixed order: root box test; at an interior node both
 // child boxes are tested against [tmin, tcur]; with both hit the nearer
 // child (left on a tie) is taken and the other pushed with its entry
 // distance; a popped node is visited only if its entry distance still passes
 // against the current tcur; leaves test triangles in BVH order.
-// The per-lane stack lives in private memory (the cached scratch path):
-// sized to the deepest tree the library accepts, it leaves occupancy to the
-// registers, where an LDS stack of the same size limited closest-hit kernels
-// to 3 waves per SIMD.  Callers pass (pointer, stride 1, capacity = depth).
+// Beyond its LDS entries the per-lane stack lives in private memory (the
+// cached scratch path), sized to the deepest tree the library accepts; a
+// whole stack in LDS limited closest-hit kernels to 3 waves per SIMD.
+// Callers pass (pointer, stride 1, capacity = depth) for the private part.
 // ---------------------------------------------------------------------------
 // walk(): the subtree of `ref`, whose own box the caller has tested; from
 // the root this is the whole traversal, from a predicted node (go-up level
@@ -258,11 +266,17 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
     float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
     bool found = (b.prim != kNone);
     // sp nodes are deferred: the newest (entry sp - 1) is held in registers
-    // (top_ref, top_t), the older ones in the stack, so a pop takes its node
-    // without waiting for memory and the load of the next newest entry
-    // overlaps the work on the popped node
+    // (top_ref, top_t), so a pop takes its node without waiting for memory and
+    // the load of the next newest entry overlaps the work on the popped node.
+    // The older entries: the first K in LDS, lane-interleaved (entry j of lane
+    // l at word j * kTraceBlock + l: the 64 lanes of a wave touch 64
+    // consecutive words), the rest in the private stack.  Closest hit keeps
+    // each entry's distance beside it.
     uint32_t sp = 0, top_ref = 0;
     float top_t = 0.0f;
+    constexpr uint32_t K = ANY ? kLdsStackAny : kLdsStackClosest;
+    __shared__ uint32_t s_sn[K * kTraceBlock];
+    __shared__ float s_st[ANY ? 1 : K * kTraceBlock];
     for (;;) {
         c.v[kNodesVisited]++;
         if (!(ref & kLeafFlag)) {
@@ -283,8 +297,14 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
                 else         { push_ref = n3.y; push_t = tr; ref = n3.x; }
                 if (sp >= cap) { atomicOr(a.error, 1u); return found; }
                 if (sp > 0) {
-                    stk_node[(sp - 1) * stride] = top_ref;
-                    if constexpr (!ANY) stk_t[(sp - 1) * stride] = top_t;
+                    const uint32_t j = sp - 1;
+                    if (j < K) {
+                        s_sn[j * kTraceBlock + threadIdx.x] = top_ref;
+                        if constexpr (!ANY) s_st[j * kTraceBlock + threadIdx.x] = top_t;
+                    } else {
+                        stk_node[(j - K) * stride] = top_ref;
+                        if constexpr (!ANY) stk_t[(j - K) * stride] = top_t;
+                    }
                 }
                 top_ref = push_ref;
                 top_t = push_t;
@@ -308,8 +328,14 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
             const uint32_t pref = top_ref;
             const float pt = top_t;
             if (sp > 0) {
-                top_ref = stk_node[(sp - 1) * stride];
-                if constexpr (!ANY) top_t = stk_t[(sp - 1) * stride];
+                const uint32_t j = sp - 1;
+                if (j < K) {
+                    top_ref = s_sn[j * kTraceBlock + threadIdx.x];
+                    if constexpr (!ANY) top_t = s_st[j * kTraceBlock + threadIdx.x];
+                } else {
+                    top_ref = stk_node[(j - K) * stride];
+                    if constexpr (!ANY) top_t = stk_t[(j - K) * stride];
+                }
             }
             if (ANY || pt <= tcur * far_pad()) {
                 ref = pref;
@@ -988,13 +1014,13 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
         const uint32_t mask = (1u << a.hash_bits) - 1u;
         uint32_t h = pair_slot(pair, a.hash_bits);
         for (;;) {
-            uint64_t k = __hip_atomic_load(&a.hkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (k == kNone64) k = atomicCAS((unsigned long long *)&a.hkey[h], kNone64, (unsigned long long)pair);
+            uint64_t k = __hip_atomic_load(&a.pairs[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k == kNone64) k = atomicCAS(&a.pairs[h].key, kNone64, (unsigned long long)pair);
             if (k == kNone64 || k == pair) break;
             h = (h + 1u) & mask;
         }
-        const uint32_t seen = __hip_atomic_load(&a.hmin[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (seen > base + i) atomicMin(&a.hmin[h], base + i);
+        const uint32_t seen = __hip_atomic_load(&a.pairs[h].min, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen > base + i) atomicMin(&a.pairs[h].min, base + i);
         hslot1 = h + 1u;
     }
     if (i < count && status != 0) a.rec_status[i] = status | (free_slots << 2) | (hslot1 << 8);
@@ -1013,13 +1039,14 @@ __device__ __forceinline__ void body_update_rank(const TraceArgs &a, uint32_t ba
     if ((st & 3u) != kRecFresh || (st >> 8) == 0) return;
     const uint32_t h = (st >> 8) - 1u;
     const uint32_t rid = base + i;
-    if (a.hmin[h] != rid) return;                      // a smaller ray id recorded the same pair
+    if (a.pairs[h].min != rid) return;                 // a smaller ray id recorded the same pair
     const uint32_t free_slots = (st >> 2) & 15u;
-    const uint32_t owner = entry_ptr(a, a.rec_idx[i])[2 + a.ways];
-    // sorted insertion into the owner's list of the free_slots smallest
+    const uint32_t idx = a.rec_idx[i];
+    const uint32_t owner = entry_ptr(a, idx)[2 + a.ways];
+    // sorted insertion into the entry's list of the free_slots smallest
     // (ray id, id) values; list values only ever decrease, so a plain read that
     // is already below x lets us skip the atomic at that position
-    uint64_t *list = a.topw + (size_t)(owner - base) * a.ways;
+    uint64_t *list = a.topw + (size_t)(a.topw_by_entry ? idx : owner - base) * a.ways;
     uint64_t x = ((uint64_t)rid << 32) | a.rec_leaf[i];
     for (uint32_t s = 0; s < free_slots && x != kNone64; s++) {
         const uint64_t seen = __hip_atomic_load(&list[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1055,7 +1082,7 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
             } else {
                 while (used < W && e[2 + used] != kNone) used++;
             }
-            uint64_t *list = a.topw + (size_t)i * W;
+            uint64_t *list = a.topw + (size_t)(a.topw_by_entry ? idx : i) * W;
             if (a.policy & 1u) {
                 // FIFO: the oldest (front) slots make room for the new ids
                 uint32_t nf = 0;
@@ -1079,8 +1106,8 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
         // (every record of the pair writes the same values)
         const uint32_t st = a.rec_status[i];
         if ((st >> 8) != 0) {
-            a.hkey[(st >> 8) - 1u] = kNone64;
-            a.hmin[(st >> 8) - 1u] = kNone;
+            a.pairs[(st >> 8) - 1u].key = kNone64;
+            a.pairs[(st >> 8) - 1u].min = kNone;
         }
         if (!STATS) a.rec_idx[i] = kNone;            // no drop count to take: retire the record now
     }
