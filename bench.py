@@ -548,7 +548,7 @@ def main():
         frames = [torch.from_numpy(sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32),
                                                             seed=w["seed"] + 100 + k, light_center=w["light_center"],
                                                             light_size=w["light_size"])).cuda()
-                  for k in range(4)]
+                  for k in range(6)]
         shadow_info["warm"] = measure_warm(args, torch, hrpp, bvh, frames, "any",
                                            dict(cfg_any, epoch_rays=1 << 21, first_epoch_rays=0))
         del frames
@@ -761,7 +761,7 @@ def main():
             frames = [torch.from_numpy(sg.ao_rays_from_hits(tris, cam_rays, hh[:, 0], hh[:, 3].view(np.uint32),
                                                             seed=wi["seed"] + 100 + k, samples=wi["samples"],
                                                             tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))).cuda()
-                      for k in range(3)]
+                      for k in range(4)]
             ao_info["warm"] = measure_warm(args, torch, hrpp, bvh, frames, "any",
                                            dict(log2_entries=wi["log2_entries"], ways=wi["ways"],
                                                 origin_bits=wi["origin_bits"], dir_bits=wi["dir_bits"],
@@ -895,35 +895,42 @@ def main():
 
 def measure_warm(args, torch, hrpp, bvh, frames, query, cfg):
     """HRPP with tables kept across frames against plain traversal of the same frames.
-    The first frame fills the table (untimed); each timed trace takes the next frame of
-    the others in turn, on the table the previous traces left."""
+    The first frame fills the table (untimed); every later frame is traced once, timed,
+    on the table all earlier frames left (no frame is traced on a table that has seen
+    it); medians over those frames.  The counters are the last frame's, traced with
+    counters on a copy of the table it was timed on."""
     pred = hrpp.Predictor(bvh, **cfg)
     out = torch.empty(frames[0].shape[0], dtype=torch.uint8, device="cuda")
     pred.reset()
     hrpp.trace_anyhit(bvh, pred, frames[0], out=out)
-    k = [0]
-
-    def warm():
-        k[0] = k[0] % (len(frames) - 1) + 1
-        hrpp.trace_anyhit(bvh, pred, frames[k[0]], out=out)
-
-    def plain():
-        k[0] = k[0] % (len(frames) - 1) + 1
-        hrpp.trace_anyhit(bvh, None, frames[k[0]], out=out)
-
     n = frames[0].shape[0]
-    ms_h = timed(torch, warm, args.steps, 1)[0]
-    ms_p = timed(torch, plain, args.steps, 1)[0]
+    ms_h, ms_p = [], []
+    before_last = None
+    for k, f in enumerate(frames[1:], 1):
+        if k == len(frames) - 1:
+            before_last = pred.export_raw()
+        for p, acc in ((None, ms_p), (pred, ms_h)):
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            hrpp.trace_anyhit(bvh, p, f, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            acc.append(a.elapsed_time(b))
     sh, sp = hrpp.new_stats(), hrpp.new_stats()
-    hrpp.trace_anyhit(bvh, pred, frames[1], out=out, stats=sh)
-    hrpp.trace_anyhit(bvh, None, frames[1], out=out, stats=sp)
+    copy = hrpp.Predictor(bvh, **cfg)
+    copy.import_raw(before_last)
+    hrpp.trace_anyhit(bvh, copy, frames[-1], out=out, stats=sh)
+    hrpp.trace_anyhit(bvh, None, frames[-1], out=out, stats=sp)
     h, p = hrpp.stats_dict(sh), hrpp.stats_dict(sp)
-    return dict(frames=len(frames), epoch_rays=cfg["epoch_rays"], hrpp_mrays_s=round(n / ms_h / 1e3, 2),
-                plain_mrays_s=round(n / ms_p / 1e3, 2), speedup_vs_plain=round(ms_p / ms_h, 4),
+    h_ms, p_ms = sorted(ms_h)[len(ms_h) // 2], sorted(ms_p)[len(ms_p) // 2]
+    return dict(frames=len(frames), timed_frames=len(frames) - 1, epoch_rays=cfg["epoch_rays"],
+                hrpp_mrays_s=round(n / h_ms / 1e3, 2), plain_mrays_s=round(n / p_ms / 1e3, 2),
+                speedup_vs_plain=round(p_ms / h_ms, 4),
                 pct_nodes_skipped=round(100.0 * (1 - h["nodes_visited"] / p["nodes_visited"]), 3),
                 prediction_hit_rate=round(h["pred_hits"] / n, 4), false_positive_rate=round(h["false_pos"] / n, 4),
-                records=h["records"], note="table kept across frames of new samples, one epoch per 2^21/2^22 rays, "
-                                           "no reset")
+                records=h["records"], note="table kept across frames of new samples, one epoch per 2^21 / 2^22 "
+                                           "rays, no reset; each timed frame is new to the table")
 
 
 def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, hits_out, occ_out, on_two_streams,
