@@ -40,10 +40,11 @@ if ROOT not in sys.path:
 METRIC = "Mrays/s HRPP vs plain BVH traversal (shadow/AO), % nodes skipped, p99 lat"
 HBM_PEAK_GBS = 8000.0
 NODE_B, TRI_B, RAY_B, LEAFBOX_B = 64, 48, 32, 32
-# inline_lanes of the serving and batched predictors, from an A/B of 65 / 1 / 48:
-# queue-only fallback gave serving the lowest p99 (4.1 ms at 80% load against
-# 4.8 and 6.1), in-place fallback gave the batched any-hit scenes the highest rate
-SERVE_INLINE = 65
+# inline_lanes of the serving and batched predictors: in-place fallback (1). With
+# the current traversal kernels it gives serving a higher saturation (807 against 754
+# Mrays/s) and a lower p99 at 80% load (6.6 against 13.8 ms) than queue-only
+# fallback (65), and the batched any-hit scenes their highest rate
+SERVE_INLINE = 1
 BATCH_INLINE = 1
 
 
