@@ -302,9 +302,15 @@ def main():
     args = parse()
     if args.summarize_traffic:
         import scenegen as sg
-        w = sg.AT_SCALE
-        cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1], epoch_rays=q[2],
-                     inline_lanes=q[3], first_epoch_rays=q[4]) for q in (w["primary_q"], w["shadow_q"])]
+        w, wi = sg.AT_SCALE, sg.INCOHERENT
+        if args.probe == "ao":
+            cfgs = [dict(log2_entries=wi["log2_entries"], ways=wi["ways"], origin_bits=wi["origin_bits"],
+                         dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"], inline_lanes=wi["inline_lanes"],
+                         first_epoch_rays=wi["first_epoch"])]
+        else:
+            cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1],
+                         epoch_rays=q[2], inline_lanes=q[3], first_epoch_rays=q[4])
+                    for q in (w["primary_q"], w["shadow_q"])]
         cfgs.append(dict(leaf_max=w["leaf_max"]))
         summarize_traffic(*args.summarize_traffic, configs=cfgs)
         return
@@ -1125,7 +1131,8 @@ def run_autotune(args, np, torch, hrpp, sg):
                                             ("shadow_warm", warm[1][1], "any", w["shadow_q"], warm[0][1])):
         if args.tune_queries and name not in args.tune_queries.split(","):
             continue
-        start = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1],
+        wt = wi if name == "ao" else w
+        start = dict(log2_entries=wt["log2_entries"], ways=wt["ways"], origin_bits=q[0], dir_bits=q[1],
                      epoch_rays=q[2], inline_lanes=q[3], first_epoch_rays=q[4])
         if "leaf_max" in knobs:
             start["leaf_max"] = sg.AT_SCALE["leaf_max"]
