@@ -396,7 +396,8 @@ typedef struct {
 
 typedef struct hrpp_batch hrpp_batch;
 
-/* Device bytes of the job table of a batch of njobs jobs. */
+/* Device bytes of the job table, job ids and launch-grid offsets of a batch of
+   njobs jobs (a buffer of this size, 256-byte aligned, for hrpp_batch_create). */
 size_t hrpp_batch_required_bytes(uint32_t njobs);
 
 /* Validate the jobs (as the trace calls do; EINVAL also for a predictor used

@@ -696,10 +696,14 @@ static bool bj_inline(const hrpp_predictor *p) {
     return v <= 64;
 }
 
+// Block offsets: count + 1 per group for the two plain groups, and three
+// arrays of count + 1 per predictor group (at most six groups).
+static size_t batch_offset_words(uint32_t njobs) { return ((size_t)njobs + 2) + 3 * ((size_t)njobs + 6); }
+
 size_t hrpp_batch_required_bytes(uint32_t njobs) {
-    // job table, job ids, and block offsets of the two plain groups
+    // job table, job ids, and the groups' block offsets
     return align256((size_t)njobs * sizeof(BatchJob)) + align256((size_t)njobs * sizeof(uint32_t)) +
-           align256(2 * ((size_t)njobs + 2) * sizeof(uint32_t));
+           align256(batch_offset_words(njobs) * sizeof(uint32_t));
 }
 
 hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *d_buf, size_t bytes, void *stream,
@@ -748,9 +752,6 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
             const BatchJob &bj = b->jobs[j];
             b->ids.push_back(j);
             g.count++;
-            g.max_epoch = std::max(g.max_epoch, std::min(bj.epoch, bj.n));
-            g.max_cap = std::max(g.max_cap, bj.a.stack_cap);
-            g.max_n = std::max(g.max_n, bj.n);
             g.rounds = std::max(g.rounds, bj.n <= bj.first ? 1u : 1u + (bj.n - bj.first + bj.epoch - 1) / bj.epoch);
             if (bj.a.stats) g.stats = true;
         }
@@ -764,19 +765,40 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
     b->d_ids = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)));
     uint32_t *d_off = reinterpret_cast<uint32_t *>(base + align256((size_t)njobs * sizeof(BatchJob)) +
                                                    align256((size_t)njobs * sizeof(uint32_t)));
-    // plain groups: one lane per ray of each job
+    // flat grids: plain groups get one lane per ray of each job; predictor
+    // groups one lane per ray of each job's longest epoch (the first epoch is
+    // never longer than the others), which every round reuses
     std::vector<uint32_t> offs;
-    for (BatchGroup &g : b->groups) {
-        if (g.kind != kBatchAnyPlain && g.kind != kBatchClosestPlain) continue;
-        g.d_block_off = d_off + offs.size();
+    auto add_offsets = [&](const BatchGroup &g, uint32_t lanes, uint32_t cap, bool whole) {
+        const uint32_t at = (uint32_t)offs.size();
         uint32_t acc = 0;
         for (uint32_t k = 0; k < g.count; k++) {
+            const BatchJob &bj = b->jobs[b->ids[g.first_id + k]];
+            const uint32_t rays = whole ? bj.n : std::min(bj.epoch, bj.n);
             offs.push_back(acc);
-            acc += std::max(1u, (b->jobs[b->ids[g.first_id + k]].n + 127u) / 128u);
+            acc += std::min(cap, std::max(1u, (rays + lanes - 1u) / lanes));
         }
         offs.push_back(acc);
-        g.total_blocks = acc;
+        return std::make_pair(at, acc);
+    };
+    for (BatchGroup &g : b->groups) {
+        if (g.kind == kBatchAnyPlain || g.kind == kBatchClosestPlain) {
+            const auto p = add_offsets(g, 128u, ~0u, true);
+            g.d_block_off = d_off + p.first;
+            g.total_blocks = p.second;
+        } else {
+            const auto p128 = add_offsets(g, 128u, ~0u, false);
+            const auto p256 = add_offsets(g, 256u, ~0u, false);
+            const auto pq = add_offsets(g, 128u, kQueueBlocks, false);
+            g.d_off128 = d_off + p128.first;
+            g.d_off256 = d_off + p256.first;
+            g.d_offq = d_off + pq.first;
+            g.blocks128 = p128.second;
+            g.blocks256 = p256.second;
+            g.blocksq = pq.second;
+        }
     }
+    if (offs.size() > batch_offset_words(njobs)) { delete b; return HRPP_EINVAL; }   // cannot happen
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(b->d_jobs, b->jobs.data(), b->jobs.size() * sizeof(BatchJob),
                                   hipMemcpyHostToDevice, s);

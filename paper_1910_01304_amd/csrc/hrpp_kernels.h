@@ -109,17 +109,26 @@ struct BatchJob {
 
 enum BatchKind : int { kBatchAnyHrpp, kBatchPaperHrpp, kBatchExactHrpp, kBatchAnyPlain, kBatchClosestPlain };
 
-// Jobs of one kind, listed in ids[first_id .. first_id + count).
+// Jobs of one kind, listed in ids[first_id .. first_id + count).  Every
+// launch of a group is one flat grid in which job k owns the blocks
+// [off[k], off[k + 1]); offsets are increasing (every job has a block).
 struct BatchGroup {
     int kind;
-    uint32_t first_id, count, max_epoch, max_cap, rounds, max_n;
+    uint32_t first_id, count, rounds;
     bool stats;
     bool subtree;                 // predictors of go-up level >= 1
     bool inline_any;              // some job traverses failing waves in place
-    // plain groups: flat grid of total_blocks, job k owns blocks [off[k], off[k+1])
+    // plain groups: blocks of 128 lanes covering each job's rays
     uint32_t total_blocks;
     const uint32_t *d_block_off;
+    // predictor groups, per round: blocks of 128 lanes and of 256 lanes covering
+    // each job's longest epoch, and the queue kernel's grid (128 lanes, at most
+    // kQueueBlocks per job)
+    uint32_t blocks128, blocks256, blocksq;
+    const uint32_t *d_off128, *d_off256, *d_offq;
 };
+
+constexpr uint32_t kQueueBlocks = 4096;   // grid cap of one epoch's queue traversal
 
 void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<BatchGroup> &groups,
                   uint32_t max_rounds, uint32_t max_blocks, hipStream_t s);

@@ -949,6 +949,7 @@ __global__ __launch_bounds__(128) void k_traverse_queue(TraceArgs a, uint32_t ba
 //       slot, reset the queue count.
 // ---------------------------------------------------------------------------
 enum : uint32_t { kRecConflict = 1, kRecPresent = 2, kRecFresh = 3 };
+constexpr uint32_t kRecOwner = 1u << 6;   // status flag: this record's ray holds the entry's claim
 constexpr uint64_t kNone64 = 0xFFFFFFFFFFFFFFFFull;
 
 __device__ __forceinline__ uint32_t pair_slot(uint64_t pair, uint32_t bits) {
@@ -962,11 +963,12 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
     const uint32_t i = bx * blockDim.x + threadIdx.x;
     const uint32_t W = a.ways;
     // a fresh record's pair: the claiming ray and the id to insert
-    uint32_t ins_owner = kNone, ins_leaf = kNone, free_slots = 0, status = 0;
+    uint32_t ins_owner = kNone, ins_leaf = kNone, free_slots = 0, status = 0, own = 0;
     if (i < count && a.rec_idx[i] != kNone) {
         const uint32_t idx = a.rec_idx[i];
         const uint32_t *e = entry_ptr(a, idx);
         const uint32_t owner = e[2 + W];                // smallest ray id (claim)
+        if (owner == base + i) own = kRecOwner;         // the claim is final until the apply pass
         // with the resident policy an entry may have no claim: every record
         // of the epoch had another key than the resident tag
         const uint64_t kstar = owner == kNone ? ~a.rec_key[i] : a.rec_key[owner - base];
@@ -1023,7 +1025,8 @@ __device__ __forceinline__ void body_update_classify(const TraceArgs &a, uint32_
         if (seen > base + i) atomicMin(&a.pairs[h].min, base + i);
         hslot1 = h + 1u;
     }
-    if (i < count && status != 0) a.rec_status[i] = status | (free_slots << 2) | (hslot1 << 8);
+    if (i < count && status != 0)
+        a.rec_status[i] = status | (free_slots << 2) | (hslot1 << 8) | own;
     flush_counters<STATS>(c, a.stats);
 }
 
@@ -1068,8 +1071,9 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
     if (i < count && a.rec_idx[i] != kNone) {
         const uint32_t idx = a.rec_idx[i];
         const uint32_t W = a.ways;
-        uint32_t *e = (uint32_t *)entry_ptr(a, idx);
-        if (e[2 + W] == base + i) {                    // this ray owns the entry
+        const uint32_t st = a.rec_status[i];
+        if (st & kRecOwner) {                          // this ray owns the entry
+            uint32_t *e = (uint32_t *)entry_ptr(a, idx);
             const uint64_t kstar = a.rec_key[i];
             uint32_t used = 0;
             if (*(const uint64_t *)e != kstar) {
@@ -1104,7 +1108,6 @@ __device__ __forceinline__ void body_update_apply(const TraceArgs &a, uint32_t b
         }
         // the pair set is read no more in this epoch: empty this record's slot
         // (every record of the pair writes the same values)
-        const uint32_t st = a.rec_status[i];
         if ((st >> 8) != 0) {
             a.pairs[(st >> 8) - 1u].key = kNone64;
             a.pairs[(st >> 8) - 1u].min = kNone;
@@ -1149,9 +1152,10 @@ __global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t bas
 
 // ---------------------------------------------------------------------------
 // Batched execution: many independent (BVH, predictor, rays) jobs.  Round r
-// runs epoch r of every job of a group in one launch per kernel, with
-// blockIdx.y selecting the job; each job's epochs stay in order, and jobs
-// share nothing, so every job computes exactly what its own call computes.
+// runs epoch r of every job of a group in one launch per kernel, over a flat
+// grid in which each job owns as many blocks as its longest epoch needs; each
+// job's epochs stay in order, and jobs share nothing, so every job computes
+// exactly what its own call computes.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool batch_epoch(const BatchJob &J, uint32_t round, uint32_t &base, uint32_t &count) {
     // round 0 is the first epoch (J.first rays), round r >= 1 the r-th of J.epoch
@@ -1162,74 +1166,102 @@ __device__ __forceinline__ bool batch_epoch(const BatchJob &J, uint32_t round, u
     return true;
 }
 
+// The job owning block bx of a flat grid: the k with off[k] <= bx < off[k + 1]
+// (off increasing, off[0] = 0), counted 64 offsets at a time with one load
+// and a ballot per wave.  Called by every lane of the wave.
+__device__ __forceinline__ uint32_t batch_job_of(const uint32_t *__restrict__ off, uint32_t njobs, uint32_t bx) {
+    uint32_t le = 0;
+    for (uint32_t c = 0; c < njobs; c += 64u) {
+        const uint32_t j = c + __lane_id();
+        const uint32_t m = (uint32_t)__popcll(__ballot(j < njobs && off[j] <= bx));
+        le += m;
+        if (m < 64u) break;
+    }
+    return le - 1u;
+}
+
+// Resolve block blockIdx.x of a group's flat grid to its job, the job's epoch
+// of this round, and the block's index among the job's blocks.
+struct BatchBlock {
+    const BatchJob *J;
+    uint32_t base, count, bx, gx;
+};
+__device__ __forceinline__ bool batch_block(const BatchJob *__restrict__ jobs, const uint32_t *__restrict__ ids,
+                                            const uint32_t *__restrict__ off, uint32_t njobs, uint32_t round,
+                                            BatchBlock &b) {
+    const uint32_t k = batch_job_of(off, njobs, blockIdx.x);
+    const uint32_t first = off[k];
+    b.J = &jobs[ids[k]];
+    b.bx = blockIdx.x - first;
+    b.gx = off[k + 1] - first;
+    return batch_epoch(*b.J, round, b.base, b.count) && b.bx * blockDim.x < b.count;
+}
+
 template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
 __global__ __launch_bounds__(256) void kb_predict(const BatchJob *__restrict__ jobs, const uint32_t *__restrict__ ids,
-                                                  uint32_t round) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * blockDim.x >= count) return;
-    body_predict<ANY, EXACT, STATS, SUBTREE, INLINE>(J.a, base, count, blockIdx.x, gridDim.x);
+                                                  const uint32_t *__restrict__ off, uint32_t njobs, uint32_t round) {
+    BatchBlock b;
+    if (!batch_block(jobs, ids, off, njobs, round, b)) return;
+    body_predict<ANY, EXACT, STATS, SUBTREE, INLINE>(b.J->a, b.base, b.count, b.bx, b.gx);
 }
 
 template <bool ANY, bool EXACT, bool STATS>
 __global__ __launch_bounds__(128) void kb_traverse_queue(const BatchJob *__restrict__ jobs,
-                                                         const uint32_t *__restrict__ ids, uint32_t round) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * 128u >= count) return;
-    body_traverse_queue<ANY, EXACT, STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+                                                         const uint32_t *__restrict__ ids,
+                                                         const uint32_t *__restrict__ off, uint32_t njobs,
+                                                         uint32_t round) {
+    BatchBlock b;
+    if (!batch_block(jobs, ids, off, njobs, round, b)) return;
+    body_traverse_queue<ANY, EXACT, STATS>(b.J->a, b.base, b.count, b.bx, b.gx);
 }
 
 template <bool STATS>
 __global__ __launch_bounds__(256) void kb_update_classify(const BatchJob *__restrict__ jobs,
-                                                          const uint32_t *__restrict__ ids, uint32_t round) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
-    body_update_classify<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+                                                          const uint32_t *__restrict__ ids,
+                                                          const uint32_t *__restrict__ off, uint32_t njobs,
+                                                          uint32_t round) {
+    BatchBlock b;
+    if (!batch_block(jobs, ids, off, njobs, round, b)) return;
+    body_update_classify<STATS>(b.J->a, b.base, b.count, b.bx, b.gx);
 }
 
 __global__ __launch_bounds__(256) void kb_update_rank(const BatchJob *__restrict__ jobs,
-                                                      const uint32_t *__restrict__ ids, uint32_t round) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
-    body_update_rank(J.a, base, count, blockIdx.x, gridDim.x);
+                                                      const uint32_t *__restrict__ ids,
+                                                      const uint32_t *__restrict__ off, uint32_t njobs,
+                                                      uint32_t round) {
+    BatchBlock b;
+    if (!batch_block(jobs, ids, off, njobs, round, b)) return;
+    body_update_rank(b.J->a, b.base, b.count, b.bx, b.gx);
 }
 
 template <bool STATS>
 __global__ __launch_bounds__(256) void kb_update_apply(const BatchJob *__restrict__ jobs,
-                                                       const uint32_t *__restrict__ ids, uint32_t round) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
-    body_update_apply<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+                                                       const uint32_t *__restrict__ ids,
+                                                       const uint32_t *__restrict__ off, uint32_t njobs,
+                                                       uint32_t round) {
+    BatchBlock b;
+    if (!batch_block(jobs, ids, off, njobs, round, b)) return;
+    body_update_apply<STATS>(b.J->a, b.base, b.count, b.bx, b.gx);
 }
 
 template <bool STATS>
 __global__ __launch_bounds__(256) void kb_update_finish(const BatchJob *__restrict__ jobs,
-                                                        const uint32_t *__restrict__ ids, uint32_t round) {
-    const BatchJob &J = jobs[ids[blockIdx.y]];
-    uint32_t base, count;
-    if (!batch_epoch(J, round, base, count) || blockIdx.x * 256u >= count) return;
-    body_update_finish<STATS>(J.a, base, count, blockIdx.x, gridDim.x);
+                                                        const uint32_t *__restrict__ ids,
+                                                        const uint32_t *__restrict__ off, uint32_t njobs,
+                                                        uint32_t round) {
+    BatchBlock b;
+    if (!batch_block(jobs, ids, off, njobs, round, b)) return;
+    body_update_finish<STATS>(b.J->a, b.base, b.count, b.bx, b.gx);
 }
 
-// Plain jobs: one flat grid, each job getting blocks in proportion to its
-// rays; block_off[k] is the first block of the group's k-th job (count + 1
-// entries), found by binary search.
+// Plain jobs: one flat grid, each job getting blocks in proportion to its rays.
 template <bool ANY, bool STATS>
 __global__ __launch_bounds__(128) void kb_traverse_plain(const BatchJob *__restrict__ jobs,
                                                          const uint32_t *__restrict__ ids,
                                                          const uint32_t *__restrict__ block_off, uint32_t count) {
-    uint32_t lo = 0, hi = count;   // find k with block_off[k] <= blockIdx.x < block_off[k + 1]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (block_off[mid] <= blockIdx.x) lo = mid;
-        else hi = mid;
-    }
-    const BatchJob &J = jobs[ids[lo]];
-    body_traverse_plain<ANY, STATS>(J.a, J.n, blockIdx.x - block_off[lo], block_off[lo + 1] - block_off[lo]);
+    const uint32_t k = batch_job_of(block_off, count, blockIdx.x);
+    const BatchJob &J = jobs[ids[k]];
+    body_traverse_plain<ANY, STATS>(J.a, J.n, blockIdx.x - block_off[k], block_off[k + 1] - block_off[k]);
 }
 
 // Fill a region with a 32-bit pattern (predictor reset; a kernel rather than
@@ -1485,21 +1517,25 @@ namespace hrpp {
 template <bool ANY, bool EXACT, bool STATS>
 static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, uint32_t r,
                                hipStream_t s) {
-    const dim3 g256(ceil_div(g.max_epoch, 256), g.count), g128(std::min(ceil_div(g.max_epoch, 128), 4096u), g.count);
     const uint32_t *gid = ids + g.first_id;
+    const uint32_t nj = g.count;
     const size_t lds = 0;   // traversal stacks live in private memory
-    const dim3 gp(ceil_div(g.max_epoch, 128), g.count);
+    const dim3 g128(g.blocks128), g256(g.blocks256), gq(g.blocksq);
     if (g.subtree)
-        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, true, true>), gp, dim3(128), lds, s, jobs, gid, r);
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, true, true>), g128, dim3(128), lds, s, jobs, gid,
+                           g.d_off128, nj, r);
     else if (g.inline_any)
-        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, true>), gp, dim3(128), lds, s, jobs, gid, r);
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, true>), g128, dim3(128), lds, s, jobs, gid,
+                           g.d_off128, nj, r);
     else
-        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, false>), g256, dim3(256), 0, s, jobs, gid, r);
-    hipLaunchKernelGGL((kb_traverse_queue<ANY, EXACT, STATS>), g128, dim3(128), lds, s, jobs, gid, r);
-    hipLaunchKernelGGL((kb_update_classify<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
-    hipLaunchKernelGGL(kb_update_rank, g256, dim3(256), 0, s, jobs, gid, r);
-    hipLaunchKernelGGL((kb_update_apply<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
-    if (STATS) hipLaunchKernelGGL((kb_update_finish<STATS>), g256, dim3(256), 0, s, jobs, gid, r);
+        hipLaunchKernelGGL((kb_predict<ANY, EXACT, STATS, false, false>), g256, dim3(256), 0, s, jobs, gid,
+                           g.d_off256, nj, r);
+    hipLaunchKernelGGL((kb_traverse_queue<ANY, EXACT, STATS>), gq, dim3(128), lds, s, jobs, gid, g.d_offq, nj, r);
+    hipLaunchKernelGGL((kb_update_classify<STATS>), g256, dim3(256), 0, s, jobs, gid, g.d_off256, nj, r);
+    hipLaunchKernelGGL(kb_update_rank, g256, dim3(256), 0, s, jobs, gid, g.d_off256, nj, r);
+    hipLaunchKernelGGL((kb_update_apply<STATS>), g256, dim3(256), 0, s, jobs, gid, g.d_off256, nj, r);
+    if (STATS)
+        hipLaunchKernelGGL((kb_update_finish<STATS>), g256, dim3(256), 0, s, jobs, gid, g.d_off256, nj, r);
 }
 
 template <bool ANY, bool STATS>
