@@ -209,8 +209,8 @@ hrpp_status hrpp_bvh_upload(hrpp_bvh *bvh, void *d_buf, size_t bytes, void *stre
  * different tree from the host builder's SAH tree, with the same query
  * results.
  *
- * Scratch bytes the build needs for num_tris triangles (0 when num_tris is 0
- * or >= 2^28, or when no HIP device answers the sort's size query). */
+ * Scratch bytes the build needs for num_tris triangles, about 121 per
+ * triangle (0 when num_tris is 0 or >= 2^28). */
 size_t hrpp_bvh_device_build_scratch_bytes(uint32_t num_tris);
 
 /* d_verts: device array of 9 floats per triangle (original order =
@@ -241,7 +241,7 @@ hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const
  * several host threads) race and must be serialised by the caller.  Errors
  * as hrpp_build_bvh_device, plus ENOMEM when the build needs more than the
  * static 64 MiB (hrpp_bvh_device_build_scratch_bytes(num_tris) > 64 MiB:
- * about 470,000 triangles and more; then nothing is enqueued). */
+ * from about 554,000 triangles on; then nothing is enqueued). */
 hrpp_status hrpp_build_bvh_device_static(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
                                          void *d_buf, size_t bytes, void *stream, hrpp_bvh **out);
 

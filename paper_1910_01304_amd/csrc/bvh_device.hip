@@ -24,9 +24,10 @@
 // dependency is a kernel boundary.  In launch order:
 //   k_lbvh_bounds / k_lbvh_bounds_final  centre bounds (per-block partials)
 //   k_lbvh_codes, radix sort             Morton codes in (code, id) order
+//                                        (device_sort.hip)
 //   k_lbvh_karras                        each internal node's range and split
 //   k_lbvh_mark, exclusive scan          output leaves starting before each
-//                                        sorted position
+//                                        sorted position (device_sort.hip)
 //   k_lbvh_number                        depth and DFS pre-order index
 //   k_lbvh_leaf_boxes, k_lbvh_level      leaf boxes, then interior boxes one
 //                                        depth at a time, deepest first
@@ -36,12 +37,12 @@
 // k leaves has 2k - 1 nodes, so index = 2 * (output leaves before its first
 // position) + (ancestors it descends from on the left).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstdint>
 #include <mutex>
 
+#include "device_sort.h"
 #include "hrpp_internal.h"
 #include "hrpp_kernels.h"
 
@@ -398,29 +399,22 @@ __global__ __launch_bounds__(256) void k_lbvh_emit(Tree tr, const float *__restr
 }
 
 struct ScratchLayout {
-    size_t hdr, partial, code_in, code_out, id_in, perm, sort_tmp, sort_tmp_bytes, scan_tmp, scan_tmp_bytes, parent,
-        left, right, lo, hi, mark, lb, pre, dep, box, total;
+    size_t hdr, partial, code_a, code_b, id_a, id_b, sort_tmp, scan_tmp, parent, left, right, lo, hi, mark, lb, pre,
+        dep, box, total;
 };
 
 ScratchLayout scratch_layout(uint32_t n) {
     ScratchLayout L{};
-    size_t sort_tmp = 0, scan_tmp = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                           (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)n, 0, 63,
-                                           (hipStream_t)0) != hipSuccess ||
-        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_tmp, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                         (int)n + 1, (hipStream_t)0) != hipSuccess)
-        return L;   // total = 0
     const size_t N = n, M = 2 * (size_t)n - 1, I = n > 1 ? (size_t)n - 1 : 1;
     size_t off = 0;
     L.hdr = off; off += 256;
     L.partial = off; off += align256((size_t)kBoundBlocks * 7 * 4);
-    L.code_in = off; off += align256(N * 8);
-    L.code_out = off; off += align256(N * 8);
-    L.id_in = off; off += align256(N * 4);
-    L.perm = off; off += align256(N * 4);
-    L.sort_tmp = off; L.sort_tmp_bytes = sort_tmp; off += align256(sort_tmp);
-    L.scan_tmp = off; L.scan_tmp_bytes = scan_tmp; off += align256(scan_tmp);
+    L.code_a = off; off += align256(N * 8);      // codes and ids, then the sort's two buffers
+    L.code_b = off; off += align256(N * 8);
+    L.id_a = off; off += align256(N * 4);
+    L.id_b = off; off += align256(N * 4);
+    L.sort_tmp = off; off += align256(radix_sort_scratch_bytes(n));
+    L.scan_tmp = off; off += align256(exclusive_scan_scratch_bytes(n + 1));
     L.parent = off; off += align256(M * 4);
     L.left = off; off += align256(I * 4);
     L.right = off; off += align256(I * 4);
@@ -479,10 +473,10 @@ hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint3
     char *base = static_cast<char *>(d_scratch);
     auto *h = reinterpret_cast<LbvhHeader *>(base + L.hdr);
     auto *partial = reinterpret_cast<uint32_t *>(base + L.partial);
-    auto *code_in = reinterpret_cast<uint64_t *>(base + L.code_in);
-    auto *code_out = reinterpret_cast<uint64_t *>(base + L.code_out);
-    auto *id_in = reinterpret_cast<uint32_t *>(base + L.id_in);
-    auto *perm = reinterpret_cast<uint32_t *>(base + L.perm);
+    auto *code_a = reinterpret_cast<uint64_t *>(base + L.code_a);
+    auto *code_b = reinterpret_cast<uint64_t *>(base + L.code_b);
+    auto *id_a = reinterpret_cast<uint32_t *>(base + L.id_a);
+    auto *id_b = reinterpret_cast<uint32_t *>(base + L.id_b);
     auto *parent = reinterpret_cast<uint32_t *>(base + L.parent);
     auto *left = reinterpret_cast<uint32_t *>(base + L.left);
     auto *right = reinterpret_cast<uint32_t *>(base + L.right);
@@ -501,17 +495,18 @@ hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint3
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lbvh_bounds, dim3(bound_blocks), dim3(256), 0, s, d_verts, n, partial);
     hipLaunchKernelGGL(k_lbvh_bounds_final, dim3(1), dim3(256), 0, s, partial, bound_blocks, h, parent);
-    hipLaunchKernelGGL(k_lbvh_codes, grid_for(n, 256), dim3(256), 0, s, d_verts, n, h, code_in, id_in);
-    size_t tmp = L.sort_tmp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(base + L.sort_tmp, tmp, code_in, code_out, id_in, perm, (int)n, 0, 63, s);
+    hipLaunchKernelGGL(k_lbvh_codes, grid_for(n, 256), dim3(256), 0, s, d_verts, n, h, code_a, id_a);
+    uint32_t sorted_in = 0;
+    e = radix_sort_pairs(code_a, id_a, code_b, id_b, n, 63, base + L.sort_tmp, s, &sorted_in);
     if (e != hipSuccess) return e;
+    const uint64_t *code_out = sorted_in ? code_b : code_a;   // codes in (code, id) order
+    const uint32_t *perm = sorted_in ? id_b : id_a;            // their primitive ids
     if (n_internal)
         hipLaunchKernelGGL(k_lbvh_karras, grid_for(n_internal, 256), dim3(256), 0, s, code_out, n, parent, left,
                            right, lo, hi);
     Tree tr{n, leaf_max, parent, left, right, lo, hi};
     hipLaunchKernelGGL(k_lbvh_mark, grid_for((size_t)n + 1, 256), dim3(256), 0, s, tr, mark);
-    tmp = L.scan_tmp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(base + L.scan_tmp, tmp, mark, lb, (int)n + 1, s);
+    e = exclusive_scan_u32(mark, lb, n + 1, base + L.scan_tmp, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lbvh_number, grid_for(m, 256), dim3(256), 0, s, tr, lb, pre, dep, h);
     e = hipGetLastError();

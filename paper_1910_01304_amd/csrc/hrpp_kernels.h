@@ -164,7 +164,7 @@ struct LbvhResult {
     uint32_t max_depth, num_nodes;
     float root_box[6];
 };
-// Scratch bytes for n triangles (0 when the sort's size query fails).
+// Scratch bytes for n triangles (0 for n = 0).
 size_t lbvh_scratch_bytes(uint32_t n);
 // The device build's static scratch (one per GPU, kStaticBuildScratchBytes):
 // its device address on the current device, looked up on first use.
