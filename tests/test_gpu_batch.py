@@ -162,3 +162,44 @@ def test_batch_rejects_shared_predictor(hrpp):
     r = torch.from_numpy(sg.tiny_shadow_rays(5, 300)).cuda()
     with pytest.raises(hrpp.HrppError):
         hrpp.Batch([dict(bvh=bvh, pred=p, rays=r), dict(bvh=bvh, pred=p, rays=r)])
+
+
+def test_batch_many_jobs_per_group(hrpp):
+    # 140 predictor jobs in one group and 70 plain ones: each launch's flat
+    # grid finds a block's job among more than 64 offsets (several wave-wide
+    # rounds), so jobs past the first 64 are placed correctly; every job is
+    # checked against the oracle
+    import torch
+    _say("batch: many jobs per group")
+    scenes = []
+    for s in range(5):
+        tris = sg.mixed_scene(40 + s, 300 + 400 * s)
+        scenes.append((tris, hrpp.BVH(tris), oracle.build_sah(tris)))
+    rng = np.random.default_rng(7)
+    jobs, specs = [], []
+    for k in range(210):
+        tris, bvh, ob = scenes[k % len(scenes)]
+        n = int(rng.integers(1, 3000))
+        sh, ao = sg.secondary_rays_on_surface(tris, n, 500 + k)
+        rays = np.ascontiguousarray(np.concatenate([sh, ao]))
+        pc = None if k >= 140 else (int(rng.integers(6, 12)), 4, 5, 6, int(rng.integers(64, 1024)))
+        specs.append((tris, ob, rays, pc))
+        jobs.append(dict(bvh=bvh, rays=torch.from_numpy(rays).cuda(), query="any"))
+    for use_graph in (False, True):
+        preds = [hrpp.Predictor(j["bvh"], *pc) if pc else None for j, (_, _, _, pc) in zip(jobs, specs)]
+        stats = [hrpp.new_stats() for _ in jobs]
+        b = hrpp.Batch([dict(j, pred=p, stats=s) for j, p, s in zip(jobs, preds, stats)])
+        torch.cuda.synchronize()
+        b.launch(use_graph=use_graph)
+        torch.cuda.synchronize()
+        hrpp.get_error()
+        for k, (tris, ob, rays, pc) in enumerate(specs):
+            tb = oracle.Table(*pc[:4]) if pc else None
+            want, ws = oracle.trace(ob, tris, rays, query="any", table=tb, epoch=pc[4] if pc else 1 << 30)
+            assert b.outputs[k].cpu().numpy().tobytes() == want.tobytes(), f"job {k}: results (graph={use_graph})"
+            got = _method_stats(hrpp, stats[k])
+            assert {n: v for n, v in got.items() if n in ws} == ws, f"job {k}: counters (graph={use_graph})"
+            if pc:
+                tags, slots = preds[k].export()
+                assert np.array_equal(tags, tb.tags) and np.array_equal(slots, tb.slots), f"job {k}: table"
+        b.close()
