@@ -262,7 +262,6 @@ template <bool ANY>
 __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best &b, Counters &c, uint32_t ref,
                                      uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     const float4 *__restrict__ nodes = (const float4 *)a.nodes;
-    const float4 *__restrict__ tris = (const float4 *)a.tris;
     float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
     bool found = (b.prim != kNone);
     // sp nodes are deferred: the newest (entry sp - 1) is held in registers
@@ -625,7 +624,6 @@ template <bool ANY>
 __device__ __forceinline__ bool traverse_wide(const TraceArgs &a, const RayState &r, Best &b, Counters &c,
                                               uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     const float4 *__restrict__ wn = (const float4 *)a.wide;
-    const float4 *__restrict__ tris = (const float4 *)a.tris;
     float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
     bool found = (b.prim != kNone);
     float tn;
