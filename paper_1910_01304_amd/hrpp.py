@@ -93,7 +93,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise HrppError(f"HRPP HIP library not built: {path} is missing (run __graft_entry__.build())")
+        raise HrppError(f"HRPP HIP library not built: {path} is missing (run python -m paper_1910_01304_amd.build)")
     lib = C.CDLL(path)
     vp, u32, sz = C.c_void_p, C.c_uint32, C.c_size_t
     lib.hrpp_bvh_required_bytes.restype = sz

@@ -60,7 +60,7 @@ def test_autotune_warm_tables():
 
 def test_autotune_leaf_size():
     # with a tree builder the tuner also picks the leaf size; each size is built
-    # once and judged against its own plain traversal
+    # once and compared with its own plain traversal
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
