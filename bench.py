@@ -791,6 +791,22 @@ def main():
             hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc)
 
         ms_t_h = timed(torch, tiny_hrpp, args.steps, 2)[0]
+        eager_out = tocc.clone()
+        # the same trace as a one-job batch captured once as a hipGraph and
+        # replayed (the reset stays a launch of its own): launch costs fall,
+        # the work is the same, and the results must be the eager call's
+        tgo = torch.empty_like(tocc)
+        tbatch = hrpp.Batch([dict(bvh=tbvh, pred=tpred, rays=tr_d, query="any", out=tgo)])
+
+        def tiny_graph():
+            tpred.reset()
+            tbatch.launch(use_graph=True)
+
+        ms_t_g = timed(torch, tiny_graph, args.steps, 2)[0]
+        torch.cuda.synchronize()
+        if not torch.equal(tgo, eager_out):
+            raise SystemExit("tiny configuration: the graph-replayed batch differs from the eager call")
+        tbatch.close()
         ms_t_p = timed(torch, lambda: hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc), args.steps, 2)[0]
         tsh, tsp = hrpp.new_stats(), hrpp.new_stats()
         tpred.reset()
@@ -799,6 +815,7 @@ def main():
         th, tp = hrpp.stats_dict(tsh), hrpp.stats_dict(tsp)
         nt = trays.shape[0]
         tiny_info = dict(rays=nt, query="any hit", epoch_rays=tw["epoch"], hrpp_mrays_s=round(mrays(nt, ms_t_h), 2),
+                         graph_hrpp_mrays_s=round(mrays(nt, ms_t_g), 2), graph_hrpp_ms=round(ms_t_g, 4),
                          plain_mrays_s=round(mrays(nt, ms_t_p), 2), hrpp_ms=round(ms_t_h, 4),
                          plain_ms=round(ms_t_p, 4), pct_nodes_skipped=round(pct_saved("nodes_visited", th, tp), 3),
                          pct_box_tests_skipped=round(pct_saved("box_tests", th, tp), 3),
