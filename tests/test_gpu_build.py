@@ -39,7 +39,11 @@ def _dev(tris):
 
 
 @pytest.mark.parametrize("n,leaf_max", [(1, 4), (3, 4), (4, 4), (5, 4), (64, 1), (257, 2), (3000, 4), (3000, 8),
-                                        (4097, 3), (70001, 4)])
+                                        (4097, 3), (70001, 4),
+                                        # the sort's sub-tiles of 1,024 items and the prefix sum's
+                                        # tiles of 4,096 words (n + 1 of them): sizes at both edges
+                                        (1023, 2), (1024, 2), (1025, 2), (2048, 1), (2049, 2), (4094, 2),
+                                        (4095, 2), (4096, 2), (8191, 2), (8193, 2), (263169, 2)])
 def test_device_build_equals_oracle(hrpp, n, leaf_max):
     _say(f"device build soup n={n} leaf_max={leaf_max}")
     tris = sg.triangle_soup(70 + n, n)
