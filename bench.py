@@ -108,6 +108,8 @@ def parse():
     ap.add_argument("--serve-replicas", type=int, default=2, help="predictor replicas per scene and query kind")
     ap.add_argument("--probe", default="step", choices=("step", "ao"),
                     help="--traffic-probe workload: the at-scale step's queries, or the incoherent AO rays")
+    ap.add_argument("--ao-log2-entries", type=int, default=0,
+                    help="--probe ao: the AO predictor's table size (log2 entries; 0 = the workload's)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 256 MiB calibration copy, then one HRPP and one plain step (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"),
@@ -449,7 +451,7 @@ def main():
                                       samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
             ao_d = torch.from_numpy(ao).cuda()
             ao_out = torch.empty(ao.shape[0], dtype=torch.uint8, device="cuda")
-            pred_ao = hrpp.Predictor(bvh, log2_entries=wi["log2_entries"], ways=wi["ways"],
+            pred_ao = hrpp.Predictor(bvh, log2_entries=args.ao_log2_entries or wi["log2_entries"], ways=wi["ways"],
                                      origin_bits=wi["origin_bits"], dir_bits=wi["dir_bits"], epoch_rays=wi["epoch"],
                                      inline_lanes=wi["inline_lanes"], first_epoch_rays=wi["first_epoch"])
             torch.cuda.synchronize()
