@@ -9,7 +9,7 @@
 //                append theirs to the epoch's fallback queue (one atomic per
 //                block on one of kSubQueues striped counters).
 //   k_epoch_empty  the first epoch after a reset (empty table): every valid
-//                ray traverses, in a persistent loop.
+//                ray traverses, one lane per ray, without reading the table.
 //   k_traverse_queue  stack traversal of the queued rays.
 //                A traversed ray with a hit emits one update record and
 //                claims the record's entry with a 32-bit atomicMin on the ray
