@@ -382,13 +382,16 @@ AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin
                 # of up to 4 straddle cells, and plain and HRPP traversal both run faster
                 # with leaves of 2 (measured at leaf sizes 1 to 4)
                 leaf_max=2)
-# the AO predictor: q_o 6, q_d 5, a first epoch of 2^16 rays then epochs of 2^22,
-# waves with >= 16 failing lanes traverse in place (the autotuner's choice); a
-# table of 2^16 x 8 entries (4 MB), which stays in the last-level cache: the
-# randomly addressed lookups of short incoherent rays missed it at 2^20 (64 MB),
-# and a sweep of 2^16 .. 2^20 entries ran fastest at the smallest
+# the AO predictor: q_o 6, q_d 5, epochs of 2^22 rays (the largest; 7,372,800 rays
+# make two), waves with >= 16 failing lanes traverse in place; a table of 2^16 x 8
+# entries (4 MB), which stays in the last-level cache: the randomly addressed
+# lookups of short incoherent rays missed it at 2^20 (64 MB), and a sweep of
+# 2^16 .. 2^20 entries ran fastest at the smallest.  With the 2^20 table a short
+# first epoch (2^16 rays) paid off; with 2^16 entries, which predict fewer rays,
+# the schedule with the fewest epochs runs fastest (a sweep of first epochs 0 and
+# 2^16 .. 2^18, epochs 2^21 and 2^22, in-place thresholds 1, 16, 32)
 INCOHERENT = dict(seed=3, width=1280, height=720, samples=8, log2_entries=16, ways=8, origin_bits=6,
-                  dir_bits=5, epoch=1 << 22, inline_lanes=16, first_epoch=1 << 16, tmax_frac=0.05)
+                  dir_bits=5, epoch=1 << 22, inline_lanes=16, first_epoch=0, tmax_frac=0.05)
 
 
 def tiny_workload():
