@@ -92,8 +92,9 @@ def parse():
                     help="inline_lanes of the batched and serving predictors (-1: the workload's default)")
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--batch-epoch", type=int, default=1 << 17)
-    ap.add_argument("--batch-rounds", type=int, default=8,
-                    help="batched workload: size each job's epoch for about this many rounds (0 = --batch-epoch)")
+    ap.add_argument("--batch-rounds", type=int, default=-1,
+                    help="batched workload: size each job's epoch for about this many rounds (0 = --batch-epoch; "
+                         "-1 = choose 2, 4 or 8 by measured batch time)")
     ap.add_argument("--scene-leaf-max", type=int, default=2,
                     help="leaf size of the batched and serving scenes' BVHs (the at-scale scene uses its own)")
     ap.add_argument("--tune-queries", default="",
@@ -1766,11 +1767,12 @@ def run_batched(args, np, torch, hrpp, sg):
     # about the same number of rounds (so the rounds stay full to the end instead of
     # ending with the largest scenes alone), clamped to [2^14, 2^22]
     from paper_1910_01304_amd import autotune
-    rounds_target = args.batch_rounds
+    rounds_auto = args.batch_rounds < 0
+    rounds_target = 4 if rounds_auto else args.batch_rounds   # the tuner's epochs; the sweep below may change them
 
-    def job_epoch(n):
+    def job_epoch(n, rounds=None):
         e = 1 << 14
-        while e < (1 << 22) and e * rounds_target < n:
+        while e < (1 << 22) and e * (rounds or rounds_target) < n:
             e <<= 1
         return e
 
@@ -1789,6 +1791,32 @@ def run_batched(args, np, torch, hrpp, sg):
             f"q_o {res.best['origin_bits']} q_d {res.best['dir_bits']} epoch {res.best['epoch_rays']}")
     tune_s = time.perf_counter() - t_tune
     log(f"batched: autotuned {len(tuned)} scenes in {tune_s:.1f} s")
+    outs = [torch.empty(r.shape[0], dtype=torch.uint8, device="cuda") for r in rays_d]
+    steps = max(1, args.steps // 2)
+    rounds_sweep = None
+    if rounds_auto:
+        # the chunk size (each job's epoch) of the batch: about 2, 4 or 8 rounds per
+        # job, with the scenes' tuned tables, chosen by measured batch time (never one
+        # round: a job of a single epoch would meet only the reset table)
+        rounds_sweep = {}
+        for rr in (2, 4, 8):
+            ps = [hrpp.Predictor(b, **dict({k: v for k, v in c.items() if k in (
+                      "log2_entries", "ways", "origin_bits", "dir_bits", "inline_lanes")},
+                      epoch_rays=job_epoch(r.shape[0], rr))) for b, c, r in zip(bvhs, tuned, rays_d)]
+            bt = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o) for b, p, r, o in zip(bvhs, ps, rays_d, outs)])
+
+            def step_r():
+                for p in ps:
+                    p.reset()
+                bt.launch(use_graph=True)
+
+            rounds_sweep[rr] = round(total / (timed(torch, step_r, steps, 1)[0] * 1e-3) / 1e6, 2)
+            bt.close()
+            del ps
+            log(f"batched: about {rr} rounds per job: {rounds_sweep[rr]} Mrays/s")
+        rounds_target = max(rounds_sweep, key=rounds_sweep.get)
+        for c, r in zip(tuned, rays_d):
+            c["epoch_rays"] = job_epoch(r.shape[0])
     preds = [hrpp.Predictor(b, **{k: v for k, v in c.items() if k in (
                  "log2_entries", "ways", "origin_bits", "dir_bits", "epoch_rays", "inline_lanes")})
              for b, c in zip(bvhs, tuned)]
@@ -1796,7 +1824,6 @@ def run_batched(args, np, torch, hrpp, sg):
     preds_fixed = [hrpp.Predictor(b, log2_entries=sp["log2_entries"], ways=8, origin_bits=5, dir_bits=6,
                                   epoch_rays=E, inline_lanes=il)
                    for b, sp in zip(bvhs, specs)]
-    outs = [torch.empty(r.shape[0], dtype=torch.uint8, device="cuda") for r in rays_d]
     batch = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o) for b, p, r, o in zip(bvhs, preds, rays_d, outs)])
     batch_fixed = hrpp.Batch([dict(bvh=b, pred=p, rays=r, out=o)
                               for b, p, r, o in zip(bvhs, preds_fixed, rays_d, outs)])
@@ -1820,7 +1847,6 @@ def run_batched(args, np, torch, hrpp, sg):
         for b, p, r, o in zip(bvhs, preds, rays_d, outs):
             hrpp.trace_anyhit(b, p, r, out=o)
 
-    steps = max(1, args.steps // 2)
     ms_batch = timed(torch, step_batch, steps, 1)[0]
     ms_batch_fixed = timed(torch, step_batch_fixed, steps, 1)[0]
     ms_seq = timed(torch, step_sequential, steps, 1)[0]
@@ -1866,11 +1892,13 @@ def run_batched(args, np, torch, hrpp, sg):
         "config": {"workload": f"{len(specs)} scenes (soup/heightfield 50/50, 1e4-2e6 tris log-uniform), "
                                "rays 2^16-2^22 log-uniform per scene (60% shadow, 40% AO), any-hit, "
                                "per-scene table size 2^16-2^20 x 8 and q_o, q_d 3-7 autotuned, epochs sized "
-                               f"for about {rounds_target} rounds per job",
+                               f"for about {rounds_target} rounds per job"
+                               + (" (chosen among 2, 4 and 8 by measured batch time)" if rounds_auto else ""),
                    "scenes": len(specs), "triangles": int(sum(sp["tris"] for sp in specs)), "rays": total,
                    "bvh_leaf_max": args.scene_leaf_max, "per_scene": tuned, "autotune_s": round(tune_s, 1)},
         "plain_batched_mrays_s": round(total / (ms_plain * 1e-3) / 1e6, 2),
         "speedup_vs_plain": round(ms_plain / ms_batch, 4),
+        "rounds_per_job": rounds_target, "rounds_sweep_mrays_s": rounds_sweep,
         "untuned_batched_mrays_s": round(total / (ms_batch_fixed * 1e-3) / 1e6, 2),
         "untuned_config": f"tables 2^16-2^20 (random) x 8, q 5/6, epoch {E} for every job",
         "sequential_calls_mrays_s": round(total / (ms_seq * 1e-3) / 1e6, 2),
