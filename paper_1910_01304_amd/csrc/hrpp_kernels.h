@@ -136,7 +136,7 @@ void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<B
 enum KernelKind : int {
     kKindPredict, kKindTraverseQueue, kKindTraversePlain, kKindUpdateClassify, kKindUpdateApply,
     kKindUpdateFinish, kKindFill, kKindTraverseWide, kKindEpochEmpty, kKindResetTable, kKindUpdateRank,
-    kNumKernelKinds
+    kKindEpochsBlock, kNumKernelKinds
 };
 const char *kernel_kind_name(int k);
 void profile_start();

@@ -236,8 +236,9 @@ __device__ __forceinline__ bool test_leaf(const TraceArgs &a, uint32_t leaf, con
     return changed;
 }
 
-// Traversal kernels run blocks of kTraceBlock lanes; the first entries of each
-// lane's traversal stack live in LDS (walk()).  8 entries: for closest hit 4
+// Traversal kernels run blocks of kTraceBlock lanes (BLK where a kernel runs
+// larger blocks); the first entries of each lane's traversal stack live in
+// LDS (walk()).  8 entries: for closest hit 4
 // and 12 measured slower, for any hit 4 was slower and 12 or 16 no faster;
 // 4 KB of LDS per block for any hit, 8 KB with the distances for closest hit.
 constexpr uint32_t kTraceBlock = 128;
@@ -258,7 +259,7 @@ constexpr uint32_t kLdsStackClosest = 8;
 // walk(): the subtree of `ref`, whose own box the caller has tested; from
 // the root this is the whole traversal, from a predicted node (go-up level
 // >= 1) the evaluation of that prediction.
-template <bool ANY>
+template <bool ANY, uint32_t BLK = kTraceBlock>
 __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best &b, Counters &c, uint32_t ref,
                                      uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     const float4 *__restrict__ nodes = (const float4 *)a.nodes;
@@ -268,14 +269,14 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
     // (top_ref, top_t), so a pop takes its node without waiting for memory and
     // the load of the next newest entry overlaps the work on the popped node.
     // The older entries: the first K in LDS, lane-interleaved (entry j of lane
-    // l at word j * kTraceBlock + l: the 64 lanes of a wave touch 64
+    // l at word j * BLK + l: the 64 lanes of a wave touch 64
     // consecutive words), the rest in the private stack.  Closest hit keeps
     // each entry's distance beside it.
     uint32_t sp = 0, top_ref = 0;
     float top_t = 0.0f;
     constexpr uint32_t K = ANY ? kLdsStackAny : kLdsStackClosest;
-    __shared__ uint32_t s_sn[K * kTraceBlock];
-    __shared__ float s_st[ANY ? 1 : K * kTraceBlock];
+    __shared__ uint32_t s_sn[K * BLK];
+    __shared__ float s_st[ANY ? 1 : K * BLK];
     for (;;) {
         c.v[kNodesVisited]++;
         if (!(ref & kLeafFlag)) {
@@ -298,8 +299,8 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
                 if (sp > 0) {
                     const uint32_t j = sp - 1;
                     if (j < K) {
-                        s_sn[j * kTraceBlock + threadIdx.x] = top_ref;
-                        if constexpr (!ANY) s_st[j * kTraceBlock + threadIdx.x] = top_t;
+                        s_sn[j * BLK + threadIdx.x] = top_ref;
+                        if constexpr (!ANY) s_st[j * BLK + threadIdx.x] = top_t;
                     } else {
                         stk_node[(j - K) * stride] = top_ref;
                         if constexpr (!ANY) stk_t[(j - K) * stride] = top_t;
@@ -329,8 +330,8 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
             if (sp > 0) {
                 const uint32_t j = sp - 1;
                 if (j < K) {
-                    top_ref = s_sn[j * kTraceBlock + threadIdx.x];
-                    if constexpr (!ANY) top_t = s_st[j * kTraceBlock + threadIdx.x];
+                    top_ref = s_sn[j * BLK + threadIdx.x];
+                    if constexpr (!ANY) top_t = s_st[j * BLK + threadIdx.x];
                 } else {
                     top_ref = stk_node[(j - K) * stride];
                     if constexpr (!ANY) top_t = stk_t[(j - K) * stride];
@@ -344,7 +345,7 @@ __device__ __forceinline__ bool walk(const TraceArgs &a, const RayState &r, Best
     }
 }
 
-template <bool ANY>
+template <bool ANY, uint32_t BLK = kTraceBlock>
 __device__ __forceinline__ bool traverse(const TraceArgs &a, const RayState &r, Best &b, Counters &c,
                                          uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     const float tcur = (!ANY && b.prim != kNone) ? b.t : r.tmax;
@@ -353,7 +354,7 @@ __device__ __forceinline__ bool traverse(const TraceArgs &a, const RayState &r, 
     c.v[kBoxTests]++;
     if (!slab(a.root_box[0], a.root_box[1], a.root_box[2], a.root_box[3], a.root_box[4], a.root_box[5], r, tcur, tn))
         return b.prim != kNone;
-    return walk<ANY>(a, r, b, c, a.root_ref, stk_node, stk_t, stride, cap);
+    return walk<ANY, BLK>(a, r, b, c, a.root_ref, stk_node, stk_t, stride, cap);
 }
 
 // Canonical node record: min xyz, max x | max yz, reference, depth | parent,
@@ -419,7 +420,7 @@ __device__ __forceinline__ const uint32_t *entry_ptr(const TraceArgs &a, uint32_
 // leaves or, at go-up level >= 1, walk the predicted subtrees).  Returns true
 // if the ray must still traverse; then *seed_leaf is the leaf of the best
 // predicted hit (EXACT) or kNone.
-template <bool ANY, bool EXACT, bool SUBTREE>
+template <bool ANY, bool EXACT, bool SUBTREE, uint32_t BLK = kTraceBlock>
 __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Counters &c, uint32_t &seed_leaf,
                                             uint32_t *stk_node, float *stk_t, uint32_t stride, uint32_t cap) {
     float4 ra, rb;
@@ -463,7 +464,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
             if (!slab(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, r, tcur, tn)) continue;
             const float bt = b.t;
             const uint32_t bp = b.prim;
-            const bool f = walk<ANY>(a, r, b, c, __float_as_uint(n1.z), stk_node, stk_t, stride, cap);
+            const bool f = walk<ANY, BLK>(a, r, b, c, __float_as_uint(n1.z), stk_node, stk_t, stride, cap);
             if (b.prim != bp || b.t != bt) skip_depth = __float_as_uint(n1.w);
             if (f) {
                 hit = true;
@@ -535,7 +536,7 @@ __device__ __forceinline__ bool predict_one(const TraceArgs &a, uint32_t rid, Co
 // counted by the prediction step, from the queue, in place, or in the first
 // epoch after a reset); emit its update record and claim the entry.  PLAIN:
 // validate and count here.
-template <bool ANY, bool EXACT, bool HRPP>
+template <bool ANY, bool EXACT, bool HRPP, uint32_t BLK = kTraceBlock>
 __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, uint32_t rid, uint32_t seed_leaf,
                                              Counters &c, uint32_t *stk_node, float *stk_t, uint32_t stride,
                                              uint32_t cap) {
@@ -556,7 +557,7 @@ __device__ __forceinline__ void traverse_one(const TraceArgs &a, uint32_t base, 
         const float4 s = ((const float4 *)a.hits)[rid];
         b.t = s.x; b.u = s.y; b.v = s.z; b.prim = __float_as_uint(s.w); b.leaf = seed_leaf;
     }
-    const bool hit = traverse<ANY>(a, r, b, c, stk_node, stk_t, stride, cap);
+    const bool hit = traverse<ANY, BLK>(a, r, b, c, stk_node, stk_t, stride, cap);
     write_result<ANY>(a, rid, hit, b);
     if (hit) c.v[kHits]++;
     if (HRPP) {
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(128) void k_traverse_plain(TraceArgs a, uint32_t co
 // compacted fallback queue.  Either way a ray runs the same traversal and
 // emits the same record, so results do not depend on the split.
 // ---------------------------------------------------------------------------
-template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE, uint32_t BLK = kTraceBlock>
 __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     // SUBTREE (go-up level >= 1) walks predicted nodes and INLINE traverses
     // failing rays in place, both with a traversal stack; without either the
@@ -790,7 +791,7 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
     const uint32_t i = bx * blockDim.x + threadIdx.x;
     bool enq = false;
     uint32_t seed_leaf = kNone;
-    if (i < count) enq = predict_one<ANY, EXACT, SUBTREE>(a, base + i, c, seed_leaf, stk_node, stk_t, stride, cap);
+    if (i < count) enq = predict_one<ANY, EXACT, SUBTREE, BLK>(a, base + i, c, seed_leaf, stk_node, stk_t, stride, cap);
     const bool inline_wave = INLINE && (uint32_t)__popcll(__ballot(enq)) >= a.inline_min;   // uniform per wave
     const bool now = enq && inline_wave;
     enq = enq && !inline_wave;
@@ -814,7 +815,7 @@ __device__ __forceinline__ void body_predict(const TraceArgs &a, uint32_t base, 
         const uint32_t pos = s_base + wave_off + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
         a.queue[(size_t)sub * a.queue_subcap + pos] = (uint64_t)(base + i) | ((uint64_t)seed_leaf << 32);
     }
-    if (INLINE && now) traverse_one<ANY, EXACT, true>(a, base, base + i, seed_leaf, c, stk_node, stk_t, stride, cap);
+    if (INLINE && now) traverse_one<ANY, EXACT, true, BLK>(a, base, base + i, seed_leaf, c, stk_node, stk_t, stride, cap);
     flush_counters<STATS>(c, a.stats);
 }
 
@@ -830,8 +831,8 @@ __global__ __launch_bounds__(256) void k_predict(TraceArgs a, uint32_t base, uin
 // entry reads and the queue; a grid-stride loop like plain traversal,
 // launched with one lane per ray.
 // ---------------------------------------------------------------------------
-template <bool ANY, bool EXACT, bool STATS>
-__global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base, uint32_t count) {
+template <bool ANY, bool EXACT, bool STATS, uint32_t BLK = kTraceBlock>
+__device__ __forceinline__ void body_epoch_empty(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     uint32_t stk_node[kMaxDepth];                // per-lane stack in private memory
     float stk_t[ANY ? 1 : kMaxDepth];
     const uint32_t stride = 1;
@@ -839,8 +840,8 @@ __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base,
     Counters c;
     c.zero();
     bind_touch<STATS>(c, a, kTouchEmpty);
-    const uint32_t step = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += step) {
+    const uint32_t step = gx * blockDim.x;
+    for (uint32_t i = bx * blockDim.x + threadIdx.x; i < count; i += step) {
         const uint32_t rid = base + i;
         float4 ra, rb;
         load_ray((const float4 *)a.rays, rid, ra, rb);
@@ -858,7 +859,7 @@ __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base,
             h.x = __builtin_inff(); h.y = 0.0f; h.z = 0.0f; h.w = __uint_as_float(kNone);
             ((float4 *)a.hits)[rid] = h;
         }
-        traverse_one<ANY, EXACT, true>(a, base, rid, kNone, c, stk_node, stk_t, stride, cap);
+        traverse_one<ANY, EXACT, true, BLK>(a, base, rid, kNone, c, stk_node, stk_t, stride, cap);
     }
     // schedule counters: all of this kernel's work is first-epoch work
     c.v[kEmptyRays] = c.v[kRays];
@@ -868,11 +869,16 @@ __global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base,
     flush_counters<STATS>(c, a.stats);
 }
 
+template <bool ANY, bool EXACT, bool STATS>
+__global__ __launch_bounds__(128) void k_epoch_empty(TraceArgs a, uint32_t base, uint32_t count) {
+    body_epoch_empty<ANY, EXACT, STATS>(a, base, count, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Traversal of the epoch's fallback queue (its length is read on the device;
 // the grid covers the epoch, lanes past the queue's end exit at once).
 // ---------------------------------------------------------------------------
-template <bool ANY, bool EXACT, bool STATS>
+template <bool ANY, bool EXACT, bool STATS, uint32_t BLK = kTraceBlock>
 __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t base, uint32_t count, uint32_t bx, uint32_t gx) {
     uint32_t stk_node[kMaxDepth];                // per-lane stack in private memory
     float stk_t[ANY ? 1 : kMaxDepth];
@@ -906,7 +912,7 @@ __device__ __forceinline__ void body_traverse_queue(const TraceArgs &a, uint32_t
             }
         }
         const uint64_t q = a.queue[(size_t)sub * a.queue_subcap + off];
-        traverse_one<ANY, EXACT, true>(a, base, (uint32_t)q, (uint32_t)(q >> 32), c, stk_node, stk_t, stride, cap);
+        traverse_one<ANY, EXACT, true, BLK>(a, base, (uint32_t)q, (uint32_t)(q >> 32), c, stk_node, stk_t, stride, cap);
     }
     // schedule counters: all of this kernel's work is queued fallback work
     c.v[kQueueTraversals] = c.v[kTraversals];
@@ -1149,6 +1155,58 @@ __global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t bas
 }
 
 // ---------------------------------------------------------------------------
+// A whole call in one workgroup, for epochs of at most kBlockEpoch rays.  The
+// workgroup runs each epoch's prediction (or first-epoch traversal), queue
+// traversal and update passes in order, with a workgroup barrier where the
+// multi-launch form has a kernel boundary; it calls the same bodies, the
+// epoch split into chunks of blockDim lanes (chunk k playing block k), so
+// every result, record, table entry and counter equals the multi-launch
+// form's.  With small epochs a call is otherwise a chain of four or five
+// launches per epoch whose cost is mostly launch and drain.  The waves of a
+// workgroup run on one compute unit and share its L1 cache; the barrier
+// (a workgroup-scope release and acquire) makes every phase's stores and
+// atomics visible to the next phase's loads.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBlockEpoch = 256;
+
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
+__device__ __forceinline__ void body_epochs_block(const TraceArgs &a, uint32_t n, uint32_t first, uint32_t epoch,
+                                                  bool empty_table) {
+    for (uint32_t base = 0; base < n;) {
+        const uint32_t cnt = min(base == 0 ? first : epoch, n - base);
+        const uint32_t chunks = (cnt + blockDim.x - 1) / blockDim.x;
+        if (base == 0 && empty_table) {
+            body_epoch_empty<ANY, EXACT, STATS, kBlockEpoch>(a, base, cnt, 0, 1);
+        } else {
+            for (uint32_t k = 0; k < chunks; k++)
+                body_predict<ANY, EXACT, STATS, SUBTREE, INLINE, kBlockEpoch>(a, base, cnt, k, chunks);
+            if (a.inline_min > 1) {
+                __syncthreads();
+                body_traverse_queue<ANY, EXACT, STATS, kBlockEpoch>(a, base, cnt, 0, 1);
+            }
+        }
+        __syncthreads();
+        for (uint32_t k = 0; k < chunks; k++) body_update_classify<STATS>(a, base, cnt, k, chunks);
+        __syncthreads();
+        for (uint32_t k = 0; k < chunks; k++) body_update_rank(a, base, cnt, k, chunks);
+        __syncthreads();
+        for (uint32_t k = 0; k < chunks; k++) body_update_apply<STATS>(a, base, cnt, k, chunks);
+        __syncthreads();
+        if (STATS) {
+            for (uint32_t k = 0; k < chunks; k++) body_update_finish<STATS>(a, base, cnt, k, chunks);
+            __syncthreads();
+        }
+        base += cnt;
+    }
+}
+
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
+__global__ __launch_bounds__(kBlockEpoch) void k_epochs_block(TraceArgs a, uint32_t n, uint32_t first,
+                                                              uint32_t epoch, uint32_t empty_table) {
+    body_epochs_block<ANY, EXACT, STATS, SUBTREE, INLINE>(a, n, first, epoch, empty_table != 0);
+}
+
+// ---------------------------------------------------------------------------
 // Batched execution: many independent (BVH, predictor, rays) jobs.  Round r
 // runs epoch r of every job of a group in one launch per kernel, over a flat
 // grid in which each job owns as many blocks as its longest epoch needs; each
@@ -1343,7 +1401,7 @@ const char *kernel_kind_name(int k) {
     static const char *names[kNumKernelKinds] = {"k_predict", "k_traverse_queue", "k_traverse_plain",
                                                  "k_update_classify", "k_update_apply", "k_update_finish",
                                                  "k_fill32", "k_traverse_wide", "k_epoch_empty", "k_reset_table",
-                                                 "k_update_rank"};
+                                                 "k_update_rank", "k_epochs_block"};
     return (k >= 0 && k < kNumKernelKinds) ? names[k] : "unknown";
 }
 
@@ -1429,6 +1487,22 @@ static void launch_epoch(const TraceArgs &a, uint32_t base, uint32_t count, bool
     }
 }
 
+template <bool ANY, bool EXACT, bool STATS>
+static void launch_epochs_block(const TraceArgs &a, uint32_t n, uint32_t first, uint32_t epoch, bool empty_table,
+                                hipStream_t s) {
+    ProfScope p(kKindEpochsBlock, s);
+    const dim3 g(1), b(kBlockEpoch);
+    const uint32_t e0 = empty_table ? 1u : 0u;
+    const bool inl = a.inline_min <= 64;
+    if (a.go_up != 0) {
+        if (inl) hipLaunchKernelGGL((k_epochs_block<ANY, EXACT, STATS, true, true>), g, b, 0, s, a, n, first, epoch, e0);
+        else     hipLaunchKernelGGL((k_epochs_block<ANY, EXACT, STATS, true, false>), g, b, 0, s, a, n, first, epoch, e0);
+    } else {
+        if (inl) hipLaunchKernelGGL((k_epochs_block<ANY, EXACT, STATS, false, true>), g, b, 0, s, a, n, first, epoch, e0);
+        else     hipLaunchKernelGGL((k_epochs_block<ANY, EXACT, STATS, false, false>), g, b, 0, s, a, n, first, epoch, e0);
+    }
+}
+
 template <bool ANY, bool STATS>
 static void launch_plain(const TraceArgs &a, uint32_t n, hipStream_t s) {
     const size_t lds = 0;   // the traversal stack lives in private memory
@@ -1446,6 +1520,20 @@ void launch_trace(const TraceArgs &args, uint32_t n, bool any, bool exact, bool 
     if (!hrpp) {
         if (any) { if (st) launch_plain<true, true>(args, n, s); else launch_plain<true, false>(args, n, s); }
         else     { if (st) launch_plain<false, true>(args, n, s); else launch_plain<false, false>(args, n, s); }
+        return;
+    }
+    if (first_epoch <= kBlockEpoch && epoch <= kBlockEpoch) {
+        // small epochs: the whole call in one workgroup, one launch
+        if (any) {
+            if (st) launch_epochs_block<true, false, true>(args, n, first_epoch, epoch, empty_table, s);
+            else    launch_epochs_block<true, false, false>(args, n, first_epoch, epoch, empty_table, s);
+        } else if (exact) {
+            if (st) launch_epochs_block<false, true, true>(args, n, first_epoch, epoch, empty_table, s);
+            else    launch_epochs_block<false, true, false>(args, n, first_epoch, epoch, empty_table, s);
+        } else {
+            if (st) launch_epochs_block<false, false, true>(args, n, first_epoch, epoch, empty_table, s);
+            else    launch_epochs_block<false, false, false>(args, n, first_epoch, epoch, empty_table, s);
+        }
         return;
     }
     for (uint32_t base = 0; base < n;) {

@@ -385,6 +385,22 @@ def test_inline_or_queued_fallback_same_results(hrpp, small_terrain, inline):
                pred_cfg=(14, 8, 5, 6, 4096, 0, 1, inline))
 
 
+@pytest.mark.parametrize("inline", [1, 32, 65])
+def test_small_epochs_one_workgroup(hrpp, small_terrain, inline):
+    # epochs of at most 256 rays: the whole call runs in one workgroup, every
+    # phase of every epoch (queue included) as the multi-launch form runs it
+    tris, prim = small_terrain
+    check_case(hrpp, f"terrain primary paper E=256 first 64 inline {inline}", tris, prim[:6000], query="closest",
+               mode="paper", pred_cfg=(12, 8, 5, 6, 256, 0, 0, inline, 0, 64), calls=2)
+    check_case(hrpp, f"terrain primary exact E=200 inline {inline}", tris, prim[:3000], query="closest",
+               mode="exact", pred_cfg=(12, 4, 4, 5, 200, 0, 0, inline))
+    ob = oracle.build_sah(tris)
+    he, _ = oracle.trace(ob, tris, prim[:5000], query="closest", mode="exact")
+    shadow = sg.shadow_rays_from_hits(tris, prim[:5000], he[:, 0], he[:, 3].view(np.uint32), seed=2)
+    check_case(hrpp, f"terrain shadow E=128 first 100 go-up 1 fifo inline {inline}", tris, shadow,
+               pred_cfg=(12, 8, 6, 3, 128, 0, 1, inline, 1, 100), calls=2)
+
+
 # ---------------------------------------------------------------------------
 # The paper's IEEE-754 bit hash (hash mode 1)
 # ---------------------------------------------------------------------------
