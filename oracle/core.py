@@ -128,8 +128,11 @@ def build_median(tris: np.ndarray, leaf_max: int = 4, max_depth: int = 100) -> C
     return _run_build(_L().orc_build_median, tris, leaf_max, max_depth)
 
 
-def build_lbvh(tris: np.ndarray, leaf_max: int = 4, max_depth: int = 64) -> CanonBVH:
-    """Linear BVH: Morton order of the triangle centres, radix-tree splits."""
+def build_lbvh(tris: np.ndarray, leaf_max: int = 4, max_depth: int = 64, treelet_passes: int = 0) -> CanonBVH:
+    """Linear BVH: Morton order of the triangle centres, radix-tree splits;
+    with treelet_passes >= 1, that many passes of treelet restructuring."""
+    if treelet_passes:
+        return _run_build(_L().orc_build_lbvh_treelet, tris, leaf_max, max_depth, treelet_passes)
     return _run_build(_L().orc_build_lbvh, tris, leaf_max, max_depth)
 
 

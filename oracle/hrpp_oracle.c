@@ -457,6 +457,217 @@ int orc_build_lbvh(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t ma
     return ctx.error ? -2 : 0;
 }
 
+/* Treelet restructuring of the linear BVH (Karras and Aila, "Fast Parallel
+   Construction of High-Quality Bounding Volume Hierarchies", HPG 2013),
+   written from its description, with this library's choices:
+   * the linear BVH's leaves (at most leaf_max triangles) stay as they are;
+     only interior nodes are rearranged;
+   * a pass visits every interior node after every interior node below it
+     (post-order).  At node r the treelet's leaves start as r's two
+     children; while there are fewer than 7, the one with the largest half
+     surface area among those that are interior nodes (the first in list
+     order on ties) is expanded: its left child takes its place in the list
+     and its right child goes to the end;
+   * the cost of a treelet topology is the sum of the half surface areas of
+     its interior nodes (what lies below the treelet's leaves is fixed).
+     The optimum over every binary tree on the leaves, by dynamic
+     programming over subsets S of the leaves: c({i}) = 0,
+     c(S) = A(S) + min over P of (c(P) + c(S \ P)), P ranging in increasing
+     bitmask order over the proper subsets of S that hold S's lowest member,
+     the first minimum kept; A(S) = half area of the union of S's boxes;
+   * the treelet is rebuilt only when the optimum is below the current
+     topology's cost (the same recurrence along the current topology).  r
+     stays the root; the other new interior nodes, in depth-first pre-order,
+     take the identities of the expanded nodes in expansion order; P (the
+     part with the lowest member) is the left child;
+   * an interior node's box is the union of its children's boxes, the left
+     child's value kept on ties, as everywhere in this library;
+   * half area of a box: dx*dy + dy*dz + dz*dx in binary32, summed left to
+     right.
+   The result is written in depth-first pre-order with the triangles in leaf
+   order. */
+#define TL_LEAVES 7
+
+typedef struct {
+    uint32_t *left, *right;    /* interior: children; leaf: right = NONE32 */
+    uint32_t *first, *count;   /* leaf: range of the linear BVH's triangle order */
+    float *box;
+} tl_tree;
+
+static float tl_half_area(const float *b)
+{
+    float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+static void tl_union(const float *l, const float *r, float *out)
+{
+    for (int a = 0; a < 3; a++) {
+        out[a] = r[a] < l[a] ? r[a] : l[a];
+        out[3 + a] = r[3 + a] > l[3 + a] ? r[3 + a] : l[3 + a];
+    }
+}
+
+static int tl_popc(uint32_t x) { int c = 0; while (x) { c += x & 1u; x >>= 1; } return c; }
+static int tl_ctz(uint32_t x) { int c = 0; while (!(x & 1u)) { x >>= 1; c++; } return c; }
+
+static void tl_treelet(tl_tree *t, uint32_t r)
+{
+    uint32_t L[TL_LEAVES], I[TL_LEAVES - 1];
+    int nl = 2, ni = 1;
+    L[0] = t->left[r]; L[1] = t->right[r]; I[0] = r;
+    while (nl < TL_LEAVES) {
+        int best = -1;
+        float ba = 0.0f;
+        for (int i = 0; i < nl; i++) {
+            if (t->right[L[i]] == NONE32) continue;
+            float a = tl_half_area(t->box + 6 * (size_t)L[i]);
+            if (best < 0 || a > ba) { best = i; ba = a; }
+        }
+        if (best < 0) break;
+        uint32_t x = L[best];
+        I[ni++] = x;
+        L[best] = t->left[x];
+        L[nl++] = t->right[x];
+    }
+    if (nl < 3) return;                 /* two leaves: one topology */
+    const uint32_t full = (1u << nl) - 1u;
+    float area[1u << TL_LEAVES], cost[1u << TL_LEAVES];
+    uint32_t bestp[1u << TL_LEAVES];
+    for (uint32_t S = 1; S <= full; S++) {
+        float u[6];
+        int have = 0;
+        for (int i = 0; i < nl; i++) {
+            if (!((S >> i) & 1u)) continue;
+            const float *b = t->box + 6 * (size_t)L[i];
+            if (!have) { memcpy(u, b, sizeof u); have = 1; }
+            else tl_union(u, b, u);
+        }
+        area[S] = tl_half_area(u);
+    }
+    for (uint32_t S = 1; S <= full; S++) {
+        if (tl_popc(S) == 1) { cost[S] = 0.0f; bestp[S] = 0; continue; }
+        const uint32_t low = S & (~S + 1u);
+        float best = 0.0f;
+        uint32_t bp = 0;
+        for (uint32_t P = 1; P < S; P++) {
+            if ((P & S) != P || !(P & low)) continue;
+            float c = cost[P] + cost[S ^ P];
+            if (bp == 0 || c < best) { best = c; bp = P; }
+        }
+        cost[S] = area[S] + best;
+        bestp[S] = bp;
+    }
+    /* the current topology's cost: expanded nodes' children were expanded
+       later, so a reverse sweep sees children first */
+    uint32_t mask[TL_LEAVES - 1];
+    float cur[TL_LEAVES - 1];
+    for (int j = ni - 1; j >= 0; j--) {
+        uint32_t ch[2] = { t->left[I[j]], t->right[I[j]] }, m[2];
+        float cc[2];
+        for (int k = 0; k < 2; k++) {
+            m[k] = 0; cc[k] = 0.0f;
+            for (int i = 0; i < nl; i++) if (L[i] == ch[k]) m[k] = 1u << i;
+            for (int q = j + 1; q < ni; q++) if (I[q] == ch[k]) { m[k] = mask[q]; cc[k] = cur[q]; }
+        }
+        mask[j] = m[0] | m[1];
+        cur[j] = area[mask[j]] + (cc[0] + cc[1]);
+    }
+    if (!(cost[full] < cur[0])) return;
+    /* rebuild: identities in pre-order, then boxes children first */
+    uint32_t id_of[1u << TL_LEAVES], order[TL_LEAVES - 1], stack[TL_LEAVES];
+    int sp = 0, no = 0, next = 1;
+    stack[sp++] = full;
+    while (sp) {
+        uint32_t S = stack[--sp];
+        id_of[S] = (S == full) ? r : I[next++];
+        order[no++] = S;
+        uint32_t P = bestp[S], Q = S ^ P;
+        if (tl_popc(Q) > 1) stack[sp++] = Q;
+        if (tl_popc(P) > 1) stack[sp++] = P;
+    }
+    for (int k = no - 1; k >= 0; k--) {
+        uint32_t S = order[k], P = bestp[S], Q = S ^ P;
+        uint32_t id = id_of[S];
+        uint32_t l = tl_popc(P) == 1 ? L[tl_ctz(P)] : id_of[P];
+        uint32_t rr = tl_popc(Q) == 1 ? L[tl_ctz(Q)] : id_of[Q];
+        t->left[id] = l;
+        t->right[id] = rr;
+        tl_union(t->box + 6 * (size_t)l, t->box + 6 * (size_t)rr, t->box + 6 * (size_t)id);
+    }
+}
+
+static void tl_visit(tl_tree *t, uint32_t v)
+{
+    if (t->right[v] == NONE32) return;
+    tl_visit(t, t->left[v]);
+    tl_visit(t, t->right[v]);
+    tl_treelet(t, v);
+}
+
+typedef struct {
+    const tl_tree *t;
+    const uint32_t *perm_in;
+    orc_bvh *out;
+    uint32_t max_depth, tri;
+    int error;
+} tl_emit_ctx;
+
+static void tl_emit(tl_emit_ctx *e, uint32_t v, uint32_t depth)
+{
+    orc_bvh *o = e->out;
+    uint32_t node = o->num_nodes++;
+    memcpy(o->box + 6 * (size_t)node, e->t->box + 6 * (size_t)v, 6 * sizeof(float));
+    o->depth[node] = depth;
+    if (e->t->right[v] == NONE32) {
+        if (depth > e->max_depth) e->error = 1;
+        o->right[node] = NONE32;
+        o->first[node] = e->tri;
+        o->count[node] = e->t->count[v];
+        for (uint32_t k = 0; k < e->t->count[v]; k++) o->perm[e->tri++] = e->perm_in[e->t->first[v] + k];
+        return;
+    }
+    o->first[node] = 0; o->count[node] = 0;
+    tl_emit(e, e->t->left[v], depth + 1);
+    o->right[node] = o->num_nodes;
+    tl_emit(e, e->t->right[v], depth + 1);
+}
+
+/* The linear BVH of orc_build_lbvh after `passes` treelet passes.  Returns
+   as orc_build_lbvh; -2 also when the restructured tree is deeper than
+   max_depth. */
+int orc_build_lbvh_treelet(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t max_depth, uint32_t passes,
+                           orc_bvh *out)
+{
+    if (passes > 16) return -1;
+    /* the linear BVH first, deep enough for any radix tree */
+    int rc = orc_build_lbvh(tris, n, leaf_max, 120, out);
+    if (rc != 0) return rc;
+    const uint32_t m = out->num_nodes;
+    tl_tree t;
+    t.left = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    t.right = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    t.first = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    t.count = (uint32_t *)malloc(sizeof(uint32_t) * m);
+    t.box = (float *)malloc(sizeof(float) * 6 * (size_t)m);
+    uint32_t *perm_in = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    memcpy(perm_in, out->perm, sizeof(uint32_t) * (size_t)n);
+    memcpy(t.box, out->box, sizeof(float) * 6 * (size_t)m);
+    for (uint32_t i = 0; i < m; i++) {
+        t.right[i] = out->right[i];
+        t.left[i] = out->right[i] == NONE32 ? NONE32 : i + 1;   /* pre-order: the left child is next */
+        t.first[i] = out->first[i];
+        t.count[i] = out->count[i];
+    }
+    for (uint32_t p = 0; p < passes; p++) tl_visit(&t, 0);
+    tl_emit_ctx e = { &t, perm_in, out, max_depth, 0, 0 };
+    out->num_nodes = 0;
+    tl_emit(&e, 0, 0);
+    free(t.left); free(t.right); free(t.first); free(t.count); free(t.box); free(perm_in);
+    if (out->num_nodes != m || e.tri != n) return -1;
+    return e.error ? -2 : 0;
+}
+
 /* ======================================================================== */
 /* Ray primitives                                                           */
 /* ======================================================================== */

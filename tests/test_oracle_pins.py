@@ -11,6 +11,8 @@ import os
 from decimal import Decimal, getcontext
 from fractions import Fraction
 
+import itertools
+
 import numpy as np
 import pytest
 
@@ -354,6 +356,84 @@ def test_lbvh_is_the_radix_tree_of_the_sorted_codes(n, leaf_max):
 
 
 # ---------------------------------------------------------------------------
+# Treelet restructuring of the linear BVH (Karras and Aila, HPG 2013)
+# ---------------------------------------------------------------------------
+
+def _all_trees(items):
+    """Every full binary tree on the leaves `items`, children unordered, as
+    nested pairs: (2k - 3)!! trees for k leaves."""
+    if len(items) == 1:
+        yield items[0]
+        return
+    first, rest = items[0], items[1:]
+    for r in range(len(rest)):
+        for comb in itertools.combinations(rest, r):
+            other = [x for x in rest if x not in comb]
+            for a in _all_trees([first, *comb]):
+                for b in _all_trees(other):
+                    yield (a, b)
+
+
+def _tree_cost64(tree, lo, hi):
+    """(box lo, box hi, sum of the half areas of the interior nodes), fp64."""
+    if not isinstance(tree, tuple):
+        return lo[tree], hi[tree], 0.0
+    la, ha, ca = _tree_cost64(tree[0], lo, hi)
+    lb, hb, cb = _tree_cost64(tree[1], lo, hi)
+    l, h = np.minimum(la, lb), np.maximum(ha, hb)
+    d = h - l
+    return l, h, ca + cb + float(d[0] * d[1] + d[1] * d[2] + d[2] * d[0])
+
+
+def _bvh_cost64(b):
+    inner = b.right != NONE32
+    d = b.box[inner, 3:].astype(np.float64) - b.box[inner, :3].astype(np.float64)
+    return float((d[:, 0] * d[:, 1] + d[:, 1] * d[:, 2] + d[:, 2] * d[:, 0]).sum())
+
+
+def test_treelet_count_of_trees():
+    assert [sum(1 for _ in _all_trees(list(range(k)))) for k in range(1, 8)] == [1, 1, 3, 15, 105, 945, 10395]
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6, 7])
+def test_treelet_pass_finds_the_optimal_tree_of_seven_leaves(k):
+    # with at most 7 leaves the root's treelet holds every leaf, so one pass
+    # must reach the least sum of interior half areas over all (2k-3)!! trees
+    worse = 0
+    for seed in range(12):
+        tris = sg.triangle_soup(900 + 17 * k + seed, k, edge=0.3)
+        v = tris.reshape(-1, 3, 3).astype(np.float64)
+        lo, hi = v.min(1), v.max(1)
+        best = min(_tree_cost64(t, lo, hi)[2] for t in _all_trees(list(range(k))))
+        b = oracle.build_lbvh(tris, leaf_max=1, treelet_passes=1)
+        oracle.validate_bvh(b, tris, 1, 64)
+        assert _bvh_cost64(b) == pytest.approx(best, rel=1e-6), seed
+        worse += _bvh_cost64(oracle.build_lbvh(tris, leaf_max=1)) > best * (1 + 1e-6)
+    assert worse >= 3          # the radix tree alone is often not optimal
+
+
+@pytest.mark.parametrize("n,leaf_max", [(50, 1), (1000, 2), (5000, 4)])
+def test_treelet_passes_keep_leaves_and_lower_the_cost(n, leaf_max):
+    tris = sg.triangle_soup(300 + n, n)
+    base = oracle.build_lbvh(tris, leaf_max=leaf_max)
+
+    def leaf_sets(b):
+        lf = np.nonzero(b.right == NONE32)[0]
+        return sorted(tuple(sorted(b.perm[b.first[i]:b.first[i] + b.count[i]].tolist())) for i in lf)
+
+    prev = _bvh_cost64(base)
+    for p in (1, 2, 3):
+        b = oracle.build_lbvh(tris, leaf_max=leaf_max, treelet_passes=p)
+        oracle.validate_bvh(b, tris, leaf_max, 64)
+        assert leaf_sets(b) == leaf_sets(base)
+        c = _bvh_cost64(b)
+        assert c <= prev * (1 + 1e-6)
+        prev = c
+    assert prev < _bvh_cost64(base) * 0.99
+    assert oracle.build_lbvh(tris, leaf_max=leaf_max, treelet_passes=0).perm.tolist() == base.perm.tolist()
+
+
+# ---------------------------------------------------------------------------
 # Traversal versus brute force (plain definitions of any-hit and closest hit)
 # ---------------------------------------------------------------------------
 
@@ -429,11 +509,11 @@ def test_results_do_not_depend_on_tree_shape():
     ha, _ = oracle.trace(a, tris, rays, query="closest", mode="exact")
     hm, _ = oracle.trace(m, tris, rays, query="closest", mode="exact")
     _allowed_mismatch(tris, rays, np.any(ha.view(np.uint32) != hm.view(np.uint32), axis=1))
-    lb = oracle.build_lbvh(tris)
-    ol, _ = oracle.trace(lb, tris, rays)
-    _allowed_mismatch(tris, rays, oa != ol)
-    hl, _ = oracle.trace(lb, tris, rays, query="closest", mode="exact")
-    _allowed_mismatch(tris, rays, np.any(ha.view(np.uint32) != hl.view(np.uint32), axis=1))
+    for lb in (oracle.build_lbvh(tris), oracle.build_lbvh(tris, treelet_passes=2)):
+        ol, _ = oracle.trace(lb, tris, rays)
+        _allowed_mismatch(tris, rays, oa != ol)
+        hl, _ = oracle.trace(lb, tris, rays, query="closest", mode="exact")
+        _allowed_mismatch(tris, rays, np.any(ha.view(np.uint32) != hl.view(np.uint32), axis=1))
 
 
 def test_invalid_rays_are_counted_misses():
