@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ao", action="store_true")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny configuration (256 triangles)")
+    ap.add_argument("--treelet-passes", default="0,1,2",
+                    help="build workload: treelet passes of the device builds compared (comma-separated)")
+    ap.add_argument("--no-arrival", action="store_true", help="build workload: skip the scene-arrival measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-table shadow and AO measurements")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement that gives the line its p99 latency")
@@ -314,7 +317,7 @@ def main():
             cfgs = [dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=q[0], dir_bits=q[1],
                          epoch_rays=q[2], inline_lanes=q[3], first_epoch_rays=q[4])
                     for q in (w["primary_q"], w["shadow_q"])]
-        cfgs.append(dict(leaf_max=w["leaf_max"]))
+        cfgs.append(dict(leaf_max=w["leaf_max"], treelet_passes=w["treelet_passes"]))
         summarize_traffic(*args.summarize_traffic, configs=cfgs)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -362,7 +365,7 @@ def main():
     tris, prim = sg.terrain_workload()
     n_prim = prim.shape[0]
     t0 = time.perf_counter()
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     build_s = time.perf_counter() - t0
     log(f"BVH: {bvh.num_nodes} nodes, depth {bvh.max_depth}, built in {build_s:.2f} s")
     pq, sq = w["primary_q"], w["shadow_q"]
@@ -627,7 +630,8 @@ def main():
         dom = max((k for k in kernels if k.startswith("hrpp:")), key=lambda k: kernels[k]["ms_per_step"])
         d = kernels[dom]
         kname = dom.split(":", 1)[1]
-        traffic = load_traffic(kname, [cfg_all, cfg_any, dict(leaf_max=w["leaf_max"])])
+        traffic = load_traffic(kname, [cfg_all, cfg_any, dict(leaf_max=w["leaf_max"],
+                                                             treelet_passes=w["treelet_passes"])])
         hbm_frac = d["compulsory_gbs"] / HBM_PEAK_GBS
         alu_frac = d["valu_tops"] / VALU_PEAK_TOPS
         hbm = {"achieved": round(d["compulsory_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -829,7 +833,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         log("oracle on the host cores")
-        ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+        ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
         vtx = oracle.bvh_vertices(tris, ob)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         times = []
@@ -1055,7 +1059,7 @@ def run_progressive(args, np, torch, hrpp, sg):
     (a pass with the two queries on one stream); one JSON line."""
     w = sg.AT_SCALE
     tris, prim = sg.terrain_workload()
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     n = prim.shape[0]
     pq, sq = w["primary_q"], w["shadow_q"]
     cfg_all = dict(log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1], epoch_rays=pq[2],
@@ -1110,7 +1114,7 @@ def run_autotune(args, np, torch, hrpp, sg):
 
     tris, prim = sg.terrain_workload()
     w = sg.AT_SCALE
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     trees = {sg.AT_SCALE["leaf_max"]: bvh}
 
     def tree_for(leaf):
@@ -1182,7 +1186,7 @@ def run_sweep(args, np, torch, hrpp, sg):
     wi = sg.INCOHERENT
     log("generating the incoherent AO workload")
     tris, _ = sg.terrain_scene(sg.AT_SCALE["seed"])
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     cam_rays, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
     cam_d = torch.from_numpy(cam_rays).cuda()
     hh = hrpp.trace_closest(bvh, None, cam_d, mode="exact").cpu().numpy()
@@ -1234,7 +1238,7 @@ def run_sweep(args, np, torch, hrpp, sg):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+        ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
         vtx = oracle.bvh_vertices(tris, ob)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         sample_pts = [(m, T, q) for m in modes for (T, q) in ((16, 3), (16, 7), (22, 3), (22, 7), (20, 5))]
@@ -1268,7 +1272,7 @@ def run_goup(args, np, torch, hrpp, sg):
     w = sg.AT_SCALE
     log("generating the at-scale workload")
     tris, prim = sg.terrain_workload()
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     prim_d = torch.from_numpy(prim).cuda()
     he = hrpp.trace_closest(bvh, None, prim_d, mode="exact").cpu().numpy()
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
@@ -1347,29 +1351,37 @@ def run_build(args, np, torch, hrpp, sg):
     host_s = []
     for _ in range(3):
         t0 = time.perf_counter()
-        sah = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], device=None)
+        sah = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], device=None, treelet_passes=sg.AT_SCALE["treelet_passes"])
         host_s.append(time.perf_counter() - t0)
     t0 = time.perf_counter()
     sah.upload()
     torch.cuda.synchronize()
     upload_ms = (time.perf_counter() - t0) * 1e3
     verts_d = torch.from_numpy(np.ascontiguousarray(tris.reshape(-1, 9))).cuda()
-    dev_ms, dev_wall = [], []
-    for rep in range(6):
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record()
-        lb = hrpp.BVH.build_on_device(verts_d, leaf_max=sg.AT_SCALE["leaf_max"])
-        e1.record()
-        torch.cuda.synchronize()
-        if rep:                              # the first build pays for the allocations
-            dev_wall.append((time.perf_counter() - t0) * 1e3)
-            dev_ms.append(e0.elapsed_time(e1))
-        if rep < 5:
-            lb.close()
-    log(f"host SAH {statistics.median(host_s):.2f} s + upload {upload_ms:.1f} ms; device LBVH "
-        f"{statistics.median(dev_ms):.3f} ms (wall {statistics.median(dev_wall):.3f} ms)")
+    passes_list = [int(x) for x in str(args.treelet_passes).split(",") if x != ""]
+    dev_trees, dev_times = {}, {}
+    for passes in passes_list:
+        dev_ms, dev_wall = [], []
+        for rep in range(6):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            lb = hrpp.BVH.build_on_device(verts_d, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=passes)
+            e1.record()
+            torch.cuda.synchronize()
+            if rep:                              # the first build pays for the allocations
+                dev_wall.append((time.perf_counter() - t0) * 1e3)
+                dev_ms.append(e0.elapsed_time(e1))
+            if rep < 5:
+                lb.close()
+        name = "device_lbvh" if passes == 0 else f"device_treelet_{passes}"
+        dev_trees[name] = lb
+        dev_times[name] = dict(build_ms=round(statistics.median(dev_ms), 3), build_min_ms=round(min(dev_ms), 3),
+                               build_wall_ms=round(statistics.median(dev_wall), 3), treelet_passes=passes)
+        log(f"host SAH {statistics.median(host_s):.2f} s + upload {upload_ms:.1f} ms; {name} "
+            f"{statistics.median(dev_ms):.3f} ms (wall {statistics.median(dev_wall):.3f} ms)")
+    first_dev = "device_lbvh" if 0 in passes_list else next(iter(dev_trees))
     prim_d = torch.from_numpy(prim).cuda()
     he = hrpp.trace_closest(sah, None, prim_d, mode="exact").cpu().numpy()
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
@@ -1393,7 +1405,7 @@ def run_build(args, np, torch, hrpp, sg):
         cur.wait_stream(s_b)
 
     trees = {}
-    for name, bvh in (("host_sah", sah), ("device_lbvh", lb)):
+    for name, bvh in (("host_sah", sah), *dev_trees.items()):
         pa = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=pq[0], dir_bits=pq[1],
                             epoch_rays=pq[2], inline_lanes=pq[3], first_epoch_rays=pq[4])
         pb = hrpp.Predictor(bvh, log2_entries=w["log2_entries"], ways=w["ways"], origin_bits=sq[0], dir_bits=sq[1],
@@ -1429,31 +1441,38 @@ def run_build(args, np, torch, hrpp, sg):
             shadow_nodes_per_ray_plain=round(d["sp"]["nodes_visited"] / n_sh, 2),
             primary_pct_nodes_skipped=round(100 * (1 - d["ph"]["nodes_visited"] / d["pp"]["nodes_visited"]), 2),
             shadow_pct_nodes_skipped=round(100 * (1 - d["sh"]["nodes_visited"] / d["sp"]["nodes_visited"]), 2))
+        if name in dev_times:
+            trees[name].update(dev_times[name])
+            trees[name]["step_hrpp_vs_sah_tree"] = round(trees[name]["step_hrpp_mrays_s"] /
+                                                         trees["host_sah"]["step_hrpp_mrays_s"], 3)
+            trees[name]["step_plain_vs_sah_tree"] = round(trees[name]["step_plain_mrays_s"] /
+                                                          trees["host_sah"]["step_plain_mrays_s"], 3)
         log(f"{name}: {trees[name]}")
         del pa, pb
-    arrival = measure_scene_arrival(np, torch, hrpp, sg, sah, shadow)
+    arrival = None if args.no_arrival else measure_scene_arrival(np, torch, hrpp, sg, sah, shadow)
     # device build time against scene size (heightfields; median of 3 after one
     # untimed build; HIP events around the call)
     scaling = []
     for lg in (16, 18, 20, 22, 24):
         v = torch.from_numpy(np.ascontiguousarray(sg.heightfield_scene(91, 1 << lg).reshape(-1, 9))).cuda()
-        ts = []
-        for rep in range(4):
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            b = hrpp.BVH.build_on_device(v, leaf_max=w["leaf_max"])
-            e1.record()
-            torch.cuda.synchronize()
-            if rep:
-                ts.append(e0.elapsed_time(e1))
-            nodes, depth = b.num_nodes, b.max_depth
-            b.close()
-            del b
-        ms = statistics.median(ts)
-        scaling.append(dict(triangles=1 << lg, build_ms=round(ms, 3), mtris_s=round((1 << lg) / (ms * 1e-3) / 1e6, 1),
-                            nodes=nodes, depth=depth))
-        log(f"device build scaling: {scaling[-1]}")
+        for passes in passes_list:
+            ts = []
+            for rep in range(4):
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                b = hrpp.BVH.build_on_device(v, leaf_max=w["leaf_max"], treelet_passes=passes)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep:
+                    ts.append(e0.elapsed_time(e1))
+                nodes, depth = b.num_nodes, b.max_depth
+                b.close()
+                del b
+            ms = statistics.median(ts)
+            scaling.append(dict(triangles=1 << lg, treelet_passes=passes, build_ms=round(ms, 3),
+                                mtris_s=round((1 << lg) / (ms * 1e-3) / 1e6, 1), nodes=nodes, depth=depth))
+            log(f"device build scaling: {scaling[-1]}")
         del v
         torch.cuda.empty_cache()
     print(json.dumps({
@@ -1461,10 +1480,10 @@ def run_build(args, np, torch, hrpp, sg):
         "config": {"workload": f"terrain {n_tris} tris; step = 1920x1080 primary closest (PAPER) + shadow any-hit, "
                                f"tables 2^{w['log2_entries']} x {w['ways']}", "steps": args.steps},
         "host_sah_build_s": round(statistics.median(host_s), 3), "host_upload_ms": round(upload_ms, 2),
-        "device_lbvh_build_ms": round(statistics.median(dev_ms), 3),
-        "device_lbvh_build_min_ms": round(min(dev_ms), 3),
-        "device_lbvh_build_wall_ms": round(statistics.median(dev_wall), 3),
-        "build_speedup": round(statistics.median(host_s) * 1e3 / statistics.median(dev_wall), 1),
+        "device_lbvh_build_ms": dev_times[first_dev]["build_ms"],
+        "device_lbvh_build_min_ms": dev_times[first_dev]["build_min_ms"],
+        "device_lbvh_build_wall_ms": dev_times[first_dev]["build_wall_ms"],
+        "build_speedup": round(statistics.median(host_s) * 1e3 / dev_times[first_dev]["build_wall_ms"], 1),
         "trees": trees, "scene_arrival": arrival, "device_build_scaling": scaling}), flush=True)
 
 
@@ -1529,7 +1548,7 @@ def run_policy(args, np, torch, hrpp, sg):
     w, wi = sg.AT_SCALE, sg.INCOHERENT
     log("generating the at-scale and AO workloads")
     tris, prim = sg.terrain_workload()
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     prim_d = torch.from_numpy(prim).cuda()
     cam, _ = sg.camera_for(wi["width"], wi["height"]).rays("rowmajor")
     hh = hrpp.trace_closest(bvh, None, torch.from_numpy(cam).cuda(), mode="exact").cpu().numpy()

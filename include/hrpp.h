@@ -58,8 +58,12 @@ typedef struct { float t, u, v; uint32_t prim; } hrpp_hit;
 
 /* BVH build parameters (the paper takes the binary BVH as given; this
  * library builds a deterministic binned-SAH tree).  leaf_max in [1, 8]
- * (4 by default), sah_bins in [2, 256] (32), max_depth in [1, 64] (64). */
-typedef struct { uint32_t leaf_max, sah_bins, max_depth; } hrpp_bvh_desc;
+ * (4 by default), sah_bins in [2, 256] (32), max_depth in [1, 64] (64).
+ * treelet_passes in [0, 8] (0): passes of treelet restructuring applied
+ * to the built tree (the host SAH tree or the device linear BVH; see
+ * hrpp_build_bvh_device): interior nodes rearranged to lower the sum of
+ * their surface areas, leaves unchanged. */
+typedef struct { uint32_t leaf_max, sah_bins, max_depth, treelet_passes; } hrpp_bvh_desc;
 
 /* Predictor parameters.
  *  log2_entries  T: table of 2^T entries, T in [1, 26]
@@ -207,9 +211,15 @@ hrpp_status hrpp_bvh_upload(hrpp_bvh *bvh, void *d_buf, size_t bytes, void *stre
  * triangles ordered by (code, primitive id), every subtree over at most
  * leaf_max triangles kept as one leaf, exact boxes, DFS pre-order -- a
  * different tree from the host builder's SAH tree, with the same query
- * results.
+ * results.  With desc->treelet_passes >= 1 the interior nodes are then
+ * rearranged by that many passes of treelet restructuring (Karras and Aila,
+ * HPG 2013): in each pass every interior node, after all interior nodes
+ * below it, gathers a treelet of up to 7 subtrees (repeatedly opening the
+ * interior one of largest surface area) and takes the topology over them
+ * that minimises the sum of its interior nodes' surface areas, when that
+ * sum is below the current one; the leaves stay as they are.
  *
- * Scratch bytes the build needs for num_tris triangles, about 121 per
+ * Scratch bytes the build needs for num_tris triangles, about 157 per
  * triangle (0 when num_tris is 0 or >= 2^28). */
 size_t hrpp_bvh_device_build_scratch_bytes(uint32_t num_tris);
 
@@ -241,7 +251,7 @@ hrpp_status hrpp_build_bvh_device(const float *d_verts, uint32_t num_tris, const
  * several host threads) race and must be serialised by the caller.  Errors
  * as hrpp_build_bvh_device, plus ENOMEM when the build needs more than the
  * static 64 MiB (hrpp_bvh_device_build_scratch_bytes(num_tris) > 64 MiB:
- * from about 554,000 triangles on; then nothing is enqueued). */
+ * from about 427,000 triangles on; then nothing is enqueued). */
 hrpp_status hrpp_build_bvh_device_static(const float *d_verts, uint32_t num_tris, const hrpp_bvh_desc *desc,
                                          void *d_buf, size_t bytes, void *stream, hrpp_bvh **out);
 

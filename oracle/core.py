@@ -118,8 +118,12 @@ def _run_build(fn, tris, *args) -> CanonBVH:
                     arrs["count"][:m].copy(), arrs["depth"][:m].copy(), arrs["perm"].copy())
 
 
-def build_sah(tris: np.ndarray, leaf_max: int = 4, bins: int = 32, max_depth: int = 64) -> CanonBVH:
-    """Deterministic binned-SAH BVH (the reading both sides implement)."""
+def build_sah(tris: np.ndarray, leaf_max: int = 4, bins: int = 32, max_depth: int = 64,
+              treelet_passes: int = 0) -> CanonBVH:
+    """Deterministic binned-SAH BVH (the reading both sides implement); with
+    treelet_passes >= 1, that many passes of treelet restructuring after it."""
+    if treelet_passes:
+        return _run_build(_L().orc_build_sah_treelet, tris, leaf_max, bins, max_depth, treelet_passes)
     return _run_build(_L().orc_build_sah, tris, leaf_max, bins, max_depth)
 
 

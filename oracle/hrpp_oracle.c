@@ -633,16 +633,9 @@ static void tl_emit(tl_emit_ctx *e, uint32_t v, uint32_t depth)
     tl_emit(e, e->t->right[v], depth + 1);
 }
 
-/* The linear BVH of orc_build_lbvh after `passes` treelet passes.  Returns
-   as orc_build_lbvh; -2 also when the restructured tree is deeper than
-   max_depth. */
-int orc_build_lbvh_treelet(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t max_depth, uint32_t passes,
-                           orc_bvh *out)
+/* `passes` treelet passes over a built tree (in place). */
+static int tl_restructure(orc_bvh *out, uint32_t n, uint32_t max_depth, uint32_t passes)
 {
-    if (passes > 16) return -1;
-    /* the linear BVH first, deep enough for any radix tree */
-    int rc = orc_build_lbvh(tris, n, leaf_max, 120, out);
-    if (rc != 0) return rc;
     const uint32_t m = out->num_nodes;
     tl_tree t;
     t.left = (uint32_t *)malloc(sizeof(uint32_t) * m);
@@ -666,6 +659,30 @@ int orc_build_lbvh_treelet(const float *tris, uint32_t n, uint32_t leaf_max, uin
     free(t.left); free(t.right); free(t.first); free(t.count); free(t.box); free(perm_in);
     if (out->num_nodes != m || e.tri != n) return -1;
     return e.error ? -2 : 0;
+}
+
+/* The linear BVH of orc_build_lbvh after `passes` treelet passes.  Returns
+   as orc_build_lbvh; -2 also when the restructured tree is deeper than
+   max_depth. */
+int orc_build_lbvh_treelet(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t max_depth, uint32_t passes,
+                           orc_bvh *out)
+{
+    if (passes > 16) return -1;
+    /* the linear BVH first, deep enough for any radix tree */
+    int rc = orc_build_lbvh(tris, n, leaf_max, 120, out);
+    if (rc != 0) return rc;
+    return tl_restructure(out, n, max_depth, passes);
+}
+
+/* The binned-SAH BVH of orc_build_sah after `passes` treelet passes (the
+   SAH tree is built with max_depth, the result checked against it too). */
+int orc_build_sah_treelet(const float *tris, uint32_t n, uint32_t leaf_max, uint32_t bins, uint32_t max_depth,
+                          uint32_t passes, orc_bvh *out)
+{
+    if (passes > 16) return -1;
+    int rc = orc_build_sah(tris, n, leaf_max, bins, max_depth, out);
+    if (rc != 0) return rc;
+    return tl_restructure(out, n, max_depth, passes);
 }
 
 /* ======================================================================== */

@@ -36,6 +36,16 @@
 // its root path tile the sorted positions before its range, and a subtree of
 // k leaves has 2k - 1 nodes, so index = 2 * (output leaves before its first
 // position) + (ancestors it descends from on the left).
+//
+// Optional treelet passes (Karras and Aila, "Fast Parallel Construction of
+// High-Quality Bounding Volume Hierarchies", HPG 2013) then rearrange the
+// interior nodes; the output leaves stay.  Each pass runs the interior nodes
+// level by level, deepest first (k_tl_depth / k_tl_bucket list the levels,
+// k_tl_treelet restructures one level, a wave per node), so every node comes
+// after every node below it and the nodes of one launch have disjoint
+// subtrees.  A restructured tree is no longer in sorted-position order, so
+// it is numbered and laid out from explicit subtree counts instead
+// (k_tl_number, k_tl_emit): triangles in leaf order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -398,9 +408,359 @@ __global__ __launch_bounds__(256) void k_lbvh_emit(Tree tr, const float *__restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Treelet restructuring.  Node identities stay those of the radix tree
+// (interior nodes in [0, n-1), output leaves wherever the radix tree had
+// them); a restructured interior node's lo / hi no longer describe its
+// subtree, so its triangle count (cnt) and output-leaf count (atoms) are kept
+// explicitly.  The rules -- treelet growth, cost, tie-breaking, which
+// identity each new interior node takes -- are those the plain C reading of
+// the method states; only the schedule (levels, a wave per treelet) is this
+// file's.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTlLeaves = 7;            // leaves of a treelet
+constexpr uint32_t kTlLevels = kWalkLimit;   // node depths are below the walk limit
+constexpr uint32_t kTlThreads = 64;          // one wave per treelet
+
+struct TlTree {
+    uint32_t *parent, *left, *right, *dep, *cnt, *atoms;
+    float *box;
+    uint32_t *bad;                           // header word: bit 1 on an inconsistent treelet
+};
+
+__device__ inline bool tl_is_leaf(const uint32_t *dep, uint32_t v) { return (dep[v] & 0x80000000u) != 0; }
+
+// Half surface area in binary32, summed left to right.
+__device__ inline float tl_half_area(const float *b) {
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+// Subtree counts of the linear BVH's output nodes.
+__global__ __launch_bounds__(256) void k_tl_init(Tree tr, const uint32_t *__restrict__ lb,
+                                                 const uint32_t *__restrict__ dep, uint32_t *__restrict__ cnt,
+                                                 uint32_t *__restrict__ atoms) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= 2u * tr.n - 1u) return;
+    const uint32_t d = dep[v];
+    if (d == kNone) return;
+    const uint32_t f = tr.first(v), c = tr.size(v);
+    cnt[v] = c;
+    atoms[v] = (d & 0x80000000u) ? 1u : lb[f + c] - lb[f];
+}
+
+// Level counts and the deepest leaf start from zero.
+__global__ __launch_bounds__(kTlLevels) void k_tl_zero(uint32_t *__restrict__ levels, LbvhHeader *h) {
+    levels[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) h->max_depth = 0u;
+}
+
+// Depth of every output node (leaf flag kept), the deepest leaf, and the
+// number of interior nodes at each depth.
+__global__ __launch_bounds__(256) void k_tl_depth(const uint32_t *__restrict__ parent, uint32_t *__restrict__ dep,
+                                                  uint32_t m, uint32_t *__restrict__ hist, LbvhHeader *h) {
+    __shared__ uint32_t lh[kTlLevels];
+    for (uint32_t k = threadIdx.x; k < kTlLevels; k += blockDim.x) lh[k] = 0u;
+    __syncthreads();
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t leaf_depth = 0;
+    if (v < m && dep[v] != kNone) {
+        const uint32_t flag = dep[v] & 0x80000000u;
+        uint32_t depth = 0, cur = v;
+        while (cur != 0 && depth < kWalkLimit) {
+            cur = parent[cur] & ~kRightChild;
+            depth++;
+        }
+        if (cur != 0) {
+            atomicOr(&h->bad, 4u);
+        } else {
+            dep[v] = depth | flag;
+            if (flag) leaf_depth = depth;
+            else atomicAdd(&lh[depth], 1u);
+        }
+    }
+    leaf_depth = wave_max(leaf_depth);
+    if ((threadIdx.x & 63u) == 0 && leaf_depth) atomicMax(&h->max_depth, leaf_depth);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < kTlLevels; k += blockDim.x)
+        if (lh[k]) atomicAdd(&hist[k], lh[k]);
+}
+
+// Start of each level's list (exclusive prefix of the counts); fill counters
+// start from zero.
+__global__ __launch_bounds__(64) void k_tl_start(const uint32_t *__restrict__ hist, uint32_t *__restrict__ start,
+                                                 uint32_t *__restrict__ fill) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < kTlLevels; k++) {
+        start[k] = run;
+        fill[k] = 0u;
+        run += hist[k];
+    }
+}
+
+// Interior nodes listed by level (in any order within a level): a block
+// counts its nodes per level in LDS and reserves each level's range once.
+__global__ __launch_bounds__(256) void k_tl_bucket(const uint32_t *__restrict__ dep, uint32_t n_internal,
+                                                   const uint32_t *__restrict__ start, uint32_t *__restrict__ fill,
+                                                   uint32_t *__restrict__ list) {
+    __shared__ uint32_t lc[kTlLevels], lbase[kTlLevels];
+    for (uint32_t k = threadIdx.x; k < kTlLevels; k += blockDim.x) lc[k] = 0u;
+    __syncthreads();
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t d = kNone, loc = 0;
+    if (v < n_internal && dep[v] != kNone && !(dep[v] & 0x80000000u)) {
+        d = dep[v];
+        loc = atomicAdd(&lc[d], 1u);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < kTlLevels; k += blockDim.x)
+        if (lc[k]) lbase[k] = atomicAdd(&fill[k], lc[k]);
+    __syncthreads();
+    if (d != kNone) list[start[d] + lbase[d] + loc] = v;
+}
+
+// One treelet per wave: grow it, find the best topology over its leaves by
+// dynamic programming over subsets (lanes take the subsets of one size at a
+// time), and rebuild it when that beats the current topology.
+__global__ __launch_bounds__(kTlThreads) void k_tl_treelet(TlTree t, const uint32_t *__restrict__ list) {
+    constexpr uint32_t kSub = 1u << kTlLeaves;
+    __shared__ float s_area[kSub], s_cost[kSub];
+    __shared__ uint32_t s_bestp[kSub], s_id[kSub];
+    __shared__ float s_box[kTlLeaves][6];
+    __shared__ uint32_t s_L[kTlLeaves], s_I[kTlLeaves - 1], s_nl, s_ni;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t r = list[blockIdx.x];
+    if (lane == 0) {
+        // grow: open the treelet leaf of largest area among the interior ones
+        // (the first on ties); its left child takes its place, its right
+        // child goes to the end
+        uint32_t nl = 2, ni = 1;
+        s_L[0] = t.left[r];
+        s_L[1] = t.right[r];
+        s_I[0] = r;
+        while (nl < kTlLeaves) {
+            int best = -1;
+            float ba = 0.0f;
+            for (uint32_t i = 0; i < nl; i++) {
+                const uint32_t x = s_L[i];
+                if (tl_is_leaf(t.dep, x)) continue;
+                const float a = tl_half_area(t.box + 6 * (size_t)x);
+                if (best < 0 || a > ba) { best = (int)i; ba = a; }
+            }
+            if (best < 0) break;
+            const uint32_t x = s_L[best];
+            s_I[ni++] = x;
+            s_L[best] = t.left[x];
+            s_L[nl++] = t.right[x];
+        }
+        for (uint32_t i = 0; i < nl; i++)
+            for (int a = 0; a < 6; a++) s_box[i][a] = t.box[6 * (size_t)s_L[i] + a];
+        s_nl = nl;
+        s_ni = ni;
+    }
+    __syncthreads();
+    const uint32_t nl = s_nl, ni = s_ni;
+    if (nl < 3) return;                        // two leaves: one topology (uniform)
+    const uint32_t full = (1u << nl) - 1u;
+    // the union box of every subset, members in increasing order (a union
+    // keeps the earlier value on ties), and its half area
+    for (uint32_t S = lane + 1u; S <= full; S += kTlThreads) {
+        float u[6];
+        bool have = false;
+        for (uint32_t i = 0; i < nl; i++) {
+            if (!((S >> i) & 1u)) continue;
+            if (!have) {
+                for (int a = 0; a < 6; a++) u[a] = s_box[i][a];
+                have = true;
+            } else {
+                for (int a = 0; a < 3; a++) {
+                    u[a] = s_box[i][a] < u[a] ? s_box[i][a] : u[a];
+                    u[3 + a] = s_box[i][3 + a] > u[3 + a] ? s_box[i][3 + a] : u[3 + a];
+                }
+            }
+        }
+        s_area[S] = tl_half_area(u);
+        s_cost[S] = 0.0f;
+        s_bestp[S] = 0u;
+    }
+    __syncthreads();
+    // c(S) = A(S) + min over P (c(P) + c(S \ P)), P over the proper subsets
+    // of S holding its lowest member in increasing order, the first minimum
+    // kept; subsets of one size depend only on smaller ones
+    for (uint32_t sz = 2; sz <= nl; sz++) {
+        for (uint32_t S = lane + 1u; S <= full; S += kTlThreads) {
+            if ((uint32_t)__popc(S) != sz) continue;
+            const uint32_t low = S & (0u - S);
+            float best = 0.0f;
+            uint32_t bp = 0;
+            for (uint32_t P = low; P != S; P = (P - S) & S) {   // the subsets of S, increasing
+                if (!(P & low)) continue;
+                const float c = s_cost[P] + s_cost[S ^ P];
+                if (bp == 0 || c < best) { best = c; bp = P; }
+            }
+            s_cost[S] = s_area[S] + best;
+            s_bestp[S] = bp;
+        }
+        __syncthreads();
+    }
+    if (lane != 0) return;
+    // the current topology's cost by the same recurrence: an opened node's
+    // children were opened later, so a reverse sweep meets children first
+    uint32_t mask[kTlLeaves - 1];
+    float cur[kTlLeaves - 1];
+    for (int j = (int)ni - 1; j >= 0; j--) {
+        const uint32_t x = s_I[j];
+        const uint32_t ch[2] = {t.left[x], t.right[x]};
+        uint32_t m2[2];
+        float c2[2];
+        for (int k = 0; k < 2; k++) {
+            m2[k] = 0u;
+            c2[k] = 0.0f;
+            for (uint32_t i = 0; i < nl; i++)
+                if (s_L[i] == ch[k]) m2[k] = 1u << i;
+            for (uint32_t q = (uint32_t)j + 1u; q < ni; q++)
+                if (s_I[q] == ch[k]) { m2[k] = mask[q]; c2[k] = cur[q]; }
+        }
+        mask[j] = m2[0] | m2[1];
+        if (mask[j] == 0u || mask[j] > full) { atomicOr(t.bad, 2u); return; }
+        cur[j] = s_area[mask[j]] + (c2[0] + c2[1]);
+    }
+    if (!(s_cost[full] < cur[0])) return;
+    // rebuild: identities in depth-first pre-order (r, then the opened nodes
+    // in opening order), the part with the lowest member on the left
+    uint32_t order[kTlLeaves - 1], stack[kTlLeaves];
+    uint32_t sp = 0, no = 0, next = 1;
+    stack[sp++] = full;
+    while (sp) {
+        const uint32_t S = stack[--sp];
+        const uint32_t P = s_bestp[S], Q = S ^ P;
+        if (P == 0u || (P & ~S) != 0u || P == S || no >= nl - 1u || (S != full && next >= ni)) {
+            atomicOr(t.bad, 2u);
+            return;
+        }
+        s_id[S] = S == full ? r : s_I[next++];
+        order[no++] = S;
+        if (__popc(Q) > 1) stack[sp++] = Q;
+        if (__popc(P) > 1) stack[sp++] = P;
+    }
+    // children before parents: links, boxes (union, the left child's value
+    // kept on ties) and counts
+    for (int k = (int)no - 1; k >= 0; k--) {
+        const uint32_t S = order[k], P = s_bestp[S], Q = S ^ P;
+        const uint32_t id = s_id[S];
+        const uint32_t l = __popc(P) == 1 ? s_L[__ffs(P) - 1] : s_id[P];
+        const uint32_t rr = __popc(Q) == 1 ? s_L[__ffs(Q) - 1] : s_id[Q];
+        t.left[id] = l;
+        t.right[id] = rr;
+        t.parent[l] = id;
+        t.parent[rr] = id | kRightChild;
+        const float *bl = t.box + 6 * (size_t)l, *br = t.box + 6 * (size_t)rr;
+        float out[6];
+        for (int a = 0; a < 3; a++) {
+            out[a] = br[a] < bl[a] ? br[a] : bl[a];
+            out[3 + a] = br[3 + a] > bl[3 + a] ? br[3 + a] : bl[3 + a];
+        }
+        for (int a = 0; a < 6; a++) t.box[6 * (size_t)id + a] = out[a];
+        t.cnt[id] = t.cnt[l] + t.cnt[rr];
+        t.atoms[id] = t.atoms[l] + t.atoms[rr];
+    }
+}
+
+// Pre-order index, first triangle position and interior index of every
+// output node of the restructured tree, from its root path: a step up from a
+// right child passes the left sibling's subtree (2a - 1 nodes of which a - 1
+// interior, and its triangles), and every step passes the parent.
+__global__ __launch_bounds__(256) void k_tl_number(TlTree t, uint32_t m, uint32_t *__restrict__ pre,
+                                                   uint32_t *__restrict__ off, uint32_t *__restrict__ iref,
+                                                   LbvhHeader *h) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m || t.dep[v] == kNone) return;
+    uint32_t p = 0, o = 0, ir = 0, cur = v, steps = 0;
+    while (cur != 0 && steps < kWalkLimit) {
+        const uint32_t w = t.parent[cur], u = w & ~kRightChild;
+        if (w & kRightChild) {
+            const uint32_t l = t.left[u];
+            p += 2u * t.atoms[l];
+            ir += t.atoms[l];
+            o += t.cnt[l];
+        } else {
+            p += 1u;
+            ir += 1u;
+        }
+        cur = u;
+        steps++;
+    }
+    if (cur != 0) { atomicOr(&h->bad, 4u); return; }
+    pre[v] = p;
+    off[v] = o;
+    iref[v] = ir;
+    if (v == 0) h->num_nodes = 2u * t.atoms[0] - 1u;
+}
+
+__device__ inline uint32_t tl_ref_of(const TlTree &t, const uint32_t *off, const uint32_t *iref, uint32_t v) {
+    if (tl_is_leaf(t.dep, v)) return kLeafFlag | (off[v] << 3) | (t.cnt[v] - 1u);
+    return iref[v];
+}
+
+// The GPU layout of the restructured tree (the same records as k_lbvh_emit).
+__global__ __launch_bounds__(256) void k_tl_emit(Tree tr, TlTree t, const float *__restrict__ verts,
+                                                 const uint32_t *__restrict__ perm, const uint32_t *__restrict__ pre,
+                                                 const uint32_t *__restrict__ off, const uint32_t *__restrict__ iref,
+                                                 EmitOut o, LbvhHeader *h) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= 2u * tr.n - 1u) return;
+    const uint32_t dw = t.dep[v];
+    if (dw == kNone) return;
+    const bool leaf = (dw & 0x80000000u) != 0;
+    const uint32_t depth = dw & 0x7FFFFFFFu;
+    const uint32_t i = pre[v], fo = off[v], c = t.cnt[v];
+    if (i >= o.node_cap || c == 0u || fo + c > tr.n || (leaf && c > 8u)) { atomicOr(&h->bad, 2u); return; }
+    const float *b = t.box + 6 * (size_t)v;
+    uint32_t *cn = o.cnode + 12 * (size_t)i;
+    for (int a = 0; a < 6; a++) cn[a] = __float_as_uint(b[a]);
+    cn[6] = tl_ref_of(t, off, iref, v);
+    cn[7] = depth;
+    cn[8] = v == 0 ? kNone : pre[t.parent[v] & ~kRightChild];
+    cn[9] = fo;
+    cn[10] = fo + c;
+    cn[11] = 0u;
+    if (v == 0)
+        for (int a = 0; a < 6; a++) h->root_box[a] = b[a];
+    if (!leaf) {
+        const uint32_t iid = iref[v];
+        if (iid >= o.interior_cap) { atomicOr(&h->bad, 2u); return; }
+        const uint32_t l = t.left[v], r = t.right[v];
+        float *nd = o.nodes + 16 * (size_t)iid;
+        for (int a = 0; a < 6; a++) { nd[a] = t.box[6 * (size_t)l + a]; nd[6 + a] = t.box[6 * (size_t)r + a]; }
+        nd[12] = __uint_as_float(tl_ref_of(t, off, iref, l));
+        nd[13] = __uint_as_float(tl_ref_of(t, off, iref, r));
+        nd[14] = 0.0f;
+        nd[15] = 0.0f;
+        return;
+    }
+    // a leaf keeps the linear BVH's triangles, now at its own position
+    float *lbx = o.leafbox + 8 * (size_t)fo;
+    for (int a = 0; a < 6; a++) lbx[a] = b[a];
+    lbx[6] = __uint_as_float(depth);
+    lbx[7] = __uint_as_float(i);
+    const uint32_t f = tr.first(v);
+    for (uint32_t k = 0; k < c; k++) {
+        const uint32_t prim = perm[f + k];
+        const float *p = verts + 9 * (size_t)prim;
+        float *tt = o.tris + 12 * (size_t)(fo + k);
+        tt[0] = p[0]; tt[1] = p[1]; tt[2] = p[2];
+        tt[3] = __uint_as_float(prim);
+        tt[4] = p[3] - p[0]; tt[5] = p[4] - p[1]; tt[6] = p[5] - p[2];
+        tt[7] = __uint_as_float(depth);
+        tt[8] = p[6] - p[0]; tt[9] = p[7] - p[1]; tt[10] = p[8] - p[2];
+        tt[11] = 0.0f;
+    }
+}
+
 struct ScratchLayout {
     size_t hdr, partial, code_a, code_b, id_a, id_b, sort_tmp, scan_tmp, parent, left, right, lo, hi, mark, lb, pre,
-        dep, box, total;
+        dep, box, cnt, atoms, off, iref, tl_list, tl_levels, total;
 };
 
 ScratchLayout scratch_layout(uint32_t n) {
@@ -425,6 +785,12 @@ ScratchLayout scratch_layout(uint32_t n) {
     L.pre = off; off += align256(M * 4);
     L.dep = off; off += align256(M * 4);
     L.box = off; off += align256(M * 24);
+    L.cnt = off; off += align256(M * 4);         // treelet passes: triangles and output leaves per subtree,
+    L.atoms = off; off += align256(M * 4);       // and the restructured tree's numbering
+    L.off = off; off += align256(M * 4);
+    L.iref = off; off += align256(M * 4);
+    L.tl_list = off; off += align256(I * 4);     // interior nodes grouped by level
+    L.tl_levels = off; off += align256(3 * kTlLevels * 4);   // per level: count, start, fill
     L.total = off;
     return L;
 }
@@ -466,8 +832,8 @@ hipError_t lbvh_static_scratch(void **ptr) {
     return hipSuccess;
 }
 
-hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, void *d_scratch,
-                      const LbvhOut &out, hipStream_t s, LbvhResult *res) {
+hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, uint32_t passes,
+                      void *d_scratch, const LbvhOut &out, hipStream_t s, LbvhResult *res) {
     const ScratchLayout L = scratch_layout(n);
     if (L.total == 0) return hipErrorInvalidValue;
     char *base = static_cast<char *>(d_scratch);
@@ -487,6 +853,13 @@ hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint3
     auto *pre = reinterpret_cast<uint32_t *>(base + L.pre);
     auto *dep = reinterpret_cast<uint32_t *>(base + L.dep);
     auto *box = reinterpret_cast<float *>(base + L.box);
+    auto *cnt = reinterpret_cast<uint32_t *>(base + L.cnt);
+    auto *atoms = reinterpret_cast<uint32_t *>(base + L.atoms);
+    auto *offs = reinterpret_cast<uint32_t *>(base + L.off);
+    auto *iref = reinterpret_cast<uint32_t *>(base + L.iref);
+    auto *tl_list = reinterpret_cast<uint32_t *>(base + L.tl_list);
+    auto *tl_hist = reinterpret_cast<uint32_t *>(base + L.tl_levels);
+    uint32_t *tl_start = tl_hist + kTlLevels, *tl_fill = tl_hist + 2 * kTlLevels;
     const uint32_t n_internal = n - 1u;
     const size_t m = 2 * (size_t)n - 1;
     const uint32_t bound_blocks = (uint32_t)std::min<size_t>(kBoundBlocks, (n + 255) / 256);
@@ -519,14 +892,52 @@ hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint3
     res->bad = hh.bad;
     res->max_depth = hh.max_depth;
     res->num_nodes = hh.num_nodes;
-    if (hh.bad || hh.max_depth > max_depth || hh.num_nodes == 0 || hh.num_nodes > m) return hipSuccess;
+    // with treelet passes the depth that counts is the restructured tree's
+    if (hh.bad || (!passes && hh.max_depth > max_depth) || hh.num_nodes == 0 || hh.num_nodes > m) return hipSuccess;
     hipLaunchKernelGGL(k_lbvh_leaf_boxes, grid_for(m, 256), dim3(256), 0, s, tr, d_verts, perm, dep, box);
     for (uint32_t level = hh.max_depth; level-- > 0;)
         hipLaunchKernelGGL(k_lbvh_level, grid_for(n_internal ? n_internal : 1, 256), dim3(256), 0, s, tr, dep,
                            level, box);
     EmitOut o{static_cast<float *>(out.nodes), static_cast<float *>(out.tris), static_cast<float *>(out.leafbox),
               static_cast<uint32_t *>(out.cnode), (uint32_t)m, n_internal ? n_internal : 1u};
-    hipLaunchKernelGGL(k_lbvh_emit, grid_for(m, 256), dim3(256), 0, s, tr, d_verts, perm, box, pre, lb, dep, o, h);
+    if (passes == 0) {
+        hipLaunchKernelGGL(k_lbvh_emit, grid_for(m, 256), dim3(256), 0, s, tr, d_verts, perm, box, pre, lb, dep, o, h);
+    } else {
+        TlTree t{parent, left, right, dep, cnt, atoms, box, &h->bad};
+        hipLaunchKernelGGL(k_tl_init, grid_for(m, 256), dim3(256), 0, s, tr, lb, dep, cnt, atoms);
+        uint32_t hist[kTlLevels];
+        // depths and level sizes of the current tree (one synchronisation)
+        auto levels = [&]() -> hipError_t {
+            hipLaunchKernelGGL(k_tl_zero, dim3(1), dim3(kTlLevels), 0, s, tl_hist, h);
+            hipLaunchKernelGGL(k_tl_depth, grid_for(m, 256), dim3(256), 0, s, parent, dep, (uint32_t)m, tl_hist, h);
+            hipError_t e2 = hipMemcpyAsync(hist, tl_hist, sizeof hist, hipMemcpyDeviceToHost, s);
+            if (e2 == hipSuccess) e2 = hipMemcpyAsync(&hh, h, sizeof hh, hipMemcpyDeviceToHost, s);
+            if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+            return e2;
+        };
+        for (uint32_t p = 0; p < passes && n_internal > 1; p++) {
+            e = levels();
+            if (e != hipSuccess) return e;
+            if (hh.bad) { res->bad = hh.bad; return hipSuccess; }
+            uint32_t start[kTlLevels], run = 0;
+            for (uint32_t k = 0; k < kTlLevels; k++) { start[k] = run; run += hist[k]; }
+            if (run != (hh.num_nodes - 1u) / 2u) { res->bad = 2u; return hipSuccess; }
+            hipLaunchKernelGGL(k_tl_start, dim3(1), dim3(64), 0, s, tl_hist, tl_start, tl_fill);
+            hipLaunchKernelGGL(k_tl_bucket, grid_for(n_internal, 256), dim3(256), 0, s, dep, n_internal, tl_start,
+                               tl_fill, tl_list);
+            for (uint32_t level = kTlLevels; level-- > 0;)
+                if (hist[level])
+                    hipLaunchKernelGGL(k_tl_treelet, dim3(hist[level]), dim3(kTlThreads), 0, s, t,
+                                       tl_list + start[level]);
+        }
+        e = levels();
+        if (e != hipSuccess) return e;
+        res->bad = hh.bad;
+        res->max_depth = hh.max_depth;
+        if (hh.bad || hh.max_depth > max_depth) return hipSuccess;
+        hipLaunchKernelGGL(k_tl_number, grid_for(m, 256), dim3(256), 0, s, t, (uint32_t)m, pre, offs, iref, h);
+        hipLaunchKernelGGL(k_tl_emit, grid_for(m, 256), dim3(256), 0, s, tr, t, d_verts, perm, pre, offs, iref, o, h);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(&hh, h, sizeof hh, hipMemcpyDeviceToHost, s);

@@ -277,7 +277,8 @@ static hrpp_status device_build(const float *d_verts, uint32_t num_tris, const h
     if (!out) return HRPP_EINVAL;
     *out = nullptr;
     if (!d_verts || !desc || !d_scratch || !d_buf || num_tris == 0 || num_tris >= (1u << 28)) return HRPP_EINVAL;
-    if (desc->leaf_max < 1 || desc->leaf_max > 8 || desc->max_depth < 1 || desc->max_depth > (uint32_t)kMaxDepth)
+    if (desc->leaf_max < 1 || desc->leaf_max > 8 || desc->max_depth < 1 || desc->max_depth > (uint32_t)kMaxDepth ||
+        desc->treelet_passes > kMaxTreeletPasses)
         return HRPP_EINVAL;
     if (reinterpret_cast<uintptr_t>(d_buf) % 256 || reinterpret_cast<uintptr_t>(d_scratch) % 256 ||
         reinterpret_cast<uintptr_t>(d_verts) % 4)
@@ -291,7 +292,8 @@ static hrpp_status device_build(const float *d_verts, uint32_t num_tris, const h
     if (hipMemsetAsync(base, 0, kHeaderBytes, s) != hipSuccess) return HRPP_EDEVICE;
     LbvhOut o{base + L.nodes, base + L.tris, base + L.leafbox, base + L.cnode};
     LbvhResult r{};
-    if (lbvh_build(d_verts, num_tris, desc->leaf_max, desc->max_depth, d_scratch, o, s, &r) != hipSuccess)
+    if (lbvh_build(d_verts, num_tris, desc->leaf_max, desc->max_depth, desc->treelet_passes, d_scratch, o, s, &r) !=
+        hipSuccess)
         return HRPP_EDEVICE;
     if (r.bad & 1u) return HRPP_EINVAL;
     const uint32_t m = r.num_nodes;

@@ -14,6 +14,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kLeafFlag = 0x80000000u;   // node reference names a leaf
 constexpr uint64_t kEmptyTag = 0xFFFFFFFFFFFFFFFFull;
 constexpr int kMaxDepth = 64;                  // deepest leaf the kernels accept
+constexpr uint32_t kMaxTreeletPasses = 8;      // treelet restructuring passes a build accepts
 
 // Counter slots, in the order of hrpp_stats.
 enum Stat : int {

@@ -170,11 +170,13 @@ size_t lbvh_scratch_bytes(uint32_t n);
 // its device address on the current device, looked up on first use.
 constexpr size_t kStaticBuildScratchBytes = size_t(64) << 20;
 hipError_t lbvh_static_scratch(void **ptr);
-// Enqueues the build on `s` and synchronises it twice: once to read the
-// tree's depth (a tree deeper than max_depth, or a non-finite vertex, ends
-// the build there) and once at the end.
-hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, void *d_scratch,
-                      const LbvhOut &out, hipStream_t s, LbvhResult *res);
+// Enqueues the build on `s` and synchronises it: once to read the linear
+// BVH's depth (a tree deeper than max_depth, or a non-finite vertex, ends
+// the build there; with treelet passes, deeper than the walk limit), once
+// per treelet pass and after the last one to read the levels' sizes and
+// the depth, and once at the end.
+hipError_t lbvh_build(const float *d_verts, uint32_t n, uint32_t leaf_max, uint32_t max_depth, uint32_t passes,
+                      void *d_scratch, const LbvhOut &out, hipStream_t s, LbvhResult *res);
 
 // Plain traversal of the 4-wide tree (a.wide, a.wide_root; a.stack_cap = the
 // tree's stack need); closest hit is the exact one.

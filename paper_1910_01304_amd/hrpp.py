@@ -50,7 +50,8 @@ class HrppError(RuntimeError):
 
 
 class _BvhDesc(C.Structure):
-    _fields_ = [("leaf_max", C.c_uint32), ("sah_bins", C.c_uint32), ("max_depth", C.c_uint32)]
+    _fields_ = [("leaf_max", C.c_uint32), ("sah_bins", C.c_uint32), ("max_depth", C.c_uint32),
+                ("treelet_passes", C.c_uint32)]
 
 
 class _PredDesc(C.Structure):
@@ -173,12 +174,13 @@ class BVH:
     """A BVH built on the host and resident in device memory."""
 
     def __init__(self, tris: np.ndarray, leaf_max: int = 4, sah_bins: int = 32, max_depth: int = 64,
-                 device: str | None = "cuda"):
-        """Build the tree on the host; upload it to ``device`` unless None."""
+                 device: str | None = "cuda", treelet_passes: int = 0):
+        """Build the tree on the host (binned SAH, then `treelet_passes` passes of treelet
+        restructuring); upload it to ``device`` unless None."""
         lib = load_library()
         v = np.ascontiguousarray(np.asarray(tris, np.float32).reshape(-1, 9))
         self.num_tris = int(v.shape[0])
-        self.desc = _BvhDesc(leaf_max, sah_bins, max_depth)
+        self.desc = _BvhDesc(leaf_max, sah_bins, max_depth, treelet_passes)
         h = C.c_void_p()
         _check(lib.hrpp_bvh_build_host(v.ctypes.data, self.num_tris, C.byref(self.desc), C.byref(h)),
                "hrpp_bvh_build_host")
@@ -193,18 +195,18 @@ class BVH:
 
     @classmethod
     def build_on_device(cls, verts: torch.Tensor, leaf_max: int = 4, max_depth: int = 64,
-                        static_scratch: bool = False) -> "BVH":
+                        static_scratch: bool = False, treelet_passes: int = 0) -> "BVH":
         """Linear BVH built on the GPU from a device tensor of [n, 9] (or [n, 3, 3]) float32 vertices.
 
         static_scratch: build in the library's static scratch (hrpp_build_bvh_device_static) instead of a
-        scratch buffer allocated here."""
+        scratch buffer allocated here.  treelet_passes: passes of treelet restructuring (0 = none)."""
         lib = load_library()
         if not (isinstance(verts, torch.Tensor) and verts.is_cuda and verts.dtype == torch.float32):
             raise HrppError("build_on_device takes a float32 device tensor")
         v = verts.reshape(-1, 9).contiguous()
         self = cls.__new__(cls)
         self.num_tris = int(v.shape[0])
-        self.desc = _BvhDesc(leaf_max, 32, max_depth)
+        self.desc = _BvhDesc(leaf_max, 32, max_depth, treelet_passes)
         if static_scratch:
             # the library's static scratch: the build allocates no scratch
             self.device_bytes = lib.hrpp_bvh_required_bytes(self.num_tris, C.byref(self.desc))

@@ -381,7 +381,11 @@ AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin
                 # SAH leaves of at most 2 triangles (a terrain quad): on this scene leaves
                 # of up to 4 straddle cells, and plain and HRPP traversal both run faster
                 # with leaves of 2 (measured at leaf sizes 1 to 4)
-                leaf_max=2)
+                leaf_max=2,
+                # two passes of treelet restructuring after the SAH build: the sum of
+                # interior half areas falls from 151 to 128 and the two-stream step
+                # runs faster over the restructured tree, plain and HRPP alike
+                treelet_passes=2)
 # the AO predictor: q_o 6, q_d 5, epochs of 2^22 rays (the largest; 7,372,800 rays
 # make two), waves with >= 16 failing lanes traverse in place; a table of 2^16 x 8
 # entries (4 MB), which stays in the last-level cache: the randomly addressed

@@ -54,6 +54,22 @@ def test_host_builder_matches_oracle_bit_for_bit():
             oracle.validate_bvh(o, tris, leaf_max, 64)
 
 
+def test_host_treelet_passes_match_oracle_bit_for_bit():
+    # the SAH tree after treelet restructuring (host C++) against the oracle's
+    hrpp = pytest.importorskip("paper_1910_01304_amd")
+    cases = [sg.triangle_soup(11, 7), sg.triangle_soup(12, 300), np.repeat(sg.triangle_soup(4, 1), 40, axis=0),
+             sg.scaled_terrain_scene(5, 20000)[0]]
+    for tris in cases:
+        for leaf_max, passes in ((1, 1), (2, 2), (4, 3)):
+            b = hrpp.BVH(tris, leaf_max=leaf_max, device=None, treelet_passes=passes)
+            e = b.export()
+            o = oracle.build_sah(tris, leaf_max=leaf_max, treelet_passes=passes)
+            for k in ("box", "right", "first", "count", "depth", "perm"):
+                assert np.array_equal(e[k].view(np.uint32), getattr(o, k).view(np.uint32)), (k, passes)
+            assert b.max_depth == o.max_depth()
+            oracle.validate_bvh(o, tris, leaf_max, 64)
+
+
 def test_host_argument_validation():
     hrpp = pytest.importorskip("paper_1910_01304_amd")
     lib = hrpp.load_library()
@@ -90,6 +106,10 @@ def test_host_argument_validation():
     assert lib.hrpp_build_bvh_device(p16, 16, C.byref(hrpp.hrpp._BvhDesc(4, 32, 65)), p16, 1 << 20, p16, 1 << 20,
                                      None, C.byref(h)) == 1
     assert lib.hrpp_build_bvh_device(p16, 16, C.byref(desc), p16, 1 << 20, p16, 1 << 20, None, None) == 1
+    # treelet passes: at most 8
+    assert lib.hrpp_build_bvh_device(p16, 16, C.byref(hrpp.hrpp._BvhDesc(4, 32, 64, 9)), p16, 1 << 20, p16, 1 << 20,
+                                     None, C.byref(h)) == 1
+    assert lib.hrpp_bvh_build_host(v.ctypes.data, 16, C.byref(hrpp.hrpp._BvhDesc(4, 32, 64, 9)), C.byref(h)) == 1
     idx = C.c_uint32()
     assert lib.hrpp_serve_add_scene(None, None, C.byref(idx)) == 1
     assert lib.hrpp_serve_remove_scene(None, 0) == 1

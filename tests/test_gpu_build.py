@@ -53,6 +53,29 @@ def test_device_build_equals_oracle(hrpp, n, leaf_max):
     oracle.validate_bvh(ob, tris, leaf_max, 64)
 
 
+@pytest.mark.parametrize("n,leaf_max,passes", [(2, 1, 1), (3, 1, 1), (7, 1, 1), (8, 1, 3), (64, 1, 2), (257, 2, 1),
+                                               (3000, 4, 2), (4097, 3, 1), (70001, 2, 2), (263169, 2, 1)])
+def test_device_treelet_build_equals_oracle(hrpp, n, leaf_max, passes):
+    _say(f"device treelet build soup n={n} leaf_max={leaf_max} passes={passes}")
+    tris = sg.triangle_soup(170 + n, n)
+    if n >= 3000:
+        tris[: n // 3] = tris[n // 3: 2 * (n // 3)]         # many equal codes
+    bvh, ob = device_bvh(hrpp, tris, leaf_max, passes=passes)
+    oracle.validate_bvh(ob, tris, leaf_max, 64)
+
+
+def test_device_treelet_build_scenes(hrpp):
+    _say("device treelet build: heightfield 2^20, degenerate scenes")
+    device_bvh(hrpp, sg.heightfield_scene(93, 1 << 20), 2, passes=2)
+    device_bvh(hrpp, np.repeat(sg.triangle_soup(5, 1), 50, axis=0), 1, passes=2)
+    signed = sg.triangle_soup(7, 300) - 0.5
+    signed[::7, 0, 0] = 0.0
+    signed[1::7, 1, 0] = -0.0
+    signed[2::7, :, 2] = -0.0
+    device_bvh(hrpp, signed, 2, passes=3)
+    device_bvh(hrpp, np.zeros((9, 9), np.float32), 2, passes=1)
+
+
 def test_device_build_large(hrpp):
     # 2^22 triangles (a heightfield), and 2^20 copies of one triangle, where
     # every split falls back to the positions' bits
@@ -177,6 +200,26 @@ def test_device_tree_terrain_queries(hrpp, small_terrain):
     got, _ = check_case(hrpp, "terrain shadow hrpp go-up 1 (device tree)", tris, shadow,
                         pred_cfg=(16, 8, 6, 3, 8192, 0, 1), builder="device")
     assert np.array_equal(got, occ_sah)
+
+
+def test_treelet_tree_queries(hrpp, small_terrain):
+    # traces over the restructured device tree: leaves at new positions,
+    # predicted subtrees named by the new canonical numbering
+    tris, rays = sg.tiny_workload()
+    check_case(hrpp, "tiny hrpp (treelet tree)", tris, rays, pred_cfg=(12, 4, 5, 6, 256), builder="device",
+               passes=2, calls=2)
+    check_case(hrpp, "tiny closest exact go-up 2 (treelet tree)", tris, rays, query="closest", mode="exact",
+               pred_cfg=(12, 4, 5, 6, 256, 0, 2), builder="device", passes=2)
+    tris, prim = small_terrain
+    check_case(hrpp, "terrain primary paper (treelet tree)", tris, prim, query="closest", mode="paper",
+               pred_cfg=(16, 8, 5, 7, 4096, 0, 0, 0, 0, 1024), builder="device", passes=2, leaf_max=2)
+    he, _ = oracle.trace(oracle.build_sah(tris), tris, prim, query="closest", mode="exact")
+    got, _ = check_case(hrpp, "terrain primary exact go-up 1 (treelet tree)", tris, prim, query="closest",
+                        mode="exact", pred_cfg=(14, 8, 5, 7, 4096, 0, 1), builder="device", passes=1)
+    assert got.tobytes() == he.tobytes()
+    shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=5)
+    check_case(hrpp, "terrain shadow go-up 1 (treelet tree)", tris, shadow, pred_cfg=(16, 8, 6, 3, 8192, 0, 1),
+               builder="device", passes=2, leaf_max=2)
 
 
 @pytest.fixture(scope="module")

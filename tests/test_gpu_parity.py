@@ -68,12 +68,13 @@ def assert_same_table(pred, tb: oracle.Table):
     assert np.array_equal(slots, tb.slots), f"{int(np.count_nonzero(np.any(slots != tb.slots, 1)))} entries differ"
 
 
-def device_bvh(hrpp, tris, leaf_max=4, max_depth=64):
-    """The library's device-built linear BVH, checked against the oracle's."""
+def device_bvh(hrpp, tris, leaf_max=4, max_depth=64, passes=0):
+    """The library's device-built linear BVH (after `passes` treelet passes),
+    checked against the oracle's."""
     import torch
     bvh = hrpp.BVH.build_on_device(torch.from_numpy(np.ascontiguousarray(tris, np.float32)).cuda(),
-                                   leaf_max=leaf_max, max_depth=max_depth)
-    ob = oracle.build_lbvh(tris, leaf_max=leaf_max, max_depth=max_depth)
+                                   leaf_max=leaf_max, max_depth=max_depth, treelet_passes=passes)
+    ob = oracle.build_lbvh(tris, leaf_max=leaf_max, max_depth=max_depth, treelet_passes=passes)
     got = bvh.export()
     assert bvh.num_nodes == ob.num_nodes
     assert np.array_equal(got["box"].view(np.uint32), ob.box.view(np.uint32)), "boxes differ"
@@ -84,18 +85,19 @@ def device_bvh(hrpp, tris, leaf_max=4, max_depth=64):
 
 
 def check_case(hrpp, name, tris, rays, query="any", mode="paper", pred_cfg=None, calls=1, leaf_max=4,
-               builder="sah"):
+               builder="sah", passes=0):
     """Run `calls` successive traces of `rays` on both sides and compare all.
 
     builder "sah": the host SAH tree on both sides; "device": the library's
-    device-built linear BVH against the oracle's linear BVH."""
+    device-built linear BVH against the oracle's; either after `passes`
+    treelet passes."""
     _say(f"{name}: {tris.shape[0]} tris, {rays.shape[0]} rays, {query}/{mode}, pred={pred_cfg}, calls={calls}, "
-         f"builder={builder}")
+         f"builder={builder}, passes={passes}")
     if builder == "device":
-        bvh, ob = device_bvh(hrpp, tris, leaf_max)
+        bvh, ob = device_bvh(hrpp, tris, leaf_max, passes=passes)
     else:
-        bvh = hrpp.BVH(tris, leaf_max=leaf_max)
-        ob = oracle.build_sah(tris, leaf_max=leaf_max)
+        bvh = hrpp.BVH(tris, leaf_max=leaf_max, treelet_passes=passes)
+        ob = oracle.build_sah(tris, leaf_max=leaf_max, treelet_passes=passes)
     vtx = oracle.bvh_vertices(tris, ob)
     pred = tb = None
     if pred_cfg is not None:
@@ -238,11 +240,11 @@ def test_terrain_table_shapes(hrpp, small_terrain, cfg):
 # (rays, invalid, hits, traversals) match, the visit counts are its own
 # ---------------------------------------------------------------------------
 
-def wide_case(hrpp, name, tris, rays, query="any", leaf_max=4):
+def wide_case(hrpp, name, tris, rays, query="any", leaf_max=4, passes=0):
     import torch
-    _say(f"{name}: wide {query}, {tris.shape[0]} tris, {rays.shape[0]} rays")
-    bvh = hrpp.BVH(tris, leaf_max=leaf_max)
-    ob = oracle.build_sah(tris, leaf_max=leaf_max)
+    _say(f"{name}: wide {query}, {tris.shape[0]} tris, {rays.shape[0]} rays, treelet passes {passes}")
+    bvh = hrpp.BVH(tris, leaf_max=leaf_max, treelet_passes=passes)
+    ob = oracle.build_sah(tris, leaf_max=leaf_max, treelet_passes=passes)
     vtx = oracle.bvh_vertices(tris, ob)
     r = torch.from_numpy(np.ascontiguousarray(rays)).cuda()
     st = hrpp.new_stats()
@@ -304,12 +306,14 @@ def test_wide_terrain(hrpp, small_terrain):
 def test_wide_full_size(hrpp, full_terrain):
     w = sg.AT_SCALE
     tris, prim = full_terrain
-    wide_case(hrpp, "full primary", tris, prim, "closest", leaf_max=sg.AT_SCALE["leaf_max"])
+    wide_case(hrpp, "full primary", tris, prim, "closest", leaf_max=sg.AT_SCALE["leaf_max"],
+              passes=sg.AT_SCALE["treelet_passes"])
     ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
-    wide_case(hrpp, "full shadow", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"])
+    wide_case(hrpp, "full shadow", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"],
+              passes=sg.AT_SCALE["treelet_passes"])
 
 
 # ---------------------------------------------------------------------------
@@ -348,7 +352,7 @@ def test_full_size_policy(hrpp, full_terrain):
     pq = w["primary_q"]
     _, st = check_case(hrpp, "full primary paper, FIFO + resident, 2^12 x 4", tris, prim, query="closest",
                        mode="paper", pred_cfg=(12, 4, pq[0], pq[1], pq[2], 0, 0, pq[3], 3, pq[4]),
-                           leaf_max=sg.AT_SCALE["leaf_max"])
+                       leaf_max=sg.AT_SCALE["leaf_max"], passes=sg.AT_SCALE["treelet_passes"])
     assert st["evictions"] > 0
 
 
@@ -462,7 +466,7 @@ def test_full_size_go_up(hrpp, full_terrain):
     pq = w["primary_q"]
     check_case(hrpp, "full primary paper go-up 1", tris, prim, query="closest", mode="paper",
                pred_cfg=(w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 1, pq[3], 0, pq[4]),
-                   leaf_max=sg.AT_SCALE["leaf_max"])
+               leaf_max=sg.AT_SCALE["leaf_max"], passes=sg.AT_SCALE["treelet_passes"])
 
 
 def test_import_validates_slots(hrpp, small_terrain):
@@ -661,16 +665,18 @@ def test_full_size_primary_and_shadow(hrpp, full_terrain, tuned):
     cfg_all = (w["log2_entries"], w["ways"], pq[0], pq[1], pq[2], 0, 0, pq[3], 0, pq[4])
     cfg_any = (w["log2_entries"], w["ways"], sq[0], sq[1], sq[2], 0, 0, sq[3], 0, sq[4])
     _, st = check_case(hrpp, "full primary paper", tris, prim, query="closest", mode="paper", pred_cfg=cfg_all,
-                       leaf_max=sg.AT_SCALE["leaf_max"])
+                       leaf_max=sg.AT_SCALE["leaf_max"], passes=sg.AT_SCALE["treelet_passes"])
     assert st["rays"] == 1920 * 1080
     ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
     he, _ = oracle.trace(ob, tris, prim, query="closest", mode="exact")
     check_case(hrpp, "full primary exact (plain)", tris, prim, query="closest", mode="exact",
-               leaf_max=sg.AT_SCALE["leaf_max"])
+               leaf_max=sg.AT_SCALE["leaf_max"], passes=sg.AT_SCALE["treelet_passes"])
     shadow = sg.shadow_rays_from_hits(tris, prim, he[:, 0], he[:, 3].view(np.uint32), seed=w["seed"],
                                       light_center=w["light_center"], light_size=w["light_size"])
-    check_case(hrpp, "full shadow plain", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"])
-    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any, leaf_max=sg.AT_SCALE["leaf_max"])
+    check_case(hrpp, "full shadow plain", tris, shadow, leaf_max=sg.AT_SCALE["leaf_max"],
+               passes=sg.AT_SCALE["treelet_passes"])
+    check_case(hrpp, "full shadow hrpp", tris, shadow, pred_cfg=cfg_any, leaf_max=sg.AT_SCALE["leaf_max"],
+               passes=sg.AT_SCALE["treelet_passes"])
 
 
 def test_full_size_progressive_frames(hrpp, full_terrain):
@@ -681,8 +687,8 @@ def test_full_size_progressive_frames(hrpp, full_terrain):
     import torch
     w = sg.AT_SCALE
     tris, _ = full_terrain
-    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"])
-    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"])
+    bvh = hrpp.BVH(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
+    ob = oracle.build_sah(tris, leaf_max=sg.AT_SCALE["leaf_max"], treelet_passes=sg.AT_SCALE["treelet_passes"])
     vtx = oracle.bvh_vertices(tris, ob)
     pq, sq = w["primary_q"], w["shadow_q"]
     E = 1 << 21
@@ -731,7 +737,8 @@ def test_full_size_ao(hrpp, full_terrain, cfg):
     ao = sg.ao_rays_from_hits(tris, cam, hh[:, 0], hh[:, 3].view(np.uint32), seed=wi["seed"],
                               samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
     assert ao.shape[0] == 7372800
-    _, st = check_case(hrpp, f"full AO {cfg}", tris, ao, pred_cfg=cfg, leaf_max=sg.AT_SCALE["leaf_max"])
+    _, st = check_case(hrpp, f"full AO {cfg}", tris, ao, pred_cfg=cfg, leaf_max=sg.AT_SCALE["leaf_max"],
+                       passes=sg.AT_SCALE["treelet_passes"])
     assert st["rays"] == 7372800
 
 
@@ -747,7 +754,8 @@ def test_maximum_epoch_and_large_table(hrpp, full_terrain):
                               samples=wi["samples"], tmax=wi["tmax_frac"] * sg.scene_diagonal(tris))
     for inline in (65, 1):
         _, st = check_case(hrpp, f"AO, epoch 2^22, table 2^24 x 4, inline {inline}", tris, ao,
-                           pred_cfg=(24, 4, 5, 6, 1 << 22, 0, 0, inline), leaf_max=sg.AT_SCALE["leaf_max"])
+                           pred_cfg=(24, 4, 5, 6, 1 << 22, 0, 0, inline), leaf_max=sg.AT_SCALE["leaf_max"],
+                           passes=sg.AT_SCALE["treelet_passes"])
         assert st["rays"] == 7372800 and st["pred_hits"] > 0
 
 
