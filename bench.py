@@ -100,6 +100,8 @@ def parse():
                          "-1 = choose 2, 4 or 8 by measured batch time)")
     ap.add_argument("--scene-leaf-max", type=int, default=2,
                     help="leaf size of the batched and serving scenes' BVHs (the at-scale scene uses its own)")
+    ap.add_argument("--scene-treelet-passes", type=int, default=2,
+                    help="treelet passes of the batched workload's device-built trees")
     ap.add_argument("--tune-queries", default="",
                     help="comma list of primary,shadow,ao,primary_warm,shadow_warm (default all)")
     ap.add_argument("--tune-knobs",
@@ -1887,7 +1889,8 @@ def run_batched(args, np, torch, hrpp, sg):
         dev = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dev = [hrpp.BVH.build_on_device(v, leaf_max=args.scene_leaf_max) for v in verts_d]
+        dev = [hrpp.BVH.build_on_device(v, leaf_max=args.scene_leaf_max, treelet_passes=args.scene_treelet_passes)
+               for v in verts_d]
         torch.cuda.synchronize()
         dev_ms = (time.perf_counter() - t0) * 1e3
     log(f"batched: device build of {len(dev)} scenes {dev_ms:.1f} ms (host {build_s:.2f} s)")
@@ -1930,9 +1933,10 @@ def run_batched(args, np, torch, hrpp, sg):
         "occluded_fraction": round(h["hits"] / total, 4),
         "device_trees": {"bvh_build_ms": round(dev_ms, 2), "hrpp_batched_mrays_s": round(total / (ms_dbatch * 1e-3) / 1e6, 2),
                          "plain_batched_mrays_s": round(total / (ms_dplain * 1e-3) / 1e6, 2),
+                         "treelet_passes": args.scene_treelet_passes,
                          "note": "the same scenes as linear BVHs built on the GPU (all 64, resident vertices, "
-                                 "wall time including the calls); host_bvh_build_s is the host SAH build on "
-                                 "8 threads"},
+                                 "wall time including the calls), restructured by treelet_passes passes; "
+                                 "host_bvh_build_s is the host SAH build on 8 threads"},
     }
     print(json.dumps(out), flush=True)
 
