@@ -11,7 +11,7 @@ One step = the whole query path over one frame of the at-scale workload
 with the predictor quantisation, epoch sizes and fallback split chosen by the
 autotuner and a sweep of the two-stream step (hit-all: q_o 5, q_d 7, a first
 epoch of 2^17 rays -- one of the 16 interleaved pixel passes -- then the rest
-of the frame as one epoch; hit-any: q_o 6, q_d 3, a first epoch of 2^20; every
+of the frame as one epoch; hit-any: q_o 6, q_d 3, a first epoch of 2^19; every
 failing ray traversed in place; the line also reports the untuned q_o 5 /
 q_d 6 step at epochs of 2^17).  The same rays are
 also traced without a predictor ("plain"), on the binary and on the 4-wide

@@ -375,11 +375,9 @@ AT_SCALE = dict(seed=2, width=1920, height=1080, log2_entries=20, ways=8, origin
                 # rays) of the hit-all and hit-any predictors, chosen by the autotuner
                 # (table fixed at 2^20 x 8) and a sweep of the two-stream step: a first
                 # epoch of one Bayer pass (2^17 rays, the whole view at 1/16 density)
-                # for the hit-all predictor and eight (2^20 rays, half the frame) for
-                # the hit-any one, then the rest of the frame in one epoch (over the
-                # restructured tree a shadow first epoch of 2^20 ran the step 8% faster
-                # than 2^19, and 2^18 or 2^16..2^18 for the primaries were slower)
-                primary_q=(5, 7, 1 << 21, 1, 1 << 17), shadow_q=(6, 3, 1 << 21, 1, 1 << 20),
+                # for the hit-all predictor and four (2^19 rays) for the hit-any one,
+                # then the rest of the frame in one epoch
+                primary_q=(5, 7, 1 << 21, 1, 1 << 17), shadow_q=(6, 3, 1 << 21, 1, 1 << 19),
                 # SAH leaves of at most 2 triangles (a terrain quad): on this scene leaves
                 # of up to 4 straddle cells, and plain and HRPP traversal both run faster
                 # with leaves of 2 (measured at leaf sizes 1 to 4)

@@ -76,6 +76,26 @@ def test_device_treelet_build_scenes(hrpp):
     device_bvh(hrpp, np.zeros((9, 9), np.float32), 2, passes=1)
 
 
+def test_device_treelet_depth_limit(hrpp):
+    # with treelet passes max_depth bounds the restructured tree, not the
+    # linear BVH before them: here the passes make the tree one level
+    # shallower, so the limit of the restructured depth builds while the
+    # linear BVH alone would not, and one level less reports EDEPTH, on both
+    # sides
+    tris = sg.triangle_soup(211, 3000)
+    deep = oracle.build_lbvh(tris, leaf_max=1, treelet_passes=2).max_depth()
+    base = oracle.build_lbvh(tris, leaf_max=1).max_depth()
+    _say(f"device treelet depth limit: linear {base}, restructured {deep}")
+    assert deep < base
+    with pytest.raises(hrpp.HrppError, match="deeper"):
+        hrpp.BVH.build_on_device(_dev(tris), leaf_max=1, max_depth=deep)
+    device_bvh(hrpp, tris, 1, max_depth=deep, passes=2)
+    with pytest.raises(ValueError):
+        oracle.build_lbvh(tris, leaf_max=1, max_depth=deep - 1, treelet_passes=2)
+    with pytest.raises(hrpp.HrppError, match="deeper"):
+        hrpp.BVH.build_on_device(_dev(tris), leaf_max=1, max_depth=deep - 1, treelet_passes=2)
+
+
 def test_device_build_large(hrpp):
     # 2^22 triangles (a heightfield), and 2^20 copies of one triangle, where
     # every split falls back to the positions' bits

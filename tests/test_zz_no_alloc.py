@@ -108,6 +108,16 @@ def test_static_build_equals_scratch_build_twice(hrpp):
     assert np.array_equal(first[1].view(np.uint32), again[1].view(np.uint32))
 
 
+def test_static_build_with_treelet_passes(hrpp):
+    # the treelet passes' scratch lives in the same static array
+    small = sg.triangle_soup(33, 20_011)
+    _say(f"static device build with 2 treelet passes: soup n={len(small)}")
+    a = hrpp.BVH.build_on_device(_dev(small), leaf_max=2, static_scratch=True, treelet_passes=2)
+    b = hrpp.BVH.build_on_device(_dev(small), leaf_max=2, treelet_passes=2)
+    _same_tree(a, b)
+    _trace_both(hrpp, a, b, _rays(small, 43, 5_000))
+
+
 def test_static_build_refuses_oversize_and_bad_arguments(hrpp):
     import torch
     lib = hrpp.load_library()
