@@ -1120,9 +1120,9 @@ def run_autotune(args, np, torch, hrpp, sg):
     trees = {sg.AT_SCALE["leaf_max"]: bvh}
 
     def tree_for(leaf):
-        # the at-scale scene's SAH tree at another leaf size (knob "leaf_max")
+        # the at-scale scene's tree at another leaf size (knob "leaf_max")
         if leaf not in trees:
-            trees[leaf] = hrpp.BVH(tris, leaf_max=leaf)
+            trees[leaf] = hrpp.BVH(tris, leaf_max=leaf, treelet_passes=sg.AT_SCALE["treelet_passes"])
         return trees[leaf]
 
     prim_d = torch.from_numpy(prim).cuda()
