@@ -3,6 +3,7 @@
 // AddressSanitizer and UndefinedBehaviorSanitizer (tests/test_sanitizers.py).
 // Exits non-zero on the first broken invariant; the sanitizers abort on the
 // first memory or undefined-behaviour error.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -42,8 +43,8 @@ std::vector<float> scene(std::mt19937 &g, uint32_t n, int kind) {
     return v;
 }
 
-void check_tree(const std::vector<float> &v, uint32_t n, uint32_t leaf_max) {
-    hrpp_bvh_desc d{leaf_max, 32, 64};
+void check_tree(const std::vector<float> &v, uint32_t n, uint32_t leaf_max, uint32_t passes = 0) {
+    hrpp_bvh_desc d{leaf_max, 32, 64, passes};
     hrpp::CanonTree t;
     const hrpp_status st = hrpp::build_sah_tree(v.data(), n, d, t);
     if (st == HRPP_EDEPTH) return;
@@ -63,6 +64,12 @@ void check_tree(const std::vector<float> &v, uint32_t n, uint32_t leaf_max) {
     for (size_t i = 0; i < m; i++) {
         if (t.right[i] != hrpp::kNone) {
             expect(t.right[i] > i + 1 && t.right[i] < m, "right child after the left subtree", n, leaf_max);
+            if (t.right[i] < m)
+                for (int a = 0; a < 3; a++) {
+                    const float *l = &t.box[6 * (i + 1)], *r = &t.box[6 * (size_t)t.right[i]], *b = &t.box[6 * i];
+                    expect(b[a] == std::min(l[a], r[a]) && b[3 + a] == std::max(l[3 + a], r[3 + a]),
+                           "interior box is the union of its children", n, leaf_max);
+                }
             continue;
         }
         expect(t.count[i] >= 1 && t.count[i] <= leaf_max, "leaf size", n, leaf_max);
@@ -134,6 +141,11 @@ int main() {
     for (uint32_t n : sizes)
         for (uint32_t leaf_max = 1; leaf_max <= 8; leaf_max++)
             for (int kind = 0; kind < 4; kind++) check_tree(scene(g, n, kind), n, leaf_max);
+    // the same checks after treelet restructuring
+    for (uint32_t n : sizes)
+        for (uint32_t leaf_max : {1u, 2u, 4u})
+            for (uint32_t passes = 1; passes <= 3; passes++)
+                for (int kind = 0; kind < 4; kind++) check_tree(scene(g, n, kind), n, leaf_max, passes);
     check_pool(g);
     // invalid input is refused, not read out of bounds
     {
