@@ -699,7 +699,8 @@ static bool bj_inline(const hrpp_predictor *p) {
 }
 
 // Block offsets: count + 1 per group for the two plain groups, and three
-// arrays of count + 1 per predictor group (at most six groups).
+// arrays of count + 1 per predictor group that runs in rounds (at most six
+// such groups; groups of small-epoch jobs need none).
 static size_t batch_offset_words(uint32_t njobs) { return ((size_t)njobs + 2) + 3 * ((size_t)njobs + 6); }
 
 size_t hrpp_batch_required_bytes(uint32_t njobs) {
@@ -739,17 +740,23 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
         if (J.pred) kind_of[j] = any ? kBatchAnyHrpp : (J.mode == HRPP_CLOSEST_EXACT ? kBatchExactHrpp : kBatchPaperHrpp);
         else kind_of[j] = any ? kBatchAnyPlain : kBatchClosestPlain;
     }
+    // groups: by kind; predictor kinds also by go-up level (bit 0 of sub) and
+    // by whether the job's epochs are small enough for one workgroup (bit 1)
     for (int kind = kBatchAnyHrpp; kind <= kBatchClosestPlain; kind++)
-    for (int sub = 0; sub < 2; sub++) {
+    for (int sub = 0; sub < 4; sub++) {
         const bool hrpp_kind = (kind == kBatchAnyHrpp || kind == kBatchPaperHrpp || kind == kBatchExactHrpp);
         if (sub && !hrpp_kind) continue;
         BatchGroup g{};
         g.kind = kind;
-        g.subtree = (sub == 1);
+        g.subtree = (sub & 1) != 0;
+        g.block_epochs = (sub & 2) != 0;
         g.first_id = (uint32_t)b->ids.size();
         for (uint32_t j = 0; j < njobs; j++) {
             if ((int)kind_of[j] != kind || jobs[j].n == 0) continue;
             if (hrpp_kind && (jobs[j].pred->desc.go_up_level > 0) != g.subtree) continue;
+            if (hrpp_kind && (b->jobs[j].first <= kBlockEpochRays && b->jobs[j].epoch <= kBlockEpochRays) !=
+                                 g.block_epochs)
+                continue;
             if (hrpp_kind && bj_inline(jobs[j].pred)) g.inline_any = true;
             const BatchJob &bj = b->jobs[j];
             b->ids.push_back(j);
@@ -758,7 +765,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
             if (bj.a.stats) g.stats = true;
         }
         if (g.count == 0) continue;
-        if (kind == kBatchAnyPlain || kind == kBatchClosestPlain) g.rounds = 0;
+        if (kind == kBatchAnyPlain || kind == kBatchClosestPlain || g.block_epochs) g.rounds = 0;
         b->max_rounds = std::max(b->max_rounds, g.rounds);
         b->groups.push_back(g);
     }
@@ -784,6 +791,7 @@ hrpp_status hrpp_batch_create(const hrpp_batch_job *jobs, uint32_t njobs, void *
         return std::make_pair(at, acc);
     };
     for (BatchGroup &g : b->groups) {
+        if (g.block_epochs) continue;   // one workgroup per job: no block offsets
         if (g.kind == kBatchAnyPlain || g.kind == kBatchClosestPlain) {
             const auto p = add_offsets(g, 128u, ~0u, true);
             g.d_block_off = d_off + p.first;

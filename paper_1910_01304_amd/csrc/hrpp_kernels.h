@@ -118,6 +118,8 @@ struct BatchGroup {
     bool stats;
     bool subtree;                 // predictors of go-up level >= 1
     bool inline_any;              // some job traverses failing waves in place
+    bool block_epochs;            // every job's epochs hold at most kBlockEpochRays rays: one
+                                  // workgroup per job runs all of its epochs, in one launch
     // plain groups: blocks of 128 lanes covering each job's rays
     uint32_t total_blocks;
     const uint32_t *d_block_off;
@@ -129,6 +131,7 @@ struct BatchGroup {
 };
 
 constexpr uint32_t kQueueBlocks = 4096;   // grid cap of one epoch's queue traversal
+constexpr uint32_t kBlockEpochRays = 256; // epochs this small run a whole call in one workgroup
 
 void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<BatchGroup> &groups,
                   uint32_t max_rounds, uint32_t max_blocks, hipStream_t s);

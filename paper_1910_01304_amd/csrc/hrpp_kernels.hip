@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(256) void k_update_finish(TraceArgs a, uint32_t bas
 // (a workgroup-scope release and acquire) makes every phase's stores and
 // atomics visible to the next phase's loads.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kBlockEpoch = 256;
+constexpr uint32_t kBlockEpoch = kBlockEpochRays;
 
 template <bool ANY, bool EXACT, bool STATS, bool SUBTREE, bool INLINE>
 __device__ __forceinline__ void body_epochs_block(const TraceArgs &a, uint32_t n, uint32_t first, uint32_t epoch,
@@ -1308,6 +1308,16 @@ __global__ __launch_bounds__(256) void kb_update_finish(const BatchJob *__restri
     BatchBlock b;
     if (!batch_block(jobs, ids, off, njobs, round, b)) return;
     body_update_finish<STATS>(b.J->a, b.base, b.count, b.bx, b.gx);
+}
+
+// Jobs whose epochs all hold at most kBlockEpoch rays: one workgroup per job
+// runs all of the job's epochs (as k_epochs_block does for one call; the
+// batch's first epoch goes through the prediction kernel, as in its rounds).
+template <bool ANY, bool EXACT, bool STATS, bool SUBTREE>
+__global__ __launch_bounds__(kBlockEpoch) void kb_epochs_block(const BatchJob *__restrict__ jobs,
+                                                               const uint32_t *__restrict__ ids) {
+    const BatchJob &J = jobs[ids[blockIdx.x]];
+    body_epochs_block<ANY, EXACT, STATS, SUBTREE, true>(J.a, J.n, J.first, J.epoch, false);
 }
 
 // Plain jobs: one flat grid, each job getting blocks in proportion to its rays.
@@ -1624,6 +1634,18 @@ static void launch_batch_round(const BatchJob *jobs, const uint32_t *ids, const 
         hipLaunchKernelGGL((kb_update_finish<STATS>), g256, dim3(256), 0, s, jobs, gid, g.d_off256, nj, r);
 }
 
+template <bool ANY, bool EXACT, bool STATS>
+static void launch_batch_block_epochs(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g,
+                                      hipStream_t s) {
+    const uint32_t *gid = ids + g.first_id;
+    if (g.subtree)
+        hipLaunchKernelGGL((kb_epochs_block<ANY, EXACT, STATS, true>), dim3(g.count), dim3(kBlockEpoch), 0, s, jobs,
+                           gid);
+    else
+        hipLaunchKernelGGL((kb_epochs_block<ANY, EXACT, STATS, false>), dim3(g.count), dim3(kBlockEpoch), 0, s, jobs,
+                           gid);
+}
+
 template <bool ANY, bool STATS>
 static void launch_batch_plain(const BatchJob *jobs, const uint32_t *ids, const BatchGroup &g, hipStream_t s) {
     const size_t lds = 0;   // traversal stacks live in private memory
@@ -1640,6 +1662,18 @@ void launch_batch(const BatchJob *jobs, const uint32_t *ids, const std::vector<B
         } else if (g.kind == kBatchClosestPlain) {
             if (g.stats) launch_batch_plain<false, true>(jobs, ids, g, s);
             else launch_batch_plain<false, false>(jobs, ids, g, s);
+        } else if (g.block_epochs) {
+            // small epochs: every epoch of every job of the group in one launch
+            if (g.kind == kBatchAnyHrpp) {
+                if (g.stats) launch_batch_block_epochs<true, false, true>(jobs, ids, g, s);
+                else launch_batch_block_epochs<true, false, false>(jobs, ids, g, s);
+            } else if (g.kind == kBatchExactHrpp) {
+                if (g.stats) launch_batch_block_epochs<false, true, true>(jobs, ids, g, s);
+                else launch_batch_block_epochs<false, true, false>(jobs, ids, g, s);
+            } else {
+                if (g.stats) launch_batch_block_epochs<false, false, true>(jobs, ids, g, s);
+                else launch_batch_block_epochs<false, false, false>(jobs, ids, g, s);
+            }
         }
     }
     for (uint32_t r = 0; r < max_rounds; r++) {

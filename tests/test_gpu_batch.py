@@ -50,6 +50,11 @@ def _jobs_spec():
         # a short first epoch (its rounds differ from the other jobs')
         (24, 6000, 14000, "any", "paper", (12, 8, 5, 6, 8192, 0, 0, 1, 0, 700)),
         (25, 4000, 10000, "closest", "exact", (12, 4, 5, 6, 6000, 0, 0, 0, 0, 1)),
+        # epochs of at most 256 rays: one workgroup per job runs all its epochs
+        (26, 5000, 3000, "any", "paper", (12, 4, 5, 6, 256)),
+        (27, 3000, 2000, "closest", "exact", (12, 4, 5, 6, 100, 0, 1)),
+        (28, 4000, 2500, "closest", "paper", (12, 8, 5, 6, 200, 0, 0, 65, 0, 50)),
+        (29, 2000, 300, "any", "paper", (10, 4, 5, 6, 1)),
     ]
 
 
