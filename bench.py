@@ -601,8 +601,8 @@ def main():
                 per_launch_b = nb * reps / launches
                 avg_ms = total_ms / launches
                 kernels[f"{label}:{k}"] = dict(launches_per_step=launches // reps, avg_us=avg_ms * 1e3,
-                                               ms_per_step=total_ms / reps, bytes_per_launch=per_launch_b,
-                                               gbs=per_launch_b / (avg_ms * 1e-3) / 1e9)
+                                               ms_per_step=total_ms / reps, logical_bytes_per_launch=per_launch_b,
+                                               logical_gbs=per_launch_b / (avg_ms * 1e-3) / 1e9)
         # compulsory traffic: the distinct 128-byte lines of nodes, triangles, leaf boxes, table
         # entries and node records each kernel kind touched in one counted step, plus its
         # streamed bytes (rays, results, queue and record writes)
@@ -650,7 +650,7 @@ def main():
                                      if traffic is not None else None),
                     "avg_launch_us": round(d["avg_us"], 2), "hbm": hbm, "alu": alu,
                     # every node, triangle and entry read counted each time (mostly served by L2 and MALL)
-                    "logical_bytes_per_launch": int(d["bytes_per_launch"])}
+                    "logical_bytes_per_launch": int(d["logical_bytes_per_launch"])}
 
     ref_info = None
     if args.reference_epoch:
@@ -1057,7 +1057,7 @@ def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, 
 
 def run_progressive(args, np, torch, hrpp, sg):
     """Frames of one view traced with the tables kept (see measure_progressive),
-    with per-kernel HIP-event timing and algorithmic bytes of each configuration
+    with per-kernel HIP-event timing and logical bytes of each configuration
     (a pass with the two queries on one stream); one JSON line."""
     w = sg.AT_SCALE
     tris, prim = sg.terrain_workload()
@@ -1094,9 +1094,12 @@ def run_progressive(args, np, torch, hrpp, sg):
         for k, (launches, total_ms) in res.items():
             nb = kernel_bytes(k, ga, gb, entry_b, frames * n, frames * n)
             avg_ms = total_ms / launches
-            out[k] = {"launches": launches, "avg_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(nb / launches),
-                      "gbs": round(nb / launches / (avg_ms * 1e-3) / 1e9, 1),
-                      "frac_of_hbm_peak": round(nb / launches / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            # logical bytes: every node, triangle and entry read counted each
+            # time a ray reads it (most are served by the L2s and the MALL), so
+            # their rate is not HBM traffic and is not compared with HBM's peak
+            out[k] = {"launches": launches, "avg_us": round(avg_ms * 1e3, 2),
+                      "logical_bytes_per_launch": int(nb / launches),
+                      "logical_gbs": round(nb / launches / (avg_ms * 1e-3) / 1e9, 1)}
         return out
 
     info = measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, hits_out, occ_out,
