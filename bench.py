@@ -85,7 +85,7 @@ def parse():
                     help="also time the HRPP step at this epoch size (0 = skip)")
     ap.add_argument("--workload", default="at_scale",
                     choices=["at_scale", "batched", "autotune", "serving", "sweep", "goup", "policy", "progressive",
-                             "build"],
+                             "build", "tiny"],
                     help="at_scale (default): the headline step; batched: 64 scenes of uneven size in one "
                          "graph-captured batch")
     ap.add_argument("--sweep-epoch", type=int, default=1 << 17,
@@ -361,6 +361,12 @@ def main():
         return
     if args.workload == "build":
         run_build(args, np, torch, hrpp, sg)
+        return
+    if args.workload == "tiny":
+        print(json.dumps({"metric": "Mrays/s HRPP vs plain, tiny configuration", "unit": "Mrays/s", "dtype": "f32",
+                          "data": "synthetic", "steps": args.steps,
+                          "config": {"workload": "256 triangles, 4,096 shadow rays, table 2^12 x 4, epochs of 256"},
+                          "tiny": measure_tiny(args, torch, hrpp, sg)}), flush=True)
         return
     w = sg.AT_SCALE
     log("generating the at-scale workload")
@@ -785,51 +791,7 @@ def main():
             del frames
 
     # the tiny configuration: 256 triangles, 4,096 shadow rays, epochs of 256 rays
-    # (16 epochs, each a launch sequence: launch latency is the whole cost at this size)
-    tiny_info = None
-    if not args.no_tiny:
-        ttris, trays = sg.tiny_workload()
-        tw = sg.TINY
-        tbvh = hrpp.BVH(ttris, leaf_max=4)
-        tpred = hrpp.Predictor(tbvh, tw["log2_entries"], tw["ways"], tw["origin_bits"], tw["dir_bits"], tw["epoch"])
-        tr_d = torch.from_numpy(trays).cuda()
-        tocc = torch.empty(trays.shape[0], dtype=torch.uint8, device="cuda")
-
-        def tiny_hrpp():
-            tpred.reset()
-            hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc)
-
-        ms_t_h = timed(torch, tiny_hrpp, args.steps, 2)[0]
-        eager_out = tocc.clone()
-        # the same trace as a one-job batch captured once as a hipGraph and
-        # replayed (the reset stays a launch of its own): launch costs fall,
-        # the work is the same, and the results must be the eager call's
-        tgo = torch.empty_like(tocc)
-        tbatch = hrpp.Batch([dict(bvh=tbvh, pred=tpred, rays=tr_d, query="any", out=tgo)])
-
-        def tiny_graph():
-            tpred.reset()
-            tbatch.launch(use_graph=True)
-
-        ms_t_g = timed(torch, tiny_graph, args.steps, 2)[0]
-        torch.cuda.synchronize()
-        if not torch.equal(tgo, eager_out):
-            raise SystemExit("tiny configuration: the graph-replayed batch differs from the eager call")
-        tbatch.close()
-        ms_t_p = timed(torch, lambda: hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc), args.steps, 2)[0]
-        tsh, tsp = hrpp.new_stats(), hrpp.new_stats()
-        tpred.reset()
-        hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc, stats=tsh)
-        hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc, stats=tsp)
-        th, tp = hrpp.stats_dict(tsh), hrpp.stats_dict(tsp)
-        nt = trays.shape[0]
-        tiny_info = dict(rays=nt, query="any hit", epoch_rays=tw["epoch"], hrpp_mrays_s=round(mrays(nt, ms_t_h), 2),
-                         graph_hrpp_mrays_s=round(mrays(nt, ms_t_g), 2), graph_hrpp_ms=round(ms_t_g, 4),
-                         plain_mrays_s=round(mrays(nt, ms_t_p), 2), hrpp_ms=round(ms_t_h, 4),
-                         plain_ms=round(ms_t_p, 4), pct_nodes_skipped=round(pct_saved("nodes_visited", th, tp), 3),
-                         pct_box_tests_skipped=round(pct_saved("box_tests", th, tp), 3),
-                         prediction_hit_rate=round(th["pred_hits"] / nt, 4),
-                         occluded_fraction=round(th["hits"] / nt, 4))
+    tiny_info = None if args.no_tiny else measure_tiny(args, torch, hrpp, sg)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -866,6 +828,8 @@ def main():
                                 "sample": f"one full step, {t1:.2f} s"}
         if tiny_info is not None:
             # the tiny configuration on the host: the same rays, epochs and table
+            ttris, trays = sg.tiny_workload()
+            tw = sg.TINY
             tob = oracle.build_sah(ttris, leaf_max=4)
             tvtx = oracle.bvh_vertices(ttris, tob)
             tt = {}
@@ -1053,6 +1017,61 @@ def measure_progressive(args, np, torch, hrpp, sg, bvh, tris, cfg_all, cfg_any, 
             del pa_, pb_
         del frames
     return info
+
+
+def measure_tiny(args, torch, hrpp, sg):
+    """The tiny configuration (256 triangles, 4,096 shadow rays, 16 epochs of
+    256 rays): HRPP eager (one workgroup runs the whole call), the same trace as
+    a one-job batch replayed from a hipGraph, and plain traversal."""
+    def mrays(n, ms):
+        return n / (ms * 1e-3) / 1e6
+
+    def pct_saved(key, h, p):
+        return 100.0 * (1.0 - h[key] / p[key]) if p[key] else 0.0
+
+    ttris, trays = sg.tiny_workload()
+    tw = sg.TINY
+    tbvh = hrpp.BVH(ttris, leaf_max=4)
+    tpred = hrpp.Predictor(tbvh, tw["log2_entries"], tw["ways"], tw["origin_bits"], tw["dir_bits"], tw["epoch"])
+    tr_d = torch.from_numpy(trays).cuda()
+    tocc = torch.empty(trays.shape[0], dtype=torch.uint8, device="cuda")
+
+    def tiny_hrpp():
+        tpred.reset()
+        hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc)
+
+    ms_t_h = timed(torch, tiny_hrpp, args.steps, 2)[0]
+    eager_out = tocc.clone()
+    # the same trace as a one-job batch captured once as a hipGraph and
+    # replayed (the reset stays a launch of its own): launch costs fall,
+    # the work is the same, and the results must be the eager call's
+    tgo = torch.empty_like(tocc)
+    tbatch = hrpp.Batch([dict(bvh=tbvh, pred=tpred, rays=tr_d, query="any", out=tgo)])
+
+    def tiny_graph():
+        tpred.reset()
+        tbatch.launch(use_graph=True)
+
+    ms_t_g = timed(torch, tiny_graph, args.steps, 2)[0]
+    torch.cuda.synchronize()
+    if not torch.equal(tgo, eager_out):
+        raise SystemExit("tiny configuration: the graph-replayed batch differs from the eager call")
+    tbatch.close()
+    ms_t_p = timed(torch, lambda: hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc), args.steps, 2)[0]
+    tsh, tsp = hrpp.new_stats(), hrpp.new_stats()
+    tpred.reset()
+    hrpp.trace_anyhit(tbvh, tpred, tr_d, out=tocc, stats=tsh)
+    hrpp.trace_anyhit(tbvh, None, tr_d, out=tocc, stats=tsp)
+    th, tp = hrpp.stats_dict(tsh), hrpp.stats_dict(tsp)
+    nt = trays.shape[0]
+    return dict(rays=nt, query="any hit", epoch_rays=tw["epoch"], hrpp_mrays_s=round(mrays(nt, ms_t_h), 2),
+                graph_hrpp_mrays_s=round(mrays(nt, ms_t_g), 2), graph_hrpp_ms=round(ms_t_g, 4),
+                plain_mrays_s=round(mrays(nt, ms_t_p), 2), hrpp_ms=round(ms_t_h, 4),
+                plain_ms=round(ms_t_p, 4), pct_nodes_skipped=round(pct_saved("nodes_visited", th, tp), 3),
+                pct_box_tests_skipped=round(pct_saved("box_tests", th, tp), 3),
+                prediction_hit_rate=round(th["pred_hits"] / nt, 4),
+                occluded_fraction=round(th["hits"] / nt, 4))
+
 
 
 def run_progressive(args, np, torch, hrpp, sg):
